@@ -1,0 +1,59 @@
+"""Error measures of Appendix B and related checks.
+
+With the ALF sign convention (+lam^T (A(X) - b)) the dual multiplier of the
+standard-form dual max b^T y s.t. C - A*(y) PSD is y = -lam, so the dual slack
+is S = C + A*(lam).  The appendix writes the smallest singular value of the
+slack; since min{0, .} of a singular value is always 0 the only meaningful
+reading is the smallest eigenvalue, which is what is computed.
+
+  primal infeasibility  ||A(X) - b||_2 / (1 + ||b||_1)
+  dual infeasibility    |min(0, lambda_min(C - A*(y)))| / (1 + ||vec C||_1)
+  primal-dual gap       (<C, X> - b^T y) / (1 + |<C, X>| + |b^T y|)
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse.linalg as spla
+
+from . import operators
+
+
+def lambda_min(prob, lam) -> float:
+    S = operators.assemble(prob, lam, 1.0)
+    if prob.n <= 2500:
+        return float(np.linalg.eigvalsh(S.toarray())[0])
+    vals = spla.eigsh(S, k=1, which="SA", tol=1e-10, maxiter=20000,
+                      v0=np.ones(prob.n) / np.sqrt(prob.n))[0]
+    return float(vals[0])
+
+
+def appendix_b(prob, U, lam):
+    nrm = operators.norms(prob)
+    z = operators.forward(prob, U, U)
+    obj = operators.cost_inner(prob, U, U)
+    y = -np.asarray(lam)
+    by = float(prob.b @ y)
+    lmin = lambda_min(prob, lam)
+    return dict(
+        obj=obj,
+        dual_obj=by,
+        pinf=float(np.linalg.norm(z - prob.b)) / (1.0 + nrm["b_1"]),
+        pinf_inf=float(np.linalg.norm(z - prob.b)) / (1.0 + nrm["b_inf"]),
+        dinf=abs(min(0.0, lmin)) / (1.0 + nrm["c_1"]),
+        gap=(obj - by) / (1.0 + abs(obj) + abs(by)),
+        lambda_min=lmin,
+    )
+
+
+def mc_recovery_error(prob, U):
+    """||U1 U2^T - M||_F / ||M||_F with M = L R^T (the off-diagonal block of
+    X = U U^T estimates M under the halved completion scaling)."""
+    n1 = prob.meta["n1"]
+    L, R = prob.meta["L"], prob.meta["R"]
+    U1, U2 = U[:n1], U[n1:]
+    # Frobenius norms through small Gram matrices
+    g11, g22 = U1.T @ U1, U2.T @ U2
+    lu, ru = L.T @ U1, R.T @ U2
+    ll, rr = L.T @ L, R.T @ R
+    e2 = np.sum(g11 * g22) - 2.0 * np.sum(lu * ru) + np.sum(ll * rr)
+    return float(np.sqrt(max(e2, 0.0)) / np.sqrt(np.sum(ll * rr)))

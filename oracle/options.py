@@ -1,0 +1,77 @@
+"""Solver parameters of the oracle.
+
+Values fixed by the paper (Section 5.1 and 5.2):
+  * rho grows by 1.2 every 5 ADMM iterations up to rho_max = 5000;
+  * the ADMM iteration cap is 5000;
+  * the rank grows by a factor 1.5 when the warm-start subproblems get hard;
+  * the phase switch happens at primal infeasibility 1e-2 for MaxCut, 1e-3
+    otherwise; rho is multiplied by a heuristic factor h at the switch.
+
+Readings where the paper is silent (the GPU library implements the same rules):
+  * gamma is constant over the ADMM run, gamma = 1 + ||C||_F / sqrt(n): the
+    penalty on U - V in units of the cost's per-row scale.  (Tying gamma to rho
+    makes the proximal term dominate once rho reaches rho_max and the method
+    stalls; much smaller gamma lets U and V drift apart and diverge.)
+  * CG stops at ||R|| <= tau ||R0||, tau = min(0.1, max(floor, 0.01 * KKT_prev)),
+    at most min(n r, 2000) iterations, warm start x0 = the other factor;
+  * ALM: L-BFGS memory 4 with exact quartic line search; inner stop
+    ||grad||_F / (1 + ||C||_F) <= max(0.1 v, 1e-8); multipliers updated when the
+    infeasibility v fell below 0.25 of its last value at an update, otherwise
+    rho *= 10; rho0 = 1/max(1, ||b||_inf);
+  * rank growth: an inner solve that reaches 300 iterations stops, the rank
+    becomes min(ceil(1.5 r), floor(sqrt(2m)), n), new columns are
+    N(0, (1e-3 ||U||_F / sqrt(n r))^2) from the counter-based SplitMix64 stream.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+
+@dataclasses.dataclass
+class Options:
+    eps: float = 1e-6              # final KKT tolerance on eq. (stop)
+    switch_tol: float = 1e-3       # phase-I exit on primal infeasibility
+    h: float = 1.0                 # rho factor at the phase switch
+    rho_growth: float = 1.2
+    rho_every: int = 5
+    rho_max: float = 5000.0
+    max_admm_iter: int = 5000
+    gamma_fixed: float = 0.0       # > 0: fixed gamma; 0: the scale rule below
+    gamma_scale: float = 1.0       # gamma = gamma_scale * (1 + ||C||_F / sqrt(n))
+    cg_tol_max: float = 0.1
+    cg_tol_floor: float = 1e-12
+    cg_tol_kkt: float = 1e-2
+    cg_maxit: int = 2000
+    lbfgs_mem: int = 4
+    alm_inner_max: int = 500
+    rank_grow_iters: int = 300
+    rank_factor: float = 1.5
+    r_max: int = 0                 # 0: floor(sqrt(2m)) capped by n
+    alm_inner_rel: float = 0.1
+    alm_inner_floor: float = 1e-8
+    alm_eta: float = 0.25
+    alm_rho_factor: float = 10.0
+    alm_outer_max: int = 200
+    rho0: float = 0.0              # 0: 1/max(1, ||b||_inf)
+    seed: int = 0                  # rank-growth column stream
+    phase1: bool = True
+
+    def gamma(self, c_fro: float, n: int) -> float:
+        if self.gamma_fixed > 0:
+            return self.gamma_fixed
+        return self.gamma_scale * (1.0 + c_fro / math.sqrt(n))
+
+    def rank_cap(self, n: int, m: int) -> int:
+        if self.r_max > 0:
+            return min(self.r_max, n)
+        return max(1, min(int(math.floor(math.sqrt(2.0 * m))), n))
+
+
+def paper_defaults(kind: str, n: int) -> dict:
+    """Switch tolerance and heuristic factor h of Section 5.1 by problem family."""
+    if kind == "maxcut":
+        return dict(switch_tol=1e-2, h=10.0)
+    if kind == "mc":
+        return dict(switch_tol=1e-3, h=5.0 if n < 10000 else 2.5)
+    return dict(switch_tol=1e-3, h=1.0)
