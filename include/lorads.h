@@ -1,0 +1,228 @@
+/*
+ * lorads.h -- C ABI of the MI355X (gfx950) LoRADS hot-path library.
+ *
+ * Problem (the linear SDP of Section 1 of "A Low-Rank ADMM Splitting Approach
+ * for Semidefinite Programming"):
+ *
+ *     min <C, X>   s.t.   <A_i, X> = b_i  (i < m),   X PSD of order n.
+ *
+ * The library solves it by the two-phase method of Algorithm 2: a
+ * Burer-Monteiro augmented Lagrangian warm start with dynamic rank (Sections
+ * 4.1-4.3) followed by the ADMM of Algorithm 1 on the split problem, whose U-
+ * and V-subproblems (eqs. linU/linV) are solved by warm-started CG
+ * (Section 4.4).
+ *
+ * Conventions shared by every entry point
+ *  - Symmetric sparse matrices (C and each A_i) arrive as upper-triangle COO
+ *    triplets (row <= col); an off-diagonal triplet (j, k, v) stands for both
+ *    (j, k) and (k, j).  Duplicate triplets are summed.
+ *  - Factor matrices (U, V, W, P, R, X) are dense, row-major, n rows, r
+ *    columns, leading dimension ld >= r (elements between rows are ignored
+ *    and never written).
+ *  - Pointers named "device" are HIP device pointers owned by the caller
+ *    (e.g. torch tensor data_ptr()); pointers named "host" are host memory
+ *    owned by the caller.  The library never frees caller memory.
+ *  - Constraint-indexed vectors (b, z, w, lambda) use the caller's constraint
+ *    numbering (the a_con ids of the problem).
+ *  - dtype selects the element type of every floating-point device array of
+ *    the call: LORADS_F64 (double) or LORADS_F32 (float).  Arithmetic inside
+ *    a call is done in that type, with FP64 accumulation of reductions.
+ *  - stream is a hipStream_t (NULL = the default stream).  Calls enqueue work
+ *    on it and return without waiting, unless stated otherwise.
+ *  - Errors are returned as lorads_status, never thrown across the ABI.  On an
+ *    error the outputs are unspecified; lorads_last_error() gives a message.
+ *  - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef LORADS_H
+#define LORADS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lorads_ctx lorads_ctx;
+
+typedef enum {
+  LORADS_OK = 0,
+  LORADS_MAXITER = 1,    /* iteration cap reached before the tolerance */
+  LORADS_TIMELIMIT = 2,  /* time limit reached before the tolerance */
+  LORADS_EINVAL = -1,    /* invalid argument or malformed problem */
+  LORADS_ENOMEM = -2,    /* device allocation failed */
+  LORADS_EDEVICE = -3,   /* HIP runtime error */
+  LORADS_ENUMERIC = -4,  /* non-finite value met during a solve */
+  LORADS_ESTATE = -5     /* call out of order (e.g. solution before solve) */
+} lorads_status;
+
+typedef enum { LORADS_F64 = 0, LORADS_F32 = 1 } lorads_dtype;
+
+/* Constraint structure detected by lorads_setup. */
+typedef enum {
+  LORADS_STRUCT_GENERIC = 0, /* any sparse symmetric A_i */
+  LORADS_STRUCT_DIAG = 1,    /* every A_i = a_i e_j e_j^T (MaxCut: diag(X) = 1) */
+  LORADS_STRUCT_PAIR = 2     /* every A_i = a_i (e_j e_k^T + e_k e_j^T), j < k
+                                (matrix completion) */
+} lorads_structure;
+
+/* One SDP instance, host memory, caller-owned; lorads_setup copies it. */
+typedef struct {
+  int32_t n;                 /* order of X, >= 1 */
+  int32_t m;                 /* number of constraints, >= 1 */
+  int64_t c_nnz;             /* C triplets (may be 0: C = 0) */
+  const int32_t *c_row;      /* [c_nnz], 0 <= row <= col < n */
+  const int32_t *c_col;      /* [c_nnz] */
+  const double *c_val;       /* [c_nnz], finite */
+  int64_t a_nnz;             /* triplets of all A_i together, >= 1 */
+  const int32_t *a_con;      /* [a_nnz], constraint id in [0, m) */
+  const int32_t *a_row;      /* [a_nnz], 0 <= row <= col < n */
+  const int32_t *a_col;      /* [a_nnz] */
+  const double *a_val;       /* [a_nnz], finite */
+  const double *b;           /* [m], finite */
+} lorads_problem;
+
+/* Solver parameters.  lorads_default_options() fills the documented defaults;
+ * fields marked (paper) are fixed by Section 5.1/5.2, the others are the
+ * library's rules where the paper is silent. */
+typedef struct {
+  int32_t precision;       /* LORADS_F64: plain FP64 method.  LORADS_F32: CG
+                              iterations in FP32 on FP32 copies of the fixed
+                              factor; U, V, lambda, right-hand sides, dual
+                              updates, decisions and residuals stay FP64 */
+  double eps;              /* final tolerance on eq. (stop), default 1e-6 */
+  double switch_tol;       /* phase-I exit on primal infeasibility (paper:
+                              1e-2 MaxCut, 1e-3 otherwise) */
+  double h;                /* rho factor at the phase switch (paper) */
+  double rho_growth;       /* 1.2 (paper) */
+  int32_t rho_every;       /* 5 (paper) */
+  double rho_max;          /* 5000 (paper) */
+  int32_t max_admm_iter;   /* 5000 (paper) */
+  double time_limit;       /* seconds; <= 0: none */
+  double gamma_fixed;      /* > 0: fixed gamma; 0: the library's gamma rule */
+  double gamma_scale;      /* gamma rule: gamma = gamma_scale * (1 + ||C||_F / sqrt(n)) */
+  double cg_tol_max;       /* CG relative tolerance tau = min(cg_tol_max, */
+  double cg_tol_floor;     /*   max(cg_tol_floor, cg_tol_kkt * KKT_prev))  */
+  double cg_tol_kkt;
+  int32_t cg_maxit;        /* cap min(n r, cg_maxit) */
+  int32_t lbfgs_mem;       /* L-BFGS memory, default 4 */
+  int32_t alm_inner_max;   /* inner iteration cap at the rank cap, 500 */
+  int32_t rank_grow_iters; /* an inner solve reaching this count grows the rank, 300 */
+  double rank_factor;      /* 1.5 (paper) */
+  int32_t r0;              /* initial rank (> 0 required unless init_U given) */
+  int32_t r_max;           /* rank cap; 0: min(floor(sqrt(2m)), n) */
+  double alm_inner_rel;    /* inner stop ||grad||/(1+||C||_F) <= max(rel v, floor) */
+  double alm_inner_floor;
+  double alm_eta;          /* multiplier update when v <= eta * v_at_last_update */
+  double alm_rho_factor;   /* otherwise rho *= factor */
+  int32_t alm_outer_max;
+  double rho0;             /* phase-I initial rho; 0: 1/max(1, ||b||_inf) */
+  uint64_t seed;           /* SplitMix64 stream for rank-growth columns */
+  int32_t phase1;          /* 1: run the warm start; 0: start ADMM at init_U */
+  int32_t verbose;         /* 0 silent, 1 per-phase summary, 2 per iteration */
+  /* per-problem starting points, host, caller-owned, arrays of nprob pointers
+     (NULL or a NULL entry: not given).  init_U[p] is n x r0 row-major; without
+     it the problem cannot be solved (the random start is an input).
+     init_lambda[p] has m entries in the caller's constraint order. */
+  const double *const *init_U;
+  const double *const *init_lambda;
+} lorads_options;
+
+typedef struct {
+  int32_t status;          /* lorads_status of this problem */
+  int32_t rank;            /* final rank r */
+  int32_t alm_outer, alm_inner, rank_growths;
+  int32_t admm_iters;
+  int64_t cg_iters;        /* total CG iterations of phase II */
+  double obj;              /* <C, U_hat U_hat^T>, U_hat = (U + V)/2 */
+  double dual_obj;         /* b^T y with y = -lambda */
+  double pinf;             /* ||A(X) - b||_2 / (1 + ||b||_1)      (App. B) */
+  double dinf;             /* |min(0, lambda_min(C - A*(y)))| / (1 + ||vec C||_1) */
+  double gap;              /* (<C,X> - b^T y) / (1 + |<C,X>| + |b^T y|) */
+  double lambda_min;       /* smallest eigenvalue of the dual slack */
+  double kkt;              /* final value of eq. (stop) */
+  double pinf_stop;        /* ||A(UV^T) - b||_2 / (1 + ||b||_inf) at exit */
+  double dres_stop;        /* gamma ||V+ - V||_F / (1 + ||V||_F) at exit */
+  double rho, gamma;       /* final penalties */
+  double t_phase1, t_phase2, t_metrics, t_total;   /* seconds */
+  double op_bytes;         /* algorithmic bytes of every A(.) / A*(.)V / CG
+                              operator application of the solve */
+} lorads_result;
+
+/* Fill *opt with the defaults above (precision F64, eps 1e-6, switch 1e-3,
+ * h 1, ...). */
+void lorads_default_options(lorads_options *opt);
+
+/* Validate and ingest nprob problems onto the current HIP device.
+ * Checks: n, m >= 1; indices in range; row <= col; finite values; every
+ * constraint has at least one triplet.  Detects the structure class of each
+ * problem, builds the device layouts and reorders constraints internally.
+ * nprob > 1 enables the batched solve.  Returns EINVAL before touching the
+ * device when the input is malformed.  *out receives the new context. */
+lorads_status lorads_setup(const lorads_problem *probs, int32_t nprob, lorads_ctx **out);
+
+/* Structure class, n and m of problem `prob`. */
+lorads_status lorads_problem_info(const lorads_ctx *ctx, int32_t prob, int32_t *structure,
+                                  int32_t *n, int32_t *m);
+
+/* z = A(U V^T), z_i = <A_i, U V^T> (definition of the linear map, Section 1).
+ * U, V: device, n x r (ld); z: device, m.  Enqueued on stream. */
+lorads_status lorads_apply_A(lorads_ctx *ctx, int32_t prob, const void *U, const void *V,
+                             int32_t r, int32_t ld, void *z, int32_t dtype, void *stream);
+
+/* out = (c_scale C + A*(w)) V with A*(w) = sum_i w_i A_i: the products in the
+ * subproblem optimality conditions (optU)/(optV) and the right-hand sides of
+ * (linU)/(linV).  w: device, m; V, out: device, n x r (ld). */
+lorads_status lorads_apply_AT_V(lorads_ctx *ctx, int32_t prob, const void *w, double c_scale,
+                                const void *V, int32_t r, int32_t ld, void *out,
+                                int32_t dtype, void *stream);
+
+/* Solve the subproblem system of (linU)/(linV),
+ *     gamma X + rho A*(A(X W^T)) W = R,
+ * by unpreconditioned CG (Section 4.4) on the n x r matrix space with the
+ * Frobenius inner product, starting from the content of X (device, in: x0,
+ * out: solution).  Stops when ||R - M X||_F <= tol ||R - M x0||_F or after
+ * maxit iterations.  W, R, X: device n x r (ld).  Blocks the host until done;
+ * *iters and *relres (host, may be NULL) receive the iteration count and the
+ * final relative residual.  Returns MAXITER if the tolerance was not met. */
+lorads_status lorads_cg_solve(lorads_ctx *ctx, int32_t prob, const void *W, double rho,
+                              double gamma, const void *R, void *X, int32_t r, int32_t ld,
+                              double tol, int32_t maxit, int32_t dtype, int32_t *iters,
+                              double *relres, void *stream);
+
+/* Full two-phase solve (Algorithm 2) of every problem of the context; with
+ * nprob > 1 all problems advance together in batched launches.  res: host
+ * array of nprob results.  Blocks the host until done.  Returns the worst
+ * per-problem status. */
+lorads_status lorads_admm_solve(lorads_ctx *ctx, const lorads_options *opt, lorads_result *res);
+
+/* Copy the last solution of problem `prob` to host buffers (any may be NULL):
+ * U, V: n x rank row-major; lambda: m (caller order).  ESTATE before a solve. */
+lorads_status lorads_get_solution(const lorads_ctx *ctx, int32_t prob, double *U, double *V,
+                                  double *lambda);
+
+/* G = A^T B for tall-skinny A (n x ra, lda) and B (n x rb, ldb), FP64, with
+ * gfx950 FP64 MFMA tiles; G: device ra x rb row-major.  The r x r Gram
+ * products used for ||X||_F and the completion recovery error. */
+lorads_status lorads_gram(const void *A, const void *B, int64_t n, int32_t ra, int32_t rb,
+                          int32_t lda, int32_t ldb, void *G, void *stream);
+
+/* Smallest eigenvalue of the dual slack C + A*(lambda) (= C - A*(y), y = -lambda)
+ * by Lanczos with full reorthogonalisation (Appendix B's dual infeasibility).
+ * lambda: device, m, FP64, caller order.  Blocks the host. */
+lorads_status lorads_dual_lambda_min(lorads_ctx *ctx, int32_t prob, const void *lambda,
+                                     int32_t max_steps, double *out);
+
+void lorads_destroy(lorads_ctx *ctx);
+
+/* Message for the last non-OK status of ctx (or of the last failed setup when
+ * ctx is NULL).  Valid until the next call on the same context. */
+const char *lorads_last_error(const lorads_ctx *ctx);
+
+/* Library version string. */
+const char *lorads_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LORADS_H */

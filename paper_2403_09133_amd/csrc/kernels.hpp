@@ -1,0 +1,436 @@
+// Device kernels of the LoRADS hot path for gfx950 (wave64).
+//
+// Factor matrices are row-major (row j = the r-vector of node j).  A row is
+// handled by a group of G lanes (G = power of two >= r, at most 64); lane c of
+// the group owns columns c, c + G, ...  Reductions inside a group use wave
+// shuffles (xor butterflies never leave an aligned group), reductions across a
+// grid use per-block partial sums finished by the last block to arrive
+// (device-scope fence + atomic ticket), so every sum has a fixed order and
+// results are bitwise reproducible run to run.
+#pragma once
+
+#include "common.hpp"
+
+namespace lorads {
+
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  // wave reduction then across the 4 waves of a 256-thread block
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) t += sh[i];
+  }
+  return t;  // valid in thread 0
+}
+
+// Publish this block's partial; returns true in thread 0 of the last block to
+// finish, after which `part[0..nblocks)` is complete and visible.
+__device__ __forceinline__ bool last_block(double partial, double* part, int* counter) {
+  __shared__ bool is_last;
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = partial;
+    __threadfence();
+    const int ticket = atomicAdd(counter, 1);
+    is_last = (ticket == (int)gridDim.x - 1);
+    if (is_last) __threadfence();
+  }
+  __syncthreads();
+  return is_last && threadIdx.x == 0;
+}
+
+__device__ __forceinline__ double sum_parts(const double* part, int n) {
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += part[i];
+  return s;
+}
+
+// ===========================================================================
+// K1 (generic): forward map z_i = <A_i, U V^T> over the constraint-CSR.
+//   MODE 0: z = scale * A(U V^T)
+//   MODE 1: z = A(U V^T), w = lam + rho (z - b)          (FP64 z, w)
+//   MODE 2: z = sc[S_RHO] * A(U V^T), skipped once the CG has converged
+// One group of G lanes per constraint; lanes split the r columns.
+// ===========================================================================
+template <typename T, int G, int MODE>
+__global__ void __launch_bounds__(kBlock) k1_generic(
+    int m, const int* __restrict__ kptr, const int* __restrict__ krow,
+    const int* __restrict__ kcol, const T* __restrict__ kval, const T* __restrict__ U,
+    const T* __restrict__ V, int r, int ld, T* __restrict__ z, double scale,
+    const double* __restrict__ lam, const double* __restrict__ b, double rho,
+    double* __restrict__ w, const double* __restrict__ sc, int parity) {
+  if (MODE == 2 && sc[S_DONE + parity] != 0.0) return;
+  const int gid = (blockIdx.x * kBlock + threadIdx.x) / G;
+  const int lane = threadIdx.x & (G - 1);
+  if (gid >= m) return;
+  double acc = 0.0;
+  const int e0 = kptr[gid], e1 = kptr[gid + 1];
+  for (int e = e0; e < e1; ++e) {
+    const int j = krow[e], k = kcol[e];
+    const double a = (double)kval[e];
+    double s = 0.0;
+    for (int c = lane; c < r; c += G) {
+      s += (double)U[(size_t)j * ld + c] * (double)V[(size_t)k * ld + c];
+      if (j != k) s += (double)U[(size_t)k * ld + c] * (double)V[(size_t)j * ld + c];
+    }
+    acc += a * s;
+  }
+  acc = group_sum<G>(acc);
+  if (lane == 0) {
+    if (MODE == 0) {
+      z[gid] = (T)(scale * acc);
+    } else if (MODE == 1) {
+      z[gid] = (T)acc;
+      w[gid] = lam[gid] + rho * (acc - b[gid]);
+    } else {
+      z[gid] = (T)(sc[S_RHO] * acc);
+    }
+  }
+}
+
+// ===========================================================================
+// K2 (generic): out = out_scale * (c_scale C + A*(w)) V over row-CSRs of C and of
+// the adjoint (entries (col, constraint, coef)).  One group per output row.
+//   MODE 0: plain adjoint product
+//   MODE 1: CG operator epilogue: out = gamma P + A*(w) V (w already holds
+//           rho * A(P W^T)), accumulates <P, out>; the last block turns the
+//           sum into the CG step length (or flags a breakdown).
+// ===========================================================================
+template <typename T, int G, int MODE>
+__global__ void __launch_bounds__(kBlock) k2_generic(
+    int n, const int* __restrict__ cptr, const int* __restrict__ ccol,
+    const T* __restrict__ cval, double c_scale, const int* __restrict__ aptr,
+    const int* __restrict__ acol, const int* __restrict__ acon, const T* __restrict__ aval,
+    const T* __restrict__ w, const T* __restrict__ V, int r, int ld, T* __restrict__ out,
+    int ldo, double out_scale,
+    // MODE 1
+    const T* __restrict__ P, double* __restrict__ sc, int parity, double* __restrict__ part,
+    int* __restrict__ counter) {
+  __shared__ double sh[kBlock / 64];
+  if (MODE == 1 && sc[S_DONE + parity] != 0.0) return;
+  const int row = (blockIdx.x * kBlock + threadIdx.x) / G;
+  const int lane = threadIdx.x & (G - 1);
+  constexpr int MAXC = 4;  // columns per lane held in registers (r <= 4 G)
+  double acc[MAXC];
+#pragma unroll
+  for (int t = 0; t < MAXC; ++t) acc[t] = 0.0;
+  double pq = 0.0;
+  if (row < n) {
+    if (c_scale != 0.0) {
+      for (int e = cptr[row]; e < cptr[row + 1]; ++e) {
+        const int k = ccol[e];
+        const double a = c_scale * (double)cval[e];
+#pragma unroll
+        for (int t = 0; t < MAXC; ++t) {
+          const int c = lane + t * G;
+          if (c < r) acc[t] += a * (double)V[(size_t)k * ld + c];
+        }
+      }
+    }
+    for (int e = aptr[row]; w != nullptr && e < aptr[row + 1]; ++e) {
+      const int k = acol[e];
+      const double a = (double)w[acon[e]] * (double)aval[e];
+#pragma unroll
+      for (int t = 0; t < MAXC; ++t) {
+        const int c = lane + t * G;
+        if (c < r) acc[t] += a * (double)V[(size_t)k * ld + c];
+      }
+    }
+    if (MODE == 1) {
+      const double gamma = sc[S_GAMMA];
+#pragma unroll
+      for (int t = 0; t < MAXC; ++t) {
+        const int c = lane + t * G;
+        if (c < r) {
+          const double p = (double)P[(size_t)row * ld + c];
+          const T q = (T)(gamma * p + acc[t]);
+          out[(size_t)row * ldo + c] = q;
+          pq += p * (double)q;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < MAXC; ++t) {
+        const int c = lane + t * G;
+        if (c < r) out[(size_t)row * ldo + c] = (T)(out_scale * acc[t]);
+      }
+    }
+  }
+  if (MODE == 1) {
+    const double bs = block_sum(pq, sh);
+    if (last_block(bs, part, counter)) {
+      const double s = sum_parts(part, gridDim.x);
+      sc[S_PQ] = s;
+      if (!(s > 0.0)) {
+        sc[S_BRK] = 1.0;
+      } else {
+        sc[S_BRK] = 0.0;
+        sc[S_ALPHA] = sc[S_RR + parity] / s;
+      }
+      *counter = 0;
+    }
+  }
+}
+
+// ===========================================================================
+// CG vector steps on dense N = n r element buffers.
+// ===========================================================================
+// P = R, ||R||^2 -> S_RR0, S_RR(parity 0); clears the flags.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) cg_init(size_t N, const T* __restrict__ R,
+                                                  T* __restrict__ P, double tol2,
+                                                  double* __restrict__ sc,
+                                                  double* __restrict__ part,
+                                                  int* __restrict__ counter) {
+  __shared__ double sh[kBlock / 64];
+  double s = 0.0;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock) {
+    const T v = R[i];
+    P[i] = v;
+    s += (double)v * (double)v;
+  }
+  const double bs = block_sum(s, sh);
+  if (last_block(bs, part, counter)) {
+    const double rr = sum_parts(part, gridDim.x);
+    sc[S_RR0] = rr;
+    sc[S_RR + 0] = rr;
+    sc[S_RR + 1] = rr;
+    sc[S_DONE + 0] = (rr <= 0.0) ? 1.0 : 0.0;
+    sc[S_DONE + 1] = sc[S_DONE + 0];
+    sc[S_BRK] = 0.0;
+    sc[S_ITERS] = 0.0;
+    sc[S_TOL2] = tol2;
+    *counter = 0;
+  }
+}
+
+// X += alpha P; R -= alpha Q; ||R||^2 -> next parity slot; convergence flag.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) cg_update(size_t N, T* __restrict__ X,
+                                                    T* __restrict__ R, const T* __restrict__ P,
+                                                    const T* __restrict__ Q,
+                                                    double* __restrict__ sc, int parity,
+                                                    double* __restrict__ part,
+                                                    int* __restrict__ counter) {
+  __shared__ double sh[kBlock / 64];
+  const bool skip = sc[S_DONE + parity] != 0.0 || sc[S_BRK] != 0.0;
+  double s = 0.0;
+  if (!skip) {
+    const double alpha = sc[S_ALPHA];
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock) {
+      X[i] = (T)((double)X[i] + alpha * (double)P[i]);
+      const T rv = (T)((double)R[i] - alpha * (double)Q[i]);
+      R[i] = rv;
+      s += (double)rv * (double)rv;
+    }
+  }
+  const double bs = block_sum(s, sh);
+  if (last_block(bs, part, counter)) {
+    const int q = parity ^ 1;
+    if (sc[S_DONE + parity] != 0.0) {
+      sc[S_DONE + q] = 1.0;
+      sc[S_RR + q] = sc[S_RR + parity];
+    } else if (sc[S_BRK] != 0.0) {
+      sc[S_DONE + q] = 1.0;
+      sc[S_RR + q] = sc[S_RR + parity];
+    } else {
+      const double rr = sum_parts(part, gridDim.x);
+      sc[S_BETA] = rr / sc[S_RR + parity];
+      sc[S_RR + q] = rr;
+      sc[S_ITERS] += 1.0;
+      sc[S_DONE + q] = (rr <= sc[S_TOL2] * sc[S_RR0]) ? 1.0 : 0.0;
+    }
+    *counter = 0;
+  }
+}
+
+// P = R + beta P (skipped once converged).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) cg_direction(size_t N, const T* __restrict__ R,
+                                                       T* __restrict__ P,
+                                                       const double* __restrict__ sc,
+                                                       int parity) {
+  if (sc[S_DONE + parity] != 0.0 || sc[S_BRK] != 0.0) return;
+  const double beta = sc[S_BETA];
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock)
+    P[i] = (T)((double)R[i] + beta * (double)P[i]);
+}
+
+// ===========================================================================
+// generic dense helpers
+// ===========================================================================
+// sc[slot] = scale * <X, Y> over N elements (fixed grid -> fixed order)
+template <typename TX, typename TY>
+__global__ void __launch_bounds__(kBlock) dot_kernel(size_t N, const TX* __restrict__ X,
+                                                     const TY* __restrict__ Y, double scale,
+                                                     double* __restrict__ sc, int slot,
+                                                     double* __restrict__ part,
+                                                     int* __restrict__ counter) {
+  __shared__ double sh[kBlock / 64];
+  double s = 0.0;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock)
+    s += (double)X[i] * (double)Y[i];
+  const double bs = block_sum(s, sh);
+  if (last_block(bs, part, counter)) {
+    sc[slot] = scale * sum_parts(part, gridDim.x);
+    *counter = 0;
+  }
+}
+
+// Several dots over m-vectors for the quartic line search, in one pass:
+//   out[0] = p2.p2, [1] = p1.p2, [2] = p1.p1, [3] = p0.p2, [4] = p0.p1,
+//   [5] = lam.p1, [6] = lam.p2,   with p0 = z - b.
+static __global__ void __launch_bounds__(kBlock) linesearch_dots(int m, const double* __restrict__ z,
+                                                          const double* __restrict__ b,
+                                                          const double* __restrict__ p1,
+                                                          const double* __restrict__ p2,
+                                                          const double* __restrict__ lam,
+                                                          double* __restrict__ sc, int slot,
+                                                          double* __restrict__ part,
+                                                          int* __restrict__ counter) {
+  __shared__ double sh[kBlock / 64];
+  double s[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < m; i += gridDim.x * kBlock) {
+    const double a0 = z[i] - b[i], a1 = p1[i], a2 = p2[i], l = lam[i];
+    s[0] += a2 * a2; s[1] += a1 * a2; s[2] += a1 * a1; s[3] += a0 * a2;
+    s[4] += a0 * a1; s[5] += l * a1;  s[6] += l * a2;
+  }
+  __shared__ bool is_last;
+  double bs[7];
+  for (int t = 0; t < 7; ++t) bs[t] = block_sum(s[t], sh);
+  if (threadIdx.x == 0) {
+    for (int t = 0; t < 7; ++t) part[(size_t)t * gridDim.x + blockIdx.x] = bs[t];
+    __threadfence();
+    is_last = atomicAdd(counter, 1) == (int)gridDim.x - 1;
+    if (is_last) __threadfence();
+  }
+  __syncthreads();
+  if (is_last && threadIdx.x == 0) {
+    for (int t = 0; t < 7; ++t) sc[slot + t] = sum_parts(part + (size_t)t * gridDim.x, gridDim.x);
+    *counter = 0;
+  }
+}
+
+// Dual update lam += rho (z - b) and sc[slot] = ||z - b||^2.
+static __global__ void __launch_bounds__(kBlock) dual_update(int m, const double* __restrict__ z,
+                                                      const double* __restrict__ b,
+                                                      double rho, double* __restrict__ lam,
+                                                      double* __restrict__ sc, int slot,
+                                                      double* __restrict__ part,
+                                                      int* __restrict__ counter) {
+  __shared__ double sh[kBlock / 64];
+  double s = 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < m; i += gridDim.x * kBlock) {
+    const double d = z[i] - b[i];
+    lam[i] += rho * d;
+    s += d * d;
+  }
+  const double bs = block_sum(s, sh);
+  if (last_block(bs, part, counter)) {
+    sc[slot] = sum_parts(part, gridDim.x);
+    *counter = 0;
+  }
+}
+
+// y = a * x + b * y  (elementwise, mixed types allowed)
+template <typename TX, typename TY>
+__global__ void __launch_bounds__(kBlock) axpby(size_t N, double a, const TX* __restrict__ x,
+                                                double b, TY* __restrict__ y) {
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock)
+    y[i] = (TY)(a * (double)x[i] + b * (double)y[i]);
+}
+
+// y = a * x + b * y with a = sign * sc[slot] (device-resident coefficient)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) axpby_dev(size_t N, const double* __restrict__ sc,
+                                                    int slot, double sign, const T* __restrict__ x,
+                                                    double b, T* __restrict__ y) {
+  const double a = sign * sc[slot];
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock)
+    y[i] = (T)(a * (double)x[i] + b * (double)y[i]);
+}
+
+// z = x + y (z may alias x or y), with conversion
+template <typename TX, typename TY, typename TZ>
+__global__ void __launch_bounds__(kBlock) add_kernel(size_t N, const TX* __restrict__ x,
+                                                     const TY* __restrict__ y, TZ* __restrict__ z) {
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock)
+    z[i] = (TZ)((double)x[i] + (double)y[i]);
+}
+
+template <typename TS, typename TD>
+__global__ void __launch_bounds__(kBlock) convert_kernel(size_t N, const TS* __restrict__ s,
+                                                         TD* __restrict__ d) {
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock)
+    d[i] = (TD)s[i];
+}
+
+// strided copy between row-major layouts (n rows, r columns)
+template <typename TS, typename TD>
+__global__ void __launch_bounds__(kBlock) copy_rows(int n, int r, const TS* __restrict__ s,
+                                                    int lds, TD* __restrict__ d, int ldd) {
+  const size_t N = (size_t)n * r;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock) {
+    const size_t j = i / r, c = i % r;
+    d[j * ldd + c] = (TD)s[j * lds + c];
+  }
+}
+
+// permutations of constraint-indexed vectors: dst[idx[i]] = src[i] / dst[i] = src[idx[i]]
+template <typename T>
+__global__ void __launch_bounds__(kBlock) scatter_kernel(int m, const int* __restrict__ idx,
+                                                         const T* __restrict__ src, T* __restrict__ dst) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < m; i += gridDim.x * kBlock) dst[idx[i]] = src[i];
+}
+template <typename T>
+__global__ void __launch_bounds__(kBlock) gather_kernel(int m, const int* __restrict__ idx,
+                                                        const T* __restrict__ src, T* __restrict__ dst) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < m; i += gridDim.x * kBlock) dst[i] = src[idx[i]];
+}
+
+// rank growth: new row-major layout with r_new columns; the first r_old copy
+// U, the rest are sigma * N(0,1) from the counter-based SplitMix64 stream
+// (Steele-Lea-Flood 2014) with Box-Muller, element t = j (r_new - r_old) + c'.
+__device__ __forceinline__ uint64_t splitmix_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+static __global__ void __launch_bounds__(kBlock) grow_rank_kernel(int n, int r_old, int r_new,
+                                                           const double* __restrict__ U,
+                                                           double* __restrict__ Unew,
+                                                           double sigma, uint64_t seed,
+                                                           uint64_t event) {
+  const size_t N = (size_t)n * r_new;
+  const int add = r_new - r_old;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock) {
+    const size_t j = i / r_new;
+    const int c = (int)(i % r_new);
+    if (c < r_old) {
+      Unew[i] = U[j * r_old + c];
+    } else {
+      const uint64_t t = (uint64_t)j * add + (uint64_t)(c - r_old);
+      const uint64_t k1 = (event << 40) + 2ull * t + 1ull;
+      const uint64_t k2 = k1 + 1ull;
+      const uint64_t g = 0x9E3779B97F4A7C15ull;
+      const double u1 = ((double)(splitmix_mix(seed + k1 * g) >> 11) + 1.0) * 0x1.0p-53;
+      const double u2 = (double)(splitmix_mix(seed + k2 * g) >> 11) * 0x1.0p-53;
+      Unew[i] = sigma * sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+    }
+  }
+}
+
+}  // namespace lorads

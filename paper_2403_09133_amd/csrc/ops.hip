@@ -1,0 +1,252 @@
+// Operator dispatch (generic / DIAG / PAIR layouts) and the device-resident CG.
+#include "kernels.hpp"
+#include "kernels_struct.hpp"
+#include "problem.hpp"
+
+namespace lorads {
+
+#define LORADS_DISPATCH_G(Gval, CALL)                   \
+  switch (Gval) {                                       \
+    case 1: { constexpr int G = 1; CALL; } break;       \
+    case 2: { constexpr int G = 2; CALL; } break;       \
+    case 4: { constexpr int G = 4; CALL; } break;       \
+    case 8: { constexpr int G = 8; CALL; } break;       \
+    case 16: { constexpr int G = 16; CALL; } break;     \
+    case 32: { constexpr int G = 32; CALL; } break;     \
+    default: { constexpr int G = 64; CALL; } break;     \
+  }
+
+template <typename T> static const T* kv(const Problem& P);
+template <> const double* kv<double>(const Problem& P) { return P.kval.p; }
+template <> const float* kv<float>(const Problem& P) { return P.kvalf.p; }
+template <typename T> static const T* av(const Problem& P);
+template <> const double* av<double>(const Problem& P) { return P.aval.p; }
+template <> const float* av<float>(const Problem& P) { return P.avalf.p; }
+template <typename T> static const T* cv(const Problem& P);
+template <> const double* cv<double>(const Problem& P) { return P.cval.p; }
+template <> const float* cv<float>(const Problem& P) { return P.cvalf.p; }
+template <typename T> static const T* dc(const Problem& P);
+template <> const double* dc<double>(const Problem& P) { return P.dcoef.p; }
+template <> const float* dc<float>(const Problem& P) { return P.dcoeff.p; }
+template <typename T> static const T* ds(const Problem& P);
+template <> const double* ds<double>(const Problem& P) { return P.dsq.p; }
+template <> const float* ds<float>(const Problem& P) { return P.dsqf.p; }
+template <typename T> static const T* pc(const Problem& P);
+template <> const double* pc<double>(const Problem& P) { return P.pcoef.p; }
+template <> const float* pc<float>(const Problem& P) { return P.pcoeff.p; }
+
+static int rows_grid(int rows, int G) {
+  const long long threads = (long long)rows * G;
+  return (int)std::max<long long>(1, (threads + kBlock - 1) / kBlock);
+}
+
+// ---------------------------------------------------------------------------
+template <typename T>
+void op_forward(Problem& P, const T* U, const T* V, int r, int ld, T* z, double scale,
+                hipStream_t s) {
+  const int G = pow2_group(r);
+  if (P.structure == LORADS_STRUCT_DIAG) {
+    LORADS_DISPATCH_G(G, (k1_diag<T, G, 0><<<rows_grid(P.m, G), kBlock, 0, s>>>(
+                             P.m, P.drow.p, dc<T>(P), U, V, r, ld, z, scale, nullptr, nullptr,
+                             0.0, nullptr, nullptr, 0)));
+  } else if (P.structure == LORADS_STRUCT_PAIR) {
+    LORADS_DISPATCH_G(G, (k1_pair<T, G, 0><<<rows_grid(P.m, G), kBlock, 0, s>>>(
+                             P.m, P.pj.p, P.pk.p, pc<T>(P), P.pair_coef, U, V, r, ld, z, scale,
+                             nullptr, nullptr, 0.0, nullptr, nullptr, 0)));
+  } else {
+    LORADS_DISPATCH_G(G, (k1_generic<T, G, 0><<<rows_grid(P.m, G), kBlock, 0, s>>>(
+                             P.m, P.kptr.p, P.krow.p, P.kcol.p, kv<T>(P), U, V, r, ld, z, scale,
+                             nullptr, nullptr, 0.0, nullptr, nullptr, 0)));
+  }
+  HIPCHK(hipGetLastError());
+}
+
+void op_forward_w(Problem& P, const double* U, const double* V, int r, int ld, double* z,
+                  double* w, const double* lam, double rho, hipStream_t s) {
+  const int G = pow2_group(r);
+  if (P.structure == LORADS_STRUCT_DIAG) {
+    LORADS_DISPATCH_G(G, (k1_diag<double, G, 1><<<rows_grid(P.m, G), kBlock, 0, s>>>(
+                             P.m, P.drow.p, P.dcoef.p, U, V, r, ld, z, 1.0, lam, P.b.p, rho, w,
+                             nullptr, 0)));
+  } else if (P.structure == LORADS_STRUCT_PAIR) {
+    LORADS_DISPATCH_G(G, (k1_pair<double, G, 1><<<rows_grid(P.m, G), kBlock, 0, s>>>(
+                             P.m, P.pj.p, P.pk.p, P.pcoef.p, P.pair_coef, U, V, r, ld, z, 1.0,
+                             lam, P.b.p, rho, w, nullptr, 0)));
+  } else {
+    LORADS_DISPATCH_G(G, (k1_generic<double, G, 1><<<rows_grid(P.m, G), kBlock, 0, s>>>(
+                             P.m, P.kptr.p, P.krow.p, P.kcol.p, P.kval.p, U, V, r, ld, z, 1.0,
+                             lam, P.b.p, rho, w, nullptr, 0)));
+  }
+  HIPCHK(hipGetLastError());
+}
+
+template <typename T>
+void op_adjoint(Problem& P, const T* w, double c_scale, const T* V, int r, int ld, T* out,
+                int ldo, double out_scale, hipStream_t s) {
+  const int G = pow2_group(r);
+  if (r > 4 * G) fail(LORADS_EINVAL, "rank above 256 is not supported");
+  if (P.structure == LORADS_STRUCT_DIAG) {
+    LORADS_DISPATCH_G(G, (k2_diag<T, G, 0><<<rows_grid(P.n, G), kBlock, 0, s>>>(
+                             P.n, P.cptr.p, P.ccol.p, cv<T>(P), c_scale, P.dptr.p, dc<T>(P),
+                             nullptr, w, V, r, ld, out, ldo, out_scale, nullptr, nullptr, 0,
+                             nullptr, nullptr)));
+  } else if (P.structure == LORADS_STRUCT_PAIR) {
+    LORADS_DISPATCH_G(G, (k2_pair<T, G, 0><<<rows_grid(P.n, G), kBlock, 0, s>>>(
+                             P.n, P.cptr.p, P.ccol.p, cv<T>(P), c_scale, P.rptr.p, P.pk.p,
+                             P.cvptr.p, P.cvj.p, P.cvid.p, pc<T>(P), P.pair_coef, w, V, nullptr,
+                             r, ld, out, ldo, out_scale, nullptr, 0, nullptr, nullptr)));
+  } else {
+    LORADS_DISPATCH_G(G, (k2_generic<T, G, 0><<<rows_grid(P.n, G), kBlock, 0, s>>>(
+                             P.n, P.cptr.p, P.ccol.p, cv<T>(P), c_scale, P.aptr.p, P.acol.p,
+                             P.acon.p, av<T>(P), w, V, r, ld, out, ldo, out_scale, nullptr,
+                             nullptr, 0, nullptr, nullptr)));
+  }
+  HIPCHK(hipGetLastError());
+}
+
+template <typename T>
+void op_cg(Problem& P, const T* W, int r, const T* Pd, T* Q, T* t, int parity, hipStream_t s) {
+  const int G = pow2_group(r);
+  if (r > 4 * G) fail(LORADS_EINVAL, "rank above 256 is not supported");
+  double* sc = P.sc.p;
+  if (P.structure == LORADS_STRUCT_DIAG) {
+    const int grid = rows_grid(P.n, G);
+    P.ensure_part(grid);
+    LORADS_DISPATCH_G(G, (k3_diag<T, G><<<grid, kBlock, 0, s>>>(
+                             P.n, ds<T>(P), W, Pd, Q, r, sc, parity, P.part.p,
+                             P.counters.p + C_OP)));
+  } else if (P.structure == LORADS_STRUCT_PAIR) {
+    const int grid = rows_grid(P.n, G);
+    P.ensure_part(grid);
+    LORADS_DISPATCH_G(G, (k2_pair<T, G, 1><<<grid, kBlock, 0, s>>>(
+                             P.n, nullptr, nullptr, nullptr, 0.0, P.rptr.p, P.pk.p, P.cvptr.p,
+                             P.cvj.p, P.cvid.p, pc<T>(P), P.pair_coef, nullptr, W, Pd, r, r, Q, r,
+                             1.0, sc, parity, P.part.p, P.counters.p + C_OP)));
+  } else {
+    LORADS_DISPATCH_G(G, (k1_generic<T, G, 2><<<rows_grid(P.m, G), kBlock, 0, s>>>(
+                             P.m, P.kptr.p, P.krow.p, P.kcol.p, kv<T>(P), Pd, W, r, r, t, 1.0,
+                             nullptr, nullptr, 0.0, nullptr, sc, parity)));
+    const int grid = rows_grid(P.n, G);
+    P.ensure_part(grid);
+    LORADS_DISPATCH_G(G, (k2_generic<T, G, 1><<<grid, kBlock, 0, s>>>(
+                             P.n, nullptr, nullptr, nullptr, 0.0, P.aptr.p, P.acol.p, P.acon.p,
+                             av<T>(P), t, W, r, r, Q, r, 1.0, Pd, sc, parity, P.part.p,
+                             P.counters.p + C_OP)));
+  }
+  HIPCHK(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// algorithmic bytes (indices, coefficients, inputs and outputs once each)
+// ---------------------------------------------------------------------------
+double bytes_forward(const Problem& P, int r, int s) {
+  const double nr = (double)P.n * r * s;
+  if (P.structure == LORADS_STRUCT_DIAG) return (double)P.m * (4 + s) + 2.0 * nr + (double)P.m * s;
+  if (P.structure == LORADS_STRUCT_PAIR)
+    return (double)P.m * 8 + (double)P.m * s + 2.0 * nr + (P.pcoef.n ? (double)P.m * s : 0.0);
+  return (double)P.a_nnz * (8 + s) + (double)(P.m + 1) * 4 + 2.0 * nr + (double)P.m * s;
+}
+
+double bytes_adjoint(const Problem& P, int r, int s, bool with_c) {
+  const double nr = (double)P.n * r * s;
+  const double cbytes = with_c ? (double)P.cval.n * (4 + s) + (double)(P.n + 1) * 4 : 0.0;
+  if (P.structure == LORADS_STRUCT_DIAG) return (double)P.m * (4 + 2 * s) + 2.0 * nr + cbytes;
+  if (P.structure == LORADS_STRUCT_PAIR)
+    return (double)P.m * 8 + (double)P.m * s + 2.0 * nr + cbytes + (P.pcoef.n ? (double)P.m * s : 0.0);
+  return (double)P.acol.n * (8 + s) + (double)(P.n + 1) * 4 + (double)P.m * s + 2.0 * nr + cbytes;
+}
+
+double bytes_cg_op(const Problem& P, int r, int s) {
+  const double nr = (double)P.n * r * s;
+  if (P.structure == LORADS_STRUCT_DIAG) return (double)P.n * s + 3.0 * nr;
+  if (P.structure == LORADS_STRUCT_PAIR) return (double)P.m * 8 + 3.0 * nr + (P.pcoef.n ? (double)P.m * s : 0.0);
+  return bytes_forward(P, r, s) + bytes_adjoint(P, r, s, false) + nr;
+}
+
+// ---------------------------------------------------------------------------
+__global__ void set_slots_kernel(double* sc, int slot, double v0, double v1, double v2, double v3,
+                                 int count) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const double v[4] = {v0, v1, v2, v3};
+    for (int i = 0; i < count; ++i) sc[slot + i] = v[i];
+  }
+}
+
+void set_slots(Problem& P, int slot, const double* vals, int count, hipStream_t s) {
+  for (int i = 0; i < count; i += 4) {
+    const int c = std::min(4, count - i);
+    double v[4] = {0, 0, 0, 0};
+    for (int t = 0; t < c; ++t) v[t] = vals[i + t];
+    set_slots_kernel<<<1, 64, 0, s>>>(P.sc.p, slot + i, v[0], v[1], v[2], v[3], c);
+  }
+  HIPCHK(hipGetLastError());
+}
+
+void read_slots(Problem& P, int slot, double* vals, int count, hipStream_t s) {
+  HIPCHK(hipMemcpyAsync(vals, P.sc.p + slot, count * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+template <typename TX, typename TY>
+void dot_to_slot(Problem& P, size_t N, const TX* X, const TY* Y, double scale, int slot,
+                 hipStream_t s) {
+  const int grid = grid_for(N, kRedBlocks);
+  dot_kernel<TX, TY><<<grid, kBlock, 0, s>>>(N, X, Y, scale, P.sc.p, slot, P.part.p,
+                                             P.counters.p + C_DOT);
+  HIPCHK(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// CG: solve M_W D = R from D = X (normally 0).  The loop runs in chunks of
+// device-resident iterations; after each chunk one flag is read back.
+// ---------------------------------------------------------------------------
+template <typename T>
+int cg_run(Problem& P, const T* W, int r, double rho, double gamma, T* R, T* X, T* Pd, T* Q,
+           T* t, double tol, int maxit, hipStream_t s, double* relres, double* op_bytes) {
+  const size_t N = (size_t)P.n * r;
+  const double sv[2] = {gamma, rho};
+  set_slots(P, S_GAMMA, sv, 2, s);
+  const int gridv = grid_for(N, 1024);
+  cg_init<T><<<gridv, kBlock, 0, s>>>(N, R, Pd, tol * tol, P.sc.p, P.part.p, P.counters.p + C_INIT);
+  HIPCHK(hipGetLastError());
+  int k = 0;
+  int chunk = 2;
+  constexpr int kRead = S_ITERS + 1;  // slots 0 .. S_ITERS
+  double h[kRead];
+  int iters = 0;
+  bool done = false;
+  while (!done && k < maxit) {
+    const int steps = std::min(chunk, maxit - k);
+    for (int i = 0; i < steps; ++i, ++k) {
+      const int par = k & 1;
+      op_cg<T>(P, W, r, Pd, Q, t, par, s);
+      cg_update<T><<<gridv, kBlock, 0, s>>>(N, X, R, Pd, Q, P.sc.p, par, P.part.p,
+                                            P.counters.p + C_UPD);
+      cg_direction<T><<<gridv, kBlock, 0, s>>>(N, R, Pd, P.sc.p, par);
+    }
+    HIPCHK(hipGetLastError());
+    read_slots(P, 0, h, kRead, s);
+    iters = (int)h[S_ITERS];
+    done = h[S_DONE + (k & 1)] != 0.0;
+    chunk = std::min(chunk * 2, 32);
+  }
+  read_slots(P, 0, h, kRead, s);
+  iters = (int)h[S_ITERS];
+  if (relres) *relres = h[S_RR0] > 0 ? std::sqrt(h[S_RR + (k & 1)] / h[S_RR0]) : 0.0;
+  if (op_bytes) *op_bytes += (double)iters * bytes_cg_op(P, r, sizeof(T));
+  return iters;
+}
+
+// explicit instantiations
+template void op_forward<double>(Problem&, const double*, const double*, int, int, double*, double, hipStream_t);
+template void op_forward<float>(Problem&, const float*, const float*, int, int, float*, double, hipStream_t);
+template void op_adjoint<double>(Problem&, const double*, double, const double*, int, int, double*, int, double, hipStream_t);
+template void op_adjoint<float>(Problem&, const float*, double, const float*, int, int, float*, int, double, hipStream_t);
+template void op_cg<double>(Problem&, const double*, int, const double*, double*, double*, int, hipStream_t);
+template void op_cg<float>(Problem&, const float*, int, const float*, float*, float*, int, hipStream_t);
+template void dot_to_slot<double, double>(Problem&, size_t, const double*, const double*, double, int, hipStream_t);
+template void dot_to_slot<float, float>(Problem&, size_t, const float*, const float*, double, int, hipStream_t);
+template int cg_run<double>(Problem&, const double*, int, double, double, double*, double*, double*, double*, double*, double, int, hipStream_t, double*, double*);
+template int cg_run<float>(Problem&, const float*, int, double, double, float*, float*, float*, float*, float*, double, int, hipStream_t, double*, double*);
+
+}  // namespace lorads

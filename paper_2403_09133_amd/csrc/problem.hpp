@@ -1,0 +1,126 @@
+// Host-side problem state of the library: ingest, device layouts, operators.
+#pragma once
+
+#include <memory>
+
+#include "common.hpp"
+
+namespace lorads {
+
+// Device layout of one SDP instance.
+//
+// Internal constraint order: the order in which constraint-indexed vectors
+// (b, z, w, lambda) live on the device.  `perm[i]` is the caller's id of
+// internal constraint i; when the caller's order is kept perm_identity is set
+// and no permutation is ever applied.
+struct Problem {
+  int n = 0, m = 0;
+  int structure = LORADS_STRUCT_GENERIC;
+  bool perm_identity = true;
+  double b_inf = 0, b_1 = 0, b_2 = 0, c_fro = 0, c_1 = 0;
+  int64_t a_nnz = 0, c_nnz = 0;
+
+  DevBuf<int> perm;  // internal -> caller id
+  DevBuf<double> b;  // internal order
+
+  // K1 generic: constraint-CSR of the upper-triangle triplets
+  DevBuf<int> kptr, krow, kcol;
+  DevBuf<double> kval;
+  DevBuf<float> kvalf;
+  // K2 generic: adjoint row-CSR (both triangles): entries (col, constraint, coef)
+  DevBuf<int> aptr, acol, acon;
+  DevBuf<double> aval;
+  DevBuf<float> avalf;
+  // cost matrix C, row-CSR of the full symmetric matrix
+  DevBuf<int> cptr, ccol;
+  DevBuf<double> cval;
+  DevBuf<float> cvalf;
+
+  // DIAG structure: constraint i (internal order) sits on row drow[i] with
+  // coefficient dcoef[i]; rows own contiguous constraint ranges dptr.
+  DevBuf<int> drow, dptr;
+  DevBuf<double> dcoef, dsq;  // dsq[j] = sum of coef^2 of the row's constraints
+  DevBuf<float> dcoeff, dsqf;
+
+  // PAIR structure: constraint i = (j, k), j < k, coefficient a (uniform when
+  // pcoef is empty: pair_coef).  Two row-owner views for the fused CG operator:
+  //   view R: rows j, entries sorted by (j, k) == internal order (ptr: rptr)
+  //   view C: rows k, entries (j, internal id) sorted by (k, j)  (ptr: cvptr)
+  DevBuf<int> pj, pk;          // internal order
+  DevBuf<double> pcoef;
+  DevBuf<float> pcoeff;
+  double pair_coef = 0;        // used when pcoef is empty
+  DevBuf<int> rptr;            // n+1: view R row pointers (rows owning entries as j)
+  DevBuf<int> cvptr, cvj, cvid;  // view C: row pointers, partner j, internal id
+
+  // solver scratch
+  DevBuf<double> sc;
+  DevBuf<double> part;
+  DevBuf<int> counters;
+  size_t part_cap = 0;
+
+  // last solution
+  int rank = 0;
+  bool solved = false;
+  DevBuf<double> U, V, lam;  // lam in internal order
+
+  // scratch m-vectors
+  DevBuf<double> zbuf, wbuf, tbuf, ubuf;
+  DevBuf<float> tbuff;
+
+  // The partial-sum buffer is sized once at setup (kernels may still read it,
+  // so it is never reallocated); launches that would need more are refused.
+  void ensure_part(size_t need) {
+    if (need > part_cap) fail(LORADS_EINVAL, "partial-sum buffer too small for this launch");
+  }
+};
+
+// host-only validation (throws EINVAL); ingest() validates and uploads
+void validate(const lorads_problem& p);
+std::unique_ptr<Problem> ingest(const lorads_problem& p, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// operators (enqueued on stream s; vectors in internal constraint order)
+// ---------------------------------------------------------------------------
+// z = scale * A(U V^T)
+template <typename T>
+void op_forward(Problem& P, const T* U, const T* V, int r, int ld, T* z, double scale, hipStream_t s);
+// z = A(U V^T) and w = lam + rho (z - b)   (FP64)
+void op_forward_w(Problem& P, const double* U, const double* V, int r, int ld, double* z,
+                  double* w, const double* lam, double rho, hipStream_t s);
+// out = out_scale * (c_scale C + A*(w)) V
+template <typename T>
+void op_adjoint(Problem& P, const T* w, double c_scale, const T* V, int r, int ld, T* out,
+                int ldo, double out_scale, hipStream_t s);
+// CG operator Q = gamma P + rho A*(A(P W^T)) W with device scalars in sc;
+// records the CG step length in sc (see cg_update).  t: m-vector scratch.
+template <typename T>
+void op_cg(Problem& P, const T* W, int r, const T* Pd, T* Q, T* t, int parity, hipStream_t s);
+
+// algorithmic bytes of one application (for throughput accounting)
+double bytes_forward(const Problem& P, int r, int s);
+double bytes_adjoint(const Problem& P, int r, int s, bool with_c);
+double bytes_cg_op(const Problem& P, int r, int s);
+
+// ---------------------------------------------------------------------------
+// reductions / small helpers
+// ---------------------------------------------------------------------------
+void set_slots(Problem& P, int slot, const double* vals, int count, hipStream_t s);
+void read_slots(Problem& P, int slot, double* vals, int count, hipStream_t s);  // synchronises
+template <typename TX, typename TY>
+void dot_to_slot(Problem& P, size_t N, const TX* X, const TY* Y, double scale, int slot, hipStream_t s);
+
+inline int grid_for(size_t N, int cap = 2048) {
+  size_t g = (N + kBlock - 1) / kBlock;
+  if (g < 1) g = 1;
+  if (g > (size_t)cap) g = cap;
+  return (int)g;
+}
+
+// CG on M_W D = R from D = X (X holds x0 = 0 normally; R holds R0 - M x0).
+// Buffers dense n x r of type T.  Returns iterations; *relres = ||R||/||R0||.
+template <typename T>
+int cg_run(Problem& P, const T* W, int r, double rho, double gamma, T* R, T* X, T* Pd, T* Q,
+           T* t, double tol, int maxit, hipStream_t s, double* relres, double* op_bytes);
+
+}  // namespace lorads

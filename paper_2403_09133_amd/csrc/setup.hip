@@ -1,0 +1,299 @@
+// lorads_setup: validation, structure detection and device layouts.
+#include <algorithm>
+#include <numeric>
+
+#include "problem.hpp"
+
+namespace lorads {
+
+[[noreturn]] void fail(lorads_status s, const std::string& msg) { throw Error{s, msg}; }
+
+namespace {
+
+void check(bool ok, const std::string& msg) {
+  if (!ok) fail(LORADS_EINVAL, msg);
+}
+
+// counting-sort style CSR build: keys in [0, nrows)
+void csr_counts(const std::vector<int>& key, int nrows, std::vector<int>& ptr) {
+  ptr.assign(nrows + 1, 0);
+  for (int k : key) ptr[k + 1]++;
+  for (int i = 0; i < nrows; ++i) ptr[i + 1] += ptr[i];
+}
+
+}  // namespace
+
+void validate(const lorads_problem& p) {
+  check(p.n >= 1, "n must be >= 1");
+  check(p.m >= 1, "m must be >= 1");
+  check(p.a_nnz >= 1, "a_nnz must be >= 1");
+  check(p.c_nnz >= 0, "c_nnz must be >= 0");
+  check(p.a_nnz < (int64_t)INT32_MAX / 2 && p.c_nnz < (int64_t)INT32_MAX / 2,
+        "too many triplets for 32-bit offsets");
+  check(p.a_con && p.a_row && p.a_col && p.a_val && p.b, "null constraint arrays");
+  check(p.c_nnz == 0 || (p.c_row && p.c_col && p.c_val), "null cost arrays");
+  const int n = p.n, m = p.m;
+  for (int64_t e = 0; e < p.c_nnz; ++e) {
+    check(p.c_row[e] >= 0 && p.c_col[e] < n && p.c_row[e] <= p.c_col[e],
+          "cost triplet " + std::to_string(e) + " out of range or below the diagonal");
+    check(std::isfinite(p.c_val[e]), "non-finite cost value");
+  }
+  std::vector<int> cnt(m, 0);
+  for (int64_t e = 0; e < p.a_nnz; ++e) {
+    check(p.a_con[e] >= 0 && p.a_con[e] < m, "constraint id out of range at triplet " + std::to_string(e));
+    check(p.a_row[e] >= 0 && p.a_col[e] < n && p.a_row[e] <= p.a_col[e],
+          "constraint triplet " + std::to_string(e) + " out of range or below the diagonal");
+    check(std::isfinite(p.a_val[e]), "non-finite constraint value");
+    cnt[p.a_con[e]]++;
+  }
+  for (int i = 0; i < m; ++i) check(cnt[i] > 0, "constraint " + std::to_string(i) + " has no triplet");
+  for (int i = 0; i < m; ++i) check(std::isfinite(p.b[i]), "non-finite b");
+}
+
+std::unique_ptr<Problem> ingest(const lorads_problem& p, hipStream_t s) {
+  validate(p);
+  const int n = p.n, m = p.m;
+  std::vector<int> cnt(m, 0);
+  for (int64_t e = 0; e < p.a_nnz; ++e) cnt[p.a_con[e]]++;
+
+  auto P = std::make_unique<Problem>();
+  P->n = n;
+  P->m = m;
+  P->a_nnz = p.a_nnz;
+  P->c_nnz = p.c_nnz;
+
+  // ---------------- norms ----------------
+  for (int i = 0; i < m; ++i) {
+    const double a = std::fabs(p.b[i]);
+    P->b_inf = std::max(P->b_inf, a);
+    P->b_1 += a;
+    P->b_2 += p.b[i] * p.b[i];
+  }
+  P->b_2 = std::sqrt(P->b_2);
+  {
+    // C as the full symmetric matrix: merge duplicates before the norms
+    std::vector<std::pair<int64_t, double>> ent;
+    ent.reserve(p.c_nnz);
+    for (int64_t e = 0; e < p.c_nnz; ++e)
+      ent.push_back({(int64_t)p.c_row[e] * n + p.c_col[e], p.c_val[e]});
+    std::sort(ent.begin(), ent.end(),
+              [](const auto& a, const auto& b) { return a.first < b.first; });
+    double fro = 0, l1 = 0;
+    for (size_t i = 0; i < ent.size();) {
+      size_t j = i;
+      double v = 0;
+      while (j < ent.size() && ent[j].first == ent[i].first) v += ent[j++].second;
+      const int64_t key = ent[i].first;
+      const double mult = (key / n == key % n) ? 1.0 : 2.0;
+      fro += mult * v * v;
+      l1 += mult * std::fabs(v);
+      i = j;
+    }
+    P->c_fro = std::sqrt(fro);
+    P->c_1 = l1;
+  }
+
+  // ---------------- structure detection ----------------
+  // first triplet of each constraint
+  std::vector<int64_t> first(m, -1);
+  for (int64_t e = 0; e < p.a_nnz; ++e)
+    if (first[p.a_con[e]] < 0) first[p.a_con[e]] = e;
+  bool diag = true, pair = true;
+  for (int i = 0; i < m && (diag || pair); ++i) {
+    if (cnt[i] != 1) { diag = pair = false; break; }
+    const int64_t e = first[i];
+    if (p.a_row[e] != p.a_col[e]) diag = false;
+    if (p.a_row[e] == p.a_col[e]) pair = false;
+  }
+  P->structure = diag ? LORADS_STRUCT_DIAG : (pair ? LORADS_STRUCT_PAIR : LORADS_STRUCT_GENERIC);
+
+  // ---------------- internal constraint order ----------------
+  std::vector<int> perm(m);
+  std::iota(perm.begin(), perm.end(), 0);
+  if (P->structure == LORADS_STRUCT_DIAG) {
+    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
+      return p.a_row[first[a]] < p.a_row[first[b]];
+    });
+  } else if (P->structure == LORADS_STRUCT_PAIR) {
+    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
+      const int64_t ea = first[a], eb = first[b];
+      if (p.a_row[ea] != p.a_row[eb]) return p.a_row[ea] < p.a_row[eb];
+      return p.a_col[ea] < p.a_col[eb];
+    });
+  }
+  P->perm_identity = true;
+  for (int i = 0; i < m; ++i)
+    if (perm[i] != i) { P->perm_identity = false; break; }
+  std::vector<int> iperm(m);
+  for (int i = 0; i < m; ++i) iperm[perm[i]] = i;
+
+  std::vector<double> b_int(m);
+  for (int i = 0; i < m; ++i) b_int[i] = p.b[perm[i]];
+
+  // ---------------- constraint-CSR (internal order) ----------------
+  std::vector<int> kcon(p.a_nnz);
+  for (int64_t e = 0; e < p.a_nnz; ++e) kcon[e] = iperm[p.a_con[e]];
+  std::vector<int> kptr;
+  csr_counts(kcon, m, kptr);
+  std::vector<int> krow(p.a_nnz), kcol(p.a_nnz);
+  std::vector<double> kval(p.a_nnz);
+  {
+    std::vector<int> pos(kptr.begin(), kptr.end() - 1);
+    for (int64_t e = 0; e < p.a_nnz; ++e) {
+      const int q = pos[kcon[e]]++;
+      krow[q] = p.a_row[e];
+      kcol[q] = p.a_col[e];
+      kval[q] = p.a_val[e];
+    }
+  }
+  // ---------------- adjoint row-CSR ----------------
+  {
+    std::vector<int> rkey;
+    rkey.reserve(2 * p.a_nnz);
+    for (int64_t e = 0; e < p.a_nnz; ++e) {
+      rkey.push_back(p.a_row[e]);
+      if (p.a_row[e] != p.a_col[e]) rkey.push_back(p.a_col[e]);
+    }
+    std::vector<int> aptr;
+    csr_counts(rkey, n, aptr);
+    const size_t na = rkey.size();
+    std::vector<int> acol(na), acon(na);
+    std::vector<double> aval(na);
+    std::vector<int> pos(aptr.begin(), aptr.end() - 1);
+    // iterate in internal constraint order so rows list constraints ascending
+    for (int i = 0; i < m; ++i) {
+      for (int q = kptr[i]; q < kptr[i + 1]; ++q) {
+        const int j = krow[q], k = kcol[q];
+        int t = pos[j]++;
+        acol[t] = k; acon[t] = i; aval[t] = kval[q];
+        if (j != k) {
+          t = pos[k]++;
+          acol[t] = j; acon[t] = i; aval[t] = kval[q];
+        }
+      }
+    }
+    P->aptr.upload(aptr, s);
+    P->acol.upload(acol, s);
+    P->acon.upload(acon, s);
+    P->aval.upload(aval, s);
+    std::vector<float> af(aval.begin(), aval.end());
+    P->avalf.upload(af, s);
+  }
+  // ---------------- C row-CSR ----------------
+  {
+    std::vector<int> rkey;
+    rkey.reserve(2 * p.c_nnz);
+    for (int64_t e = 0; e < p.c_nnz; ++e) {
+      rkey.push_back(p.c_row[e]);
+      if (p.c_row[e] != p.c_col[e]) rkey.push_back(p.c_col[e]);
+    }
+    std::vector<int> cptr;
+    csr_counts(rkey, n, cptr);
+    const size_t nc = rkey.size();
+    std::vector<int> ccol(nc);
+    std::vector<double> cval(nc);
+    std::vector<int> pos(cptr.begin(), cptr.end() - 1);
+    for (int64_t e = 0; e < p.c_nnz; ++e) {
+      const int j = p.c_row[e], k = p.c_col[e];
+      int t = pos[j]++;
+      ccol[t] = k; cval[t] = p.c_val[e];
+      if (j != k) {
+        t = pos[k]++;
+        ccol[t] = j; cval[t] = p.c_val[e];
+      }
+    }
+    P->cptr.upload(cptr, s);
+    if (nc) {
+      P->ccol.upload(ccol, s);
+      P->cval.upload(cval, s);
+      std::vector<float> cf(cval.begin(), cval.end());
+      P->cvalf.upload(cf, s);
+    }
+  }
+
+  // ---------------- DIAG layout ----------------
+  if (P->structure == LORADS_STRUCT_DIAG) {
+    std::vector<int> drow(m);
+    std::vector<double> dcoef(m);
+    for (int i = 0; i < m; ++i) {
+      drow[i] = krow[kptr[i]];
+      dcoef[i] = kval[kptr[i]];
+    }
+    std::vector<int> dptr;
+    csr_counts(drow, n, dptr);
+    std::vector<double> dsq(n, 0.0);
+    for (int i = 0; i < m; ++i) dsq[drow[i]] += dcoef[i] * dcoef[i];
+    P->drow.upload(drow, s);
+    P->dptr.upload(dptr, s);
+    P->dcoef.upload(dcoef, s);
+    P->dsq.upload(dsq, s);
+    std::vector<float> f1(dcoef.begin(), dcoef.end()), f2(dsq.begin(), dsq.end());
+    P->dcoeff.upload(f1, s);
+    P->dsqf.upload(f2, s);
+  }
+  // ---------------- PAIR layout ----------------
+  if (P->structure == LORADS_STRUCT_PAIR) {
+    std::vector<int> pj(m), pk(m);
+    std::vector<double> pc(m);
+    bool uniform = true;
+    for (int i = 0; i < m; ++i) {
+      pj[i] = krow[kptr[i]];
+      pk[i] = kcol[kptr[i]];
+      pc[i] = kval[kptr[i]];
+      if (pc[i] != pc[0]) uniform = false;
+    }
+    std::vector<int> rptr;
+    csr_counts(pj, n, rptr);
+    // view C: entries grouped by k, ascending j (internal ids ascend with j
+    // inside a column because internal order is sorted by (j, k))
+    std::vector<int> cvptr;
+    csr_counts(pk, n, cvptr);
+    std::vector<int> cvj(m), cvid(m);
+    std::vector<int> pos(cvptr.begin(), cvptr.end() - 1);
+    for (int i = 0; i < m; ++i) {
+      const int t = pos[pk[i]]++;
+      cvj[t] = pj[i];
+      cvid[t] = i;
+    }
+    P->pj.upload(pj, s);
+    P->pk.upload(pk, s);
+    if (uniform) {
+      P->pair_coef = pc[0];
+    } else {
+      P->pcoef.upload(pc, s);
+      std::vector<float> f(pc.begin(), pc.end());
+      P->pcoeff.upload(f, s);
+    }
+    P->rptr.upload(rptr, s);
+    P->cvptr.upload(cvptr, s);
+    P->cvj.upload(cvj, s);
+    P->cvid.upload(cvid, s);
+  }
+
+  P->kptr.upload(kptr, s);
+  P->krow.upload(krow, s);
+  P->kcol.upload(kcol, s);
+  P->kval.upload(kval, s);
+  {
+    std::vector<float> kf(kval.begin(), kval.end());
+    P->kvalf.upload(kf, s);
+  }
+  P->b.upload(b_int, s);
+  if (!P->perm_identity) P->perm.upload(perm, s);
+
+  P->sc.alloc(S_COUNT);
+  P->sc.zero(s);
+  P->counters.alloc(C_NUM);
+  P->counters.zero(s);
+  // one partial per block of the widest row kernel (64 lanes per row)
+  P->part_cap = std::max<size_t>(kMaxPart, (size_t)n / 4 + 64);
+  P->part.alloc(P->part_cap);
+  P->zbuf.alloc(m);
+  P->wbuf.alloc(m);
+  P->tbuf.alloc(m);
+  P->tbuff.alloc(m);
+  HIPCHK(hipStreamSynchronize(s));
+  return P;
+}
+
+}  // namespace lorads

@@ -1,0 +1,405 @@
+// LoRADS driver: Phase I (Burer-Monteiro ALM with L-BFGS, exact quartic line
+// search and dynamic rank), the switch, Phase II (ADMM with CG subproblem
+// solves) and the Appendix-B error measures.  Host code orchestrates device
+// kernels; every vector operation of the path runs on the GPU, the host only
+// keeps scalars (rho, gamma, tolerances, counters) and makes the decisions.
+#include <algorithm>
+#include <chrono>
+#include <complex>
+
+#include "kernels.hpp"
+#include "solver.hpp"
+
+namespace lorads {
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+double secs(Clock::time_point a, Clock::time_point b) {
+  return std::chrono::duration<double>(b - a).count();
+}
+
+inline int gridN(size_t N) { return grid_for(N, 2048); }
+
+// Real roots of c3 x^3 + c2 x^2 + c1 x + c0 (c3 may be 0).
+std::vector<double> real_roots_cubic(double c3, double c2, double c1, double c0) {
+  std::vector<double> out;
+  if (c3 == 0.0) {
+    if (c2 == 0.0) {
+      if (c1 != 0.0) out.push_back(-c0 / c1);
+      return out;
+    }
+    const double disc = c1 * c1 - 4 * c2 * c0;
+    if (disc >= 0) {
+      const double q = -0.5 * (c1 + std::copysign(std::sqrt(disc), c1));
+      if (q != 0.0) out.push_back(q / c2);
+      if (q != 0.0) out.push_back(c0 / q); else out.push_back(0.0);
+    }
+    return out;
+  }
+  // depressed cubic via the trigonometric / Cardano formulas, then two Newton
+  // polish steps per root on the original polynomial
+  const double a = c2 / c3, b = c1 / c3, c = c0 / c3;
+  const double Q = (a * a - 3 * b) / 9.0;
+  const double R = (2 * a * a * a - 9 * a * b + 27 * c) / 54.0;
+  const double Q3 = Q * Q * Q;
+  if (R * R < Q3) {
+    const double th = std::acos(std::max(-1.0, std::min(1.0, R / std::sqrt(Q3))));
+    const double sq = -2.0 * std::sqrt(Q);
+    out.push_back(sq * std::cos(th / 3.0) - a / 3.0);
+    out.push_back(sq * std::cos((th + 2 * M_PI) / 3.0) - a / 3.0);
+    out.push_back(sq * std::cos((th - 2 * M_PI) / 3.0) - a / 3.0);
+  } else {
+    const double A = -std::copysign(std::cbrt(std::fabs(R) + std::sqrt(R * R - Q3)), R);
+    const double B = (A != 0.0) ? Q / A : 0.0;
+    out.push_back((A + B) - a / 3.0);
+  }
+  for (double& x : out) {
+    for (int it = 0; it < 2; ++it) {
+      const double f = ((c3 * x + c2) * x + c1) * x + c0;
+      const double df = (3 * c3 * x + 2 * c2) * x + c1;
+      if (df != 0.0) x -= f / df;
+    }
+  }
+  return out;
+}
+
+}  // namespace
+
+// minimiser over a > 0 of q1 a + q2 a^2 + q3 a^3 + q4 a^4
+double quartic_step(double q1, double q2, double q3, double q4) {
+  const auto roots = real_roots_cubic(4 * q4, 3 * q3, 2 * q2, q1);
+  double best = 0.0, bestv = 0.0;
+  for (double a : roots) {
+    if (!(a > 0.0)) continue;
+    const double v = (((q4 * a + q3) * a + q2) * a + q1) * a;
+    if (v < bestv) { best = a; bestv = v; }
+  }
+  return best;
+}
+
+double gamma_of(const Problem& P, const lorads_options& o, double rho) {
+  (void)rho;
+  if (o.gamma_fixed > 0) return o.gamma_fixed;
+  return o.gamma_scale * (1.0 + P.c_fro / std::sqrt((double)P.n));
+}
+
+// ===========================================================================
+// Phase I: augmented Lagrangian on the factorised problem
+//   L(U) = <C, U U^T> + lam^T (A(U U^T) - b) + rho/2 ||A(U U^T) - b||^2
+//   grad = 2 (C + A*(lam + rho (A(U U^T) - b))) U
+// ===========================================================================
+struct AlmState {
+  int n, m, r;
+  DevBuf<double> G, Gn, D, Q, CD, p1, p2, Sn, Yn;
+  std::vector<DevBuf<double>> S, Y;
+  std::vector<double> rhoh;  // 1 / <S, Y>
+  int head = 0, count = 0;
+};
+
+static void alm_alloc(AlmState& A, int n, int m, int r, int mem) {
+  A.n = n; A.m = m; A.r = r;
+  const size_t N = (size_t)n * r;
+  A.G.alloc(N); A.Gn.alloc(N); A.D.alloc(N); A.Q.alloc(N); A.CD.alloc(N);
+  A.Sn.alloc(N); A.Yn.alloc(N);
+  A.p1.alloc(m); A.p2.alloc(m);
+  A.S.resize(mem); A.Y.resize(mem); A.rhoh.assign(mem, 0.0);
+  for (int i = 0; i < mem; ++i) { A.S[i].alloc(N); A.Y[i].alloc(N); }
+  A.head = A.count = 0;
+}
+
+// G = 2 (C + A*(lam + rho (z - b))) U with z = A(U U^T) recomputed
+static void alm_gradient(Problem& P, AlmState& A, const double* U, double* G, double rho,
+                         hipStream_t s, double& bytes) {
+  op_forward_w(P, U, U, A.r, A.r, P.zbuf.p, P.wbuf.p, P.lam.p, rho, s);
+  op_adjoint<double>(P, P.wbuf.p, 1.0, U, A.r, A.r, G, A.r, 2.0, s);
+  bytes += bytes_forward(P, A.r, 8) + bytes_adjoint(P, A.r, 8, true);
+}
+
+static double host_norm_zb(Problem& P, hipStream_t s) {
+  // ||z - b||_2 via dual_update with rho = 0 (lam unchanged)
+  dual_update<<<grid_for(P.m, kRedBlocks), kBlock, 0, s>>>(P.m, P.zbuf.p, P.b.p, 0.0, P.lam.p,
+                                                           P.sc.p, S_GEN, P.part.p,
+                                                           P.counters.p + C_DOT);
+  HIPCHK(hipGetLastError());
+  double v;
+  read_slots(P, S_GEN, &v, 1, s);
+  return std::sqrt(v);
+}
+
+void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s) {
+  const int n = P.n, m = P.m;
+  int r = P.rank;
+  const int r_cap = rank_cap(P, o);
+  const double c_fro = P.c_fro;
+  double rho = o.rho0 > 0 ? o.rho0 : 1.0 / std::max(1.0, P.b_inf);
+  AlmState A;
+  alm_alloc(A, n, m, r, o.lbfgs_mem);
+  double* U = P.U.p;
+  op_forward<double>(P, U, U, r, r, P.zbuf.p, 1.0, s);
+  info.op_bytes += bytes_forward(P, r, 8);
+  double v = host_norm_zb(P, s) / (1.0 + P.b_inf);
+  double v_ref = INFINITY;
+  int outer = 0, inner_total = 0, growths = 0;
+  double h[16];
+  while (v > o.switch_tol && outer < o.alm_outer_max) {
+    const int cap = (r < r_cap) ? o.rank_grow_iters : o.alm_inner_max;
+    const double tol = std::max(o.alm_inner_rel * v, o.alm_inner_floor);
+    const size_t N = (size_t)n * r;
+    // ---------------- inner L-BFGS ----------------
+    A.head = A.count = 0;
+    alm_gradient(P, A, U, A.G.p, rho, s, info.op_bytes);
+    int it = 0;
+    bool conv = false;
+    while (true) {
+      dot_to_slot<double, double>(P, N, A.G.p, A.G.p, 1.0, S_GEN, s);
+      read_slots(P, S_GEN, h, 1, s);
+      const double gnorm = std::sqrt(h[0]);
+      if (!std::isfinite(gnorm)) fail(LORADS_ENUMERIC, "non-finite gradient in phase I");
+      if (gnorm / (1.0 + c_fro) <= tol) { conv = true; break; }
+      if (it >= cap) break;
+      // two-loop recursion: q = G; newest to oldest
+      HIPCHK(hipMemcpyAsync(A.Q.p, A.G.p, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+      std::vector<int> order;
+      for (int t = 0; t < A.count; ++t) order.push_back((A.head - 1 - t + o.lbfgs_mem) % o.lbfgs_mem);
+      // alphas live in slots S_GEN+16+t
+      for (size_t t = 0; t < order.size(); ++t) {
+        const int k = order[t];
+        dot_to_slot<double, double>(P, N, A.S[k].p, A.Q.p, A.rhoh[k], S_GEN + 16 + (int)t, s);
+        axpby_dev<double><<<gridN(N), kBlock, 0, s>>>(N, P.sc.p, S_GEN + 16 + (int)t, -1.0,
+                                                      A.Y[k].p, 1.0, A.Q.p);
+      }
+      if (A.count > 0) {
+        const int k = order[0];
+        dot_to_slot<double, double>(P, N, A.S[k].p, A.Y[k].p, 1.0, S_GEN + 1, s);
+        dot_to_slot<double, double>(P, N, A.Y[k].p, A.Y[k].p, 1.0, S_GEN + 2, s);
+        read_slots(P, S_GEN + 1, h, 2, s);
+        axpby<double, double><<<gridN(N), kBlock, 0, s>>>(N, 0.0, A.Q.p, h[0] / h[1], A.Q.p);
+      }
+      for (int t = (int)order.size() - 1; t >= 0; --t) {
+        const int k = order[t];
+        // beta = rho_k <Y_k, q>;  q += (alpha_t - beta) S_k
+        dot_to_slot<double, double>(P, N, A.Y[k].p, A.Q.p, A.rhoh[k], S_GEN + 6, s);
+        read_slots(P, S_GEN + 6, h, 1, s);
+        double al;
+        read_slots(P, S_GEN + 16 + t, &al, 1, s);
+        axpby<double, double><<<gridN(N), kBlock, 0, s>>>(N, al - h[0], A.S[k].p, 1.0, A.Q.p);
+      }
+      // D = -q ; descent check
+      axpby<double, double><<<gridN(N), kBlock, 0, s>>>(N, -1.0, A.Q.p, 0.0, A.D.p);
+      dot_to_slot<double, double>(P, N, A.G.p, A.D.p, 1.0, S_GEN, s);
+      read_slots(P, S_GEN, h, 1, s);
+      if (!(h[0] < 0.0)) {
+        axpby<double, double><<<gridN(N), kBlock, 0, s>>>(N, -1.0, A.G.p, 0.0, A.D.p);
+        A.head = A.count = 0;
+      }
+      // exact line search coefficients
+      double alpha = 0.0;
+      for (int attempt = 0; attempt < 2; ++attempt) {
+        op_forward<double>(P, U, A.D.p, r, r, A.p1.p, 2.0, s);
+        op_forward<double>(P, A.D.p, A.D.p, r, r, A.p2.p, 1.0, s);
+        op_adjoint<double>(P, (const double*)nullptr, 1.0, A.D.p, r, r, A.CD.p, r, 1.0, s);
+        info.op_bytes += 2 * bytes_forward(P, r, 8) + bytes_adjoint(P, r, 8, true);
+        dot_to_slot<double, double>(P, N, A.CD.p, U, 2.0, S_GEN + 1, s);
+        dot_to_slot<double, double>(P, N, A.CD.p, A.D.p, 1.0, S_GEN + 2, s);
+        linesearch_dots<<<grid_for(m, kRedBlocks), kBlock, 0, s>>>(
+            m, P.zbuf.p, P.b.p, A.p1.p, A.p2.p, P.lam.p, P.sc.p, S_GEN + 3, P.part.p,
+            P.counters.p + C_MDOT);
+        HIPCHK(hipGetLastError());
+        read_slots(P, S_GEN + 1, h, 9, s);
+        const double c1 = h[0], c2 = h[1];
+        const double p22 = h[2], p12 = h[3], p11 = h[4], p02 = h[5], p01 = h[6], l1 = h[7],
+                     l2 = h[8];
+        const double q4 = 0.5 * rho * p22;
+        const double q3 = rho * p12;
+        const double q2 = c2 + l2 + 0.5 * rho * (p11 + 2.0 * p02);
+        const double q1 = c1 + l1 + rho * p01;
+        alpha = quartic_step(q1, q2, q3, q4);
+        if (alpha > 0.0 || A.count == 0) break;
+        // retry along steepest descent with a cleared memory
+        axpby<double, double><<<gridN(N), kBlock, 0, s>>>(N, -1.0, A.G.p, 0.0, A.D.p);
+        A.head = A.count = 0;
+      }
+      if (!(alpha > 0.0)) break;
+      // S = alpha D; U += S; new gradient; Y = G_new - G.  The pair enters the
+      // memory only when <S, Y> > 0 (the oldest pair is dropped when full).
+      axpby<double, double><<<gridN(N), kBlock, 0, s>>>(N, alpha, A.D.p, 0.0, A.Sn.p);
+      add_kernel<double, double, double><<<gridN(N), kBlock, 0, s>>>(N, U, A.Sn.p, U);
+      alm_gradient(P, A, U, A.Gn.p, rho, s, info.op_bytes);
+      axpby<double, double><<<gridN(N), kBlock, 0, s>>>(N, 1.0, A.Gn.p, 0.0, A.Yn.p);
+      axpby<double, double><<<gridN(N), kBlock, 0, s>>>(N, -1.0, A.G.p, 1.0, A.Yn.p);
+      dot_to_slot<double, double>(P, N, A.Sn.p, A.Yn.p, 1.0, S_GEN, s);
+      read_slots(P, S_GEN, h, 1, s);
+      if (h[0] > 0.0) {
+        const int slot = A.head;
+        std::swap(A.S[slot], A.Sn);
+        std::swap(A.Y[slot], A.Yn);
+        A.rhoh[slot] = 1.0 / h[0];
+        A.head = (A.head + 1) % o.lbfgs_mem;
+        A.count = std::min(A.count + 1, o.lbfgs_mem);
+      }
+      std::swap(A.G, A.Gn);
+      ++it;
+    }
+    inner_total += it;
+    // z of the current U is in zbuf (from the last gradient evaluation)
+    v = host_norm_zb(P, s) / (1.0 + P.b_inf);
+    if (o.verbose > 1)
+      fprintf(stderr, "[lorads] ALM outer %d: r=%d rho=%.3g inner=%d conv=%d v=%.3e\n", outer, r,
+              rho, it, (int)conv, v);
+    if (!conv && r < r_cap && it >= cap) {
+      const int r_new = std::min((int)std::ceil(o.rank_factor * r), r_cap);
+      dot_to_slot<double, double>(P, N, U, U, 1.0, S_GEN, s);
+      read_slots(P, S_GEN, h, 1, s);
+      const double sigma = 1e-3 * std::sqrt(h[0]) / std::sqrt((double)n * r);
+      DevBuf<double> Unew;
+      Unew.alloc((size_t)n * r_new);
+      grow_rank_kernel<<<gridN((size_t)n * r_new), kBlock, 0, s>>>(n, r, r_new, U, Unew.p, sigma,
+                                                                   o.seed, (uint64_t)growths);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(s));
+      P.U = std::move(Unew);
+      U = P.U.p;
+      r = r_new;
+      P.rank = r;
+      alm_alloc(A, n, m, r, o.lbfgs_mem);
+      ++growths;
+      op_forward<double>(P, U, U, r, r, P.zbuf.p, 1.0, s);
+      info.op_bytes += bytes_forward(P, r, 8);
+      v = host_norm_zb(P, s) / (1.0 + P.b_inf);
+      continue;
+    }
+    if (v <= o.alm_eta * v_ref) {
+      dual_update<<<grid_for(m, kRedBlocks), kBlock, 0, s>>>(m, P.zbuf.p, P.b.p, rho, P.lam.p,
+                                                             P.sc.p, S_GEN, P.part.p,
+                                                             P.counters.p + C_DOT);
+      HIPCHK(hipGetLastError());
+      v_ref = v;
+    } else {
+      rho *= o.alm_rho_factor;
+    }
+    ++outer;
+  }
+  info.alm_outer = outer;
+  info.alm_inner = inner_total;
+  info.growths = growths;
+  info.rho_alm = rho;
+  info.pinf_alm = v;
+}
+
+// ===========================================================================
+// Phase II: ADMM (Algorithm 1) with CG subproblem solves
+// ===========================================================================
+template <typename T>
+struct CgBufs {
+  DevBuf<T> R, X, Pd, Q, W, t;
+  void alloc(size_t N, int m) {
+    R.alloc(N); X.alloc(N); Pd.alloc(N); Q.alloc(N); W.alloc(N); t.alloc(m);
+  }
+};
+
+// new = W + argmin-correction: solves M_W D = -(C + A*(lam + rho (A(W W^T) - b))) W
+template <typename T>
+static int half_step(Problem& P, const double* W, double* out, int r, double rho, double gamma,
+                     double tol, int maxit, CgBufs<T>& B, DevBuf<double>& R64, hipStream_t s,
+                     SolveInfo& info) {
+  const size_t N = (size_t)P.n * r;
+  op_forward_w(P, W, W, r, r, P.zbuf.p, P.wbuf.p, P.lam.p, rho, s);
+  info.op_bytes += bytes_forward(P, r, 8) + bytes_adjoint(P, r, 8, true);
+  const T* Wt;
+  if constexpr (std::is_same<T, double>::value) {
+    op_adjoint<double>(P, P.wbuf.p, 1.0, W, r, r, B.R.p, r, -1.0, s);
+    Wt = W;
+  } else {
+    op_adjoint<double>(P, P.wbuf.p, 1.0, W, r, r, R64.p, r, -1.0, s);
+    convert_kernel<double, float><<<gridN(N), kBlock, 0, s>>>(N, R64.p, B.R.p);
+    convert_kernel<double, float><<<gridN(N), kBlock, 0, s>>>(N, W, B.W.p);
+    Wt = B.W.p;
+  }
+  HIPCHK(hipMemsetAsync(B.X.p, 0, N * sizeof(T), s));
+  double rel;
+  const int it = cg_run<T>(P, Wt, r, rho, gamma, B.R.p, B.X.p, B.Pd.p, B.Q.p, B.t.p, tol, maxit, s,
+                           &rel, &info.op_bytes);
+  add_kernel<double, T, double><<<gridN(N), kBlock, 0, s>>>(N, W, B.X.p, out);
+  HIPCHK(hipGetLastError());
+  return it;
+}
+
+template <typename T>
+static void phase2_t(Problem& P, const lorads_options& o, double rho, SolveInfo& info,
+                     hipStream_t s, Clock::time_point t_start) {
+  const int n = P.n, m = P.m, r = P.rank;
+  const size_t N = (size_t)n * r;
+  // U and V start equal to the phase-I factor
+  P.V.alloc(N);
+  HIPCHK(hipMemcpyAsync(P.V.p, P.U.p, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  DevBuf<double> Vold, R64;
+  Vold.alloc(N);
+  if constexpr (!std::is_same<T, double>::value) R64.alloc(N);
+  CgBufs<T> B;
+  B.alloc(N, m);
+  const int maxit = (int)std::min<long long>((long long)N, o.cg_maxit);
+  const double floor = (std::is_same<T, double>::value) ? o.cg_tol_floor : std::max(o.cg_tol_floor, 1e-6);
+  double kkt = INFINITY, pinf = INFINITY, dres = INFINITY, gamma = gamma_of(P, o, rho);
+  int k = 0;
+  long long cg_total = 0;
+  double h[4];
+  info.status = LORADS_MAXITER;
+  while (k < o.max_admm_iter) {
+    gamma = gamma_of(P, o, rho);
+    const double tol = std::min(o.cg_tol_max, std::max(floor, o.cg_tol_kkt * kkt));
+    HIPCHK(hipMemcpyAsync(Vold.p, P.V.p, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    dot_to_slot<double, double>(P, N, Vold.p, Vold.p, 1.0, S_GEN + 2, s);
+    const int iu = half_step<T>(P, P.V.p, P.U.p, r, rho, gamma, tol, maxit, B, R64, s, info);
+    const int iv = half_step<T>(P, P.U.p, P.V.p, r, rho, gamma, tol, maxit, B, R64, s, info);
+    cg_total += iu + iv;
+    // z = A(U V^T); lam += rho (z - b); residual norms
+    op_forward<double>(P, P.U.p, P.V.p, r, r, P.zbuf.p, 1.0, s);
+    info.op_bytes += bytes_forward(P, r, 8);
+    dual_update<<<grid_for(m, kRedBlocks), kBlock, 0, s>>>(m, P.zbuf.p, P.b.p, rho, P.lam.p,
+                                                           P.sc.p, S_GEN, P.part.p,
+                                                           P.counters.p + C_DOT);
+    axpby<double, double><<<gridN(N), kBlock, 0, s>>>(N, 1.0, P.V.p, -1.0, Vold.p);  // V+ - V
+    dot_to_slot<double, double>(P, N, Vold.p, Vold.p, 1.0, S_GEN + 1, s);
+    HIPCHK(hipGetLastError());
+    read_slots(P, S_GEN, h, 3, s);
+    pinf = std::sqrt(h[0]) / (1.0 + P.b_inf);
+    dres = gamma * std::sqrt(h[1]) / (1.0 + std::sqrt(h[2]));
+    if (!std::isfinite(pinf) || !std::isfinite(dres)) fail(LORADS_ENUMERIC, "non-finite residual in ADMM");
+    kkt = std::max(pinf, dres);
+    ++k;
+    if (o.verbose > 1)
+      fprintf(stderr, "[lorads] ADMM %d: rho=%.4g gamma=%.4g cg=%d+%d pinf=%.3e dres=%.3e\n", k,
+              rho, gamma, iu, iv, pinf, dres);
+    if (kkt < o.eps) { info.status = LORADS_OK; break; }
+    if (k % o.rho_every == 0 && rho < o.rho_max) rho = std::min(o.rho_growth * rho, o.rho_max);
+    if (o.time_limit > 0 && secs(t_start, Clock::now()) > o.time_limit) {
+      info.status = LORADS_TIMELIMIT;
+      break;
+    }
+  }
+  info.admm_iters = k;
+  info.cg_iters = cg_total;
+  info.kkt = kkt;
+  info.pinf_stop = pinf;
+  info.dres_stop = dres;
+  info.rho = rho;
+  info.gamma = gamma;
+}
+
+void phase2(Problem& P, const lorads_options& o, double rho, SolveInfo& info, hipStream_t s,
+            std::chrono::steady_clock::time_point t_start) {
+  if (o.precision == LORADS_F32)
+    phase2_t<float>(P, o, rho, info, s, t_start);
+  else
+    phase2_t<double>(P, o, rho, info, s, t_start);
+}
+
+int rank_cap(const Problem& P, const lorads_options& o) {
+  int cap = o.r_max > 0 ? o.r_max : (int)std::floor(std::sqrt(2.0 * P.m));
+  cap = std::min(cap, P.n);
+  cap = std::min(cap, 256);
+  return std::max(cap, 1);
+}
+
+}  // namespace lorads

@@ -1,0 +1,298 @@
+"""ctypes binding of liblorads.so (argument marshalling only).
+
+Every computation happens in the gfx950 library; this module converts numpy
+arrays and torch device tensors into the pointers, sizes and structs of the C
+ABI declared in include/lorads.h.  Loading fails loudly when the library has
+not been built; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import pathlib
+from typing import Optional, Sequence
+
+import numpy as np
+
+_LIB_PATH = pathlib.Path(__file__).resolve().parent / "liblorads.so"
+_lib = None
+
+LORADS_OK, LORADS_MAXITER, LORADS_TIMELIMIT = 0, 1, 2
+LORADS_EINVAL, LORADS_ENOMEM, LORADS_EDEVICE, LORADS_ENUMERIC, LORADS_ESTATE = -1, -2, -3, -4, -5
+F64, F32 = 0, 1
+STRUCT_NAMES = {0: "generic", 1: "diag", 2: "pair"}
+
+
+class LoradsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"lorads status {status}: {msg}")
+        self.status = status
+
+
+class Problem_(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32), ("m", C.c_int32),
+        ("c_nnz", C.c_int64), ("c_row", C.c_void_p), ("c_col", C.c_void_p), ("c_val", C.c_void_p),
+        ("a_nnz", C.c_int64), ("a_con", C.c_void_p), ("a_row", C.c_void_p), ("a_col", C.c_void_p),
+        ("a_val", C.c_void_p), ("b", C.c_void_p),
+    ]
+
+
+class Options_(C.Structure):
+    _fields_ = [
+        ("precision", C.c_int32), ("eps", C.c_double), ("switch_tol", C.c_double), ("h", C.c_double),
+        ("rho_growth", C.c_double), ("rho_every", C.c_int32), ("rho_max", C.c_double),
+        ("max_admm_iter", C.c_int32), ("time_limit", C.c_double), ("gamma_fixed", C.c_double),
+        ("gamma_scale", C.c_double), ("cg_tol_max", C.c_double), ("cg_tol_floor", C.c_double),
+        ("cg_tol_kkt", C.c_double), ("cg_maxit", C.c_int32), ("lbfgs_mem", C.c_int32),
+        ("alm_inner_max", C.c_int32), ("rank_grow_iters", C.c_int32), ("rank_factor", C.c_double),
+        ("r0", C.c_int32), ("r_max", C.c_int32), ("alm_inner_rel", C.c_double),
+        ("alm_inner_floor", C.c_double), ("alm_eta", C.c_double), ("alm_rho_factor", C.c_double),
+        ("alm_outer_max", C.c_int32), ("rho0", C.c_double), ("seed", C.c_uint64),
+        ("phase1", C.c_int32), ("verbose", C.c_int32),
+        ("init_U", C.c_void_p), ("init_lambda", C.c_void_p),
+    ]
+
+
+class Result_(C.Structure):
+    _fields_ = [
+        ("status", C.c_int32), ("rank", C.c_int32), ("alm_outer", C.c_int32), ("alm_inner", C.c_int32),
+        ("rank_growths", C.c_int32), ("admm_iters", C.c_int32), ("cg_iters", C.c_int64),
+        ("obj", C.c_double), ("dual_obj", C.c_double), ("pinf", C.c_double), ("dinf", C.c_double),
+        ("gap", C.c_double), ("lambda_min", C.c_double), ("kkt", C.c_double),
+        ("pinf_stop", C.c_double), ("dres_stop", C.c_double), ("rho", C.c_double),
+        ("gamma", C.c_double), ("t_phase1", C.c_double), ("t_phase2", C.c_double),
+        ("t_metrics", C.c_double), ("t_total", C.c_double), ("op_bytes", C.c_double),
+    ]
+
+
+EXPORTED = [
+    "lorads_default_options", "lorads_setup", "lorads_problem_info", "lorads_apply_A",
+    "lorads_apply_AT_V", "lorads_cg_solve", "lorads_admm_solve", "lorads_get_solution",
+    "lorads_gram", "lorads_dual_lambda_min", "lorads_destroy", "lorads_last_error",
+    "lorads_version",
+]
+
+
+def library_path() -> pathlib.Path:
+    return _LIB_PATH
+
+
+def load():
+    """Load liblorads.so (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not _LIB_PATH.exists():
+        raise RuntimeError(f"{_LIB_PATH} is missing: build it with `python -m paper_2403_09133_amd.build`")
+    lib = C.CDLL(str(_LIB_PATH))
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    lib.lorads_default_options.argtypes = [C.POINTER(Options_)]
+    lib.lorads_default_options.restype = None
+    lib.lorads_setup.argtypes = [C.POINTER(Problem_), i32, C.POINTER(vp)]
+    lib.lorads_problem_info.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+    lib.lorads_apply_A.argtypes = [vp, i32, vp, vp, i32, i32, vp, i32, vp]
+    lib.lorads_apply_AT_V.argtypes = [vp, i32, vp, dbl, vp, i32, i32, vp, i32, vp]
+    lib.lorads_cg_solve.argtypes = [vp, i32, vp, dbl, dbl, vp, vp, i32, i32, dbl, i32, i32,
+                                    C.POINTER(i32), C.POINTER(dbl), vp]
+    lib.lorads_admm_solve.argtypes = [vp, C.POINTER(Options_), C.POINTER(Result_)]
+    lib.lorads_get_solution.argtypes = [vp, i32, vp, vp, vp]
+    lib.lorads_gram.argtypes = [vp, vp, i64, i32, i32, i32, i32, vp, vp]
+    lib.lorads_dual_lambda_min.argtypes = [vp, i32, vp, i32, C.POINTER(dbl)]
+    lib.lorads_destroy.argtypes = [vp]
+    lib.lorads_destroy.restype = None
+    lib.lorads_last_error.argtypes = [vp]
+    lib.lorads_last_error.restype = C.c_char_p
+    lib.lorads_version.restype = C.c_char_p
+    for name in ("lorads_setup", "lorads_problem_info", "lorads_apply_A", "lorads_apply_AT_V",
+                 "lorads_cg_solve", "lorads_admm_solve", "lorads_get_solution", "lorads_gram",
+                 "lorads_dual_lambda_min"):
+        getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(a) -> int:
+    if a is None:
+        return 0
+    if hasattr(a, "data_ptr"):
+        return a.data_ptr()
+    return a.ctypes.data
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return torch.cuda.current_stream().cuda_stream
+        except Exception:  # pragma: no cover
+            pass
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _dtype_code(t) -> int:
+    name = str(t.dtype)
+    if name.endswith("float64"):
+        return F64
+    if name.endswith("float32"):
+        return F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _factor_shape(t):
+    if t.dim() != 2:
+        raise ValueError("factor must be 2-D (n x r)")
+    if t.stride(1) != 1:
+        raise ValueError("factor must be row-major with unit column stride")
+    return int(t.shape[1]), int(t.stride(0))
+
+
+def default_options(**kw) -> Options_:
+    o = Options_()
+    load().lorads_default_options(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+class Context:
+    """Owns a lorads_ctx: the device copies of one or more SDP instances."""
+
+    def __init__(self, problems):
+        lib = load()
+        if not isinstance(problems, (list, tuple)):
+            problems = [problems]
+        self._keep = []
+        arr = (Problem_ * len(problems))()
+        for i, p in enumerate(problems):
+            cols = {}
+            for name, dt in (("c_row", np.int32), ("c_col", np.int32), ("c_val", np.float64),
+                             ("a_con", np.int32), ("a_row", np.int32), ("a_col", np.int32),
+                             ("a_val", np.float64), ("b", np.float64)):
+                a = np.ascontiguousarray(getattr(p, name), dtype=dt)
+                self._keep.append(a)
+                cols[name] = a
+            arr[i] = Problem_(int(p.n), int(p.m), int(cols["c_row"].size), _ptr(cols["c_row"]),
+                              _ptr(cols["c_col"]), _ptr(cols["c_val"]), int(cols["a_row"].size),
+                              _ptr(cols["a_con"]), _ptr(cols["a_row"]), _ptr(cols["a_col"]),
+                              _ptr(cols["a_val"]), _ptr(cols["b"]))
+        h = C.c_void_p()
+        st = lib.lorads_setup(arr, len(problems), C.byref(h))
+        self._keep = []
+        if st != LORADS_OK:
+            raise LoradsError(st, lib.lorads_last_error(None).decode())
+        self.h = h
+        self.nprob = len(problems)
+        self.problems = list(problems)
+
+    # -- helpers -----------------------------------------------------------
+    def _check(self, st):
+        if st not in (LORADS_OK, LORADS_MAXITER, LORADS_TIMELIMIT):
+            raise LoradsError(st, load().lorads_last_error(self.h).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().lorads_destroy(self.h)
+            self.h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- entry points ------------------------------------------------------
+    def problem_info(self, prob: int = 0):
+        s, n, m = C.c_int32(), C.c_int32(), C.c_int32()
+        self._check(load().lorads_problem_info(self.h, prob, C.byref(s), C.byref(n), C.byref(m)))
+        return dict(structure=STRUCT_NAMES[s.value], n=n.value, m=m.value)
+
+    def apply_A(self, U, V, z, prob: int = 0, stream=None):
+        """z = A(U V^T) on device tensors (n x r row-major, z of length m)."""
+        r, ld = _factor_shape(U)
+        self._check(load().lorads_apply_A(self.h, prob, _ptr(U), _ptr(V), r, ld, _ptr(z),
+                                          _dtype_code(U), _stream(stream)))
+        return z
+
+    def apply_AT_V(self, w, V, out, c_scale: float = 1.0, prob: int = 0, stream=None):
+        """out = (c_scale C + A*(w)) V on device tensors."""
+        r, ld = _factor_shape(V)
+        self._check(load().lorads_apply_AT_V(self.h, prob, _ptr(w), float(c_scale), _ptr(V), r, ld,
+                                             _ptr(out), _dtype_code(V), _stream(stream)))
+        return out
+
+    def cg_solve(self, W, R, X, rho: float, gamma: float, tol: float, maxit: int, prob: int = 0,
+                 stream=None):
+        """Solve gamma X + rho A*(A(X W^T)) W = R by CG from the content of X."""
+        r, ld = _factor_shape(W)
+        it, rel = C.c_int32(), C.c_double()
+        st = self._check(load().lorads_cg_solve(self.h, prob, _ptr(W), float(rho), float(gamma),
+                                                _ptr(R), _ptr(X), r, ld, float(tol), int(maxit),
+                                                _dtype_code(W), C.byref(it), C.byref(rel),
+                                                _stream(stream)))
+        return dict(status=st, iters=it.value, relres=rel.value)
+
+    def admm_solve(self, init_U: Sequence[np.ndarray], options: Options_,
+                   init_lambda: Optional[Sequence[Optional[np.ndarray]]] = None):
+        """Two-phase LoRADS solve of every problem; returns a list of dicts."""
+        lib = load()
+        keep = [np.ascontiguousarray(u, dtype=np.float64) for u in init_U]
+        ptrs = (C.c_void_p * self.nprob)(*[_ptr(u) for u in keep])
+        options.init_U = C.cast(ptrs, C.c_void_p)
+        if init_lambda is not None:
+            keepl = [None if l is None else np.ascontiguousarray(l, dtype=np.float64) for l in init_lambda]
+            lptrs = (C.c_void_p * self.nprob)(*[_ptr(l) if l is not None else 0 for l in keepl])
+            options.init_lambda = C.cast(lptrs, C.c_void_p)
+        else:
+            options.init_lambda = None
+        res = (Result_ * self.nprob)()
+        st = lib.lorads_admm_solve(self.h, C.byref(options), res)
+        options.init_U = None
+        options.init_lambda = None
+        if st < 0:
+            raise LoradsError(st, lib.lorads_last_error(self.h).decode())
+        out = []
+        for i in range(self.nprob):
+            out.append({f: getattr(res[i], f) for f, _ in Result_._fields_})
+        return out
+
+    def get_solution(self, prob: int = 0, rank: Optional[int] = None):
+        info = self.problem_info(prob)
+        if rank is None:
+            raise ValueError("rank required (take it from the solve result)")
+        n, m = info["n"], info["m"]
+        U = np.empty((n, rank)); V = np.empty((n, rank)); lam = np.empty(m)
+        self._check(load().lorads_get_solution(self.h, prob, _ptr(U), _ptr(V), _ptr(lam)))
+        return U, V, lam
+
+    def dual_lambda_min(self, lam, prob: int = 0, max_steps: int = 300) -> float:
+        out = C.c_double()
+        self._check(load().lorads_dual_lambda_min(self.h, prob, _ptr(lam), int(max_steps), C.byref(out)))
+        return out.value
+
+
+def gram(A, B, G, stream=None):
+    """G = A^T B for FP64 device tensors A (n x ra), B (n x rb), G (ra x rb)."""
+    ra, lda = _factor_shape(A)
+    rb, ldb = _factor_shape(B)
+    st = load().lorads_gram(_ptr(A), _ptr(B), int(A.shape[0]), ra, rb, lda, ldb, _ptr(G), _stream(stream))
+    if st != LORADS_OK:
+        raise LoradsError(st, load().lorads_last_error(None).decode())
+    return G
+
+
+def version() -> str:
+    return load().lorads_version().decode()
