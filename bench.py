@@ -1,0 +1,209 @@
+#!/usr/bin/env python
+"""Benchmark of the LoRADS hot path on one MI355X.
+
+Workload: the planted rank-5 matrix-completion SDP with M of order 10000 x 10000
+(X of order 20000), 4,605,170 observed entries, C = I/2, solved by the
+two-phase method (warm start + ADMM with CG subproblems) to KKT residual 1e-6,
+CG in FP32 with FP64 right-hand sides, dual updates and residuals.
+
+One step = one full two-phase solve from the same random start, the instance
+already resident in HBM (setup is outside the timed region).
+
+value  = algorithmic bytes of every constraint-operator application of the
+         solves (forward map, adjoint product, fused CG operator; indices,
+         coefficients, inputs and outputs counted once) / wall time, in GB/s.
+roofline: the dominant kernel's algorithmic bytes per launch / its mean launch
+         time from HIP events recorded on the solver's stream during the timed
+         steps, against the 8 TB/s HBM peak.
+cpu_baseline: the FP64 numpy oracle's forward map and adjoint product at the
+         same size on the host, one thread, in the same unit.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    # name -> (generator key, precision code, description)
+    "mc_10000": ("mc_10000", 1, "matrix completion 10000x10000, rank 5, |Omega|=4605170, X of order 20000"),
+    "mc_20000": ("mc_20000", 1, "matrix completion 20000x20000, rank 5, 800*d draws deduplicated, X of order 40000"),
+    "maxcut_torus100": ("maxcut_torus100", 1, "MaxCut 100x100 torus, +-1 weights, n=m=10000"),
+    "maxcut_gnm20000": ("maxcut_gnm20000", 1, "MaxCut G(20000, M=60000), unit weights"),
+}
+
+
+def initial_rank(p) -> int:
+    if p.kind == "mc":
+        # Section 5.1: 2 log m, and log m for completion instances of order >= 10000
+        return int(round(math.log(p.m))) if p.n >= 10000 else int(round(2 * math.log(p.m)))
+    return int(math.ceil(math.log2(p.n)))
+
+
+def lib_options(p, r0, precision, **kw):
+    from paper_2403_09133_amd import default_options
+    from oracle.options import paper_defaults  # parameter table only (switch tol, h)
+    pd = paper_defaults(p.kind, p.n)
+    return default_options(r0=r0, switch_tol=pd["switch_tol"], h=pd["h"], precision=precision, **kw)
+
+
+def cpu_baseline(p, r: int, budget_s: float = 20.0):
+    """Time the oracle's forward map and adjoint product (FP64, numpy) on the
+    host, single thread, for a bounded number of applications."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # pragma: no cover
+        threadpool_limits = None
+    import oracle
+    rng = np.random.default_rng(0)
+    U = rng.standard_normal((p.n, r))
+    V = rng.standard_normal((p.n, r))
+    w = rng.standard_normal(p.m)
+    ctx = threadpool_limits(limits=1) if threadpool_limits else None
+    try:
+        reps, t = 0, 0.0
+        t0 = time.perf_counter()
+        while True:
+            oracle.operators.forward(p, U, V)
+            oracle.operators.adjoint(p, w, 1.0, V)
+            reps += 1
+            t = time.perf_counter() - t0
+            if t > budget_s / 2 or reps >= 8:
+                break
+    finally:
+        if ctx is not None:
+            ctx.unregister() if hasattr(ctx, "unregister") else None
+    bytes_pair = 2 * (8.0 * p.m + 8.0 * p.m + 2.0 * p.n * r * 8)
+    return dict(value=round(reps * bytes_pair / t / 1e9, 4), unit="GB/s", cores=1, kind="oracle",
+                sample=f"{reps} x (A(UV^T) + (C + A*(y))V) at full size, r={r}, FP64 numpy, "
+                       f"{t:.1f} s on the host")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="mc_10000", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solve")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU: the method's batch and single-instance paths are "
+              "measured per GPU, no multi-GPU run exists in this build (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import sdpgen
+    from paper_2403_09133_amd import Context
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    key, prec, desc = WORKLOADS[args.workload]
+    t = time.time()
+    p = sdpgen.config_instance(key)
+    t_gen = time.time() - t
+    r0 = initial_rank(p)
+    U0 = sdpgen.random_init_U(p.n, r0, 3)
+    print(f"[bench] {args.workload}: n={p.n} m={p.m} r0={r0} (generated in {t_gen:.1f}s)", file=sys.stderr, flush=True)
+    t = time.time()
+    ctx = Context(p)
+    torch.cuda.synchronize()
+    t_setup = time.time() - t
+    print(f"[bench] setup {t_setup:.2f}s {ctx.problem_info()}", file=sys.stderr, flush=True)
+
+    for i in range(args.warmup):
+        res = ctx.admm_solve([U0], lib_options(p, r0, prec))[0]
+        print(f"[bench] warmup {i}: {res['t_total']:.3f}s status {res['status']} kkt {res['kkt']:.2e}",
+              file=sys.stderr, flush=True)
+
+    results = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        res = ctx.admm_solve([U0], lib_options(p, r0, prec, profile=1))[0]
+        results.append(res)
+        print(f"[bench] step {i}: {res['t_total']:.3f}s status {res['status']} kkt {res['kkt']:.2e} "
+              f"obj {res['obj']:.10g} admm {res['admm_iters']} cg {res['cg_iters']}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    op_bytes = sum(r["op_bytes"] for r in results)
+    value = op_bytes / wall / 1e9
+
+    # dominant kernel over the timed steps (live HIP-event timings)
+    names = ["fused CG operator", "forward map A(UV^T)", "adjoint (C + A*(w))V"]
+    ms = [sum(r["prof_ms"][k] for r in results) for k in range(3)]
+    launches = [sum(r["prof_launches"][k] for r in results) for k in range(3)]
+    kbytes = [sum(r["prof_bytes"][k] for r in results) for k in range(3)]
+    dom = int(np.argmax(ms))
+    achieved = kbytes[dom] / (ms[dom] * 1e-3) / 1e9 if ms[dom] > 0 else 0.0
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    kernel=names[dom], launches=int(launches[dom]),
+                    mean_launch_us=round(ms[dom] * 1e3 / max(1, launches[dom]), 2),
+                    bytes_per_launch=round(kbytes[dom] / max(1, launches[dom])))
+    kernels = {names[k]: dict(launches=int(launches[k]), total_ms=round(ms[k], 3),
+                              mean_us=round(ms[k] * 1e3 / max(1, launches[k]), 2),
+                              gbs=round(kbytes[k] / (ms[k] * 1e-3) / 1e9, 1) if ms[k] > 0 else None)
+               for k in range(3)}
+
+    last = results[-1]
+    extra = dict(
+        time_to_kkt_s={"fp32_cg": round(wall / args.steps, 4)},
+        solve=dict(status=last["status"], kkt=last["kkt"], obj=last["obj"], pinf=last["pinf"],
+                   dinf=last["dinf"], gap=last["gap"], rank=last["rank"], admm_iters=last["admm_iters"],
+                   cg_iters=last["cg_iters"], alm_outer=last["alm_outer"], alm_inner=last["alm_inner"],
+                   t_phase1=round(last["t_phase1"], 4), t_phase2=round(last["t_phase2"], 4)),
+        kernels=kernels, setup_s=round(t_setup, 3),
+    )
+    if p.kind == "mc":
+        import oracle  # recovery error of the returned factors (host check)
+        U, V, lam = ctx.get_solution(0, last["rank"])
+        extra["mc_recovery_error"] = oracle.metrics.mc_recovery_error(p, 0.5 * (U + V))
+    if not args.no_fp64:
+        t = time.perf_counter()
+        r64 = ctx.admm_solve([U0], lib_options(p, r0, 0))[0]
+        extra["time_to_kkt_s"]["fp64"] = round(time.perf_counter() - t, 4)
+        extra["fp64_solve"] = dict(status=r64["status"], kkt=r64["kkt"], obj=r64["obj"],
+                                   admm_iters=r64["admm_iters"], cg_iters=r64["cg_iters"])
+        extra["fp32_vs_fp64_obj_rel"] = abs(last["obj"] - r64["obj"]) / max(1.0, abs(r64["obj"]))
+    ctx.close()
+
+    line = {
+        "metric": "A(UV^T)+A^*(y)V as HBM GB/s; time-to-1e-6 KKT residual, FP32/batched vs FP64",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if prec == 1 else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": desc, "n_X": p.n, "m": p.m, "r0": r0,
+                   "kkt_tol": 1e-6},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(p, r0)
+    line.update(extra)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

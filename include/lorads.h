@@ -105,8 +105,8 @@ typedef struct {
   double cg_tol_kkt;
   int32_t cg_maxit;        /* cap min(n r, cg_maxit) */
   int32_t lbfgs_mem;       /* L-BFGS memory, default 4 */
-  int32_t alm_inner_max;   /* inner iteration cap at the rank cap, 500 */
-  int32_t rank_grow_iters; /* an inner solve reaching this count grows the rank, 300 */
+  int32_t alm_inner_max;   /* inner iteration cap at the rank cap, 2000 */
+  int32_t rank_grow_iters; /* an inner solve reaching this count grows the rank, 1000 */
   double rank_factor;      /* 1.5 (paper) */
   int32_t r0;              /* initial rank (> 0 required unless init_U given) */
   int32_t r_max;           /* rank cap; 0: min(floor(sqrt(2m)), n) */
@@ -119,6 +119,8 @@ typedef struct {
   uint64_t seed;           /* SplitMix64 stream for rank-growth columns */
   int32_t phase1;          /* 1: run the warm start; 0: start ADMM at init_U */
   int32_t verbose;         /* 0 silent, 1 per-phase summary, 2 per iteration */
+  int32_t profile;         /* 1: time the operator launches with HIP events
+                              (fields prof_* of the result) */
   /* per-problem starting points, host, caller-owned, arrays of nprob pointers
      (NULL or a NULL entry: not given).  init_U[p] is n x r0 row-major; without
      it the problem cannot be solved (the random start is an input).
@@ -146,6 +148,12 @@ typedef struct {
   double t_phase1, t_phase2, t_metrics, t_total;   /* seconds */
   double op_bytes;         /* algorithmic bytes of every A(.) / A*(.)V / CG
                               operator application of the solve */
+  /* with options.profile: per kernel class (0 fused CG operator, 1 forward map,
+     2 adjoint product) the summed launch time in ms measured by HIP events on
+     the solver's stream, the number of launches and their algorithmic bytes */
+  double prof_ms[3];
+  double prof_bytes[3];
+  int64_t prof_launches[3];
 } lorads_result;
 
 /* Fill *opt with the defaults above (precision F64, eps 1e-6, switch 1e-3,

@@ -18,7 +18,7 @@ Readings where the paper is silent (the GPU library implements the same rules):
     ||grad||_F / (1 + ||C||_F) <= max(0.1 v, 1e-8); multipliers updated when the
     infeasibility v fell below 0.25 of its last value at an update, otherwise
     rho *= 10; rho0 = 1/max(1, ||b||_inf);
-  * rank growth: an inner solve that reaches 300 iterations stops, the rank
+  * rank growth: an inner solve that reaches 1000 iterations stops, the rank
     becomes min(ceil(1.5 r), floor(sqrt(2m)), n), new columns are
     N(0, (1e-3 ||U||_F / sqrt(n r))^2) from the counter-based SplitMix64 stream.
 """
@@ -44,8 +44,8 @@ class Options:
     cg_tol_kkt: float = 1e-2
     cg_maxit: int = 2000
     lbfgs_mem: int = 4
-    alm_inner_max: int = 500
-    rank_grow_iters: int = 300
+    alm_inner_max: int = 2000
+    rank_grow_iters: int = 1000
     rank_factor: float = 1.5
     r_max: int = 0                 # 0: floor(sqrt(2m)) capped by n
     alm_inner_rel: float = 0.1

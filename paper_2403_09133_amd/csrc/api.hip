@@ -83,8 +83,8 @@ void lorads_default_options(lorads_options* o) {
   o->cg_tol_kkt = 1e-2;
   o->cg_maxit = 2000;
   o->lbfgs_mem = 4;
-  o->alm_inner_max = 500;
-  o->rank_grow_iters = 300;
+  o->alm_inner_max = 2000;
+  o->rank_grow_iters = 1000;
   o->rank_factor = 1.5;
   o->r0 = 0;
   o->r_max = 0;
@@ -97,6 +97,7 @@ void lorads_default_options(lorads_options* o) {
   o->seed = 0;
   o->phase1 = 1;
   o->verbose = 0;
+  o->profile = 0;
   o->init_U = nullptr;
   o->init_lambda = nullptr;
 }
@@ -304,6 +305,8 @@ lorads_status lorads_admm_solve(lorads_ctx* ctx, const lorads_options* opt, lora
         P.lam.zero(s);
       }
       SolveInfo info;
+      P.prof.reset();
+      P.prof.on = o.profile != 0;
       double rho;
       if (o.phase1) {
         phase1(P, o, info, s);
@@ -316,6 +319,13 @@ lorads_status lorads_admm_solve(lorads_ctx* ctx, const lorads_options* opt, lora
       phase2(P, o, o.h * rho, info, s, t0);
       HIPCHK(hipStreamSynchronize(s));
       const auto t2 = std::chrono::steady_clock::now();
+      P.prof.resolve_all();
+      P.prof.on = false;
+      for (int k = 0; k < 3; ++k) {
+        R.prof_ms[k] = P.prof.ms[k];
+        R.prof_bytes[k] = P.prof.bytes[k];
+        R.prof_launches[k] = P.prof.count[k];
+      }
       P.solved = true;
       final_metrics(P, R, s, 300);
       HIPCHK(hipStreamSynchronize(s));

@@ -85,12 +85,10 @@ enum Slot : int {
   S_COUNT = 64
 };
 
-// counters for the last-block reductions (one per concurrently used site)
-enum Counter : int { C_OP = 0, C_UPD = 1, C_INIT = 2, C_DOT = 3, C_MDOT = 4, C_NUM = 8 };
-
 constexpr int kBlock = 256;        // threads per block of the row / element kernels
 constexpr int kRedBlocks = 512;    // grid of the fixed-grid reductions
 constexpr int kMaxPart = 8192;     // capacity of a partial-sum buffer
+constexpr int kPairChunk = 32;     // PAIR forward map: constraints per work item
 
 inline int pow2_group(int r) {
   int g = 1;

@@ -4,9 +4,8 @@
 // handled by a group of G lanes (G = power of two >= r, at most 64); lane c of
 // the group owns columns c, c + G, ...  Reductions inside a group use wave
 // shuffles (xor butterflies never leave an aligned group), reductions across a
-// grid use per-block partial sums finished by the last block to arrive
-// (device-scope fence + atomic ticket), so every sum has a fixed order and
-// results are bitwise reproducible run to run.
+// grid use per-block partial sums finished by a one-block kernel, so every sum
+// has a fixed order and results are bitwise reproducible run to run.
 #pragma once
 
 #include "common.hpp"
@@ -36,25 +35,48 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;  // valid in thread 0
 }
 
-// Publish this block's partial; returns true in thread 0 of the last block to
-// finish, after which `part[0..nblocks)` is complete and visible.
-__device__ __forceinline__ bool last_block(double partial, double* part, int* counter) {
-  __shared__ bool is_last;
-  if (threadIdx.x == 0) {
-    part[blockIdx.x] = partial;
-    __threadfence();
-    const int ticket = atomicAdd(counter, 1);
-    is_last = (ticket == (int)gridDim.x - 1);
-    if (is_last) __threadfence();
-  }
-  __syncthreads();
-  return is_last && threadIdx.x == 0;
+// Grid reductions are two-stage: every block stores its partial (plain store,
+// thread 0 holds the block's value) and a one-block finishing kernel sums the
+// partials in index order.  The kernel boundary makes the partials visible
+// across XCDs without device-scope fences in the producing kernels.
+__device__ __forceinline__ void publish_partial(double partial, double* part) {
+  if (threadIdx.x == 0) part[blockIdx.x] = partial;
 }
 
-__device__ __forceinline__ double sum_parts(const double* part, int n) {
+// Sum of part[0..n) by the whole block (strided per thread, then the block
+// tree): a fixed order for a given n and block size.  Result in thread 0.
+__device__ __forceinline__ double block_sum_parts(const double* part, int n, double* sh) {
   double s = 0.0;
-  for (int i = 0; i < n; ++i) s += part[i];
-  return s;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
+  return block_sum(s, sh);
+}
+
+// sc[slot + t] = scale * sum of partial array t (t < k), arrays of length np
+[[maybe_unused]] static __global__ void __launch_bounds__(kBlock) finish_slots(int np, int k, const double* __restrict__ part,
+                                                       double scale, double* __restrict__ sc, int slot) {
+  __shared__ double sh[kBlock / 64];
+  for (int t = 0; t < k; ++t) {
+    const double v = block_sum_parts(part + (size_t)t * np, np, sh);
+    if (threadIdx.x == 0) sc[slot + t] = scale * v;
+  }
+}
+
+// CG step length from the operator's <P, Q> partials: alpha = ||R||^2 / <P, Q>,
+// or the breakdown flag when <P, Q> <= 0.  Skipped once converged.
+[[maybe_unused]] static __global__ void __launch_bounds__(kBlock) cg_alpha_finish(int np, const double* __restrict__ part,
+                                                          double* __restrict__ sc, int parity) {
+  __shared__ double sh[kBlock / 64];
+  if (sc[S_DONE + parity] != 0.0) return;
+  const double s = block_sum_parts(part, np, sh);
+  if (threadIdx.x == 0) {
+    sc[S_PQ] = s;
+    if (!(s > 0.0)) {
+      sc[S_BRK] = 1.0;
+    } else {
+      sc[S_BRK] = 0.0;
+      sc[S_ALPHA] = sc[S_RR + parity] / s;
+    }
+  }
 }
 
 // ===========================================================================
@@ -105,8 +127,8 @@ __global__ void __launch_bounds__(kBlock) k1_generic(
 // the adjoint (entries (col, constraint, coef)).  One group per output row.
 //   MODE 0: plain adjoint product
 //   MODE 1: CG operator epilogue: out = gamma P + A*(w) V (w already holds
-//           rho * A(P W^T)), accumulates <P, out>; the last block turns the
-//           sum into the CG step length (or flags a breakdown).
+//           rho * A(P W^T)); per-block partials of <P, out> for the step
+//           length (cg_alpha_finish).
 // ===========================================================================
 template <typename T, int G, int MODE>
 __global__ void __launch_bounds__(kBlock) k2_generic(
@@ -116,8 +138,7 @@ __global__ void __launch_bounds__(kBlock) k2_generic(
     const T* __restrict__ w, const T* __restrict__ V, int r, int ld, T* __restrict__ out,
     int ldo, double out_scale,
     // MODE 1
-    const T* __restrict__ P, double* __restrict__ sc, int parity, double* __restrict__ part,
-    int* __restrict__ counter) {
+    const T* __restrict__ P, double* __restrict__ sc, int parity, double* __restrict__ part) {
   __shared__ double sh[kBlock / 64];
   if (MODE == 1 && sc[S_DONE + parity] != 0.0) return;
   const int row = (blockIdx.x * kBlock + threadIdx.x) / G;
@@ -168,20 +189,7 @@ __global__ void __launch_bounds__(kBlock) k2_generic(
       }
     }
   }
-  if (MODE == 1) {
-    const double bs = block_sum(pq, sh);
-    if (last_block(bs, part, counter)) {
-      const double s = sum_parts(part, gridDim.x);
-      sc[S_PQ] = s;
-      if (!(s > 0.0)) {
-        sc[S_BRK] = 1.0;
-      } else {
-        sc[S_BRK] = 0.0;
-        sc[S_ALPHA] = sc[S_RR + parity] / s;
-      }
-      *counter = 0;
-    }
-  }
+  if (MODE == 1) publish_partial(block_sum(pq, sh), part);
 }
 
 // ===========================================================================
@@ -190,10 +198,7 @@ __global__ void __launch_bounds__(kBlock) k2_generic(
 // P = R, ||R||^2 -> S_RR0, S_RR(parity 0); clears the flags.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) cg_init(size_t N, const T* __restrict__ R,
-                                                  T* __restrict__ P, double tol2,
-                                                  double* __restrict__ sc,
-                                                  double* __restrict__ part,
-                                                  int* __restrict__ counter) {
+                                                  T* __restrict__ P, double* __restrict__ part) {
   __shared__ double sh[kBlock / 64];
   double s = 0.0;
   for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock) {
@@ -201,9 +206,14 @@ __global__ void __launch_bounds__(kBlock) cg_init(size_t N, const T* __restrict_
     P[i] = v;
     s += (double)v * (double)v;
   }
-  const double bs = block_sum(s, sh);
-  if (last_block(bs, part, counter)) {
-    const double rr = sum_parts(part, gridDim.x);
+  publish_partial(block_sum(s, sh), part);
+}
+
+[[maybe_unused]] static __global__ void __launch_bounds__(kBlock) cg_init_finish(int np, const double* __restrict__ part,
+                                                         double tol2, double* __restrict__ sc) {
+  __shared__ double sh[kBlock / 64];
+  const double rr = block_sum_parts(part, np, sh);
+  if (threadIdx.x == 0) {
     sc[S_RR0] = rr;
     sc[S_RR + 0] = rr;
     sc[S_RR + 1] = rr;
@@ -212,7 +222,6 @@ __global__ void __launch_bounds__(kBlock) cg_init(size_t N, const T* __restrict_
     sc[S_BRK] = 0.0;
     sc[S_ITERS] = 0.0;
     sc[S_TOL2] = tol2;
-    *counter = 0;
   }
 }
 
@@ -221,9 +230,8 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock) cg_update(size_t N, T* __restrict__ X,
                                                     T* __restrict__ R, const T* __restrict__ P,
                                                     const T* __restrict__ Q,
-                                                    double* __restrict__ sc, int parity,
-                                                    double* __restrict__ part,
-                                                    int* __restrict__ counter) {
+                                                    const double* __restrict__ sc, int parity,
+                                                    double* __restrict__ part) {
   __shared__ double sh[kBlock / 64];
   const bool skip = sc[S_DONE + parity] != 0.0 || sc[S_BRK] != 0.0;
   double s = 0.0;
@@ -236,23 +244,28 @@ __global__ void __launch_bounds__(kBlock) cg_update(size_t N, T* __restrict__ X,
       s += (double)rv * (double)rv;
     }
   }
-  const double bs = block_sum(s, sh);
-  if (last_block(bs, part, counter)) {
-    const int q = parity ^ 1;
-    if (sc[S_DONE + parity] != 0.0) {
+  if (!skip) publish_partial(block_sum(s, sh), part);
+}
+
+// ||R||^2 of the update -> next parity slot, beta, iteration count and the
+// convergence flag; a converged or broken-down solve carries its flag forward.
+[[maybe_unused]] static __global__ void __launch_bounds__(kBlock) cg_update_finish(int np, const double* __restrict__ part,
+                                                           double* __restrict__ sc, int parity) {
+  __shared__ double sh[kBlock / 64];
+  const int q = parity ^ 1;
+  if (sc[S_DONE + parity] != 0.0 || sc[S_BRK] != 0.0) {
+    if (threadIdx.x == 0) {
       sc[S_DONE + q] = 1.0;
       sc[S_RR + q] = sc[S_RR + parity];
-    } else if (sc[S_BRK] != 0.0) {
-      sc[S_DONE + q] = 1.0;
-      sc[S_RR + q] = sc[S_RR + parity];
-    } else {
-      const double rr = sum_parts(part, gridDim.x);
-      sc[S_BETA] = rr / sc[S_RR + parity];
-      sc[S_RR + q] = rr;
-      sc[S_ITERS] += 1.0;
-      sc[S_DONE + q] = (rr <= sc[S_TOL2] * sc[S_RR0]) ? 1.0 : 0.0;
     }
-    *counter = 0;
+    return;
+  }
+  const double rr = block_sum_parts(part, np, sh);
+  if (threadIdx.x == 0) {
+    sc[S_BETA] = rr / sc[S_RR + parity];
+    sc[S_RR + q] = rr;
+    sc[S_ITERS] += 1.0;
+    sc[S_DONE + q] = (rr <= sc[S_TOL2] * sc[S_RR0]) ? 1.0 : 0.0;
   }
 }
 
@@ -271,35 +284,28 @@ __global__ void __launch_bounds__(kBlock) cg_direction(size_t N, const T* __rest
 // ===========================================================================
 // generic dense helpers
 // ===========================================================================
-// sc[slot] = scale * <X, Y> over N elements (fixed grid -> fixed order)
+// per-block partials of <X, Y> over N elements (fixed grid -> fixed order)
 template <typename TX, typename TY>
 __global__ void __launch_bounds__(kBlock) dot_kernel(size_t N, const TX* __restrict__ X,
-                                                     const TY* __restrict__ Y, double scale,
-                                                     double* __restrict__ sc, int slot,
-                                                     double* __restrict__ part,
-                                                     int* __restrict__ counter) {
+                                                     const TY* __restrict__ Y,
+                                                     double* __restrict__ part) {
   __shared__ double sh[kBlock / 64];
   double s = 0.0;
   for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock)
     s += (double)X[i] * (double)Y[i];
-  const double bs = block_sum(s, sh);
-  if (last_block(bs, part, counter)) {
-    sc[slot] = scale * sum_parts(part, gridDim.x);
-    *counter = 0;
-  }
+  publish_partial(block_sum(s, sh), part);
 }
 
-// Several dots over m-vectors for the quartic line search, in one pass:
+// Several dots over m-vectors for the quartic line search, in one pass
+// (per-block partials, array t at part + t * gridDim.x):
 //   out[0] = p2.p2, [1] = p1.p2, [2] = p1.p1, [3] = p0.p2, [4] = p0.p1,
 //   [5] = lam.p1, [6] = lam.p2,   with p0 = z - b.
-static __global__ void __launch_bounds__(kBlock) linesearch_dots(int m, const double* __restrict__ z,
+[[maybe_unused]] static __global__ void __launch_bounds__(kBlock) linesearch_dots(int m, const double* __restrict__ z,
                                                           const double* __restrict__ b,
                                                           const double* __restrict__ p1,
                                                           const double* __restrict__ p2,
                                                           const double* __restrict__ lam,
-                                                          double* __restrict__ sc, int slot,
-                                                          double* __restrict__ part,
-                                                          int* __restrict__ counter) {
+                                                          double* __restrict__ part) {
   __shared__ double sh[kBlock / 64];
   double s[7] = {0, 0, 0, 0, 0, 0, 0};
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < m; i += gridDim.x * kBlock) {
@@ -307,29 +313,17 @@ static __global__ void __launch_bounds__(kBlock) linesearch_dots(int m, const do
     s[0] += a2 * a2; s[1] += a1 * a2; s[2] += a1 * a1; s[3] += a0 * a2;
     s[4] += a0 * a1; s[5] += l * a1;  s[6] += l * a2;
   }
-  __shared__ bool is_last;
-  double bs[7];
-  for (int t = 0; t < 7; ++t) bs[t] = block_sum(s[t], sh);
-  if (threadIdx.x == 0) {
-    for (int t = 0; t < 7; ++t) part[(size_t)t * gridDim.x + blockIdx.x] = bs[t];
-    __threadfence();
-    is_last = atomicAdd(counter, 1) == (int)gridDim.x - 1;
-    if (is_last) __threadfence();
-  }
-  __syncthreads();
-  if (is_last && threadIdx.x == 0) {
-    for (int t = 0; t < 7; ++t) sc[slot + t] = sum_parts(part + (size_t)t * gridDim.x, gridDim.x);
-    *counter = 0;
+  for (int t = 0; t < 7; ++t) {
+    const double bs = block_sum(s[t], sh);
+    if (threadIdx.x == 0) part[(size_t)t * gridDim.x + blockIdx.x] = bs;
   }
 }
 
-// Dual update lam += rho (z - b) and sc[slot] = ||z - b||^2.
-static __global__ void __launch_bounds__(kBlock) dual_update(int m, const double* __restrict__ z,
+// Dual update lam += rho (z - b) and per-block partials of ||z - b||^2.
+[[maybe_unused]] static __global__ void __launch_bounds__(kBlock) dual_update(int m, const double* __restrict__ z,
                                                       const double* __restrict__ b,
                                                       double rho, double* __restrict__ lam,
-                                                      double* __restrict__ sc, int slot,
-                                                      double* __restrict__ part,
-                                                      int* __restrict__ counter) {
+                                                      double* __restrict__ part) {
   __shared__ double sh[kBlock / 64];
   double s = 0.0;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < m; i += gridDim.x * kBlock) {
@@ -337,11 +331,7 @@ static __global__ void __launch_bounds__(kBlock) dual_update(int m, const double
     lam[i] += rho * d;
     s += d * d;
   }
-  const double bs = block_sum(s, sh);
-  if (last_block(bs, part, counter)) {
-    sc[slot] = sum_parts(part, gridDim.x);
-    *counter = 0;
-  }
+  publish_partial(block_sum(s, sh), part);
 }
 
 // y = a * x + b * y  (elementwise, mixed types allowed)
@@ -409,7 +399,7 @@ __device__ __forceinline__ uint64_t splitmix_mix(uint64_t z) {
   return z ^ (z >> 31);
 }
 
-static __global__ void __launch_bounds__(kBlock) grow_rank_kernel(int n, int r_old, int r_new,
+[[maybe_unused]] static __global__ void __launch_bounds__(kBlock) grow_rank_kernel(int n, int r_old, int r_new,
                                                            const double* __restrict__ U,
                                                            double* __restrict__ Unew,
                                                            double sigma, uint64_t seed,

@@ -188,8 +188,7 @@ void final_metrics(Problem& P, lorads_result& res, hipStream_t s, int lanczos_st
   add_kernel<double, double, double><<<grid_for(N), kBlock, 0, s>>>(N, P.U.p, P.V.p, Uh.p);
   axpby<double, double><<<grid_for(N), kBlock, 0, s>>>(N, 0.0, Uh.p, 0.5, Uh.p);
   op_forward<double>(P, Uh.p, Uh.p, r, r, P.zbuf.p, 1.0, s);
-  dual_update<<<grid_for(m, kRedBlocks), kBlock, 0, s>>>(m, P.zbuf.p, P.b.p, 0.0, P.lam.p, P.sc.p,
-                                                         S_GEN, P.part.p, P.counters.p + C_DOT);
+  dual_update_slot(P, P.zbuf.p, 0.0, P.lam.p, S_GEN, s);
   op_adjoint<double>(P, (const double*)nullptr, 1.0, Uh.p, r, r, CU.p, r, 1.0, s);
   dot_to_slot<double, double>(P, N, CU.p, Uh.p, 1.0, S_GEN + 1, s);
   dot_to_slot<double, double>(P, m, P.b.p, P.lam.p, -1.0, S_GEN + 2, s);

@@ -42,16 +42,17 @@ static int rows_grid(int rows, int G) {
 
 // ---------------------------------------------------------------------------
 template <typename T>
-void op_forward(Problem& P, const T* U, const T* V, int r, int ld, T* z, double scale,
-                hipStream_t s) {
+static void op_forward_impl(Problem& P, const T* U, const T* V, int r, int ld, T* z, double scale,
+                            hipStream_t s) {
   const int G = pow2_group(r);
   if (P.structure == LORADS_STRUCT_DIAG) {
     LORADS_DISPATCH_G(G, (k1_diag<T, G, 0><<<rows_grid(P.m, G), kBlock, 0, s>>>(
                              P.m, P.drow.p, dc<T>(P), U, V, r, ld, z, scale, nullptr, nullptr,
                              0.0, nullptr, nullptr, 0)));
   } else if (P.structure == LORADS_STRUCT_PAIR) {
-    LORADS_DISPATCH_G(G, (k1_pair<T, G, 0><<<rows_grid(P.m, G), kBlock, 0, s>>>(
-                             P.m, P.pj.p, P.pk.p, pc<T>(P), P.pair_coef, U, V, r, ld, z, scale,
+    LORADS_DISPATCH_G(G, (k1_pair<T, G, 0><<<rows_grid(P.nfchunks, G), kBlock, 0, s>>>(
+                             P.nfchunks, P.fchunk_row.p, P.fchunk_start.p, P.rptr.p, P.pk.p,
+                             pc<T>(P), P.pair_coef, U, V, r, ld, z, scale,
                              nullptr, nullptr, 0.0, nullptr, nullptr, 0)));
   } else {
     LORADS_DISPATCH_G(G, (k1_generic<T, G, 0><<<rows_grid(P.m, G), kBlock, 0, s>>>(
@@ -61,16 +62,34 @@ void op_forward(Problem& P, const T* U, const T* V, int r, int ld, T* z, double 
   HIPCHK(hipGetLastError());
 }
 
+template <typename T>
+void op_forward(Problem& P, const T* U, const T* V, int r, int ld, T* z, double scale,
+                hipStream_t s) {
+  P.prof.run(1, bytes_forward(P, r, sizeof(T)), s,
+             [&] { op_forward_impl<T>(P, U, V, r, ld, z, scale, s); });
+}
+
+static void op_forward_w_impl(Problem& P, const double* U, const double* V, int r, int ld,
+                              double* z, double* w, const double* lam, double rho, hipStream_t s);
+
 void op_forward_w(Problem& P, const double* U, const double* V, int r, int ld, double* z,
                   double* w, const double* lam, double rho, hipStream_t s) {
+  // the extra w output is an m-vector write beyond the plain forward map
+  P.prof.run(1, bytes_forward(P, r, 8) + 16.0 * P.m, s,
+             [&] { op_forward_w_impl(P, U, V, r, ld, z, w, lam, rho, s); });
+}
+
+static void op_forward_w_impl(Problem& P, const double* U, const double* V, int r, int ld,
+                              double* z, double* w, const double* lam, double rho, hipStream_t s) {
   const int G = pow2_group(r);
   if (P.structure == LORADS_STRUCT_DIAG) {
     LORADS_DISPATCH_G(G, (k1_diag<double, G, 1><<<rows_grid(P.m, G), kBlock, 0, s>>>(
                              P.m, P.drow.p, P.dcoef.p, U, V, r, ld, z, 1.0, lam, P.b.p, rho, w,
                              nullptr, 0)));
   } else if (P.structure == LORADS_STRUCT_PAIR) {
-    LORADS_DISPATCH_G(G, (k1_pair<double, G, 1><<<rows_grid(P.m, G), kBlock, 0, s>>>(
-                             P.m, P.pj.p, P.pk.p, P.pcoef.p, P.pair_coef, U, V, r, ld, z, 1.0,
+    LORADS_DISPATCH_G(G, (k1_pair<double, G, 1><<<rows_grid(P.nfchunks, G), kBlock, 0, s>>>(
+                             P.nfchunks, P.fchunk_row.p, P.fchunk_start.p, P.rptr.p, P.pk.p,
+                             P.pcoef.p, P.pair_coef, U, V, r, ld, z, 1.0,
                              lam, P.b.p, rho, w, nullptr, 0)));
   } else {
     LORADS_DISPATCH_G(G, (k1_generic<double, G, 1><<<rows_grid(P.m, G), kBlock, 0, s>>>(
@@ -81,25 +100,36 @@ void op_forward_w(Problem& P, const double* U, const double* V, int r, int ld, d
 }
 
 template <typename T>
+static void op_adjoint_impl(Problem& P, const T* w, double c_scale, const T* V, int r, int ld,
+                            T* out, int ldo, double out_scale, hipStream_t s);
+
+template <typename T>
 void op_adjoint(Problem& P, const T* w, double c_scale, const T* V, int r, int ld, T* out,
                 int ldo, double out_scale, hipStream_t s) {
+  P.prof.run(2, bytes_adjoint(P, r, sizeof(T), c_scale != 0.0), s,
+             [&] { op_adjoint_impl<T>(P, w, c_scale, V, r, ld, out, ldo, out_scale, s); });
+}
+
+template <typename T>
+static void op_adjoint_impl(Problem& P, const T* w, double c_scale, const T* V, int r, int ld,
+                            T* out, int ldo, double out_scale, hipStream_t s) {
   const int G = pow2_group(r);
   if (r > 4 * G) fail(LORADS_EINVAL, "rank above 256 is not supported");
   if (P.structure == LORADS_STRUCT_DIAG) {
     LORADS_DISPATCH_G(G, (k2_diag<T, G, 0><<<rows_grid(P.n, G), kBlock, 0, s>>>(
                              P.n, P.cptr.p, P.ccol.p, cv<T>(P), c_scale, P.dptr.p, dc<T>(P),
                              nullptr, w, V, r, ld, out, ldo, out_scale, nullptr, nullptr, 0,
-                             nullptr, nullptr)));
+                             nullptr)));
   } else if (P.structure == LORADS_STRUCT_PAIR) {
-    LORADS_DISPATCH_G(G, (k2_pair<T, G, 0><<<rows_grid(P.n, G), kBlock, 0, s>>>(
+    LORADS_DISPATCH_G(G, (k2_pair<T, G, 0><<<P.n, kBlock, 0, s>>>(
                              P.n, P.cptr.p, P.ccol.p, cv<T>(P), c_scale, P.rptr.p, P.pk.p,
                              P.cvptr.p, P.cvj.p, P.cvid.p, pc<T>(P), P.pair_coef, w, V, nullptr,
-                             r, ld, out, ldo, out_scale, nullptr, 0, nullptr, nullptr)));
+                             r, ld, out, ldo, out_scale, nullptr, 0, nullptr)));
   } else {
     LORADS_DISPATCH_G(G, (k2_generic<T, G, 0><<<rows_grid(P.n, G), kBlock, 0, s>>>(
                              P.n, P.cptr.p, P.ccol.p, cv<T>(P), c_scale, P.aptr.p, P.acol.p,
                              P.acon.p, av<T>(P), w, V, r, ld, out, ldo, out_scale, nullptr,
-                             nullptr, 0, nullptr, nullptr)));
+                             nullptr, 0, nullptr)));
   }
   HIPCHK(hipGetLastError());
 }
@@ -113,15 +143,20 @@ void op_cg(Problem& P, const T* W, int r, const T* Pd, T* Q, T* t, int parity, h
     const int grid = rows_grid(P.n, G);
     P.ensure_part(grid);
     LORADS_DISPATCH_G(G, (k3_diag<T, G><<<grid, kBlock, 0, s>>>(
-                             P.n, ds<T>(P), W, Pd, Q, r, sc, parity, P.part.p,
-                             P.counters.p + C_OP)));
+                             P.n, ds<T>(P), W, Pd, Q, r, sc, parity, P.part.p)));
+    cg_alpha_finish<<<1, kBlock, 0, s>>>(grid, P.part.p, sc, parity);
   } else if (P.structure == LORADS_STRUCT_PAIR) {
-    const int grid = rows_grid(P.n, G);
-    P.ensure_part(grid);
-    LORADS_DISPATCH_G(G, (k2_pair<T, G, 1><<<grid, kBlock, 0, s>>>(
+    // t = rho A(P W^T) once per constraint, then Q = gamma P + A*(t) W
+    P.ensure_part(P.n);
+    LORADS_DISPATCH_G(G, (k1_pair<T, G, 2><<<rows_grid(P.nfchunks, G), kBlock, 0, s>>>(
+                             P.nfchunks, P.fchunk_row.p, P.fchunk_start.p, P.rptr.p, P.pk.p,
+                             pc<T>(P), P.pair_coef, Pd, W, r, r, t, 1.0, nullptr, nullptr, 0.0,
+                             nullptr, sc, parity)));
+    LORADS_DISPATCH_G(G, (k2_pair<T, G, 2><<<P.n, kBlock, 0, s>>>(
                              P.n, nullptr, nullptr, nullptr, 0.0, P.rptr.p, P.pk.p, P.cvptr.p,
-                             P.cvj.p, P.cvid.p, pc<T>(P), P.pair_coef, nullptr, W, Pd, r, r, Q, r,
-                             1.0, sc, parity, P.part.p, P.counters.p + C_OP)));
+                             P.cvj.p, P.cvid.p, pc<T>(P), P.pair_coef, t, W, Pd, r, r, Q, r,
+                             1.0, sc, parity, P.part.p)));
+    cg_alpha_finish<<<1, kBlock, 0, s>>>(P.n, P.part.p, sc, parity);
   } else {
     LORADS_DISPATCH_G(G, (k1_generic<T, G, 2><<<rows_grid(P.m, G), kBlock, 0, s>>>(
                              P.m, P.kptr.p, P.krow.p, P.kcol.p, kv<T>(P), Pd, W, r, r, t, 1.0,
@@ -130,8 +165,8 @@ void op_cg(Problem& P, const T* W, int r, const T* Pd, T* Q, T* t, int parity, h
     P.ensure_part(grid);
     LORADS_DISPATCH_G(G, (k2_generic<T, G, 1><<<grid, kBlock, 0, s>>>(
                              P.n, nullptr, nullptr, nullptr, 0.0, P.aptr.p, P.acol.p, P.acon.p,
-                             av<T>(P), t, W, r, r, Q, r, 1.0, Pd, sc, parity, P.part.p,
-                             P.counters.p + C_OP)));
+                             av<T>(P), t, W, r, r, Q, r, 1.0, Pd, sc, parity, P.part.p)));
+    cg_alpha_finish<<<1, kBlock, 0, s>>>(grid, P.part.p, sc, parity);
   }
   HIPCHK(hipGetLastError());
 }
@@ -185,14 +220,33 @@ void set_slots(Problem& P, int slot, const double* vals, int count, hipStream_t 
 void read_slots(Problem& P, int slot, double* vals, int count, hipStream_t s) {
   HIPCHK(hipMemcpyAsync(vals, P.sc.p + slot, count * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  if (P.prof.on) {  // the stream is idle: finished forward / adjoint timings
+    P.prof.resolve(1);
+    P.prof.resolve(2);
+  }
 }
 
 template <typename TX, typename TY>
 void dot_to_slot(Problem& P, size_t N, const TX* X, const TY* Y, double scale, int slot,
                  hipStream_t s) {
   const int grid = grid_for(N, kRedBlocks);
-  dot_kernel<TX, TY><<<grid, kBlock, 0, s>>>(N, X, Y, scale, P.sc.p, slot, P.part.p,
-                                             P.counters.p + C_DOT);
+  dot_kernel<TX, TY><<<grid, kBlock, 0, s>>>(N, X, Y, P.part.p);
+  finish_slots<<<1, kBlock, 0, s>>>(grid, 1, P.part.p, scale, P.sc.p, slot);
+  HIPCHK(hipGetLastError());
+}
+
+void dual_update_slot(Problem& P, const double* z, double rho, double* lam, int slot, hipStream_t s) {
+  const int grid = grid_for(P.m, kRedBlocks);
+  dual_update<<<grid, kBlock, 0, s>>>(P.m, z, P.b.p, rho, lam, P.part.p);
+  finish_slots<<<1, kBlock, 0, s>>>(grid, 1, P.part.p, 1.0, P.sc.p, slot);
+  HIPCHK(hipGetLastError());
+}
+
+void linesearch_slots(Problem& P, const double* z, const double* p1, const double* p2,
+                      const double* lam, int slot, hipStream_t s) {
+  const int grid = grid_for(P.m, kRedBlocks);
+  linesearch_dots<<<grid, kBlock, 0, s>>>(P.m, z, P.b.p, p1, p2, lam, P.part.p);
+  finish_slots<<<1, kBlock, 0, s>>>(grid, 7, P.part.p, 1.0, P.sc.p, slot);
   HIPCHK(hipGetLastError());
 }
 
@@ -207,7 +261,8 @@ int cg_run(Problem& P, const T* W, int r, double rho, double gamma, T* R, T* X, 
   const double sv[2] = {gamma, rho};
   set_slots(P, S_GAMMA, sv, 2, s);
   const int gridv = grid_for(N, 1024);
-  cg_init<T><<<gridv, kBlock, 0, s>>>(N, R, Pd, tol * tol, P.sc.p, P.part.p, P.counters.p + C_INIT);
+  cg_init<T><<<gridv, kBlock, 0, s>>>(N, R, Pd, P.part.p);
+  cg_init_finish<<<1, kBlock, 0, s>>>(gridv, P.part.p, tol * tol, P.sc.p);
   HIPCHK(hipGetLastError());
   int k = 0;
   int chunk = 2;
@@ -217,16 +272,19 @@ int cg_run(Problem& P, const T* W, int r, double rho, double gamma, T* R, T* X, 
   bool done = false;
   while (!done && k < maxit) {
     const int steps = std::min(chunk, maxit - k);
+    const int iters_before = iters;
     for (int i = 0; i < steps; ++i, ++k) {
       const int par = k & 1;
-      op_cg<T>(P, W, r, Pd, Q, t, par, s);
-      cg_update<T><<<gridv, kBlock, 0, s>>>(N, X, R, Pd, Q, P.sc.p, par, P.part.p,
-                                            P.counters.p + C_UPD);
+      P.prof.run(0, bytes_cg_op(P, r, sizeof(T)), s, [&] { op_cg<T>(P, W, r, Pd, Q, t, par, s); });
+      cg_update<T><<<gridv, kBlock, 0, s>>>(N, X, R, Pd, Q, P.sc.p, par, P.part.p);
+      cg_update_finish<<<1, kBlock, 0, s>>>(gridv, P.part.p, P.sc.p, par);
       cg_direction<T><<<gridv, kBlock, 0, s>>>(N, R, Pd, P.sc.p, par);
     }
     HIPCHK(hipGetLastError());
     read_slots(P, 0, h, kRead, s);
     iters = (int)h[S_ITERS];
+    // launches after convergence returned at once: time only the live ones
+    if (P.prof.on) P.prof.resolve(0, iters - iters_before);
     done = h[S_DONE + (k & 1)] != 0.0;
     chunk = std::min(chunk * 2, 32);
   }

@@ -7,6 +7,69 @@
 
 namespace lorads {
 
+// Live timing of the operator launches with HIP events recorded on the stream
+// the kernels run on.  Kinds: 0 CG operator, 1 forward map, 2 adjoint product.
+// Pairs are resolved at the solver's existing synchronisation points; CG
+// launches that the device skipped after convergence are not counted.
+struct KernelProfile {
+  bool on = false;
+  struct Pair { hipEvent_t a, b; double bytes; };
+  std::vector<hipEvent_t> all, free_;
+  std::vector<Pair> pending[3];
+  double ms[3] = {0, 0, 0}, bytes[3] = {0, 0, 0};
+  long long count[3] = {0, 0, 0};
+
+  hipEvent_t get() {
+    if (free_.empty()) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      all.push_back(e);
+      return e;
+    }
+    hipEvent_t e = free_.back();
+    free_.pop_back();
+    return e;
+  }
+  template <typename F>
+  void run(int kind, double b, hipStream_t s, F&& launch) {
+    if (!on) { launch(); return; }
+    hipEvent_t e0 = get(), e1 = get();
+    HIPCHK(hipEventRecord(e0, s));
+    launch();
+    HIPCHK(hipEventRecord(e1, s));
+    pending[kind].push_back({e0, e1, b});
+  }
+  // accumulate the first `keep` pending pairs of `kind` (all when keep < 0);
+  // the caller has synchronised the stream
+  void resolve(int kind, long long keep = -1) {
+    auto& v = pending[kind];
+    const size_t k = keep < 0 ? v.size() : std::min<size_t>(v.size(), (size_t)keep);
+    for (size_t i = 0; i < k; ++i) {
+      float t = 0.f;
+      HIPCHK(hipEventElapsedTime(&t, v[i].a, v[i].b));
+      ms[kind] += t;
+      bytes[kind] += v[i].bytes;
+      count[kind] += 1;
+    }
+    for (auto& pr : v) { free_.push_back(pr.a); free_.push_back(pr.b); }
+    v.clear();
+  }
+  void resolve_all() {
+    for (int k = 0; k < 3; ++k) resolve(k);
+  }
+  void reset() {
+    for (int k = 0; k < 3; ++k) {
+      for (auto& pr : pending[k]) { free_.push_back(pr.a); free_.push_back(pr.b); }
+      pending[k].clear();
+      ms[k] = bytes[k] = 0;
+      count[k] = 0;
+    }
+  }
+  ~KernelProfile() {
+    for (auto e : all) (void)hipEventDestroy(e);
+  }
+};
+
 // Device layout of one SDP instance.
 //
 // Internal constraint order: the order in which constraint-indexed vectors
@@ -51,12 +114,16 @@ struct Problem {
   DevBuf<float> pcoeff;
   double pair_coef = 0;        // used when pcoef is empty
   DevBuf<int> rptr;            // n+1: view R row pointers (rows owning entries as j)
+  // forward-map work list: chunks of at most kPairChunk consecutive view-R
+  // constraints of one row (row, first constraint); the chunk ends at the
+  // next chunk's start or the row's end
+  DevBuf<int> fchunk_row, fchunk_start;
+  int nfchunks = 0;
   DevBuf<int> cvptr, cvj, cvid;  // view C: row pointers, partner j, internal id
 
   // solver scratch
   DevBuf<double> sc;
   DevBuf<double> part;
-  DevBuf<int> counters;
   size_t part_cap = 0;
 
   // last solution
@@ -67,6 +134,8 @@ struct Problem {
   // scratch m-vectors
   DevBuf<double> zbuf, wbuf, tbuf, ubuf;
   DevBuf<float> tbuff;
+
+  KernelProfile prof;
 
   // The partial-sum buffer is sized once at setup (kernels may still read it,
   // so it is never reallocated); launches that would need more are refused.
@@ -107,6 +176,11 @@ double bytes_cg_op(const Problem& P, int r, int s);
 // ---------------------------------------------------------------------------
 void set_slots(Problem& P, int slot, const double* vals, int count, hipStream_t s);
 void read_slots(Problem& P, int slot, double* vals, int count, hipStream_t s);  // synchronises
+// lam += rho (z - b) and sc[slot] = ||z - b||^2 (rho = 0: norm only)
+void dual_update_slot(Problem& P, const double* z, double rho, double* lam, int slot, hipStream_t s);
+// the seven m-vector inner products of the quartic line search -> sc[slot .. slot+6]
+void linesearch_slots(Problem& P, const double* z, const double* p1, const double* p2,
+                      const double* lam, int slot, hipStream_t s);
 template <typename TX, typename TY>
 void dot_to_slot(Problem& P, size_t N, const TX* X, const TY* Y, double scale, int slot, hipStream_t s);
 

@@ -265,6 +265,17 @@ std::unique_ptr<Problem> ingest(const lorads_problem& p, hipStream_t s) {
       P->pcoeff.upload(f, s);
     }
     P->rptr.upload(rptr, s);
+    {
+      std::vector<int> crow, cstart;
+      for (int j = 0; j < n; ++j)
+        for (int i = rptr[j]; i < rptr[j + 1]; i += kPairChunk) {
+          crow.push_back(j);
+          cstart.push_back(i);
+        }
+      P->nfchunks = (int)crow.size();
+      P->fchunk_row.upload(crow, s);
+      P->fchunk_start.upload(cstart, s);
+    }
     P->cvptr.upload(cvptr, s);
     P->cvj.upload(cvj, s);
     P->cvid.upload(cvid, s);
@@ -283,10 +294,9 @@ std::unique_ptr<Problem> ingest(const lorads_problem& p, hipStream_t s) {
 
   P->sc.alloc(S_COUNT);
   P->sc.zero(s);
-  P->counters.alloc(C_NUM);
-  P->counters.zero(s);
   // one partial per block of the widest row kernel (64 lanes per row)
-  P->part_cap = std::max<size_t>(kMaxPart, (size_t)n / 4 + 64);
+  // (the PAIR adjoint runs one block per row)
+  P->part_cap = std::max<size_t>(kMaxPart, (size_t)n + 64);
   P->part.alloc(P->part_cap);
   P->zbuf.alloc(m);
   P->wbuf.alloc(m);

@@ -2,7 +2,7 @@
 // search and dynamic rank), the switch, Phase II (ADMM with CG subproblem
 // solves) and the Appendix-B error measures.  Host code orchestrates device
 // kernels; every vector operation of the path runs on the GPU, the host only
-// keeps scalars (rho, gamma, tolerances, counters) and makes the decisions.
+// keeps scalars (rho, gamma, tolerances, iteration counts) and makes the decisions.
 #include <algorithm>
 #include <chrono>
 #include <complex>
@@ -118,10 +118,7 @@ static void alm_gradient(Problem& P, AlmState& A, const double* U, double* G, do
 
 static double host_norm_zb(Problem& P, hipStream_t s) {
   // ||z - b||_2 via dual_update with rho = 0 (lam unchanged)
-  dual_update<<<grid_for(P.m, kRedBlocks), kBlock, 0, s>>>(P.m, P.zbuf.p, P.b.p, 0.0, P.lam.p,
-                                                           P.sc.p, S_GEN, P.part.p,
-                                                           P.counters.p + C_DOT);
-  HIPCHK(hipGetLastError());
+  dual_update_slot(P, P.zbuf.p, 0.0, P.lam.p, S_GEN, s);
   double v;
   read_slots(P, S_GEN, &v, 1, s);
   return std::sqrt(v);
@@ -202,10 +199,7 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
         info.op_bytes += 2 * bytes_forward(P, r, 8) + bytes_adjoint(P, r, 8, true);
         dot_to_slot<double, double>(P, N, A.CD.p, U, 2.0, S_GEN + 1, s);
         dot_to_slot<double, double>(P, N, A.CD.p, A.D.p, 1.0, S_GEN + 2, s);
-        linesearch_dots<<<grid_for(m, kRedBlocks), kBlock, 0, s>>>(
-            m, P.zbuf.p, P.b.p, A.p1.p, A.p2.p, P.lam.p, P.sc.p, S_GEN + 3, P.part.p,
-            P.counters.p + C_MDOT);
-        HIPCHK(hipGetLastError());
+        linesearch_slots(P, P.zbuf.p, A.p1.p, A.p2.p, P.lam.p, S_GEN + 3, s);
         read_slots(P, S_GEN + 1, h, 9, s);
         const double c1 = h[0], c2 = h[1];
         const double p22 = h[2], p12 = h[3], p11 = h[4], p02 = h[5], p01 = h[6], l1 = h[7],
@@ -270,10 +264,7 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
       continue;
     }
     if (v <= o.alm_eta * v_ref) {
-      dual_update<<<grid_for(m, kRedBlocks), kBlock, 0, s>>>(m, P.zbuf.p, P.b.p, rho, P.lam.p,
-                                                             P.sc.p, S_GEN, P.part.p,
-                                                             P.counters.p + C_DOT);
-      HIPCHK(hipGetLastError());
+      dual_update_slot(P, P.zbuf.p, rho, P.lam.p, S_GEN, s);
       v_ref = v;
     } else {
       rho *= o.alm_rho_factor;
@@ -356,9 +347,7 @@ static void phase2_t(Problem& P, const lorads_options& o, double rho, SolveInfo&
     // z = A(U V^T); lam += rho (z - b); residual norms
     op_forward<double>(P, P.U.p, P.V.p, r, r, P.zbuf.p, 1.0, s);
     info.op_bytes += bytes_forward(P, r, 8);
-    dual_update<<<grid_for(m, kRedBlocks), kBlock, 0, s>>>(m, P.zbuf.p, P.b.p, rho, P.lam.p,
-                                                           P.sc.p, S_GEN, P.part.p,
-                                                           P.counters.p + C_DOT);
+    dual_update_slot(P, P.zbuf.p, rho, P.lam.p, S_GEN, s);
     axpby<double, double><<<gridN(N), kBlock, 0, s>>>(N, 1.0, P.V.p, -1.0, Vold.p);  // V+ - V
     dot_to_slot<double, double>(P, N, Vold.p, Vold.p, 1.0, S_GEN + 1, s);
     HIPCHK(hipGetLastError());

@@ -49,7 +49,7 @@ class Options_(C.Structure):
         ("r0", C.c_int32), ("r_max", C.c_int32), ("alm_inner_rel", C.c_double),
         ("alm_inner_floor", C.c_double), ("alm_eta", C.c_double), ("alm_rho_factor", C.c_double),
         ("alm_outer_max", C.c_int32), ("rho0", C.c_double), ("seed", C.c_uint64),
-        ("phase1", C.c_int32), ("verbose", C.c_int32),
+        ("phase1", C.c_int32), ("verbose", C.c_int32), ("profile", C.c_int32),
         ("init_U", C.c_void_p), ("init_lambda", C.c_void_p),
     ]
 
@@ -63,6 +63,7 @@ class Result_(C.Structure):
         ("pinf_stop", C.c_double), ("dres_stop", C.c_double), ("rho", C.c_double),
         ("gamma", C.c_double), ("t_phase1", C.c_double), ("t_phase2", C.c_double),
         ("t_metrics", C.c_double), ("t_total", C.c_double), ("op_bytes", C.c_double),
+        ("prof_ms", C.c_double * 3), ("prof_bytes", C.c_double * 3), ("prof_launches", C.c_int64 * 3),
     ]
 
 
@@ -266,7 +267,11 @@ class Context:
             raise LoradsError(st, lib.lorads_last_error(self.h).decode())
         out = []
         for i in range(self.nprob):
-            out.append({f: getattr(res[i], f) for f, _ in Result_._fields_})
+            d = {}
+            for f, _ in Result_._fields_:
+                v = getattr(res[i], f)
+                d[f] = list(v) if f.startswith("prof_") else v
+            out.append(d)
         return out
 
     def get_solution(self, prob: int = 0, rank: Optional[int] = None):
