@@ -90,6 +90,56 @@ def cpu_baseline(p, r: int, budget_s: float = 20.0):
                        f"{t:.1f} s on the host")
 
 
+def batch_leg(count: int = 512, sample: int = 16):
+    """Batched form: `count` MaxCut SDPs, n ~ U{50..2000}, average degree ~ U[3, 20],
+    +-1 weights, rank ceil(log2 n) each, in one persistent launch (workgroup size
+    autotuned), FP64 and FP32 CG; against `sample` instances solved one after the
+    other by the single-instance path, extrapolated to `count`."""
+    import sdpgen
+    from paper_2403_09133_amd import Context, default_options
+    t = time.time()
+    probs = sdpgen.batch_maxcut(count, 2000, 50, 2000, 3.0, 20.0, "pm1")
+    U0 = [sdpgen.random_init_U(p.n, int(math.ceil(math.log2(p.n))), 2000 + i) for i, p in enumerate(probs)]
+    t_gen = time.time() - t
+    from oracle.options import paper_defaults
+    pd = paper_defaults("maxcut", 1000)
+
+    def opts(**kw):
+        return default_options(r0=1, switch_tol=pd["switch_tol"], h=pd["h"], **kw)
+
+    out = dict(instances=count, sum_n=int(sum(p.n for p in probs)),
+               sum_edges=int(sum(len(p.meta["edges"][0]) for p in probs)), gen_s=round(t_gen, 2))
+    t = time.time()
+    ctx = Context(probs)
+    out["setup_s"] = round(time.time() - t, 2)
+    best, times = ctx.batch_autotune(U0, opts(max_admm_iter=30), (64, 128, 256, 512, 1024))
+    out["autotune"] = {"block": best, "ms_short_run": {k: round(v, 2) for k, v in times.items()}}
+    for name, prec in (("fp64", 0), ("fp32", 1)):
+        t = time.perf_counter()
+        res = ctx.admm_solve(U0, opts(precision=prec, batch_mode=1))
+        dt = time.perf_counter() - t
+        out[name] = dict(s=round(dt, 4), converged=int(sum(r["status"] == 0 for r in res)),
+                         max_admm_iters=int(max(r["admm_iters"] for r in res)),
+                         median_admm_iters=float(np.median([r["admm_iters"] for r in res])),
+                         max_kkt=float(max(r["kkt"] for r in res)))
+        print(f"[bench] batch {name}: {dt:.3f}s, {out[name]['converged']}/{count} converged",
+              file=sys.stderr, flush=True)
+    ctx.close()
+    sub = probs[:sample]
+    ctx = Context(sub)
+    t = time.perf_counter()
+    res = ctx.admm_solve(U0[:sample], opts(batch_mode=2))
+    dt = time.perf_counter() - t
+    ctx.close()
+    share = sum(p.n for p in sub) / sum(p.n for p in probs)
+    out["sequential_sample"] = dict(instances=sample, s=round(dt, 3),
+                                    extrapolated_s=round(dt / share, 2),
+                                    note="first instances of the batch solved one after the other "
+                                         "(single-instance path, FP64); extrapolated by their share of sum n")
+    out["speedup_vs_sequential_fp64"] = round(out["sequential_sample"]["extrapolated_s"] / out["fp64"]["s"], 1)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +148,7 @@ def main():
     ap.add_argument("--workload", default="mc_10000", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solve")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-form leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the method's batch and single-instance paths are "
@@ -202,6 +253,10 @@ def main():
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p, r0)
     line.update(extra)
+    if not args.no_batch:
+        line["batched_maxcut"] = batch_leg()
+        line["time_to_kkt_s"]["batched_512_fp64"] = line["batched_maxcut"]["fp64"]["s"]
+        line["time_to_kkt_s"]["batched_512_fp32"] = line["batched_maxcut"]["fp32"]["s"]
     print(json.dumps(line), flush=True)
 
 

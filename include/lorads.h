@@ -121,12 +121,22 @@ typedef struct {
   int32_t verbose;         /* 0 silent, 1 per-phase summary, 2 per iteration */
   int32_t profile;         /* 1: time the operator launches with HIP events
                               (fields prof_* of the result) */
+  int32_t batch_mode;      /* 0: batched persistent launch when the context holds
+                              >= 2 problems, all with diagonal constraints
+                              (MaxCut), else one problem after the other;
+                              1: require the batched launch (EINVAL otherwise);
+                              2: always one problem after the other */
+  int32_t batch_block;     /* workgroup size of the batched launch (multiple of
+                              64 up to 1024); 0: the context's tuned value
+                              (lorads_batch_autotune), default 256 */
   /* per-problem starting points, host, caller-owned, arrays of nprob pointers
      (NULL or a NULL entry: not given).  init_U[p] is n x r0 row-major; without
      it the problem cannot be solved (the random start is an input).
      init_lambda[p] has m entries in the caller's constraint order. */
   const double *const *init_U;
   const double *const *init_lambda;
+  const int32_t *init_rank;  /* per-problem initial rank (nprob entries, NULL:
+                                r0 for every problem); init_U[p] is n x init_rank[p] */
 } lorads_options;
 
 typedef struct {
@@ -202,6 +212,16 @@ lorads_status lorads_cg_solve(lorads_ctx *ctx, int32_t prob, const void *W, doub
  * array of nprob results.  Blocks the host until done.  Returns the worst
  * per-problem status. */
 lorads_status lorads_admm_solve(lorads_ctx *ctx, const lorads_options *opt, lorads_result *res);
+
+/* Autotuner of the batched launch: runs the batched solve once per candidate
+ * workgroup size (host array cand[ncand], multiples of 64 up to 1024) with the
+ * given options (callers pass a short iteration budget), times each run with
+ * HIP events, keeps the fastest in the context for later solves with
+ * batch_block = 0 and returns it in *best (times_ms, host, may be NULL:
+ * ncand timings).  Overwrites the problems' last solutions.  EINVAL unless the
+ * context is eligible for the batched launch. */
+lorads_status lorads_batch_autotune(lorads_ctx *ctx, const lorads_options *opt, const int32_t *cand,
+                                    int32_t ncand, int32_t *best, double *times_ms);
 
 /* Copy the last solution of problem `prob` to host buffers (any may be NULL):
  * U, V: n x rank row-major; lambda: m (caller order).  ESTATE before a solve. */

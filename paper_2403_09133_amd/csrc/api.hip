@@ -3,11 +3,13 @@
 #include <cstring>
 #include <memory>
 
+#include "batch.hpp"
 #include "kernels.hpp"
 #include "solver.hpp"
 
 struct lorads_ctx {
   std::vector<std::unique_ptr<lorads::Problem>> probs;
+  lorads::Batch batch;
   std::string err;
   hipStream_t stream = nullptr;
   int device = 0;
@@ -98,8 +100,11 @@ void lorads_default_options(lorads_options* o) {
   o->phase1 = 1;
   o->verbose = 0;
   o->profile = 0;
+  o->batch_mode = 0;
+  o->batch_block = 0;
   o->init_U = nullptr;
   o->init_lambda = nullptr;
+  o->init_rank = nullptr;
 }
 
 lorads_status lorads_setup(const lorads_problem* probs, int32_t nprob, lorads_ctx** out) {
@@ -281,17 +286,35 @@ lorads_status lorads_admm_solve(lorads_ctx* ctx, const lorads_options* opt, lora
     if (!(o.eps > 0) || o.max_admm_iter < 0 || o.lbfgs_mem < 1 || o.rho_every < 1)
       fail(LORADS_EINVAL, "invalid options");
     if (!o.init_U) fail(LORADS_EINVAL, "init_U is required (the random start is an input)");
-    if (o.r0 < 1 || o.r0 > 256) fail(LORADS_EINVAL, "r0 must be in [1, 256]");
+    for (size_t pi = 0; pi < ctx->probs.size(); ++pi) {
+      const int r0 = o.init_rank ? o.init_rank[pi] : o.r0;
+      if (r0 < 1 || r0 > 256 || r0 > ctx->probs[pi]->n)
+        fail(LORADS_EINVAL, "initial rank of problem " + std::to_string(pi) + " must be in [1, min(256, n)]");
+    }
     hipStream_t s = ctx->stream;
+    if (o.batch_mode != 2 && batch_eligible(ctx->probs)) {
+      // all problems in one persistent launch
+      const auto t0 = std::chrono::steady_clock::now();
+      batch_solve(ctx->probs, ctx->batch, o, res, s,
+                  o.batch_block > 0 ? o.batch_block : ctx->batch.block);
+      const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      for (size_t pi = 0; pi < ctx->probs.size(); ++pi) {
+        res[pi].t_total = t;
+        res[pi].t_phase2 = t;
+        if (res[pi].status > worst) worst = (lorads_status)res[pi].status;
+      }
+      return;
+    }
+    if (o.batch_mode == 1) fail(LORADS_EINVAL, "batched solve needs >= 2 problems, all with diagonal constraints");
     for (size_t pi = 0; pi < ctx->probs.size(); ++pi) {
       Problem& P = *ctx->probs[pi];
       if (!o.init_U[pi]) fail(LORADS_EINVAL, "init_U missing for problem " + std::to_string(pi));
-      if (o.r0 > P.n) fail(LORADS_EINVAL, "r0 > n");
+      const int r0 = o.init_rank ? o.init_rank[pi] : o.r0;
       lorads_result& R = res[pi];
       std::memset(&R, 0, sizeof(R));
       const auto t0 = std::chrono::steady_clock::now();
-      P.rank = o.r0;
-      P.U.upload(o.init_U[pi], (size_t)P.n * o.r0, s);
+      P.rank = r0;
+      P.U.upload(o.init_U[pi], (size_t)P.n * r0, s);
       P.lam.alloc(P.m);
       if (o.init_lambda && o.init_lambda[pi]) {
         DevBuf<double> tmp;
@@ -357,6 +380,35 @@ lorads_status lorads_admm_solve(lorads_ctx* ctx, const lorads_options* opt, lora
     }
   });
   return st != LORADS_OK ? st : worst;
+}
+
+lorads_status lorads_batch_autotune(lorads_ctx* ctx, const lorads_options* opt, const int32_t* cand,
+                                    int32_t ncand, int32_t* best, double* times_ms) {
+  return guarded(ctx, [&] {
+    if (!ctx || !opt || !cand || ncand < 1 || !best) fail(LORADS_EINVAL, "null argument");
+    if (!batch_eligible(ctx->probs)) fail(LORADS_EINVAL, "context is not eligible for the batched launch");
+    hipStream_t s = ctx->stream;
+    std::vector<lorads_result> res(ctx->probs.size());
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    double best_ms = INFINITY;
+    int best_b = 0;
+    for (int i = 0; i < ncand; ++i) {
+      HIPCHK(hipEventRecord(e0, s));
+      batch_solve(ctx->probs, ctx->batch, *opt, res.data(), s, cand[i]);
+      HIPCHK(hipEventRecord(e1, s));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (times_ms) times_ms[i] = ms;
+      if (ms < best_ms) { best_ms = ms; best_b = cand[i]; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->batch.block = best_b;
+    *best = best_b;
+  });
 }
 
 lorads_status lorads_get_solution(const lorads_ctx* cctx, int32_t prob, double* U, double* V,

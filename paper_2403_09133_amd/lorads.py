@@ -50,7 +50,8 @@ class Options_(C.Structure):
         ("alm_inner_floor", C.c_double), ("alm_eta", C.c_double), ("alm_rho_factor", C.c_double),
         ("alm_outer_max", C.c_int32), ("rho0", C.c_double), ("seed", C.c_uint64),
         ("phase1", C.c_int32), ("verbose", C.c_int32), ("profile", C.c_int32),
-        ("init_U", C.c_void_p), ("init_lambda", C.c_void_p),
+        ("batch_mode", C.c_int32), ("batch_block", C.c_int32),
+        ("init_U", C.c_void_p), ("init_lambda", C.c_void_p), ("init_rank", C.c_void_p),
     ]
 
 
@@ -71,7 +72,7 @@ EXPORTED = [
     "lorads_default_options", "lorads_setup", "lorads_problem_info", "lorads_apply_A",
     "lorads_apply_AT_V", "lorads_cg_solve", "lorads_admm_solve", "lorads_get_solution",
     "lorads_gram", "lorads_dual_lambda_min", "lorads_destroy", "lorads_last_error",
-    "lorads_version",
+    "lorads_version", "lorads_batch_autotune",
 ]
 
 
@@ -100,6 +101,8 @@ def load():
     lib.lorads_get_solution.argtypes = [vp, i32, vp, vp, vp]
     lib.lorads_gram.argtypes = [vp, vp, i64, i32, i32, i32, i32, vp, vp]
     lib.lorads_dual_lambda_min.argtypes = [vp, i32, vp, i32, C.POINTER(dbl)]
+    lib.lorads_batch_autotune.argtypes = [vp, C.POINTER(Options_), C.POINTER(i32), i32,
+                                          C.POINTER(i32), C.POINTER(dbl)]
     lib.lorads_destroy.argtypes = [vp]
     lib.lorads_destroy.restype = None
     lib.lorads_last_error.argtypes = [vp]
@@ -107,7 +110,7 @@ def load():
     lib.lorads_version.restype = C.c_char_p
     for name in ("lorads_setup", "lorads_problem_info", "lorads_apply_A", "lorads_apply_AT_V",
                  "lorads_cg_solve", "lorads_admm_solve", "lorads_get_solution", "lorads_gram",
-                 "lorads_dual_lambda_min"):
+                 "lorads_dual_lambda_min", "lorads_batch_autotune"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -253,6 +256,8 @@ class Context:
         keep = [np.ascontiguousarray(u, dtype=np.float64) for u in init_U]
         ptrs = (C.c_void_p * self.nprob)(*[_ptr(u) for u in keep])
         options.init_U = C.cast(ptrs, C.c_void_p)
+        ranks = (C.c_int32 * self.nprob)(*[int(u.shape[1]) for u in keep])
+        options.init_rank = C.cast(ranks, C.c_void_p)
         if init_lambda is not None:
             keepl = [None if l is None else np.ascontiguousarray(l, dtype=np.float64) for l in init_lambda]
             lptrs = (C.c_void_p * self.nprob)(*[_ptr(l) if l is not None else 0 for l in keepl])
@@ -263,6 +268,7 @@ class Context:
         st = lib.lorads_admm_solve(self.h, C.byref(options), res)
         options.init_U = None
         options.init_lambda = None
+        options.init_rank = None
         if st < 0:
             raise LoradsError(st, lib.lorads_last_error(self.h).decode())
         out = []
@@ -273,6 +279,26 @@ class Context:
                 d[f] = list(v) if f.startswith("prof_") else v
             out.append(d)
         return out
+
+    def batch_autotune(self, init_U: Sequence[np.ndarray], options: Options_,
+                       candidates: Sequence[int] = (64, 128, 256, 512, 1024)):
+        """Time the batched launch per workgroup size; the context keeps the
+        fastest.  Returns (best, {size: ms})."""
+        lib = load()
+        keep = [np.ascontiguousarray(u, dtype=np.float64) for u in init_U]
+        ptrs = (C.c_void_p * self.nprob)(*[_ptr(u) for u in keep])
+        options.init_U = C.cast(ptrs, C.c_void_p)
+        options.init_lambda = None
+        ranks = (C.c_int32 * self.nprob)(*[int(u.shape[1]) for u in keep])
+        options.init_rank = C.cast(ranks, C.c_void_p)
+        cand = (C.c_int32 * len(candidates))(*candidates)
+        times = (C.c_double * len(candidates))()
+        best = C.c_int32()
+        st = lib.lorads_batch_autotune(self.h, C.byref(options), cand, len(candidates), C.byref(best), times)
+        options.init_U = None
+        options.init_rank = None
+        self._check(st)
+        return best.value, {int(c): float(t) for c, t in zip(candidates, times)}
 
     def get_solution(self, prob: int = 0, rank: Optional[int] = None):
         info = self.problem_info(prob)

@@ -109,7 +109,7 @@ def er_gnp_edges(n: int, p: float, rng: np.random.Generator):
     uniform subset, which is the same law as independent coin flips.
     """
     total = n * (n - 1) // 2
-    if total <= 4_000_000:
+    if total <= 200_000:
         iu, ju = np.triu_indices(n, 1)
         flips = rng.random(total) < p
         return iu[flips].astype(np.int32), ju[flips].astype(np.int32)
