@@ -242,12 +242,82 @@ lorads_status lorads_dual_lambda_min(lorads_ctx *ctx, int32_t prob, const void *
 
 void lorads_destroy(lorads_ctx *ctx);
 
-/* Message for the last non-OK status of ctx (or of the last failed setup when
- * ctx is NULL).  Valid until the next call on the same context. */
+/* Message for the last non-OK status of ctx (or, when ctx is NULL, of the last
+ * failed setup or lorads_gnn_* call on this thread).  Valid until the next call on the same context. */
 const char *lorads_last_error(const lorads_ctx *ctx);
 
 /* Library version string. */
 const char *lorads_version(void);
+
+/* ------------------------------------------------------------------------
+ * Learned warm start for Phase I.  The paper names better warm starts as
+ * future work (Section 6); this network is an addition.  A message-passing
+ * network over a weighted graph (for MaxCut, the graph itself) predicts a
+ * dual multiplier per node, used as lambda0 = -yhat, and a graph-level rank
+ * factor.  FP32 throughout; hidden width 64.
+ *
+ *   x_j  = [deg_j, sum_k w_jk, sum_k |w_jk|, sum_k w_jk^2, ln n_g] / 10
+ *   A_jk = w_jk / (1 + sum_k |w_jk|)
+ *   H0 = relu(x W_in^T + b_in);  H_l = relu(H_{l-1} W_s^T + (A H_{l-1}) W_n^T + b_l)
+ *   yhat_j = <H_L[j], v_y> + c_y;   rhat_g = <mean_{j in g} H_L[j], v_r> + c_r
+ *   loss = mean_j (yhat_j - y_j)^2 + omega mean_g (rhat_g - r_g)^2
+ *
+ * Parameters form one flat FP32 vector: W_in (64 x 5), b_in (64), per layer
+ * W_s (64 x 64), W_n (64 x 64), b (64), then v_y (64), c_y, v_r (64), c_r;
+ * matrices row-major (out x in).  lorads_gnn_param_count gives its length.
+ * All buffers in these calls are host memory unless stated; every call blocks
+ * the host until its device work is done.
+ * ------------------------------------------------------------------------ */
+typedef struct lorads_gnn lorads_gnn;
+
+/* Number of parameters for `layers` message-passing layers (hidden 64). */
+int64_t lorads_gnn_param_count(int32_t layers);
+
+/* Create a network on the current HIP device with zero parameters and zero
+ * Adam state.  layers in [1, 8].  EINVAL otherwise. */
+lorads_status lorads_gnn_create(int32_t layers, lorads_gnn **out);
+
+/* Copy count (= lorads_gnn_param_count) parameters from / to host FP32.
+ * set_params also clears the Adam moments and step counter. */
+lorads_status lorads_gnn_set_params(lorads_gnn *g, const float *theta, int64_t count);
+lorads_status lorads_gnn_get_params(const lorads_gnn *g, float *theta, int64_t count);
+
+/* Replace the resident graph set.  Graph q owns nodes [node_off[q],
+ * node_off[q+1]) (node_off: n_graphs + 1 ascending entries, node_off[0] = 0).
+ * Edges are nnz directed COO triplets (row[e], col[e], w[e]) over global node
+ * ids; an undirected edge is listed in both directions, both ends in the same
+ * graph; no self loops; weights finite.  The library builds the adjacency rows,
+ * the features and the normalised weights on the device and keeps activations
+ * for every node resident.  EINVAL on any violation. */
+lorads_status lorads_gnn_load_graphs(lorads_gnn *g, int32_t n_graphs, const int64_t *node_off,
+                                     int64_t nnz, const int32_t *row, const int32_t *col,
+                                     const float *w);
+
+/* Training targets for the whole graph set: y (one per node) and r (one per
+ * graph), host FP32. */
+lorads_status lorads_gnn_set_targets(lorads_gnn *g, const float *y, const float *r);
+
+/* Forward pass over graphs [g0, g1): yhat for their nodes (node_off[g1] -
+ * node_off[g0] entries) and rhat (g1 - g0 entries); either may be NULL. */
+lorads_status lorads_gnn_forward(lorads_gnn *g, int32_t g0, int32_t g1, float *yhat, float *rhat);
+
+/* Forward and backward pass over graphs [g0, g1) against the targets: *loss
+ * (may be NULL) and the gradient, which stays on the device for
+ * lorads_gnn_adam_step and is also copied to grad (count entries, may be
+ * NULL).  ESTATE before set_targets. */
+lorads_status lorads_gnn_loss_grad(lorads_gnn *g, int32_t g0, int32_t g1, float omega,
+                                   double *loss, float *grad, int64_t count);
+
+/* One Adam update (bias-corrected moments) with the last gradient.  ESTATE
+ * before a loss_grad call. */
+lorads_status lorads_gnn_adam_step(lorads_gnn *g, float lr, float beta1, float beta2, float eps);
+
+/* Summed HIP-event time (ms) and launch count of the dense layer kernels
+ * (message aggregation + the MFMA products) since the last call; the counters
+ * are reset by the call.  Either pointer may be NULL. */
+lorads_status lorads_gnn_layer_time(lorads_gnn *g, double *ms, int64_t *launches, double *flops);
+
+void lorads_gnn_destroy(lorads_gnn *g);
 
 #ifdef __cplusplus
 }

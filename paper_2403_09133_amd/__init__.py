@@ -4,4 +4,4 @@ The compute lives in the HIP library `liblorads.so` (sources in `csrc/`, C ABI i
 `include/lorads.h`); `lorads` is its ctypes binding.
 """
 from . import lorads  # noqa: F401
-from .lorads import Context, default_options, gram, load  # noqa: F401
+from .lorads import Context, Gnn, default_options, gram, load  # noqa: F401

@@ -58,6 +58,8 @@ void check_dtype(int dtype) {
 
 using namespace lorads;
 
+void lorads::set_global_error(const std::string& msg) { g_setup_err = msg; }
+
 extern "C" {
 
 const char* lorads_version(void) { return "lorads-gfx950 0.1"; }

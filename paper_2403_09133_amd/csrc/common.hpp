@@ -24,6 +24,9 @@ struct Error {
 
 [[noreturn]] void fail(lorads_status s, const std::string& msg);
 
+// message returned by lorads_last_error(NULL) (calls without a context)
+void set_global_error(const std::string& msg);
+
 #define HIPCHK(expr)                                                              \
   do {                                                                            \
     hipError_t e_ = (expr);                                                       \

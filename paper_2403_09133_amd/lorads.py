@@ -73,6 +73,10 @@ EXPORTED = [
     "lorads_apply_AT_V", "lorads_cg_solve", "lorads_admm_solve", "lorads_get_solution",
     "lorads_gram", "lorads_dual_lambda_min", "lorads_destroy", "lorads_last_error",
     "lorads_version", "lorads_batch_autotune",
+    "lorads_gnn_param_count", "lorads_gnn_create", "lorads_gnn_set_params",
+    "lorads_gnn_get_params", "lorads_gnn_load_graphs", "lorads_gnn_set_targets",
+    "lorads_gnn_forward", "lorads_gnn_loss_grad", "lorads_gnn_adam_step",
+    "lorads_gnn_layer_time", "lorads_gnn_destroy",
 ]
 
 
@@ -108,9 +112,26 @@ def load():
     lib.lorads_last_error.argtypes = [vp]
     lib.lorads_last_error.restype = C.c_char_p
     lib.lorads_version.restype = C.c_char_p
+    flt = C.c_float
+    lib.lorads_gnn_param_count.argtypes = [i32]
+    lib.lorads_gnn_param_count.restype = i64
+    lib.lorads_gnn_create.argtypes = [i32, C.POINTER(vp)]
+    lib.lorads_gnn_set_params.argtypes = [vp, vp, i64]
+    lib.lorads_gnn_get_params.argtypes = [vp, vp, i64]
+    lib.lorads_gnn_load_graphs.argtypes = [vp, i32, vp, i64, vp, vp, vp]
+    lib.lorads_gnn_set_targets.argtypes = [vp, vp, vp]
+    lib.lorads_gnn_forward.argtypes = [vp, i32, i32, vp, vp]
+    lib.lorads_gnn_loss_grad.argtypes = [vp, i32, i32, flt, C.POINTER(dbl), vp, i64]
+    lib.lorads_gnn_adam_step.argtypes = [vp, flt, flt, flt, flt]
+    lib.lorads_gnn_layer_time.argtypes = [vp, C.POINTER(dbl), C.POINTER(i64), C.POINTER(dbl)]
+    lib.lorads_gnn_destroy.argtypes = [vp]
+    lib.lorads_gnn_destroy.restype = None
     for name in ("lorads_setup", "lorads_problem_info", "lorads_apply_A", "lorads_apply_AT_V",
                  "lorads_cg_solve", "lorads_admm_solve", "lorads_get_solution", "lorads_gram",
-                 "lorads_dual_lambda_min", "lorads_batch_autotune"):
+                 "lorads_dual_lambda_min", "lorads_batch_autotune", "lorads_gnn_create",
+                 "lorads_gnn_set_params", "lorads_gnn_get_params", "lorads_gnn_load_graphs",
+                 "lorads_gnn_set_targets", "lorads_gnn_forward", "lorads_gnn_loss_grad",
+                 "lorads_gnn_adam_step", "lorads_gnn_layer_time"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -327,3 +348,79 @@ def gram(A, B, G, stream=None):
 
 def version() -> str:
     return load().lorads_version().decode()
+
+
+def _gcheck(st: int):
+    if st != LORADS_OK:
+        raise LoradsError(st, load().lorads_last_error(None).decode())
+
+
+class Gnn:
+    """Owns a lorads_gnn: the warm-start network, its parameters, Adam state and
+    a resident graph set (host numpy arrays in, host numpy arrays out)."""
+
+    def __init__(self, layers: int = 3):
+        lib = load()
+        h = C.c_void_p()
+        _gcheck(lib.lorads_gnn_create(int(layers), C.byref(h)))
+        self._h = h
+        self.layers = int(layers)
+        self.n_params = int(lib.lorads_gnn_param_count(int(layers)))
+        self.node_off = None
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().lorads_gnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, theta):
+        t = np.ascontiguousarray(theta, dtype=np.float32)
+        _gcheck(load().lorads_gnn_set_params(self._h, _ptr(t), t.size))
+
+    def get_params(self) -> np.ndarray:
+        t = np.empty(self.n_params, dtype=np.float32)
+        _gcheck(load().lorads_gnn_get_params(self._h, _ptr(t), t.size))
+        return t
+
+    def load_graphs(self, node_off, row, col, w):
+        no = np.ascontiguousarray(node_off, dtype=np.int64)
+        r = np.ascontiguousarray(row, dtype=np.int32)
+        c = np.ascontiguousarray(col, dtype=np.int32)
+        ww = np.ascontiguousarray(w, dtype=np.float32)
+        _gcheck(load().lorads_gnn_load_graphs(self._h, len(no) - 1, _ptr(no), r.size, _ptr(r),
+                                              _ptr(c), _ptr(ww)))
+        self.node_off = no
+
+    def set_targets(self, y, r):
+        yy = np.ascontiguousarray(y, dtype=np.float32)
+        rr = np.ascontiguousarray(r, dtype=np.float32)
+        if yy.size != self.node_off[-1] or rr.size != len(self.node_off) - 1:
+            raise ValueError("target sizes do not match the graph set")
+        _gcheck(load().lorads_gnn_set_targets(self._h, _ptr(yy), _ptr(rr)))
+
+    def forward(self, g0: int, g1: int):
+        yh = np.empty(int(self.node_off[g1] - self.node_off[g0]), dtype=np.float32)
+        rh = np.empty(g1 - g0, dtype=np.float32)
+        _gcheck(load().lorads_gnn_forward(self._h, g0, g1, _ptr(yh), _ptr(rh)))
+        return yh, rh
+
+    def loss_grad(self, g0: int, g1: int, omega: float, want_grad: bool = True):
+        loss = C.c_double()
+        grad = np.empty(self.n_params, dtype=np.float32) if want_grad else None
+        _gcheck(load().lorads_gnn_loss_grad(self._h, g0, g1, float(omega), C.byref(loss),
+                                            _ptr(grad), self.n_params if want_grad else 0))
+        return loss.value, grad
+
+    def adam_step(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        _gcheck(load().lorads_gnn_adam_step(self._h, lr, beta1, beta2, eps))
+
+    def layer_time(self):
+        ms, n, fl = C.c_double(), C.c_int64(), C.c_double()
+        _gcheck(load().lorads_gnn_layer_time(self._h, C.byref(ms), C.byref(n), C.byref(fl)))
+        return ms.value, n.value, fl.value
