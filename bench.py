@@ -45,17 +45,13 @@ WORKLOADS = {
 
 
 def initial_rank(p) -> int:
-    if p.kind == "mc":
-        # Section 5.1: 2 log m, and log m for completion instances of order >= 10000
-        return int(round(math.log(p.m))) if p.n >= 10000 else int(round(2 * math.log(p.m)))
-    return int(math.ceil(math.log2(p.n)))
+    from paper_2403_09133_amd.params import initial_rank as rule
+    return rule(p.kind, p.n, p.m)
 
 
 def lib_options(p, r0, precision, **kw):
-    from paper_2403_09133_amd import default_options
-    from oracle.options import paper_defaults  # parameter table only (switch tol, h)
-    pd = paper_defaults(p.kind, p.n)
-    return default_options(r0=r0, switch_tol=pd["switch_tol"], h=pd["h"], precision=precision, **kw)
+    from paper_2403_09133_amd.params import solver_options
+    return solver_options(p.kind, p.n, r0, precision, **kw)
 
 
 def cpu_baseline(p, r: int, budget_s: float = 20.0):
@@ -101,8 +97,8 @@ def batch_leg(count: int = 512, sample: int = 16):
     probs = sdpgen.batch_maxcut(count, 2000, 50, 2000, 3.0, 20.0, "pm1")
     U0 = [sdpgen.random_init_U(p.n, int(math.ceil(math.log2(p.n))), 2000 + i) for i, p in enumerate(probs)]
     t_gen = time.time() - t
-    from oracle.options import paper_defaults
-    pd = paper_defaults("maxcut", 1000)
+    from paper_2403_09133_amd.params import family_params
+    pd = family_params("maxcut", 1000)
 
     def opts(**kw):
         return default_options(r0=1, switch_tol=pd["switch_tol"], h=pd["h"], **kw)
@@ -221,9 +217,9 @@ def main():
         kernels=kernels, setup_s=round(t_setup, 3),
     )
     if p.kind == "mc":
-        import oracle  # recovery error of the returned factors (host check)
+        from paper_2403_09133_amd.report import completion_recovery_error
         U, V, lam = ctx.get_solution(0, last["rank"])
-        extra["mc_recovery_error"] = oracle.metrics.mc_recovery_error(p, 0.5 * (U + V))
+        extra["mc_recovery_error"] = completion_recovery_error(0.5 * (U + V), p.meta["L"], p.meta["R"])
     if not args.no_fp64:
         t = time.perf_counter()
         r64 = ctx.admm_solve([U0], lib_options(p, r0, 0))[0]

@@ -137,6 +137,11 @@ typedef struct {
   const double *const *init_lambda;
   const int32_t *init_rank;  /* per-problem initial rank (nprob entries, NULL:
                                 r0 for every problem); init_U[p] is n x init_rank[p] */
+  int32_t warm_check;      /* 1: a problem started from a given init_lambda falls
+                              back to the cold start (lambda = 0, the given U) when
+                              the first Phase-I outer iteration does not lower the
+                              primal infeasibility; such problems are solved one
+                              after the other (batch_mode 1: EINVAL).  Default 0 */
 } lorads_options;
 
 typedef struct {
@@ -164,6 +169,7 @@ typedef struct {
   double prof_ms[3];
   double prof_bytes[3];
   int64_t prof_launches[3];
+  int32_t warm_fallback;   /* 1 when options.warm_check restarted Phase I cold */
 } lorads_result;
 
 /* Fill *opt with the defaults above (precision F64, eps 1e-6, switch 1e-3,

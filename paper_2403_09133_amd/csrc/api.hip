@@ -107,6 +107,7 @@ void lorads_default_options(lorads_options* o) {
   o->init_U = nullptr;
   o->init_lambda = nullptr;
   o->init_rank = nullptr;
+  o->warm_check = 0;
 }
 
 lorads_status lorads_setup(const lorads_problem* probs, int32_t nprob, lorads_ctx** out) {
@@ -294,7 +295,12 @@ lorads_status lorads_admm_solve(lorads_ctx* ctx, const lorads_options* opt, lora
         fail(LORADS_EINVAL, "initial rank of problem " + std::to_string(pi) + " must be in [1, min(256, n)]");
     }
     hipStream_t s = ctx->stream;
-    if (o.batch_mode != 2 && batch_eligible(ctx->probs)) {
+    bool warm_checked = false;
+    if (o.warm_check && o.init_lambda)
+      for (size_t pi = 0; pi < ctx->probs.size(); ++pi) warm_checked |= o.init_lambda[pi] != nullptr;
+    if (o.batch_mode == 1 && warm_checked)
+      fail(LORADS_EINVAL, "warm_check with a given init_lambda needs the sequential path");
+    if (o.batch_mode != 2 && !warm_checked && batch_eligible(ctx->probs)) {
       // all problems in one persistent launch
       const auto t0 = std::chrono::steady_clock::now();
       batch_solve(ctx->probs, ctx->batch, o, res, s,
@@ -330,6 +336,7 @@ lorads_status lorads_admm_solve(lorads_ctx* ctx, const lorads_options* opt, lora
         P.lam.zero(s);
       }
       SolveInfo info;
+      info.warm = o.warm_check && o.init_lambda && o.init_lambda[pi];
       P.prof.reset();
       P.prof.on = o.profile != 0;
       double rho;
@@ -360,6 +367,7 @@ lorads_status lorads_admm_solve(lorads_ctx* ctx, const lorads_options* opt, lora
       R.alm_outer = info.alm_outer;
       R.alm_inner = info.alm_inner;
       R.rank_growths = info.growths;
+      R.warm_fallback = info.warm_fallback;
       R.admm_iters = info.admm_iters;
       R.cg_iters = info.cg_iters;
       R.kkt = info.kkt;

@@ -139,6 +139,15 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
   double v_ref = INFINITY;
   int outer = 0, inner_total = 0, growths = 0;
   double h[16];
+  // a caller multiplier is kept only if the first outer iteration lowers the
+  // infeasibility; otherwise Phase I restarts cold from the same U
+  const double v_start = v, rho_start = rho;
+  bool warm_pending = info.warm;
+  DevBuf<double> U_start;
+  if (warm_pending) {
+    U_start.alloc((size_t)n * r);
+    HIPCHK(hipMemcpyAsync(U_start.p, U, (size_t)n * r * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
   while (v > o.switch_tol && outer < o.alm_outer_max) {
     const int cap = (r < r_cap) ? o.rank_grow_iters : o.alm_inner_max;
     const double tol = std::max(o.alm_inner_rel * v, o.alm_inner_floor);
@@ -241,6 +250,19 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
     if (o.verbose > 1)
       fprintf(stderr, "[lorads] ALM outer %d: r=%d rho=%.3g inner=%d conv=%d v=%.3e\n", outer, r,
               rho, it, (int)conv, v);
+    if (warm_pending) {
+      warm_pending = false;
+      if (!(v < v_start)) {
+        HIPCHK(hipMemcpyAsync(U, U_start.p, (size_t)n * r * sizeof(double), hipMemcpyDeviceToDevice, s));
+        P.lam.zero(s);
+        rho = rho_start;
+        info.warm_fallback = 1;
+        op_forward<double>(P, U, U, r, r, P.zbuf.p, 1.0, s);
+        info.op_bytes += bytes_forward(P, r, 8);
+        v = host_norm_zb(P, s) / (1.0 + P.b_inf);
+        continue;
+      }
+    }
     if (!conv && r < r_cap && it >= cap) {
       const int r_new = std::min((int)std::ceil(o.rank_factor * r), r_cap);
       dot_to_slot<double, double>(P, N, U, U, 1.0, S_GEN, s);

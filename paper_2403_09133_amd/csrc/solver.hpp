@@ -15,6 +15,8 @@ struct SolveInfo {
   double rho_alm = 0, pinf_alm = 0;
   double kkt = 0, pinf_stop = 0, dres_stop = 0, rho = 0, gamma = 0;
   double op_bytes = 0;
+  bool warm = false;       // started from a caller multiplier with warm_check on
+  int warm_fallback = 0;
 };
 
 double quartic_step(double q1, double q2, double q3, double q4);

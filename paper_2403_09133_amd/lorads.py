@@ -52,6 +52,7 @@ class Options_(C.Structure):
         ("phase1", C.c_int32), ("verbose", C.c_int32), ("profile", C.c_int32),
         ("batch_mode", C.c_int32), ("batch_block", C.c_int32),
         ("init_U", C.c_void_p), ("init_lambda", C.c_void_p), ("init_rank", C.c_void_p),
+        ("warm_check", C.c_int32),
     ]
 
 
@@ -65,6 +66,7 @@ class Result_(C.Structure):
         ("gamma", C.c_double), ("t_phase1", C.c_double), ("t_phase2", C.c_double),
         ("t_metrics", C.c_double), ("t_total", C.c_double), ("op_bytes", C.c_double),
         ("prof_ms", C.c_double * 3), ("prof_bytes", C.c_double * 3), ("prof_launches", C.c_int64 * 3),
+        ("warm_fallback", C.c_int32),
     ]
 
 

@@ -1,0 +1,34 @@
+"""Per-family parameters of Section 5.1 used by callers of the library.
+
+The switching tolerance of Phase I and the factor h applied to rho at the switch
+depend on the problem family: MaxCut 1e-2 and h = 10; matrix completion 1e-3 and
+h = 5 below order 10000, 2.5 from there on; other problems 1e-3 and h = 1.  The
+initial rank is ceil(log2 n) for MaxCut (the rule of the MaxCut experiments),
+round(ln m) for completion instances of order >= 10000 and round(2 ln m) otherwise.
+"""
+from __future__ import annotations
+
+import math
+
+
+def family_params(kind: str, n: int) -> dict:
+    if kind == "maxcut":
+        return dict(switch_tol=1e-2, h=10.0)
+    if kind == "mc":
+        return dict(switch_tol=1e-3, h=5.0 if n < 10000 else 2.5)
+    return dict(switch_tol=1e-3, h=1.0)
+
+
+def initial_rank(kind: str, n: int, m: int) -> int:
+    if kind == "maxcut":
+        return int(math.ceil(math.log2(n)))
+    if kind == "mc" and n >= 10000:
+        return int(round(math.log(m)))
+    return int(round(2.0 * math.log(m)))
+
+
+def solver_options(kind: str, n: int, r0: int, precision: int = 0, **kw):
+    """lorads_options with the family's switch tolerance and h."""
+    from .lorads import default_options
+    fp = family_params(kind, n)
+    return default_options(r0=r0, switch_tol=fp["switch_tol"], h=fp["h"], precision=precision, **kw)
