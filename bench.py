@@ -136,6 +136,37 @@ def batch_leg(count: int = 512, sample: int = 16):
     return out
 
 
+def ops_profile(key: str, reps: int):
+    """Operator calls only: REPS x (forward map, adjoint product, 20-iteration CG
+    solve) in FP32 at r0 columns, then one 256 MiB device-to-device copy whose
+    known size calibrates the HBM byte counters."""
+    import torch
+    import sdpgen
+    from paper_2403_09133_amd import Context
+    dev = torch.device("cuda")
+    p = sdpgen.config_instance(key)
+    r = initial_rank(p)
+    ctx = Context(p)
+    g = torch.Generator().manual_seed(7)
+    U = torch.randn(p.n, r, generator=g).to(dev)
+    V = torch.randn(p.n, r, generator=g).to(dev) / math.sqrt(r)
+    z = torch.empty(p.m, device=dev)
+    out = torch.empty_like(V)
+    X = torch.empty_like(V)
+    for i in range(reps):
+        ctx.apply_A(U, V, z)
+        ctx.apply_AT_V(z, V, out)
+        ctx.cg_solve(V, out, X.zero_(), 2.0, 1.5, 0.0, 20)
+        torch.cuda.synchronize()
+        print(f"[bench] ops rep {i} done", file=sys.stderr, flush=True)
+    a = torch.empty(64 << 20, dtype=torch.float32, device=dev)
+    b = torch.ones_like(a)
+    a.copy_(b)
+    torch.cuda.synchronize()
+    print(f"[bench] copy of {a.numel() * 4} bytes done", file=sys.stderr, flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +176,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solve")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form leg")
+    ap.add_argument("--ops-profile", type=int, default=0, metavar="REPS",
+                    help="only run REPS applications of each operator at the workload's size (FP32, "
+                         "r0 columns) and a 256 MiB device copy, for hardware-counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the method's batch and single-instance paths are "
@@ -160,6 +194,9 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     key, prec, desc = WORKLOADS[args.workload]
+    if args.ops_profile:
+        ops_profile(key, args.ops_profile)
+        return
     t = time.time()
     p = sdpgen.config_instance(key)
     t_gen = time.time() - t

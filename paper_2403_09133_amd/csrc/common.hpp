@@ -99,4 +99,8 @@ inline int pow2_group(int r) {
   return g;
 }
 
+// lanes per factor row of the row kernels: each lane holds up to 4 columns
+// (c = lane + t G, t < 4), so a wave covers 64 / G rows at once
+inline int lane_group(int r) { return pow2_group((r + 3) / 4); }
+
 }  // namespace lorads

@@ -172,165 +172,127 @@ __global__ void __launch_bounds__(kBlock) k3_diag(int n, const T* __restrict__ d
 }
 
 // ===========================================================================
-// K2 PAIR, row-owner over both views (no atomics).  Row t's incident
-// constraints are its view-R entries (t is the smaller index, partner pk) and
-// its view-C entries (t is the larger index, partner cvj, id cvid).
-//   MODE 0: out_t = out_scale (c_scale (C V)_t + sum_i w_i a_i V_partner)
-//   MODE 1: fused CG operator.  For each incident constraint with partner p:
-//           d_i = <Pm_t, V_p> + <Pm_p, V_t>  (= <A_i, Pm V^T>), and
-//           Q_t = gamma Pm_t + rho sum_i a_i^2 d_i V_p;  accumulates <Pm, Q>.
-//           (V = the fixed factor W, Pm = the CG direction.)
-//   MODE 2: CG operator from precomputed w = rho A(Pm V^T):
-//           Q_t = gamma Pm_t + sum_i w_i a_i V_p;  accumulates <Pm, Q>.
-//           (each constraint's inner product is formed once, by the forward
-//           kernel, instead of once per view)
-// kUnroll incident constraints are gathered per step.
+// PAIR, one wave per row over the row's incident list: every constraint
+// a (e_j e_k^T + e_k e_j^T) appears in the list of row j (partner k) and of
+// row k (partner j), partners ascending.  The wave's 64/G lane groups take
+// interleaved entries (so the index loads of a step are contiguous) and
+// kUnroll entries per step; each lane holds kMaxCols columns (c = lane + t G).
+// The group partials are summed by a fixed xor butterfly across the wave.
+//   MODE 0 (adjoint):  out_t = out_scale (c_scale (C V)_t + sum_e a_e w_{id(e)} V_p);
+//                      w == nullptr drops the sum (the solver's C D and C U products)
+//   MODE 1 (CG operator, V = the fixed factor, Pm = the direction):
+//     Q_t = gamma Pm_t + rho sum_e a_e^2 (<Pm_t, V_p> + <Pm_p, V_t>) V_p,
+//     i.e. (gamma I + rho A* A(. V^T) V) applied to Pm; block partials of <Pm, Q>.
+//     Each constraint's inner product is formed by both of its rows, so no
+//     per-constraint buffer is written or gathered.
 // ===========================================================================
 template <typename T, int G, int MODE>
-__device__ __forceinline__ void pair_batch(int cnt, const int* id, const int* p,
-                                           const T* __restrict__ pcoef, double pair_coef,
-                                           const T* __restrict__ w, const T* __restrict__ V,
-                                           const T* __restrict__ Pm, int r, int ld, int lane,
-                                           const double* pt, const double* vt, double* acc) {
-  double vp[kUnroll][kMaxCols];
-  double coef[kUnroll];
-#pragma unroll
-  for (int u = 0; u < kUnroll; ++u) {
-#pragma unroll
-    for (int t = 0; t < kMaxCols; ++t) {
-      const int c = lane + t * G;
-      vp[u][t] = (c < r) ? (double)V[(size_t)p[u] * ld + c] : 0.0;
-    }
-  }
-  if (MODE == 1) {
-    double d[kUnroll];
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      double s = 0.0;
-#pragma unroll
-      for (int t = 0; t < kMaxCols; ++t) {
-        const int c = lane + t * G;
-        if (c < r) s += pt[t] * vp[u][t] + (double)Pm[(size_t)p[u] * ld + c] * vt[t];
-      }
-      d[u] = s;
-    }
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) d[u] = group_sum<G>(d[u]);
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const double a = pcoef ? (double)pcoef[id[u]] : pair_coef;
-      coef[u] = u < cnt ? a * a * d[u] : 0.0;
-    }
-  } else {
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const double a = pcoef ? (double)pcoef[id[u]] : pair_coef;
-      coef[u] = u < cnt ? (double)w[id[u]] * a : 0.0;
-    }
-  }
-#pragma unroll
-  for (int u = 0; u < kUnroll; ++u)
-#pragma unroll
-    for (int t = 0; t < kMaxCols; ++t) acc[t] += coef[u] * vp[u][t];
-}
-
-template <typename T, int G, int MODE>
-__global__ void __launch_bounds__(kBlock) k2_pair(
+__global__ void __launch_bounds__(kBlock) kpair_rows(
     int n, const int* __restrict__ cptr, const int* __restrict__ ccol,
-    const T* __restrict__ cval, double c_scale, const int* __restrict__ rptr,
-    const int* __restrict__ pk, const int* __restrict__ cvptr, const int* __restrict__ cvj,
-    const int* __restrict__ cvid, const T* __restrict__ pcoef, double pair_coef,
-    const T* __restrict__ w, const T* __restrict__ V, const T* __restrict__ Pm, int r, int ld,
-    T* __restrict__ out, int ldo, double out_scale, double* __restrict__ sc, int parity,
-    double* __restrict__ part) {
-  // one block per output row; its kBlock/G groups split the row's incident
-  // constraints (kUnroll at a time) and their partial rows are summed in LDS
-  // in group order
-  constexpr bool kCg = (MODE == 1 || MODE == 2);
-  constexpr int kBatch = (MODE == 1) ? 1 : 0;  // MODE 2 gathers like MODE 0
-  constexpr int NGR = kBlock / G;
+    const T* __restrict__ cval, double c_scale, const int* __restrict__ inc_ptr,
+    const int* __restrict__ inc_nb, const int* __restrict__ inc_id, const T* __restrict__ pcoef,
+    double pair_coef, const T* __restrict__ w, const T* __restrict__ V, const T* __restrict__ Pm,
+    int r, int ld, T* __restrict__ out, int ldo, double out_scale, double* __restrict__ sc,
+    int parity, double* __restrict__ part) {
+  constexpr int NG = 64 / G;
   __shared__ double sh[kBlock / 64];
-  __shared__ double red[kBlock * kMaxCols];
-  if (kCg && sc[S_DONE + parity] != 0.0) return;
-  const int row = blockIdx.x;
-  const int grp = threadIdx.x / G;
-  const int lane = threadIdx.x & (G - 1);
-  double acc[kMaxCols], pt[kMaxCols], vt[kMaxCols];
-#pragma unroll
-  for (int t = 0; t < kMaxCols; ++t) acc[t] = pt[t] = vt[t] = 0.0;
-  if (kCg) {
+  if (MODE == 1 && sc[S_DONE + parity] != 0.0) return;
+  const int wl = threadIdx.x & 63;
+  const int grp = wl / G, lane = wl & (G - 1);
+  const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  double pq = 0.0;
+  if (row < n) {  // wave-uniform
+    double acc[kMaxCols], pt[kMaxCols], vt[kMaxCols];
 #pragma unroll
     for (int t = 0; t < kMaxCols; ++t) {
       const int c = lane + t * G;
-      if (c < r) {
-        pt[t] = (double)Pm[(size_t)row * ld + c];
-        if (MODE == 1) vt[t] = (double)V[(size_t)row * ld + c];
-      }
+      acc[t] = 0.0;
+      pt[t] = (MODE == 1 && c < r) ? (double)Pm[(size_t)row * ld + c] : 0.0;
+      vt[t] = (MODE == 1 && c < r) ? (double)V[(size_t)row * ld + c] : 0.0;
     }
-  }
-  if (MODE == 0 && c_scale != 0.0) {
-    for (int e = cptr[row] + grp; e < cptr[row + 1]; e += NGR) {
-      const int k = ccol[e];
-      const double a = c_scale * (double)cval[e];
+    if (MODE == 0 && c_scale != 0.0) {
+      for (int e = cptr[row] + grp; e < cptr[row + 1]; e += NG) {
+        const int k = ccol[e];
+        const double a = c_scale * (double)cval[e];
 #pragma unroll
-      for (int t = 0; t < kMaxCols; ++t) {
-        const int c = lane + t * G;
-        if (c < r) acc[t] += a * (double)V[(size_t)k * ld + c];
+        for (int t = 0; t < kMaxCols; ++t) {
+          const int c = lane + t * G;
+          if (c < r) acc[t] += a * (double)V[(size_t)k * ld + c];
+        }
       }
     }
-  }
-  if (MODE != 0 || w != nullptr) {
-    const int r0 = rptr[row], nR = rptr[row + 1] - r0;
-    const int c0 = cvptr[row], total = nR + (cvptr[row + 1] - c0);
-    for (int q = grp * kUnroll; q < total; q += NGR * kUnroll) {
-      const int cnt = min(kUnroll, total - q);
-      int id[kUnroll], p[kUnroll];
+    // MODE 0 with w == nullptr is the C part alone (c_scale C V)
+    const int e0 = inc_ptr[row];
+    const int e1 = (MODE == 0 && w == nullptr) ? e0 : inc_ptr[row + 1];
+    for (int e = e0 + grp; e < e1; e += NG * kUnroll) {
+      int p[kUnroll];
+      double coef[kUnroll];
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
-        const int qq = u < cnt ? q + u : q;  // padding repeats a valid entry
-        if (qq < nR) {
-          id[u] = r0 + qq;
-          p[u] = pk[id[u]];
-        } else {
-          const int e = c0 + (qq - nR);
-          id[u] = cvid[e];
-          p[u] = cvj[e];
+        const int eu = e + u * NG;
+        const bool ok = eu < e1;
+        const int ee = ok ? eu : e;
+        p[u] = inc_nb[ee];
+        double a = pcoef ? (double)pcoef[inc_id[ee]] : pair_coef;
+        if (MODE == 0) a *= (double)w[inc_id[ee]];
+        else a *= a;
+        coef[u] = ok ? a : 0.0;
+      }
+      if (MODE == 0) {
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+          for (int t = 0; t < kMaxCols; ++t) {
+            const int c = lane + t * G;
+            if (c < r) acc[t] += coef[u] * (double)V[(size_t)p[u] * ld + c];
+          }
+      } else {
+        double vp[kUnroll][kMaxCols], d[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          double s = 0.0;
+#pragma unroll
+          for (int t = 0; t < kMaxCols; ++t) {
+            const int c = lane + t * G;
+            vp[u][t] = c < r ? (double)V[(size_t)p[u] * ld + c] : 0.0;
+            const double pp = c < r ? (double)Pm[(size_t)p[u] * ld + c] : 0.0;
+            s += pt[t] * vp[u][t] + pp * vt[t];
+          }
+          d[u] = s;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) d[u] = group_sum<G>(d[u]) * coef[u];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+          for (int t = 0; t < kMaxCols; ++t) acc[t] += d[u] * vp[u][t];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < kMaxCols; ++t)
+      for (int o = G; o < 64; o <<= 1) acc[t] += __shfl_xor(acc[t], o, 64);
+    if (grp == 0) {
+      if (MODE == 1) {
+        const double gamma = sc[S_GAMMA], rho = sc[S_RHO];
+#pragma unroll
+        for (int t = 0; t < kMaxCols; ++t) {
+          const int c = lane + t * G;
+          if (c < r) {
+            const T qv = (T)(gamma * pt[t] + rho * acc[t]);
+            out[(size_t)row * ldo + c] = qv;
+            pq += pt[t] * (double)qv;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < kMaxCols; ++t) {
+          const int c = lane + t * G;
+          if (c < r) out[(size_t)row * ldo + c] = (T)(out_scale * acc[t]);
         }
       }
-      pair_batch<T, G, kBatch>(cnt, id, p, pcoef, pair_coef, w, V, Pm, r, ld, lane, pt, vt, acc);
     }
   }
-#pragma unroll
-  for (int t = 0; t < kMaxCols; ++t) red[grp * (kMaxCols * G) + t * G + lane] = acc[t];
-  __syncthreads();
-  double pq = 0.0;
-  if (grp == 0) {
-#pragma unroll
-    for (int t = 0; t < kMaxCols; ++t) {
-      double s = 0.0;
-      for (int g = 0; g < NGR; ++g) s += red[g * (kMaxCols * G) + t * G + lane];
-      acc[t] = s;
-    }
-    if (kCg) {
-      const double gamma = sc[S_GAMMA], rho = (MODE == 1) ? sc[S_RHO] : 1.0;
-#pragma unroll
-      for (int t = 0; t < kMaxCols; ++t) {
-        const int c = lane + t * G;
-        if (c < r) {
-          const T qv = (T)(gamma * pt[t] + rho * acc[t]);
-          out[(size_t)row * ldo + c] = qv;
-          pq += pt[t] * (double)qv;
-        }
-      }
-    } else {
-#pragma unroll
-      for (int t = 0; t < kMaxCols; ++t) {
-        const int c = lane + t * G;
-        if (c < r) out[(size_t)row * ldo + c] = (T)(out_scale * acc[t]);
-      }
-    }
-  }
-  if (kCg) publish_partial(block_sum(pq, sh), part);
+  if (MODE == 1) publish_partial(block_sum(pq, sh), part);
 }
 
 }  // namespace lorads

@@ -35,6 +35,9 @@ template <typename T> static const T* pc(const Problem& P);
 template <> const double* pc<double>(const Problem& P) { return P.pcoef.p; }
 template <> const float* pc<float>(const Problem& P) { return P.pcoeff.p; }
 
+// one wave (64 lanes) per row, 4 rows per block
+static int waves_grid(int rows) { return std::max(1, (rows + kBlock / 64 - 1) / (kBlock / 64)); }
+
 static int rows_grid(int rows, int G) {
   const long long threads = (long long)rows * G;
   return (int)std::max<long long>(1, (threads + kBlock - 1) / kBlock);
@@ -44,7 +47,7 @@ static int rows_grid(int rows, int G) {
 template <typename T>
 static void op_forward_impl(Problem& P, const T* U, const T* V, int r, int ld, T* z, double scale,
                             hipStream_t s) {
-  const int G = pow2_group(r);
+  const int G = lane_group(r);
   if (P.structure == LORADS_STRUCT_DIAG) {
     LORADS_DISPATCH_G(G, (k1_diag<T, G, 0><<<rows_grid(P.m, G), kBlock, 0, s>>>(
                              P.m, P.drow.p, dc<T>(P), U, V, r, ld, z, scale, nullptr, nullptr,
@@ -81,7 +84,7 @@ void op_forward_w(Problem& P, const double* U, const double* V, int r, int ld, d
 
 static void op_forward_w_impl(Problem& P, const double* U, const double* V, int r, int ld,
                               double* z, double* w, const double* lam, double rho, hipStream_t s) {
-  const int G = pow2_group(r);
+  const int G = lane_group(r);
   if (P.structure == LORADS_STRUCT_DIAG) {
     LORADS_DISPATCH_G(G, (k1_diag<double, G, 1><<<rows_grid(P.m, G), kBlock, 0, s>>>(
                              P.m, P.drow.p, P.dcoef.p, U, V, r, ld, z, 1.0, lam, P.b.p, rho, w,
@@ -113,7 +116,7 @@ void op_adjoint(Problem& P, const T* w, double c_scale, const T* V, int r, int l
 template <typename T>
 static void op_adjoint_impl(Problem& P, const T* w, double c_scale, const T* V, int r, int ld,
                             T* out, int ldo, double out_scale, hipStream_t s) {
-  const int G = pow2_group(r);
+  const int G = lane_group(r);
   if (r > 4 * G) fail(LORADS_EINVAL, "rank above 256 is not supported");
   if (P.structure == LORADS_STRUCT_DIAG) {
     LORADS_DISPATCH_G(G, (k2_diag<T, G, 0><<<rows_grid(P.n, G), kBlock, 0, s>>>(
@@ -121,10 +124,10 @@ static void op_adjoint_impl(Problem& P, const T* w, double c_scale, const T* V, 
                              nullptr, w, V, r, ld, out, ldo, out_scale, nullptr, nullptr, 0,
                              nullptr)));
   } else if (P.structure == LORADS_STRUCT_PAIR) {
-    LORADS_DISPATCH_G(G, (k2_pair<T, G, 0><<<P.n, kBlock, 0, s>>>(
-                             P.n, P.cptr.p, P.ccol.p, cv<T>(P), c_scale, P.rptr.p, P.pk.p,
-                             P.cvptr.p, P.cvj.p, P.cvid.p, pc<T>(P), P.pair_coef, w, V, nullptr,
-                             r, ld, out, ldo, out_scale, nullptr, 0, nullptr)));
+    LORADS_DISPATCH_G(G, (kpair_rows<T, G, 0><<<waves_grid(P.n), kBlock, 0, s>>>(
+                             P.n, P.cptr.p, P.ccol.p, cv<T>(P), c_scale, P.inc_ptr.p, P.inc_nb.p,
+                             P.inc_id.p, pc<T>(P), P.pair_coef, w, V, nullptr, r, ld, out, ldo,
+                             out_scale, nullptr, 0, nullptr)));
   } else {
     LORADS_DISPATCH_G(G, (k2_generic<T, G, 0><<<rows_grid(P.n, G), kBlock, 0, s>>>(
                              P.n, P.cptr.p, P.ccol.p, cv<T>(P), c_scale, P.aptr.p, P.acol.p,
@@ -136,7 +139,7 @@ static void op_adjoint_impl(Problem& P, const T* w, double c_scale, const T* V, 
 
 template <typename T>
 void op_cg(Problem& P, const T* W, int r, const T* Pd, T* Q, T* t, int parity, hipStream_t s) {
-  const int G = pow2_group(r);
+  const int G = lane_group(r);
   if (r > 4 * G) fail(LORADS_EINVAL, "rank above 256 is not supported");
   double* sc = P.sc.p;
   if (P.structure == LORADS_STRUCT_DIAG) {
@@ -146,17 +149,14 @@ void op_cg(Problem& P, const T* W, int r, const T* Pd, T* Q, T* t, int parity, h
                              P.n, ds<T>(P), W, Pd, Q, r, sc, parity, P.part.p)));
     cg_alpha_finish<<<1, kBlock, 0, s>>>(grid, P.part.p, sc, parity);
   } else if (P.structure == LORADS_STRUCT_PAIR) {
-    // t = rho A(P W^T) once per constraint, then Q = gamma P + A*(t) W
-    P.ensure_part(P.n);
-    LORADS_DISPATCH_G(G, (k1_pair<T, G, 2><<<rows_grid(P.nfchunks, G), kBlock, 0, s>>>(
-                             P.nfchunks, P.fchunk_row.p, P.fchunk_start.p, P.rptr.p, P.pk.p,
-                             pc<T>(P), P.pair_coef, Pd, W, r, r, t, 1.0, nullptr, nullptr, 0.0,
-                             nullptr, sc, parity)));
-    LORADS_DISPATCH_G(G, (k2_pair<T, G, 2><<<P.n, kBlock, 0, s>>>(
-                             P.n, nullptr, nullptr, nullptr, 0.0, P.rptr.p, P.pk.p, P.cvptr.p,
-                             P.cvj.p, P.cvid.p, pc<T>(P), P.pair_coef, t, W, Pd, r, r, Q, r,
-                             1.0, sc, parity, P.part.p)));
-    cg_alpha_finish<<<1, kBlock, 0, s>>>(P.n, P.part.p, sc, parity);
+    // one wave per row over its incident constraints (no per-constraint buffer)
+    const int grid = waves_grid(P.n);
+    P.ensure_part(grid);
+    LORADS_DISPATCH_G(G, (kpair_rows<T, G, 1><<<grid, kBlock, 0, s>>>(
+                             P.n, nullptr, nullptr, nullptr, 0.0, P.inc_ptr.p, P.inc_nb.p,
+                             P.inc_id.p, pc<T>(P), P.pair_coef, nullptr, W, Pd, r, r, Q, r, 1.0,
+                             sc, parity, P.part.p)));
+    cg_alpha_finish<<<1, kBlock, 0, s>>>(grid, P.part.p, sc, parity);
   } else {
     LORADS_DISPATCH_G(G, (k1_generic<T, G, 2><<<rows_grid(P.m, G), kBlock, 0, s>>>(
                              P.m, P.kptr.p, P.krow.p, P.kcol.p, kv<T>(P), Pd, W, r, r, t, 1.0,

@@ -108,7 +108,8 @@ struct Problem {
   // PAIR structure: constraint i = (j, k), j < k, coefficient a (uniform when
   // pcoef is empty: pair_coef).  Two row-owner views for the fused CG operator:
   //   view R: rows j, entries sorted by (j, k) == internal order (ptr: rptr)
-  //   view C: rows k, entries (j, internal id) sorted by (k, j)  (ptr: cvptr)
+  //   incident lists: every constraint in the list of both of its rows,
+  //   partners ascending (ptr: inc_ptr)
   DevBuf<int> pj, pk;          // internal order
   DevBuf<double> pcoef;
   DevBuf<float> pcoeff;
@@ -119,7 +120,7 @@ struct Problem {
   // next chunk's start or the row's end
   DevBuf<int> fchunk_row, fchunk_start;
   int nfchunks = 0;
-  DevBuf<int> cvptr, cvj, cvid;  // view C: row pointers, partner j, internal id
+  DevBuf<int> inc_ptr, inc_nb, inc_id;  // incident lists: row pointers, partner, internal id
 
   // solver scratch
   DevBuf<double> sc;

@@ -244,16 +244,24 @@ std::unique_ptr<Problem> ingest(const lorads_problem& p, hipStream_t s) {
     }
     std::vector<int> rptr;
     csr_counts(pj, n, rptr);
-    // view C: entries grouped by k, ascending j (internal ids ascend with j
-    // inside a column because internal order is sorted by (j, k))
-    std::vector<int> cvptr;
-    csr_counts(pk, n, cvptr);
-    std::vector<int> cvj(m), cvid(m);
-    std::vector<int> pos(cvptr.begin(), cvptr.end() - 1);
-    for (int i = 0; i < m; ++i) {
-      const int t = pos[pk[i]]++;
-      cvj[t] = pj[i];
-      cvid[t] = i;
+    // incident lists: constraint i joins the list of row pj[i] (partner pk[i])
+    // and of row pk[i] (partner pj[i]).  Filling in internal order (sorted by
+    // (j, k)) leaves every list sorted by partner: a row's entries as the
+    // larger index (partners j < row) all precede its entries as the smaller.
+    std::vector<int> inc_ptr(n + 1, 0);
+    for (int i = 0; i < m; ++i) { ++inc_ptr[pj[i] + 1]; ++inc_ptr[pk[i] + 1]; }
+    for (int j = 0; j < n; ++j) inc_ptr[j + 1] += inc_ptr[j];
+    std::vector<int> inc_nb(2 * (size_t)m), inc_id(2 * (size_t)m);
+    {
+      std::vector<int> pos(inc_ptr.begin(), inc_ptr.end() - 1);
+      for (int i = 0; i < m; ++i) {
+        int t = pos[pj[i]]++;
+        inc_nb[t] = pk[i];
+        inc_id[t] = i;
+        t = pos[pk[i]]++;
+        inc_nb[t] = pj[i];
+        inc_id[t] = i;
+      }
     }
     P->pj.upload(pj, s);
     P->pk.upload(pk, s);
@@ -276,9 +284,9 @@ std::unique_ptr<Problem> ingest(const lorads_problem& p, hipStream_t s) {
       P->fchunk_row.upload(crow, s);
       P->fchunk_start.upload(cstart, s);
     }
-    P->cvptr.upload(cvptr, s);
-    P->cvj.upload(cvj, s);
-    P->cvid.upload(cvid, s);
+    P->inc_ptr.upload(inc_ptr, s);
+    P->inc_nb.upload(inc_nb, s);
+    P->inc_id.upload(inc_id, s);
   }
 
   P->kptr.upload(kptr, s);

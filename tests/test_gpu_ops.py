@@ -136,11 +136,13 @@ def test_leading_dimension(device):
 
 @pytest.mark.parametrize("name", sorted(PROBS))
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_cg_parity(device, name, dtype):
+@pytest.mark.parametrize("r", [3, 10, 37])
+def test_cg_parity(device, name, dtype, r):
+    """Ranks 3, 10 and 37 put 1, 4 and 16 lanes on a factor row (4 columns per
+    lane, the last ones partly masked)."""
     import torch
     from paper_2403_09133_amd import Context
     p = PROBS[name]
-    r = 10
     W = _rand(p.n, r, 9) / math.sqrt(r)
     R = _rand(p.n, r, 10)
     rho, gamma = 3.0, 1.5
