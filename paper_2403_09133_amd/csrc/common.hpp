@@ -99,8 +99,15 @@ inline int pow2_group(int r) {
   return g;
 }
 
-// lanes per factor row of the row kernels: each lane holds up to 4 columns
-// (c = lane + t G, t < 4), so a wave covers 64 / G rows at once
-inline int lane_group(int r) { return pow2_group((r + 3) / 4); }
+// lanes per factor row of the row kernels: a lane holds up to
+// LORADS_COLS_PER_LANE columns of a row in registers (c = lane + t G), so a
+// wave covers 64 / G rows at once.  One column per lane keeps every gathered
+// row inside a single load instruction.
+#ifndef LORADS_COLS_PER_LANE
+#define LORADS_COLS_PER_LANE 1
+#endif
+inline int lane_group(int r) {
+  return pow2_group((r + LORADS_COLS_PER_LANE - 1) / LORADS_COLS_PER_LANE);
+}
 
 }  // namespace lorads

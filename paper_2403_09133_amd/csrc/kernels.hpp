@@ -12,10 +12,32 @@
 
 namespace lorads {
 
+// Lane exchange inside a 16-lane row by a DPP move (a VALU operation, so it
+// does not queue on the CU's LDS pipeline the way a bpermute shuffle does).
+// CTRL: 0xB1 swaps lanes 2k <-> 2k+1, 0x4E swaps pairs inside a quad,
+// 0x141 mirrors each half-row (i <-> 7 - i), 0x140 mirrors the row (i <-> 15 - i).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over an aligned group of G lanes (G a power of two <= 64); every lane of
+// the group receives the same value.  Up to 16 lanes: DPP swaps and mirrors
+// (after each step a lane holds the sum of its aligned block, and a mirror
+// pairs every lane with one in the other half of the doubled block; a + b and
+// b + a round alike, so all lanes agree bit for bit).  Wider groups finish
+// with xor shuffles across rows.
 template <int G>
 __device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if (G >= 2) v += dpp_move<0xB1>(v);
+  if (G >= 4) v += dpp_move<0x4E>(v);
+  if (G >= 8) v += dpp_move<0x141>(v);
+  if (G >= 16) v += dpp_move<0x140>(v);
+  if (G >= 32) v += __shfl_xor(v, 16, 64);
+  if (G >= 64) v += __shfl_xor(v, 32, 64);
   return v;
 }
 

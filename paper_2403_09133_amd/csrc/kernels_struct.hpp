@@ -8,7 +8,11 @@
 namespace lorads {
 
 constexpr int kMaxCols = 4;  // factor columns per lane held in registers (r <= 4 G)
-constexpr int kUnroll = 4;   // incident constraints gathered per step (memory-level parallelism)
+#ifndef LORADS_UNROLL
+#define LORADS_UNROLL 4
+#endif
+constexpr int kUnroll = LORADS_UNROLL;  // constraints gathered per step (memory-level parallelism)
+constexpr int kPairStage = 256;         // PAIR incident entries staged in LDS per wave and pass
 
 // ===========================================================================
 // K1 forward map, shared MODE convention:
@@ -46,7 +50,7 @@ __global__ void __launch_bounds__(kBlock) k1_diag(
 // (j, k) of one row j (contiguous in the internal order), keeps U_j, V_j in
 // registers and gathers the partners kUnroll at a time:
 //   z_i = a_i (<U_j, V_k> + <U_k, V_j>).
-template <typename T, int G, int MODE>
+template <typename T, int G, int MODE, int KC = kMaxCols>
 __global__ void __launch_bounds__(kBlock) k1_pair(
     int nchunks, const int* __restrict__ chunk_row, const int* __restrict__ chunk_start,
     const int* __restrict__ rptr, const int* __restrict__ pk, const T* __restrict__ pcoef,
@@ -60,9 +64,9 @@ __global__ void __launch_bounds__(kBlock) k1_pair(
   if (chunk >= nchunks) return;
   const int row = chunk_row[chunk];
   const int i0 = chunk_start[chunk], i1 = min(i0 + kPairChunk, rptr[row + 1]);
-  double uj[kMaxCols], vj[kMaxCols];
+  double uj[KC], vj[KC];
 #pragma unroll
-  for (int t = 0; t < kMaxCols; ++t) {
+  for (int t = 0; t < KC; ++t) {
     const int c = lane + t * G;
     uj[t] = c < r ? (double)U[(size_t)row * ld + c] : 0.0;
     vj[t] = c < r ? (double)V[(size_t)row * ld + c] : 0.0;
@@ -78,7 +82,7 @@ __global__ void __launch_bounds__(kBlock) k1_pair(
     for (int u = 0; u < kUnroll; ++u) {
       double s = 0.0;
 #pragma unroll
-      for (int t = 0; t < kMaxCols; ++t) {
+      for (int t = 0; t < KC; ++t) {
         const int c = lane + t * G;
         if (c < r)
           s += uj[t] * (double)V[(size_t)k[u] * ld + c] + (double)U[(size_t)k[u] * ld + c] * vj[t];
@@ -176,8 +180,12 @@ __global__ void __launch_bounds__(kBlock) k3_diag(int n, const T* __restrict__ d
 // a (e_j e_k^T + e_k e_j^T) appears in the list of row j (partner k) and of
 // row k (partner j), partners ascending.  The wave's 64/G lane groups take
 // interleaved entries (so the index loads of a step are contiguous) and
-// kUnroll entries per step; each lane holds kMaxCols columns (c = lane + t G).
+// kUnroll entries per step; each lane holds KC columns (c = lane + t G; KC = 1
+// whenever r <= G).
 // The group partials are summed by a fixed xor butterfly across the wave.
+// A wave first loads a pass of kPairStage entries (partners and coefficients,
+// every load of the pass in flight at once) into its own LDS slots, so the
+// gathers of a step wait on one memory latency instead of an index chain.
 //   MODE 0 (adjoint):  out_t = out_scale (c_scale (C V)_t + sum_e a_e w_{id(e)} V_p);
 //                      w == nullptr drops the sum (the solver's C D and C U products)
 //   MODE 1 (CG operator, V = the fixed factor, Pm = the direction):
@@ -186,7 +194,7 @@ __global__ void __launch_bounds__(kBlock) k3_diag(int n, const T* __restrict__ d
 //     Each constraint's inner product is formed by both of its rows, so no
 //     per-constraint buffer is written or gathered.
 // ===========================================================================
-template <typename T, int G, int MODE>
+template <typename T, int G, int MODE, int KC = kMaxCols>
 __global__ void __launch_bounds__(kBlock) kpair_rows(
     int n, const int* __restrict__ cptr, const int* __restrict__ ccol,
     const T* __restrict__ cval, double c_scale, const int* __restrict__ inc_ptr,
@@ -195,16 +203,21 @@ __global__ void __launch_bounds__(kBlock) kpair_rows(
     int r, int ld, T* __restrict__ out, int ldo, double out_scale, double* __restrict__ sc,
     int parity, double* __restrict__ part) {
   constexpr int NG = 64 / G;
+  constexpr int CH = kPairStage;  // incident entries staged per wave and pass
   __shared__ double sh[kBlock / 64];
+  __shared__ int s_nb[kBlock / 64][CH];
+  __shared__ double s_cf[kBlock / 64][CH];
   if (MODE == 1 && sc[S_DONE + parity] != 0.0) return;
-  const int wl = threadIdx.x & 63;
+  const int wl = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int grp = wl / G, lane = wl & (G - 1);
-  const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int row = blockIdx.x * (kBlock / 64) + wid;
+  int* nbw = s_nb[wid];
+  double* cfw = s_cf[wid];
   double pq = 0.0;
   if (row < n) {  // wave-uniform
-    double acc[kMaxCols], pt[kMaxCols], vt[kMaxCols];
+    double acc[KC], pt[KC], vt[KC];
 #pragma unroll
-    for (int t = 0; t < kMaxCols; ++t) {
+    for (int t = 0; t < KC; ++t) {
       const int c = lane + t * G;
       acc[t] = 0.0;
       pt[t] = (MODE == 1 && c < r) ? (double)Pm[(size_t)row * ld + c] : 0.0;
@@ -215,7 +228,7 @@ __global__ void __launch_bounds__(kBlock) kpair_rows(
         const int k = ccol[e];
         const double a = c_scale * (double)cval[e];
 #pragma unroll
-        for (int t = 0; t < kMaxCols; ++t) {
+        for (int t = 0; t < KC; ++t) {
           const int c = lane + t * G;
           if (c < r) acc[t] += a * (double)V[(size_t)k * ld + c];
         }
@@ -224,58 +237,83 @@ __global__ void __launch_bounds__(kBlock) kpair_rows(
     // MODE 0 with w == nullptr is the C part alone (c_scale C V)
     const int e0 = inc_ptr[row];
     const int e1 = (MODE == 0 && w == nullptr) ? e0 : inc_ptr[row + 1];
-    for (int e = e0 + grp; e < e1; e += NG * kUnroll) {
-      int p[kUnroll];
-      double coef[kUnroll];
+    for (int base = e0; base < e1; base += CH) {
+      const int cnt = min(CH, e1 - base);
+      // stage: partners and per-entry coefficients (a w_id for the adjoint,
+      // a^2 for the CG operator), all loads of the pass in flight together
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int eu = e + u * NG;
-        const bool ok = eu < e1;
-        const int ee = ok ? eu : e;
-        p[u] = inc_nb[ee];
-        double a = pcoef ? (double)pcoef[inc_id[ee]] : pair_coef;
-        if (MODE == 0) a *= (double)w[inc_id[ee]];
-        else a *= a;
-        coef[u] = ok ? a : 0.0;
-      }
-      if (MODE == 0) {
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u)
-#pragma unroll
-          for (int t = 0; t < kMaxCols; ++t) {
-            const int c = lane + t * G;
-            if (c < r) acc[t] += coef[u] * (double)V[(size_t)p[u] * ld + c];
+      for (int q = 0; q < CH / 64; ++q) {
+        const int j = wl + 64 * q;
+        if (j < cnt) {
+          nbw[j] = inc_nb[base + j];
+          double a = pair_coef;
+          if (pcoef != nullptr || MODE == 0) {
+            const int id = inc_id[base + j];
+            if (pcoef != nullptr) a = (double)pcoef[id];
+            if (MODE == 0) a *= (double)w[id];
+            else a *= a;
+          } else if (MODE == 1) {
+            a *= a;
           }
-      } else {
-        double vp[kUnroll][kMaxCols], d[kUnroll];
+          cfw[j] = a;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int j = grp; j < cnt; j += NG * kUnroll) {
+        int p[kUnroll];
+        double coef[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-          double s = 0.0;
-#pragma unroll
-          for (int t = 0; t < kMaxCols; ++t) {
-            const int c = lane + t * G;
-            vp[u][t] = c < r ? (double)V[(size_t)p[u] * ld + c] : 0.0;
-            const double pp = c < r ? (double)Pm[(size_t)p[u] * ld + c] : 0.0;
-            s += pt[t] * vp[u][t] + pp * vt[t];
-          }
-          d[u] = s;
+          const int ju = j + u * NG;
+          const bool ok = ju < cnt;
+          p[u] = ok ? nbw[ju] : row;
+          coef[u] = ok ? cfw[ju] : 0.0;
         }
+        if (MODE == 0) {
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) d[u] = group_sum<G>(d[u]) * coef[u];
+          for (int u = 0; u < kUnroll; ++u)
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u)
+            for (int t = 0; t < KC; ++t) {
+              const int c = lane + t * G;
+              if (c < r) acc[t] += coef[u] * (double)V[(size_t)p[u] * ld + c];
+            }
+        } else {
+          double vp[kUnroll][KC], d[kUnroll];
 #pragma unroll
-          for (int t = 0; t < kMaxCols; ++t) acc[t] += d[u] * vp[u][t];
+          for (int u = 0; u < kUnroll; ++u) {
+            double s = 0.0;
+#pragma unroll
+            for (int t = 0; t < KC; ++t) {
+              const int c = lane + t * G;
+              vp[u][t] = c < r ? (double)V[(size_t)p[u] * ld + c] : 0.0;
+              const double pp = c < r ? (double)Pm[(size_t)p[u] * ld + c] : 0.0;
+              s += pt[t] * vp[u][t] + pp * vt[t];
+            }
+            d[u] = s;
+          }
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) d[u] = group_sum<G>(d[u]) * coef[u];
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+            for (int t = 0; t < KC; ++t) acc[t] += d[u] * vp[u][t];
+        }
       }
+      // the next pass overwrites this wave's staging slots
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 #pragma unroll
-    for (int t = 0; t < kMaxCols; ++t)
+    for (int t = 0; t < KC; ++t)
       for (int o = G; o < 64; o <<= 1) acc[t] += __shfl_xor(acc[t], o, 64);
     if (grp == 0) {
       if (MODE == 1) {
         const double gamma = sc[S_GAMMA], rho = sc[S_RHO];
 #pragma unroll
-        for (int t = 0; t < kMaxCols; ++t) {
+        for (int t = 0; t < KC; ++t) {
           const int c = lane + t * G;
           if (c < r) {
             const T qv = (T)(gamma * pt[t] + rho * acc[t]);
@@ -285,7 +323,7 @@ __global__ void __launch_bounds__(kBlock) kpair_rows(
         }
       } else {
 #pragma unroll
-        for (int t = 0; t < kMaxCols; ++t) {
+        for (int t = 0; t < KC; ++t) {
           const int c = lane + t * G;
           if (c < r) out[(size_t)row * ldo + c] = (T)(out_scale * acc[t]);
         }

@@ -35,6 +35,18 @@ template <typename T> static const T* pc(const Problem& P);
 template <> const double* pc<double>(const Problem& P) { return P.pcoef.p; }
 template <> const float* pc<float>(const Problem& P) { return P.pcoeff.p; }
 
+// G as above, plus KC = the factor columns a lane holds: 1 when r <= G
+#define LORADS_DISPATCH_GK(G, r, CALL)                          \
+  do {                                                           \
+    if ((r) <= (G)) {                                            \
+      constexpr int KC = 1;                                      \
+      LORADS_DISPATCH_G(G, CALL);                                \
+    } else {                                                     \
+      constexpr int KC = kMaxCols;                               \
+      LORADS_DISPATCH_G(G, CALL);                                \
+    }                                                            \
+  } while (0)
+
 // one wave (64 lanes) per row, 4 rows per block
 static int waves_grid(int rows) { return std::max(1, (rows + kBlock / 64 - 1) / (kBlock / 64)); }
 
@@ -53,7 +65,7 @@ static void op_forward_impl(Problem& P, const T* U, const T* V, int r, int ld, T
                              P.m, P.drow.p, dc<T>(P), U, V, r, ld, z, scale, nullptr, nullptr,
                              0.0, nullptr, nullptr, 0)));
   } else if (P.structure == LORADS_STRUCT_PAIR) {
-    LORADS_DISPATCH_G(G, (k1_pair<T, G, 0><<<rows_grid(P.nfchunks, G), kBlock, 0, s>>>(
+    LORADS_DISPATCH_GK(G, r, (k1_pair<T, G, 0, KC><<<rows_grid(P.nfchunks, G), kBlock, 0, s>>>(
                              P.nfchunks, P.fchunk_row.p, P.fchunk_start.p, P.rptr.p, P.pk.p,
                              pc<T>(P), P.pair_coef, U, V, r, ld, z, scale,
                              nullptr, nullptr, 0.0, nullptr, nullptr, 0)));
@@ -90,7 +102,7 @@ static void op_forward_w_impl(Problem& P, const double* U, const double* V, int 
                              P.m, P.drow.p, P.dcoef.p, U, V, r, ld, z, 1.0, lam, P.b.p, rho, w,
                              nullptr, 0)));
   } else if (P.structure == LORADS_STRUCT_PAIR) {
-    LORADS_DISPATCH_G(G, (k1_pair<double, G, 1><<<rows_grid(P.nfchunks, G), kBlock, 0, s>>>(
+    LORADS_DISPATCH_GK(G, r, (k1_pair<double, G, 1, KC><<<rows_grid(P.nfchunks, G), kBlock, 0, s>>>(
                              P.nfchunks, P.fchunk_row.p, P.fchunk_start.p, P.rptr.p, P.pk.p,
                              P.pcoef.p, P.pair_coef, U, V, r, ld, z, 1.0,
                              lam, P.b.p, rho, w, nullptr, 0)));
@@ -124,7 +136,7 @@ static void op_adjoint_impl(Problem& P, const T* w, double c_scale, const T* V, 
                              nullptr, w, V, r, ld, out, ldo, out_scale, nullptr, nullptr, 0,
                              nullptr)));
   } else if (P.structure == LORADS_STRUCT_PAIR) {
-    LORADS_DISPATCH_G(G, (kpair_rows<T, G, 0><<<waves_grid(P.n), kBlock, 0, s>>>(
+    LORADS_DISPATCH_GK(G, r, (kpair_rows<T, G, 0, KC><<<waves_grid(P.n), kBlock, 0, s>>>(
                              P.n, P.cptr.p, P.ccol.p, cv<T>(P), c_scale, P.inc_ptr.p, P.inc_nb.p,
                              P.inc_id.p, pc<T>(P), P.pair_coef, w, V, nullptr, r, ld, out, ldo,
                              out_scale, nullptr, 0, nullptr)));
@@ -152,7 +164,7 @@ void op_cg(Problem& P, const T* W, int r, const T* Pd, T* Q, T* t, int parity, h
     // one wave per row over its incident constraints (no per-constraint buffer)
     const int grid = waves_grid(P.n);
     P.ensure_part(grid);
-    LORADS_DISPATCH_G(G, (kpair_rows<T, G, 1><<<grid, kBlock, 0, s>>>(
+    LORADS_DISPATCH_GK(G, r, (kpair_rows<T, G, 1, KC><<<grid, kBlock, 0, s>>>(
                              P.n, nullptr, nullptr, nullptr, 0.0, P.inc_ptr.p, P.inc_nb.p,
                              P.inc_id.p, pc<T>(P), P.pair_coef, nullptr, W, Pd, r, r, Q, r, 1.0,
                              sc, parity, P.part.p)));

@@ -65,9 +65,26 @@ def test_solve_matches_oracle(device, name, precision):
     assert abs(m["lambda_min"] - res["lambda_min"]) <= 1e-7 * max(1.0, abs(m["lambda_min"]))
     assert abs(m["gap"] - res["gap"]) <= 1e-9
     if precision == 0:
-        # same trajectory as the oracle up to rounding
+        # Same trajectory as the oracle up to rounding, where rounding cannot
+        # steer it: perturbing U0 by 1e-15 (relative) moves the oracle's own
+        # eq.(stop) value after 60 ADMM iterations by 26% on torus12 and 5e-4 on
+        # er200 (MaxCut factors are unique only up to rotation, and the tail
+        # near 1e-6 is slow), but by 4e-11 on mc_60x50 and 1e-7 on generic_10x8.
+        # So the iteration count is held to 10% everywhere, and the state after
+        # a fixed number of iterations is compared on the stable cases.
         assert res["rank"] == ref["rank"]
-        assert abs(res["admm_iters"] - ref["phase2"]["iters"]) <= max(2, 0.02 * ref["phase2"]["iters"])
+        assert abs(res["admm_iters"] - ref["phase2"]["iters"]) <= max(2, 0.10 * ref["phase2"]["iters"])
+        if name in ("mc_60x50", "generic_10x8"):
+            K = max(1, ref["phase2"]["iters"] // 2)
+            p, _ = CASES[name]
+            o = Options(**paper_defaults(p.kind, p.n))
+            o.max_admm_iter = K
+            refK = oracle.lorads.lorads(p, U0, o)
+            with Context(p) as ctx:
+                rK = ctx.admm_solve([U0], _lib_opts(p, r0, max_admm_iter=K))[0]
+            assert rK["admm_iters"] == refK["phase2"]["iters"] == K
+            assert abs(rK["kkt"] - refK["phase2"]["kkt"]) <= 1e-5 * refK["phase2"]["kkt"]
+            assert abs(rK["obj"] - refK["metrics"]["obj"]) <= 1e-9 * max(1.0, abs(refK["metrics"]["obj"]))
 
 
 def test_resume_from_solution(device):
