@@ -30,6 +30,28 @@ __device__ __forceinline__ double dpp_move(double v) {
 // pairs every lane with one in the other half of the doubled block; a + b and
 // b + a round alike, so all lanes agree bit for bit).  Wider groups finish
 // with xor shuffles across rows.
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+template <int G>
+__device__ __forceinline__ float group_sum(float v) {
+  if (G >= 2) v += dpp_move<0xB1>(v);
+  if (G >= 4) v += dpp_move<0x4E>(v);
+  if (G >= 8) v += dpp_move<0x141>(v);
+  if (G >= 16) v += dpp_move<0x140>(v);
+  if (G >= 32) v += __shfl_xor(v, 16, 64);
+  if (G >= 64) v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+// Arithmetic type of the per-constraint products of the operator kernels:
+// the element type itself (the FP32 form computes its operator in FP32;
+// the scalars of CG and every solver decision stay FP64).
+template <typename T> struct OpAcc { using type = double; };
+template <> struct OpAcc<float> { using type = float; };
+
 template <int G>
 __device__ __forceinline__ double group_sum(double v) {
   if (G >= 2) v += dpp_move<0xB1>(v);
@@ -390,6 +412,18 @@ __global__ void __launch_bounds__(kBlock) convert_kernel(size_t N, const TS* __r
 }
 
 // strided copy between row-major layouts (n rows, r columns)
+// out = x + y row by row: x, out with leading dimension ldx, y with ldy
+template <typename TX, typename TY>
+__global__ void __launch_bounds__(kBlock) add_rows(int n, int r, const TX* __restrict__ x, int ldx,
+                                                   const TY* __restrict__ y, int ldy,
+                                                   TX* __restrict__ out) {
+  const size_t N = (size_t)n * r;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock) {
+    const size_t j = i / r, c = i % r;
+    out[j * ldx + c] = x[j * ldx + c] + (TX)y[j * ldy + c];
+  }
+}
+
 template <typename TS, typename TD>
 __global__ void __launch_bounds__(kBlock) copy_rows(int n, int r, const TS* __restrict__ s,
                                                     int lds, TD* __restrict__ d, int ldd) {

@@ -64,12 +64,13 @@ __global__ void __launch_bounds__(kBlock) k1_pair(
   if (chunk >= nchunks) return;
   const int row = chunk_row[chunk];
   const int i0 = chunk_start[chunk], i1 = min(i0 + kPairChunk, rptr[row + 1]);
-  double uj[KC], vj[KC];
+  using A = typename OpAcc<T>::type;
+  A uj[KC], vj[KC];
 #pragma unroll
   for (int t = 0; t < KC; ++t) {
     const int c = lane + t * G;
-    uj[t] = c < r ? (double)U[(size_t)row * ld + c] : 0.0;
-    vj[t] = c < r ? (double)V[(size_t)row * ld + c] : 0.0;
+    uj[t] = c < r ? (A)U[row * ld + c] : (A)0;
+    vj[t] = c < r ? (A)V[row * ld + c] : (A)0;
   }
   const double mult = (MODE == 2) ? sc[S_RHO] : (MODE == 0 ? scale : 1.0);
   for (int i = i0; i < i1; i += kUnroll) {
@@ -77,15 +78,15 @@ __global__ void __launch_bounds__(kBlock) k1_pair(
     int k[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) k[u] = u < cnt ? pk[i + u] : row;
-    double d[kUnroll];
+    A d[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      double s = 0.0;
+      A s = 0;
+      const int base = k[u] * ld;
 #pragma unroll
       for (int t = 0; t < KC; ++t) {
         const int c = lane + t * G;
-        if (c < r)
-          s += uj[t] * (double)V[(size_t)k[u] * ld + c] + (double)U[(size_t)k[u] * ld + c] * vj[t];
+        if (c < r) s += uj[t] * (A)V[base + c] + (A)U[base + c] * vj[t];
       }
       d[u] = s;
     }
@@ -96,7 +97,7 @@ __global__ void __launch_bounds__(kBlock) k1_pair(
       // every lane holds the reduced d[u]; lane u mod G stores it
       if (lane == (u & (G - 1)) && u < cnt) {
         const int id = i + u;
-        const double val = d[u] * (pcoef ? (double)pcoef[id] : pair_coef);
+        const double val = (double)d[u] * (pcoef ? (double)pcoef[id] : pair_coef);
         if (MODE == 1) {
           z[id] = (T)val;
           w[id] = lam[id] + rho * (val - b[id]);
@@ -206,31 +207,32 @@ __global__ void __launch_bounds__(kBlock) kpair_rows(
   constexpr int CH = kPairStage;  // incident entries staged per wave and pass
   __shared__ double sh[kBlock / 64];
   __shared__ int s_nb[kBlock / 64][CH];
-  __shared__ double s_cf[kBlock / 64][CH];
+  using A = typename OpAcc<T>::type;
+  __shared__ A s_cf[kBlock / 64][CH];
   if (MODE == 1 && sc[S_DONE + parity] != 0.0) return;
   const int wl = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int grp = wl / G, lane = wl & (G - 1);
   const int row = blockIdx.x * (kBlock / 64) + wid;
   int* nbw = s_nb[wid];
-  double* cfw = s_cf[wid];
+  A* cfw = s_cf[wid];
   double pq = 0.0;
   if (row < n) {  // wave-uniform
-    double acc[KC], pt[KC], vt[KC];
+    A acc[KC], pt[KC], vt[KC];
 #pragma unroll
     for (int t = 0; t < KC; ++t) {
       const int c = lane + t * G;
-      acc[t] = 0.0;
-      pt[t] = (MODE == 1 && c < r) ? (double)Pm[(size_t)row * ld + c] : 0.0;
-      vt[t] = (MODE == 1 && c < r) ? (double)V[(size_t)row * ld + c] : 0.0;
+      acc[t] = 0;
+      pt[t] = (MODE == 1 && c < r) ? (A)Pm[row * ld + c] : (A)0;
+      vt[t] = (MODE == 1 && c < r) ? (A)V[row * ld + c] : (A)0;
     }
     if (MODE == 0 && c_scale != 0.0) {
       for (int e = cptr[row] + grp; e < cptr[row + 1]; e += NG) {
         const int k = ccol[e];
-        const double a = c_scale * (double)cval[e];
+        const A a = (A)(c_scale * (double)cval[e]);
 #pragma unroll
         for (int t = 0; t < KC; ++t) {
           const int c = lane + t * G;
-          if (c < r) acc[t] += a * (double)V[(size_t)k * ld + c];
+          if (c < r) acc[t] += a * (A)V[k * ld + c];
         }
       }
     }
@@ -255,7 +257,7 @@ __global__ void __launch_bounds__(kBlock) kpair_rows(
           } else if (MODE == 1) {
             a *= a;
           }
-          cfw[j] = a;
+          cfw[j] = (A)a;
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -263,13 +265,13 @@ __global__ void __launch_bounds__(kBlock) kpair_rows(
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       for (int j = grp; j < cnt; j += NG * kUnroll) {
         int p[kUnroll];
-        double coef[kUnroll];
+        A coef[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           const int ju = j + u * NG;
           const bool ok = ju < cnt;
-          p[u] = ok ? nbw[ju] : row;
-          coef[u] = ok ? cfw[ju] : 0.0;
+          p[u] = (ok ? nbw[ju] : row) * ld;
+          coef[u] = ok ? cfw[ju] : (A)0;
         }
         if (MODE == 0) {
 #pragma unroll
@@ -277,18 +279,18 @@ __global__ void __launch_bounds__(kBlock) kpair_rows(
 #pragma unroll
             for (int t = 0; t < KC; ++t) {
               const int c = lane + t * G;
-              if (c < r) acc[t] += coef[u] * (double)V[(size_t)p[u] * ld + c];
+              if (c < r) acc[t] += coef[u] * (A)V[p[u] + c];
             }
         } else {
-          double vp[kUnroll][KC], d[kUnroll];
+          A vp[kUnroll][KC], d[kUnroll];
 #pragma unroll
           for (int u = 0; u < kUnroll; ++u) {
-            double s = 0.0;
+            A s = 0;
 #pragma unroll
             for (int t = 0; t < KC; ++t) {
               const int c = lane + t * G;
-              vp[u][t] = c < r ? (double)V[(size_t)p[u] * ld + c] : 0.0;
-              const double pp = c < r ? (double)Pm[(size_t)p[u] * ld + c] : 0.0;
+              vp[u][t] = c < r ? (A)V[p[u] + c] : (A)0;
+              const A pp = c < r ? (A)Pm[p[u] + c] : (A)0;
               s += pt[t] * vp[u][t] + pp * vt[t];
             }
             d[u] = s;
@@ -316,16 +318,16 @@ __global__ void __launch_bounds__(kBlock) kpair_rows(
         for (int t = 0; t < KC; ++t) {
           const int c = lane + t * G;
           if (c < r) {
-            const T qv = (T)(gamma * pt[t] + rho * acc[t]);
-            out[(size_t)row * ldo + c] = qv;
-            pq += pt[t] * (double)qv;
+            const T qv = (T)(gamma * (double)pt[t] + rho * (double)acc[t]);
+            out[row * ldo + c] = qv;
+            pq += (double)pt[t] * (double)qv;
           }
         }
       } else {
 #pragma unroll
         for (int t = 0; t < KC; ++t) {
           const int c = lane + t * G;
-          if (c < r) out[(size_t)row * ldo + c] = (T)(out_scale * acc[t]);
+          if (c < r) out[row * ldo + c] = (T)(out_scale * (double)acc[t]);
         }
       }
     }

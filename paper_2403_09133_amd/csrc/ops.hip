@@ -47,6 +47,11 @@ template <> const float* pc<float>(const Problem& P) { return P.pcoeff.p; }
     }                                                            \
   } while (0)
 
+// the PAIR kernels index factor rows with 32-bit offsets
+static void check_pair_offsets(const Problem& P, int ld) {
+  if ((long long)P.n * ld >= (1LL << 31)) fail(LORADS_EINVAL, "n * ld exceeds the 32-bit offset range");
+}
+
 // one wave (64 lanes) per row, 4 rows per block
 static int waves_grid(int rows) { return std::max(1, (rows + kBlock / 64 - 1) / (kBlock / 64)); }
 
@@ -65,6 +70,7 @@ static void op_forward_impl(Problem& P, const T* U, const T* V, int r, int ld, T
                              P.m, P.drow.p, dc<T>(P), U, V, r, ld, z, scale, nullptr, nullptr,
                              0.0, nullptr, nullptr, 0)));
   } else if (P.structure == LORADS_STRUCT_PAIR) {
+    check_pair_offsets(P, ld);
     LORADS_DISPATCH_GK(G, r, (k1_pair<T, G, 0, KC><<<rows_grid(P.nfchunks, G), kBlock, 0, s>>>(
                              P.nfchunks, P.fchunk_row.p, P.fchunk_start.p, P.rptr.p, P.pk.p,
                              pc<T>(P), P.pair_coef, U, V, r, ld, z, scale,
@@ -102,6 +108,7 @@ static void op_forward_w_impl(Problem& P, const double* U, const double* V, int 
                              P.m, P.drow.p, P.dcoef.p, U, V, r, ld, z, 1.0, lam, P.b.p, rho, w,
                              nullptr, 0)));
   } else if (P.structure == LORADS_STRUCT_PAIR) {
+    check_pair_offsets(P, ld);
     LORADS_DISPATCH_GK(G, r, (k1_pair<double, G, 1, KC><<<rows_grid(P.nfchunks, G), kBlock, 0, s>>>(
                              P.nfchunks, P.fchunk_row.p, P.fchunk_start.p, P.rptr.p, P.pk.p,
                              P.pcoef.p, P.pair_coef, U, V, r, ld, z, 1.0,
@@ -136,6 +143,7 @@ static void op_adjoint_impl(Problem& P, const T* w, double c_scale, const T* V, 
                              nullptr, w, V, r, ld, out, ldo, out_scale, nullptr, nullptr, 0,
                              nullptr)));
   } else if (P.structure == LORADS_STRUCT_PAIR) {
+    check_pair_offsets(P, std::max(ld, ldo));
     LORADS_DISPATCH_GK(G, r, (kpair_rows<T, G, 0, KC><<<waves_grid(P.n), kBlock, 0, s>>>(
                              P.n, P.cptr.p, P.ccol.p, cv<T>(P), c_scale, P.inc_ptr.p, P.inc_nb.p,
                              P.inc_id.p, pc<T>(P), P.pair_coef, w, V, nullptr, r, ld, out, ldo,
@@ -149,11 +157,18 @@ static void op_adjoint_impl(Problem& P, const T* w, double c_scale, const T* V, 
   HIPCHK(hipGetLastError());
 }
 
+int cg_ld(const Problem& P, int r, int elem_bytes) {
+  if (P.structure != LORADS_STRUCT_PAIR) return r;
+  const int per_line = 64 / elem_bytes;  // 64-byte rows: a gathered row never straddles a line
+  return (r + per_line - 1) / per_line * per_line;
+}
+
 template <typename T>
-void op_cg(Problem& P, const T* W, int r, const T* Pd, T* Q, T* t, int parity, hipStream_t s) {
+void op_cg(Problem& P, const T* W, int r, int ld, const T* Pd, T* Q, T* t, int parity, hipStream_t s) {
   const int G = lane_group(r);
   if (r > 4 * G) fail(LORADS_EINVAL, "rank above 256 is not supported");
   double* sc = P.sc.p;
+  if (P.structure != LORADS_STRUCT_PAIR && ld != r) fail(LORADS_EINVAL, "CG buffers must be compact");
   if (P.structure == LORADS_STRUCT_DIAG) {
     const int grid = rows_grid(P.n, G);
     P.ensure_part(grid);
@@ -161,13 +176,14 @@ void op_cg(Problem& P, const T* W, int r, const T* Pd, T* Q, T* t, int parity, h
                              P.n, ds<T>(P), W, Pd, Q, r, sc, parity, P.part.p)));
     cg_alpha_finish<<<1, kBlock, 0, s>>>(grid, P.part.p, sc, parity);
   } else if (P.structure == LORADS_STRUCT_PAIR) {
-    // one wave per row over its incident constraints (no per-constraint buffer)
+    check_pair_offsets(P, ld);
     const int grid = waves_grid(P.n);
     P.ensure_part(grid);
+    // one wave per row over its incident constraints, G lanes per constraint
     LORADS_DISPATCH_GK(G, r, (kpair_rows<T, G, 1, KC><<<grid, kBlock, 0, s>>>(
                              P.n, nullptr, nullptr, nullptr, 0.0, P.inc_ptr.p, P.inc_nb.p,
-                             P.inc_id.p, pc<T>(P), P.pair_coef, nullptr, W, Pd, r, r, Q, r, 1.0,
-                             sc, parity, P.part.p)));
+                             P.inc_id.p, pc<T>(P), P.pair_coef, nullptr, W, Pd, r, ld, Q, ld,
+                             1.0, sc, parity, P.part.p)));
     cg_alpha_finish<<<1, kBlock, 0, s>>>(grid, P.part.p, sc, parity);
   } else {
     LORADS_DISPATCH_G(G, (k1_generic<T, G, 2><<<rows_grid(P.m, G), kBlock, 0, s>>>(
@@ -267,9 +283,9 @@ void linesearch_slots(Problem& P, const double* z, const double* p1, const doubl
 // device-resident iterations; after each chunk one flag is read back.
 // ---------------------------------------------------------------------------
 template <typename T>
-int cg_run(Problem& P, const T* W, int r, double rho, double gamma, T* R, T* X, T* Pd, T* Q,
-           T* t, double tol, int maxit, hipStream_t s, double* relres, double* op_bytes) {
-  const size_t N = (size_t)P.n * r;
+int cg_run(Problem& P, const T* W, int r, int ld, double rho, double gamma, T* R, T* X, T* Pd,
+           T* Q, T* t, double tol, int maxit, hipStream_t s, double* relres, double* op_bytes) {
+  const size_t N = (size_t)P.n * ld;  // padding entries are zero and stay zero
   const double sv[2] = {gamma, rho};
   set_slots(P, S_GAMMA, sv, 2, s);
   const int gridv = grid_for(N, 1024);
@@ -287,7 +303,7 @@ int cg_run(Problem& P, const T* W, int r, double rho, double gamma, T* R, T* X, 
     const int iters_before = iters;
     for (int i = 0; i < steps; ++i, ++k) {
       const int par = k & 1;
-      P.prof.run(0, bytes_cg_op(P, r, sizeof(T)), s, [&] { op_cg<T>(P, W, r, Pd, Q, t, par, s); });
+      P.prof.run(0, bytes_cg_op(P, r, sizeof(T)), s, [&] { op_cg<T>(P, W, r, ld, Pd, Q, t, par, s); });
       cg_update<T><<<gridv, kBlock, 0, s>>>(N, X, R, Pd, Q, P.sc.p, par, P.part.p);
       cg_update_finish<<<1, kBlock, 0, s>>>(gridv, P.part.p, P.sc.p, par);
       cg_direction<T><<<gridv, kBlock, 0, s>>>(N, R, Pd, P.sc.p, par);
@@ -312,11 +328,11 @@ template void op_forward<double>(Problem&, const double*, const double*, int, in
 template void op_forward<float>(Problem&, const float*, const float*, int, int, float*, double, hipStream_t);
 template void op_adjoint<double>(Problem&, const double*, double, const double*, int, int, double*, int, double, hipStream_t);
 template void op_adjoint<float>(Problem&, const float*, double, const float*, int, int, float*, int, double, hipStream_t);
-template void op_cg<double>(Problem&, const double*, int, const double*, double*, double*, int, hipStream_t);
-template void op_cg<float>(Problem&, const float*, int, const float*, float*, float*, int, hipStream_t);
+template void op_cg<double>(Problem&, const double*, int, int, const double*, double*, double*, int, hipStream_t);
+template void op_cg<float>(Problem&, const float*, int, int, const float*, float*, float*, int, hipStream_t);
 template void dot_to_slot<double, double>(Problem&, size_t, const double*, const double*, double, int, hipStream_t);
 template void dot_to_slot<float, float>(Problem&, size_t, const float*, const float*, double, int, hipStream_t);
-template int cg_run<double>(Problem&, const double*, int, double, double, double*, double*, double*, double*, double*, double, int, hipStream_t, double*, double*);
-template int cg_run<float>(Problem&, const float*, int, double, double, float*, float*, float*, float*, float*, double, int, hipStream_t, double*, double*);
+template int cg_run<double>(Problem&, const double*, int, int, double, double, double*, double*, double*, double*, double*, double, int, hipStream_t, double*, double*);
+template int cg_run<float>(Problem&, const float*, int, int, double, double, float*, float*, float*, float*, float*, double, int, hipStream_t, double*, double*);
 
 }  // namespace lorads

@@ -165,7 +165,11 @@ void op_adjoint(Problem& P, const T* w, double c_scale, const T* V, int r, int l
 // CG operator Q = gamma P + rho A*(A(P W^T)) W with device scalars in sc;
 // records the CG step length in sc (see cg_update).  t: m-vector scratch.
 template <typename T>
-void op_cg(Problem& P, const T* W, int r, const T* Pd, T* Q, T* t, int parity, hipStream_t s);
+void op_cg(Problem& P, const T* W, int r, int ld, const T* Pd, T* Q, T* t, int parity, hipStream_t s);
+// leading dimension of the CG work buffers: PAIR problems pad rows to a
+// multiple of 64 bytes (zero padding), so every row the CG operator gathers
+// sits in whole, aligned 64-byte sectors; other structures use r
+int cg_ld(const Problem& P, int r, int elem_bytes);
 
 // algorithmic bytes of one application (for throughput accounting)
 double bytes_forward(const Problem& P, int r, int s);
@@ -195,7 +199,7 @@ inline int grid_for(size_t N, int cap = 2048) {
 // CG on M_W D = R from D = X (X holds x0 = 0 normally; R holds R0 - M x0).
 // Buffers dense n x r of type T.  Returns iterations; *relres = ||R||/||R0||.
 template <typename T>
-int cg_run(Problem& P, const T* W, int r, double rho, double gamma, T* R, T* X, T* Pd, T* Q,
-           T* t, double tol, int maxit, hipStream_t s, double* relres, double* op_bytes);
+int cg_run(Problem& P, const T* W, int r, int ld, double rho, double gamma, T* R, T* X, T* Pd,
+           T* Q, T* t, double tol, int maxit, hipStream_t s, double* relres, double* op_bytes);
 
 }  // namespace lorads

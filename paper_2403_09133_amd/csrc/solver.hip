@@ -303,11 +303,16 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
 // ===========================================================================
 // Phase II: ADMM (Algorithm 1) with CG subproblem solves
 // ===========================================================================
+// CG work buffers in the CG layout (leading dimension ld = cg_ld(P, r), zero
+// padding that no kernel writes)
 template <typename T>
 struct CgBufs {
   DevBuf<T> R, X, Pd, Q, W, t;
-  void alloc(size_t N, int m) {
+  int ld = 0;
+  void alloc(size_t N, int m, int ld_, hipStream_t s) {
+    ld = ld_;
     R.alloc(N); X.alloc(N); Pd.alloc(N); Q.alloc(N); W.alloc(N); t.alloc(m);
+    R.zero(s); X.zero(s); Pd.zero(s); Q.zero(s); W.zero(s);
   }
 };
 
@@ -316,24 +321,22 @@ template <typename T>
 static int half_step(Problem& P, const double* W, double* out, int r, double rho, double gamma,
                      double tol, int maxit, CgBufs<T>& B, DevBuf<double>& R64, hipStream_t s,
                      SolveInfo& info) {
-  const size_t N = (size_t)P.n * r;
+  const int ld = B.ld;
+  const size_t N = (size_t)P.n * ld;  // CG layout
   op_forward_w(P, W, W, r, r, P.zbuf.p, P.wbuf.p, P.lam.p, rho, s);
   info.op_bytes += bytes_forward(P, r, 8) + bytes_adjoint(P, r, 8, true);
-  const T* Wt;
   if constexpr (std::is_same<T, double>::value) {
-    op_adjoint<double>(P, P.wbuf.p, 1.0, W, r, r, B.R.p, r, -1.0, s);
-    Wt = W;
+    op_adjoint<double>(P, P.wbuf.p, 1.0, W, r, r, B.R.p, ld, -1.0, s);
   } else {
-    op_adjoint<double>(P, P.wbuf.p, 1.0, W, r, r, R64.p, r, -1.0, s);
+    op_adjoint<double>(P, P.wbuf.p, 1.0, W, r, r, R64.p, ld, -1.0, s);
     convert_kernel<double, float><<<gridN(N), kBlock, 0, s>>>(N, R64.p, B.R.p);
-    convert_kernel<double, float><<<gridN(N), kBlock, 0, s>>>(N, W, B.W.p);
-    Wt = B.W.p;
   }
+  copy_rows<double, T><<<gridN((size_t)P.n * r), kBlock, 0, s>>>(P.n, r, W, r, B.W.p, ld);
   HIPCHK(hipMemsetAsync(B.X.p, 0, N * sizeof(T), s));
   double rel;
-  const int it = cg_run<T>(P, Wt, r, rho, gamma, B.R.p, B.X.p, B.Pd.p, B.Q.p, B.t.p, tol, maxit, s,
-                           &rel, &info.op_bytes);
-  add_kernel<double, T, double><<<gridN(N), kBlock, 0, s>>>(N, W, B.X.p, out);
+  const int it = cg_run<T>(P, B.W.p, r, ld, rho, gamma, B.R.p, B.X.p, B.Pd.p, B.Q.p, B.t.p, tol,
+                           maxit, s, &rel, &info.op_bytes);
+  add_rows<double, T><<<gridN((size_t)P.n * r), kBlock, 0, s>>>(P.n, r, W, r, B.X.p, ld, out);
   HIPCHK(hipGetLastError());
   return it;
 }
@@ -348,9 +351,14 @@ static void phase2_t(Problem& P, const lorads_options& o, double rho, SolveInfo&
   HIPCHK(hipMemcpyAsync(P.V.p, P.U.p, N * sizeof(double), hipMemcpyDeviceToDevice, s));
   DevBuf<double> Vold, R64;
   Vold.alloc(N);
-  if constexpr (!std::is_same<T, double>::value) R64.alloc(N);
+  const int ldc = cg_ld(P, r, (int)sizeof(T));
+  const size_t Nc = (size_t)n * ldc;
+  if constexpr (!std::is_same<T, double>::value) {
+    R64.alloc(Nc);
+    R64.zero(s);
+  }
   CgBufs<T> B;
-  B.alloc(N, m);
+  B.alloc(Nc, m, ldc, s);
   const int maxit = (int)std::min<long long>((long long)N, o.cg_maxit);
   const double floor = (std::is_same<T, double>::value) ? o.cg_tol_floor : std::max(o.cg_tol_floor, 1e-6);
   double kkt = INFINITY, pinf = INFINITY, dres = INFINITY, gamma = gamma_of(P, o, rho);
