@@ -289,7 +289,8 @@ lorads_status lorads_admm_solve(lorads_ctx* ctx, const lorads_options* opt, lora
     if (!ctx || !opt || !res) fail(LORADS_EINVAL, "null argument");
     const lorads_options& o = *opt;
     if (o.precision != LORADS_F64 && o.precision != LORADS_F32) fail(LORADS_EINVAL, "precision");
-    if (!(o.eps > 0) || o.max_admm_iter < 0 || o.lbfgs_mem < 1 || o.rho_every < 1)
+    if (!(o.eps > 0) || o.max_admm_iter < 0 || o.lbfgs_mem < 1 || o.lbfgs_mem > 16 ||
+        o.rho_every < 1)
       fail(LORADS_EINVAL, "invalid options");
     if (!o.init_U) fail(LORADS_EINVAL, "init_U is required (the random start is an input)");
     for (size_t pi = 0; pi < ctx->probs.size(); ++pi) {

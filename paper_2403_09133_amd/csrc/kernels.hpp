@@ -386,6 +386,18 @@ __global__ void __launch_bounds__(kBlock) axpby(size_t N, double a, const TX* __
     y[i] = (TY)(a * (double)x[i] + b * (double)y[i]);
 }
 
+// y = a * x + b * y with a = sc[sa] - sc[sb] (ratio == 0) or sc[sa] / sc[sb]
+// (ratio == 1): device-resident coefficients, same arithmetic as axpby
+template <typename T>
+__global__ void __launch_bounds__(kBlock) axpby_slots(size_t N, const double* __restrict__ sc,
+                                                      int sa, int sb, int ratio,
+                                                      const T* __restrict__ x, double b,
+                                                      T* __restrict__ y) {
+  const double a = ratio ? sc[sa] / sc[sb] : sc[sa] - sc[sb];
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock)
+    y[i] = (T)(a * (double)x[i] + b * (double)y[i]);
+}
+
 // y = a * x + b * y with a = sign * sc[slot] (device-resident coefficient)
 template <typename T>
 __global__ void __launch_bounds__(kBlock) axpby_dev(size_t N, const double* __restrict__ sc,

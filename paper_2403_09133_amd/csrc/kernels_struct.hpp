@@ -50,6 +50,9 @@ __global__ void __launch_bounds__(kBlock) k1_diag(
 // (j, k) of one row j (contiguous in the internal order), keeps U_j, V_j in
 // registers and gathers the partners kUnroll at a time:
 //   z_i = a_i (<U_j, V_k> + <U_k, V_j>).
+// MODE 0 z = scale * A(U V^T); MODE 1 also w = lam + rho (z - b); MODE 2 the
+// CG form; MODE 3 the two maps of the exact line search in one pass with
+// V = D:  z = A(U D^T + D U^T) = 2 A(U D^T),  w = A(D D^T).
 template <typename T, int G, int MODE, int KC = kMaxCols>
 __global__ void __launch_bounds__(kBlock) k1_pair(
     int nchunks, const int* __restrict__ chunk_row, const int* __restrict__ chunk_start,
@@ -78,20 +81,29 @@ __global__ void __launch_bounds__(kBlock) k1_pair(
     int k[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) k[u] = u < cnt ? pk[i + u] : row;
-    A d[kUnroll];
+    A d[kUnroll], d2[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      A s = 0;
+      A s = 0, s2 = 0;
       const int base = k[u] * ld;
 #pragma unroll
       for (int t = 0; t < KC; ++t) {
         const int c = lane + t * G;
-        if (c < r) s += uj[t] * (A)V[base + c] + (A)U[base + c] * vj[t];
+        if (c < r) {
+          const A vk = (A)V[base + c];
+          s += uj[t] * vk + (A)U[base + c] * vj[t];
+          if (MODE == 3) s2 += vj[t] * vk;
+        }
       }
       d[u] = s;
+      d2[u] = s2;
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) d[u] = group_sum<G>(d[u]);
+    if (MODE == 3) {
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) d2[u] = group_sum<G>(d2[u]);
+    }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       // every lane holds the reduced d[u]; lane u mod G stores it
@@ -101,6 +113,10 @@ __global__ void __launch_bounds__(kBlock) k1_pair(
         if (MODE == 1) {
           z[id] = (T)val;
           w[id] = lam[id] + rho * (val - b[id]);
+        } else if (MODE == 3) {
+          const double a = pcoef ? (double)pcoef[id] : pair_coef;
+          z[id] = (T)(2.0 * val);
+          w[id] = 2.0 * a * (double)d2[u];
         } else {
           z[id] = (T)(mult * val);
         }

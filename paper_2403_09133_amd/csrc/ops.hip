@@ -121,6 +121,25 @@ static void op_forward_w_impl(Problem& P, const double* U, const double* V, int 
   HIPCHK(hipGetLastError());
 }
 
+// p1 = A(U D^T + D U^T), p2 = A(D D^T) (FP64): one pass for PAIR, two forward maps otherwise
+void op_forward_pair(Problem& P, const double* U, const double* D, int r, double* p1, double* p2,
+                     hipStream_t s) {
+  if (P.structure != LORADS_STRUCT_PAIR) {
+    op_forward<double>(P, U, D, r, r, p1, 2.0, s);
+    op_forward<double>(P, D, D, r, r, p2, 1.0, s);
+    return;
+  }
+  P.prof.run(1, bytes_forward(P, r, 8) + 8.0 * P.m, s, [&] {
+    check_pair_offsets(P, r);
+    const int G = lane_group(r);
+    LORADS_DISPATCH_GK(G, r, (k1_pair<double, G, 3, KC><<<rows_grid(P.nfchunks, G), kBlock, 0, s>>>(
+                             P.nfchunks, P.fchunk_row.p, P.fchunk_start.p, P.rptr.p, P.pk.p,
+                             P.pcoef.p, P.pair_coef, U, D, r, r, p1, 1.0, nullptr, nullptr, 0.0,
+                             p2, nullptr, 0)));
+    HIPCHK(hipGetLastError());
+  });
+}
+
 template <typename T>
 static void op_adjoint_impl(Problem& P, const T* w, double c_scale, const T* V, int r, int ld,
                             T* out, int ldo, double out_scale, hipStream_t s);

@@ -166,6 +166,9 @@ void op_adjoint(Problem& P, const T* w, double c_scale, const T* V, int r, int l
 // records the CG step length in sc (see cg_update).  t: m-vector scratch.
 template <typename T>
 void op_cg(Problem& P, const T* W, int r, int ld, const T* Pd, T* Q, T* t, int parity, hipStream_t s);
+// p1 = A(U D^T + D U^T) and p2 = A(D D^T) in FP64 (the exact line search)
+void op_forward_pair(Problem& P, const double* U, const double* D, int r, double* p1, double* p2,
+                     hipStream_t s);
 // leading dimension of the CG work buffers: PAIR problems pad rows to a
 // multiple of 64 bytes (zero padding), so every row the CG operator gathers
 // sits in whole, aligned 64-byte sectors; other structures use r

@@ -155,12 +155,13 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
     // ---------------- inner L-BFGS ----------------
     A.head = A.count = 0;
     alm_gradient(P, A, U, A.G.p, rho, s, info.op_bytes);
+    dot_to_slot<double, double>(P, N, A.G.p, A.G.p, 1.0, S_GEN, s);
+    read_slots(P, S_GEN, h, 1, s);
+    double gnorm2 = h[0];  // ||G||^2 of the current gradient
     int it = 0;
     bool conv = false;
     while (true) {
-      dot_to_slot<double, double>(P, N, A.G.p, A.G.p, 1.0, S_GEN, s);
-      read_slots(P, S_GEN, h, 1, s);
-      const double gnorm = std::sqrt(h[0]);
+      const double gnorm = std::sqrt(gnorm2);
       if (!std::isfinite(gnorm)) fail(LORADS_ENUMERIC, "non-finite gradient in phase I");
       if (gnorm / (1.0 + c_fro) <= tol) { conv = true; break; }
       if (it >= cap) break;
@@ -175,41 +176,46 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
         axpby_dev<double><<<gridN(N), kBlock, 0, s>>>(N, P.sc.p, S_GEN + 16 + (int)t, -1.0,
                                                       A.Y[k].p, 1.0, A.Q.p);
       }
+      // the scalars of the recursion stay on the device (no host round trip)
       if (A.count > 0) {
         const int k = order[0];
+        // q *= <S_k, Y_k> / <Y_k, Y_k>
         dot_to_slot<double, double>(P, N, A.S[k].p, A.Y[k].p, 1.0, S_GEN + 1, s);
         dot_to_slot<double, double>(P, N, A.Y[k].p, A.Y[k].p, 1.0, S_GEN + 2, s);
-        read_slots(P, S_GEN + 1, h, 2, s);
-        axpby<double, double><<<gridN(N), kBlock, 0, s>>>(N, 0.0, A.Q.p, h[0] / h[1], A.Q.p);
+        axpby_slots<double><<<gridN(N), kBlock, 0, s>>>(N, P.sc.p, S_GEN + 1, S_GEN + 2, 1, A.Q.p,
+                                                       0.0, A.Q.p);
       }
       for (int t = (int)order.size() - 1; t >= 0; --t) {
         const int k = order[t];
         // beta = rho_k <Y_k, q>;  q += (alpha_t - beta) S_k
         dot_to_slot<double, double>(P, N, A.Y[k].p, A.Q.p, A.rhoh[k], S_GEN + 6, s);
-        read_slots(P, S_GEN + 6, h, 1, s);
-        double al;
-        read_slots(P, S_GEN + 16 + t, &al, 1, s);
-        axpby<double, double><<<gridN(N), kBlock, 0, s>>>(N, al - h[0], A.S[k].p, 1.0, A.Q.p);
+        axpby_slots<double><<<gridN(N), kBlock, 0, s>>>(N, P.sc.p, S_GEN + 16 + t, S_GEN + 6, 0,
+                                                       A.S[k].p, 1.0, A.Q.p);
       }
-      // D = -q ; descent check
+      // D = -q.  The line search below also returns <G, D>: a direction that is
+      // not a descent direction is replaced by -G (memory cleared) and the
+      // search repeated, as is a quasi-Newton step whose exact minimiser is not
+      // positive.  One host read per search.
       axpby<double, double><<<gridN(N), kBlock, 0, s>>>(N, -1.0, A.Q.p, 0.0, A.D.p);
-      dot_to_slot<double, double>(P, N, A.G.p, A.D.p, 1.0, S_GEN, s);
-      read_slots(P, S_GEN, h, 1, s);
-      if (!(h[0] < 0.0)) {
-        axpby<double, double><<<gridN(N), kBlock, 0, s>>>(N, -1.0, A.G.p, 0.0, A.D.p);
-        A.head = A.count = 0;
-      }
-      // exact line search coefficients
       double alpha = 0.0;
-      for (int attempt = 0; attempt < 2; ++attempt) {
-        op_forward<double>(P, U, A.D.p, r, r, A.p1.p, 2.0, s);
-        op_forward<double>(P, A.D.p, A.D.p, r, r, A.p2.p, 1.0, s);
+      bool checked = false;
+      for (int attempt = 0; attempt < 3; ++attempt) {
+        op_forward_pair(P, U, A.D.p, r, A.p1.p, A.p2.p, s);
         op_adjoint<double>(P, (const double*)nullptr, 1.0, A.D.p, r, r, A.CD.p, r, 1.0, s);
         info.op_bytes += 2 * bytes_forward(P, r, 8) + bytes_adjoint(P, r, 8, true);
         dot_to_slot<double, double>(P, N, A.CD.p, U, 2.0, S_GEN + 1, s);
         dot_to_slot<double, double>(P, N, A.CD.p, A.D.p, 1.0, S_GEN + 2, s);
         linesearch_slots(P, P.zbuf.p, A.p1.p, A.p2.p, P.lam.p, S_GEN + 3, s);
-        read_slots(P, S_GEN + 1, h, 9, s);
+        if (!checked) dot_to_slot<double, double>(P, N, A.G.p, A.D.p, 1.0, S_GEN + 10, s);
+        read_slots(P, S_GEN + 1, h, checked ? 9 : 10, s);
+        if (!checked) {
+          checked = true;
+          if (!(h[9] < 0.0)) {
+            axpby<double, double><<<gridN(N), kBlock, 0, s>>>(N, -1.0, A.G.p, 0.0, A.D.p);
+            A.head = A.count = 0;
+            continue;
+          }
+        }
         const double c1 = h[0], c2 = h[1];
         const double p22 = h[2], p12 = h[3], p11 = h[4], p02 = h[5], p01 = h[6], l1 = h[7],
                      l2 = h[8];
@@ -232,7 +238,9 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
       axpby<double, double><<<gridN(N), kBlock, 0, s>>>(N, 1.0, A.Gn.p, 0.0, A.Yn.p);
       axpby<double, double><<<gridN(N), kBlock, 0, s>>>(N, -1.0, A.G.p, 1.0, A.Yn.p);
       dot_to_slot<double, double>(P, N, A.Sn.p, A.Yn.p, 1.0, S_GEN, s);
-      read_slots(P, S_GEN, h, 1, s);
+      dot_to_slot<double, double>(P, N, A.Gn.p, A.Gn.p, 1.0, S_GEN + 1, s);
+      read_slots(P, S_GEN, h, 2, s);
+      gnorm2 = h[1];
       if (h[0] > 0.0) {
         const int slot = A.head;
         std::swap(A.S[slot], A.Sn);
