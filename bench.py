@@ -35,6 +35,42 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# sources that determine the operator kernels; hardware-counter traffic recorded
+# under profiles/ applies only while their hash is unchanged
+KERNEL_SOURCES = ["paper_2403_09133_amd/csrc/kernels_struct.hpp", "paper_2403_09133_amd/csrc/kernels.hpp",
+                  "paper_2403_09133_amd/csrc/ops.hip", "paper_2403_09133_amd/csrc/common.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+
+
+def kernel_sources_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(symbol: str):
+    """HBM bytes per launch of `symbol` from the recorded FETCH_SIZE / WRITE_SIZE
+    passes (already scaled by the copy-kernel calibration), or None when no
+    record exists or the kernel sources changed since it was taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        rec = json.load(fh)
+    if rec.get("sources_sha256") != kernel_sources_hash():
+        return None
+    ent = rec.get("kernels", {}).get(symbol)
+    return None if ent is None else int(round(ent["hbm_bytes_per_launch"]))
+# kernel classes timed by the library (lorads_result.prof_*), with the kernel
+# each one runs on the completion workload
+KERNEL_CLASSES = {
+    "fused CG operator": "kpair_rows<float, 16, 1, 1>",
+    "forward map A(UV^T)": "k1_pair<double, 16, 0|1, 1>",
+    "adjoint (C + A*(w))V": "kpair_rows<double, 16, 0, 1>",
+    "line-search maps A(UD^T+DU^T), A(DD^T)": "k1_pair<double, 16, 3, 1>",
+}
 WORKLOADS = {
     # name -> (generator key, precision code, description)
     "mc_10000": ("mc_10000", 1, "matrix completion 10000x10000, rank 5, |Omega|=4605170, X of order 20000"),
@@ -228,21 +264,23 @@ def main():
     value = op_bytes / wall / 1e9
 
     # dominant kernel over the timed steps (live HIP-event timings)
-    names = ["fused CG operator", "forward map A(UV^T)", "adjoint (C + A*(w))V"]
-    ms = [sum(r["prof_ms"][k] for r in results) for k in range(3)]
-    launches = [sum(r["prof_launches"][k] for r in results) for k in range(3)]
-    kbytes = [sum(r["prof_bytes"][k] for r in results) for k in range(3)]
+    names = list(KERNEL_CLASSES)
+    K = len(names)
+    ms = [sum(r["prof_ms"][k] for r in results) for k in range(K)]
+    launches = [sum(r["prof_launches"][k] for r in results) for k in range(K)]
+    kbytes = [sum(r["prof_bytes"][k] for r in results) for k in range(K)]
     dom = int(np.argmax(ms))
     achieved = kbytes[dom] / (ms[dom] * 1e-3) / 1e9 if ms[dom] > 0 else 0.0
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                    kernel=names[dom], launches=int(launches[dom]),
+                    frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=recorded_traffic(KERNEL_CLASSES[names[dom]]),
+                    kernel=names[dom], symbol=KERNEL_CLASSES[names[dom]], launches=int(launches[dom]),
                     mean_launch_us=round(ms[dom] * 1e3 / max(1, launches[dom]), 2),
                     bytes_per_launch=round(kbytes[dom] / max(1, launches[dom])))
     kernels = {names[k]: dict(launches=int(launches[k]), total_ms=round(ms[k], 3),
                               mean_us=round(ms[k] * 1e3 / max(1, launches[k]), 2),
                               gbs=round(kbytes[k] / (ms[k] * 1e-3) / 1e9, 1) if ms[k] > 0 else None)
-               for k in range(3)}
+               for k in range(K)}
 
     last = results[-1]
     extra = dict(

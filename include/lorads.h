@@ -164,11 +164,12 @@ typedef struct {
   double op_bytes;         /* algorithmic bytes of every A(.) / A*(.)V / CG
                               operator application of the solve */
   /* with options.profile: per kernel class (0 fused CG operator, 1 forward map,
-     2 adjoint product) the summed launch time in ms measured by HIP events on
-     the solver's stream, the number of launches and their algorithmic bytes */
-  double prof_ms[3];
-  double prof_bytes[3];
-  int64_t prof_launches[3];
+     2 adjoint product, 3 the warm start's line-search pair of maps) the summed
+     launch time in ms measured by HIP events on the solver's stream, the number
+     of launches and their algorithmic bytes */
+  double prof_ms[4];
+  double prof_bytes[4];
+  int64_t prof_launches[4];
   int32_t warm_fallback;   /* 1 when options.warm_check restarted Phase I cold */
 } lorads_result;
 

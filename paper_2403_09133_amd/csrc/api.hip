@@ -357,7 +357,7 @@ lorads_status lorads_admm_solve(lorads_ctx* ctx, const lorads_options* opt, lora
       const auto t2 = std::chrono::steady_clock::now();
       P.prof.resolve_all();
       P.prof.on = false;
-      for (int k = 0; k < 3; ++k) {
+      for (int k = 0; k < kProfKinds; ++k) {
         R.prof_ms[k] = P.prof.ms[k];
         R.prof_bytes[k] = P.prof.bytes[k];
         R.prof_launches[k] = P.prof.count[k];

@@ -129,7 +129,7 @@ void op_forward_pair(Problem& P, const double* U, const double* D, int r, double
     op_forward<double>(P, D, D, r, r, p2, 1.0, s);
     return;
   }
-  P.prof.run(1, bytes_forward(P, r, 8) + 8.0 * P.m, s, [&] {
+  P.prof.run(3, bytes_forward(P, r, 8) + 8.0 * P.m, s, [&] {
     check_pair_offsets(P, r);
     const int G = lane_group(r);
     LORADS_DISPATCH_GK(G, r, (k1_pair<double, G, 3, KC><<<rows_grid(P.nfchunks, G), kBlock, 0, s>>>(
@@ -183,17 +183,18 @@ int cg_ld(const Problem& P, int r, int elem_bytes) {
 }
 
 template <typename T>
-void op_cg(Problem& P, const T* W, int r, int ld, const T* Pd, T* Q, T* t, int parity, hipStream_t s) {
+int op_cg(Problem& P, const T* W, int r, int ld, const T* Pd, T* Q, T* t, int parity, hipStream_t s) {
   const int G = lane_group(r);
   if (r > 4 * G) fail(LORADS_EINVAL, "rank above 256 is not supported");
   double* sc = P.sc.p;
+  int np = 0;  // block partials of <P, Q> written to P.part
   if (P.structure != LORADS_STRUCT_PAIR && ld != r) fail(LORADS_EINVAL, "CG buffers must be compact");
   if (P.structure == LORADS_STRUCT_DIAG) {
     const int grid = rows_grid(P.n, G);
     P.ensure_part(grid);
     LORADS_DISPATCH_G(G, (k3_diag<T, G><<<grid, kBlock, 0, s>>>(
                              P.n, ds<T>(P), W, Pd, Q, r, sc, parity, P.part.p)));
-    cg_alpha_finish<<<1, kBlock, 0, s>>>(grid, P.part.p, sc, parity);
+    np = grid;
   } else if (P.structure == LORADS_STRUCT_PAIR) {
     check_pair_offsets(P, ld);
     const int grid = waves_grid(P.n);
@@ -203,7 +204,7 @@ void op_cg(Problem& P, const T* W, int r, int ld, const T* Pd, T* Q, T* t, int p
                              P.n, nullptr, nullptr, nullptr, 0.0, P.inc_ptr.p, P.inc_nb.p,
                              P.inc_id.p, pc<T>(P), P.pair_coef, nullptr, W, Pd, r, ld, Q, ld,
                              1.0, sc, parity, P.part.p)));
-    cg_alpha_finish<<<1, kBlock, 0, s>>>(grid, P.part.p, sc, parity);
+    np = grid;
   } else {
     LORADS_DISPATCH_G(G, (k1_generic<T, G, 2><<<rows_grid(P.m, G), kBlock, 0, s>>>(
                              P.m, P.kptr.p, P.krow.p, P.kcol.p, kv<T>(P), Pd, W, r, r, t, 1.0,
@@ -213,9 +214,10 @@ void op_cg(Problem& P, const T* W, int r, int ld, const T* Pd, T* Q, T* t, int p
     LORADS_DISPATCH_G(G, (k2_generic<T, G, 1><<<grid, kBlock, 0, s>>>(
                              P.n, nullptr, nullptr, nullptr, 0.0, P.aptr.p, P.acol.p, P.acon.p,
                              av<T>(P), t, W, r, r, Q, r, 1.0, Pd, sc, parity, P.part.p)));
-    cg_alpha_finish<<<1, kBlock, 0, s>>>(grid, P.part.p, sc, parity);
+    np = grid;
   }
   HIPCHK(hipGetLastError());
+  return np;
 }
 
 // ---------------------------------------------------------------------------
@@ -322,7 +324,9 @@ int cg_run(Problem& P, const T* W, int r, int ld, double rho, double gamma, T* R
     const int iters_before = iters;
     for (int i = 0; i < steps; ++i, ++k) {
       const int par = k & 1;
-      P.prof.run(0, bytes_cg_op(P, r, sizeof(T)), s, [&] { op_cg<T>(P, W, r, ld, Pd, Q, t, par, s); });
+      int np = 0;
+      P.prof.run(0, bytes_cg_op(P, r, sizeof(T)), s, [&] { np = op_cg<T>(P, W, r, ld, Pd, Q, t, par, s); });
+      cg_alpha_finish<<<1, kBlock, 0, s>>>(np, P.part.p, P.sc.p, par);
       cg_update<T><<<gridv, kBlock, 0, s>>>(N, X, R, Pd, Q, P.sc.p, par, P.part.p);
       cg_update_finish<<<1, kBlock, 0, s>>>(gridv, P.part.p, P.sc.p, par);
       cg_direction<T><<<gridv, kBlock, 0, s>>>(N, R, Pd, P.sc.p, par);
@@ -347,8 +351,8 @@ template void op_forward<double>(Problem&, const double*, const double*, int, in
 template void op_forward<float>(Problem&, const float*, const float*, int, int, float*, double, hipStream_t);
 template void op_adjoint<double>(Problem&, const double*, double, const double*, int, int, double*, int, double, hipStream_t);
 template void op_adjoint<float>(Problem&, const float*, double, const float*, int, int, float*, int, double, hipStream_t);
-template void op_cg<double>(Problem&, const double*, int, int, const double*, double*, double*, int, hipStream_t);
-template void op_cg<float>(Problem&, const float*, int, int, const float*, float*, float*, int, hipStream_t);
+template int op_cg<double>(Problem&, const double*, int, int, const double*, double*, double*, int, hipStream_t);
+template int op_cg<float>(Problem&, const float*, int, int, const float*, float*, float*, int, hipStream_t);
 template void dot_to_slot<double, double>(Problem&, size_t, const double*, const double*, double, int, hipStream_t);
 template void dot_to_slot<float, float>(Problem&, size_t, const float*, const float*, double, int, hipStream_t);
 template int cg_run<double>(Problem&, const double*, int, int, double, double, double*, double*, double*, double*, double*, double, int, hipStream_t, double*, double*);

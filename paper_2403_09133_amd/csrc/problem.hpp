@@ -11,13 +11,16 @@ namespace lorads {
 // the kernels run on.  Kinds: 0 CG operator, 1 forward map, 2 adjoint product.
 // Pairs are resolved at the solver's existing synchronisation points; CG
 // launches that the device skipped after convergence are not counted.
+// kernel classes: 0 CG operator, 1 forward map, 2 adjoint product,
+// 3 the warm start's line-search pair A(U D^T + D U^T), A(D D^T)
+constexpr int kProfKinds = 4;
 struct KernelProfile {
   bool on = false;
   struct Pair { hipEvent_t a, b; double bytes; };
   std::vector<hipEvent_t> all, free_;
-  std::vector<Pair> pending[3];
-  double ms[3] = {0, 0, 0}, bytes[3] = {0, 0, 0};
-  long long count[3] = {0, 0, 0};
+  std::vector<Pair> pending[kProfKinds];
+  double ms[kProfKinds] = {0, 0, 0, 0}, bytes[kProfKinds] = {0, 0, 0, 0};
+  long long count[kProfKinds] = {0, 0, 0, 0};
 
   hipEvent_t get() {
     if (free_.empty()) {
@@ -55,10 +58,10 @@ struct KernelProfile {
     v.clear();
   }
   void resolve_all() {
-    for (int k = 0; k < 3; ++k) resolve(k);
+    for (int k = 0; k < kProfKinds; ++k) resolve(k);
   }
   void reset() {
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < kProfKinds; ++k) {
       for (auto& pr : pending[k]) { free_.push_back(pr.a); free_.push_back(pr.b); }
       pending[k].clear();
       ms[k] = bytes[k] = 0;
@@ -165,7 +168,8 @@ void op_adjoint(Problem& P, const T* w, double c_scale, const T* V, int r, int l
 // CG operator Q = gamma P + rho A*(A(P W^T)) W with device scalars in sc;
 // records the CG step length in sc (see cg_update).  t: m-vector scratch.
 template <typename T>
-void op_cg(Problem& P, const T* W, int r, int ld, const T* Pd, T* Q, T* t, int parity, hipStream_t s);
+// Q = M_W(Pd) (+ block partials of <Pd, Q> in P.part; returns their count)
+int op_cg(Problem& P, const T* W, int r, int ld, const T* Pd, T* Q, T* t, int parity, hipStream_t s);
 // p1 = A(U D^T + D U^T) and p2 = A(D D^T) in FP64 (the exact line search)
 void op_forward_pair(Problem& P, const double* U, const double* D, int r, double* p1, double* p2,
                      hipStream_t s);

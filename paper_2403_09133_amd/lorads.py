@@ -65,7 +65,7 @@ class Result_(C.Structure):
         ("pinf_stop", C.c_double), ("dres_stop", C.c_double), ("rho", C.c_double),
         ("gamma", C.c_double), ("t_phase1", C.c_double), ("t_phase2", C.c_double),
         ("t_metrics", C.c_double), ("t_total", C.c_double), ("op_bytes", C.c_double),
-        ("prof_ms", C.c_double * 3), ("prof_bytes", C.c_double * 3), ("prof_launches", C.c_int64 * 3),
+        ("prof_ms", C.c_double * 4), ("prof_bytes", C.c_double * 4), ("prof_launches", C.c_int64 * 4),
         ("warm_fallback", C.c_int32),
     ]
 
