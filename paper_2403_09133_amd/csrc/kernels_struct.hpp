@@ -61,9 +61,16 @@ __global__ void __launch_bounds__(kBlock) k1_pair(
     T* __restrict__ z, double scale, const double* __restrict__ lam,
     const double* __restrict__ b, double rho, double* __restrict__ w,
     const double* __restrict__ sc, int parity) {
+  // results of a chunk are collected in the group's LDS slots and written as
+  // contiguous runs at the end (groups of at least 4 lanes)
+  constexpr bool kStage = G >= 4;
+  constexpr bool kTwo = (MODE == 1 || MODE == 3);
+  __shared__ T sz[kStage ? (kBlock / G) * kPairChunk : 1];
+  __shared__ double sw[(kStage && kTwo) ? (kBlock / G) * kPairChunk : 1];
   if (MODE == 2 && sc[S_DONE + parity] != 0.0) return;
   const int chunk = (blockIdx.x * kBlock + threadIdx.x) / G;
   const int lane = threadIdx.x & (G - 1);
+  const int gslot = (threadIdx.x / G) * kPairChunk;
   if (chunk >= nchunks) return;
   const int row = chunk_row[chunk];
   const int i0 = chunk_start[chunk], i1 = min(i0 + kPairChunk, rptr[row + 1]);
@@ -110,17 +117,35 @@ __global__ void __launch_bounds__(kBlock) k1_pair(
       if (lane == (u & (G - 1)) && u < cnt) {
         const int id = i + u;
         const double val = (double)d[u] * (pcoef ? (double)pcoef[id] : pair_coef);
+        T zv;
+        double wv = 0.0;
         if (MODE == 1) {
-          z[id] = (T)val;
-          w[id] = lam[id] + rho * (val - b[id]);
+          zv = (T)val;
+          wv = lam[id] + rho * (val - b[id]);
         } else if (MODE == 3) {
           const double a = pcoef ? (double)pcoef[id] : pair_coef;
-          z[id] = (T)(2.0 * val);
-          w[id] = 2.0 * a * (double)d2[u];
+          zv = (T)(2.0 * val);
+          wv = 2.0 * a * (double)d2[u];
         } else {
-          z[id] = (T)(mult * val);
+          zv = (T)(mult * val);
+        }
+        if (kStage) {
+          sz[gslot + (id - i0)] = zv;
+          if (kTwo) sw[gslot + (id - i0)] = wv;
+        } else {
+          z[id] = zv;
+          if (kTwo) w[id] = wv;
         }
       }
+    }
+  }
+  if (kStage) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int q = lane; q < i1 - i0; q += G) {
+      z[i0 + q] = sz[gslot + q];
+      if (kTwo) w[i0 + q] = sw[gslot + q];
     }
   }
 }
