@@ -172,6 +172,45 @@ def batch_leg(count: int = 512, sample: int = 16):
     return out
 
 
+def learned_leg(count: int = 6):
+    """Learned warm start (the shipped MaxCut network) against the cold start on
+    `count` held-out graphs shaped like its training set (n ~ U{2000..5000},
+    average degree ~ U[4, 16], +-1 weights), FP64 solves to eq. (stop) <= 1e-6
+    from the same random U0: mean time-to-KKT, ADMM iterations and the App. B gap."""
+    from paper_2403_09133_amd import Context, warmstart as W
+    from paper_2403_09133_amd.params import solver_options
+    ws = W.WarmStart.load()
+    probs = W.instances(count, W.HELDOUT_SEED0 + 500)
+    t = time.perf_counter()
+    preds = ws.predict(probs)
+    t_pred = time.perf_counter() - t
+    rows = []
+    for p, pr in zip(probs, preds):
+        r0 = W.rule_rank(p.n)
+        U0 = W.random_start(p, r0)
+        with Context(p) as ctx:
+            cold = ctx.admm_solve([U0], solver_options("maxcut", p.n, r0))[0]
+            warm = ctx.admm_solve([U0], solver_options("maxcut", p.n, r0),
+                                  init_lambda=[pr["lambda0"]])[0]
+        rows.append((cold, warm))
+        print(f"[bench] learned leg n={p.n}: cold {cold['t_total']:.2f}s {cold['admm_iters']} it, "
+              f"learned {warm['t_total']:.2f}s {warm['admm_iters']} it", file=sys.stderr, flush=True)
+    mean = lambda k, i: float(np.mean([r[i][k] for r in rows]))
+    col = lambda k, i: [r[i][k] for r in rows]
+    return dict(instances=count, predict_s=round(t_pred, 3),
+                cold_admm=col("admm_iters", 0), learned_admm=col("admm_iters", 1),
+                cold_gap=[float(f"{g:.2e}") for g in col("gap", 0)],
+                learned_gap=[float(f"{g:.2e}") for g in col("gap", 1)],
+                caution="a solve that meets eq. (stop) after very few ADMM iterations at a large rho can be "
+                        "off by its App. B gap (listed); compare times only together with the gaps",
+                cold_mean_s=round(mean("t_total", 0), 3), learned_mean_s=round(mean("t_total", 1), 3),
+                cold_mean_admm=mean("admm_iters", 0), learned_mean_admm=mean("admm_iters", 1),
+                cold_converged=int(sum(r[0]["status"] == 0 for r in rows)),
+                learned_converged=int(sum(r[1]["status"] == 0 for r in rows)),
+                max_gap=float(max(max(abs(r[0]["gap"]), abs(r[1]["gap"])) for r in rows)),
+                note="held-out evaluation over 48 graphs: profiles/warmstart_maxcut_c5a_eval.md")
+
+
 def ops_profile(key: str, reps: int):
     """Operator calls only: REPS x (forward map, adjoint product, 20-iteration CG
     solve) in FP32 at r0 columns, then one 256 MiB device-to-device copy whose
@@ -212,6 +251,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solve")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form leg")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-warm-start leg")
     ap.add_argument("--ops-profile", type=int, default=0, metavar="REPS",
                     help="only run REPS applications of each operator at the workload's size (FP32, "
                          "r0 columns) and a 256 MiB device copy, for hardware-counter runs")
@@ -292,9 +332,14 @@ def main():
         kernels=kernels, setup_s=round(t_setup, 3),
     )
     if p.kind == "mc":
-        from paper_2403_09133_amd.report import completion_recovery_error
+        from paper_2403_09133_amd.report import (completion_recovery_error,
+                                                 completion_recovery_error_sampled)
         U, V, lam = ctx.get_solution(0, last["rank"])
-        extra["mc_recovery_error"] = completion_recovery_error(0.5 * (U + V), p.meta["L"], p.meta["R"])
+        Uh = 0.5 * (U + V)
+        extra["mc_recovery_error"] = dict(
+            gram_identity=completion_recovery_error(Uh, p.meta["L"], p.meta["R"]),
+            sampled_1e6_cells=completion_recovery_error_sampled(Uh, p.meta["L"], p.meta["R"]),
+            note="||U1 U2^T - M||_F / ||M||_F; the Gram identity resolves about 1e-8, the sample is exact per cell")
     if not args.no_fp64:
         t = time.perf_counter()
         r64 = ctx.admm_solve([U0], lib_options(p, r0, 0))[0]
@@ -324,6 +369,10 @@ def main():
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p, r0)
     line.update(extra)
+    if not args.no_learned:
+        line["learned_warm_start"] = learned_leg()
+        line["time_to_kkt_s"]["learned_fp64_mean"] = line["learned_warm_start"]["learned_mean_s"]
+        line["time_to_kkt_s"]["cold_fp64_mean_same_instances"] = line["learned_warm_start"]["cold_mean_s"]
     if not args.no_batch:
         line["batched_maxcut"] = batch_leg()
         line["time_to_kkt_s"]["batched_512_fp64"] = line["batched_maxcut"]["fp64"]["s"]
