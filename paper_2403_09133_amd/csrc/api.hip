@@ -228,11 +228,15 @@ void cg_api(Problem& P, const T* W, double rho, double gamma, const T* R, T* X, 
   // internal buffers in the CG layout (zero padding beyond column r)
   const int ldp = cg_ld(P, r, (int)sizeof(T));
   const size_t N = (size_t)P.n * ldp;
+  // PAIR: W and a copy of the direction share rows (stride 2 ldp)
+  const bool inter = P.structure == LORADS_STRUCT_PAIR;
+  const int ldw = inter ? 2 * ldp : ldp;
   DevBuf<T> Wd, Rd, Xd, Pd, Qd, td;
-  Wd.alloc(N); Rd.alloc(N); Xd.alloc(N); Pd.alloc(N); Qd.alloc(N); td.alloc(P.m);
+  Wd.alloc((size_t)P.n * ldw); Rd.alloc(N); Xd.alloc(N); Pd.alloc(N); Qd.alloc(N); td.alloc(P.m);
   Wd.zero(s); Rd.zero(s); Xd.zero(s); Pd.zero(s); Qd.zero(s);
+  T* P2 = inter ? Wd.p + ldp : nullptr;
   const int g = grid_for(N);
-  copy_rows<T, T><<<g, kBlock, 0, s>>>(P.n, r, W, ld, Wd.p, ldp);
+  copy_rows<T, T><<<g, kBlock, 0, s>>>(P.n, r, W, ld, Wd.p, ldw);
   copy_rows<T, T><<<g, kBlock, 0, s>>>(P.n, r, R, ld, Rd.p, ldp);
   copy_rows<T, T><<<g, kBlock, 0, s>>>(P.n, r, X, ld, Xd.p, ldp);
   // R <- R - M x0 (one operator application with the flags cleared)
@@ -241,11 +245,12 @@ void cg_api(Problem& P, const T* W, double rho, double gamma, const T* R, T* X, 
   const double flags[2] = {0.0, 0.0};
   set_slots(P, S_DONE, flags, 2, s);
   set_slots(P, S_RR, flags, 2, s);
-  op_cg<T>(P, Wd.p, r, ldp, Xd.p, Qd.p, td.p, 0, s);
+  if (P2) copy_rows<T, T><<<g, kBlock, 0, s>>>(P.n, r, Xd.p, ldp, P2, ldw);
+  op_cg<T>(P, Wd.p, ldw, r, ldp, Xd.p, P2, Qd.p, td.p, 0, s);
   axpby<T, T><<<g, kBlock, 0, s>>>(N, -1.0, Qd.p, 1.0, Rd.p);
   double rel = 0.0;
-  const int it = cg_run<T>(P, Wd.p, r, ldp, rho, gamma, Rd.p, Xd.p, Pd.p, Qd.p, td.p, tol, maxit,
-                           s, &rel, nullptr);
+  const int it = cg_run<T>(P, Wd.p, ldw, r, ldp, rho, gamma, Rd.p, Xd.p, Pd.p, P2, Qd.p, td.p, tol,
+                           maxit, s, &rel, nullptr);
   copy_rows<T, T><<<g, kBlock, 0, s>>>(P.n, r, Xd.p, ldp, X, ld);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));

@@ -242,12 +242,15 @@ __global__ void __launch_bounds__(kBlock) k2_generic(
 // P = R, ||R||^2 -> S_RR0, S_RR(parity 0); clears the flags.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) cg_init(size_t N, const T* __restrict__ R,
-                                                  T* __restrict__ P, double* __restrict__ part) {
+                                                  T* __restrict__ P, double* __restrict__ part,
+                                                  T* __restrict__ P2, int ld) {
+  // P2 (optional): second copy of P in rows of stride 2 ld (interleaved with W)
   __shared__ double sh[kBlock / 64];
   double s = 0.0;
   for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock) {
     const T v = R[i];
     P[i] = v;
+    if (P2) P2[(i / ld) * 2 * ld + i % ld] = v;
     s += (double)v * (double)v;
   }
   publish_partial(block_sum(s, sh), part);
@@ -318,11 +321,14 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock) cg_direction(size_t N, const T* __restrict__ R,
                                                        T* __restrict__ P,
                                                        const double* __restrict__ sc,
-                                                       int parity) {
+                                                       int parity, T* __restrict__ P2, int ld) {
   if (sc[S_DONE + parity] != 0.0 || sc[S_BRK] != 0.0) return;
   const double beta = sc[S_BETA];
-  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock)
-    P[i] = (T)((double)R[i] + beta * (double)P[i]);
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock) {
+    const T v = (T)((double)R[i] + beta * (double)P[i]);
+    P[i] = v;
+    if (P2) P2[(i / ld) * 2 * ld + i % ld] = v;
+  }
 }
 
 // ===========================================================================

@@ -183,12 +183,14 @@ int cg_ld(const Problem& P, int r, int elem_bytes) {
 }
 
 template <typename T>
-int op_cg(Problem& P, const T* W, int r, int ld, const T* Pd, T* Q, T* t, int parity, hipStream_t s) {
+int op_cg(Problem& P, const T* W, int ldw, int r, int ld, const T* Pd, const T* P2, T* Q, T* t,
+          int parity, hipStream_t s) {
   const int G = lane_group(r);
   if (r > 4 * G) fail(LORADS_EINVAL, "rank above 256 is not supported");
   double* sc = P.sc.p;
   int np = 0;  // block partials of <P, Q> written to P.part
-  if (P.structure != LORADS_STRUCT_PAIR && ld != r) fail(LORADS_EINVAL, "CG buffers must be compact");
+  if (P.structure != LORADS_STRUCT_PAIR && (ld != r || ldw != r || P2))
+    fail(LORADS_EINVAL, "CG buffers must be compact");
   if (P.structure == LORADS_STRUCT_DIAG) {
     const int grid = rows_grid(P.n, G);
     P.ensure_part(grid);
@@ -196,13 +198,16 @@ int op_cg(Problem& P, const T* W, int r, int ld, const T* Pd, T* Q, T* t, int pa
                              P.n, ds<T>(P), W, Pd, Q, r, sc, parity, P.part.p)));
     np = grid;
   } else if (P.structure == LORADS_STRUCT_PAIR) {
-    check_pair_offsets(P, ld);
+    // one wave per row over its incident constraints, G lanes per constraint.
+    // With P2 the direction is read from its copy interleaved with W (row p:
+    // [W_p | P_p], stride ldw = 2 ld), so one gathered line holds both rows.
+    const T* Pg = P2 ? P2 : Pd;
+    check_pair_offsets(P, ldw);
     const int grid = waves_grid(P.n);
     P.ensure_part(grid);
-    // one wave per row over its incident constraints, G lanes per constraint
     LORADS_DISPATCH_GK(G, r, (kpair_rows<T, G, 1, KC><<<grid, kBlock, 0, s>>>(
                              P.n, nullptr, nullptr, nullptr, 0.0, P.inc_ptr.p, P.inc_nb.p,
-                             P.inc_id.p, pc<T>(P), P.pair_coef, nullptr, W, Pd, r, ld, Q, ld,
+                             P.inc_id.p, pc<T>(P), P.pair_coef, nullptr, W, Pg, r, ldw, Q, ld,
                              1.0, sc, parity, P.part.p)));
     np = grid;
   } else {
@@ -304,13 +309,14 @@ void linesearch_slots(Problem& P, const double* z, const double* p1, const doubl
 // device-resident iterations; after each chunk one flag is read back.
 // ---------------------------------------------------------------------------
 template <typename T>
-int cg_run(Problem& P, const T* W, int r, int ld, double rho, double gamma, T* R, T* X, T* Pd,
-           T* Q, T* t, double tol, int maxit, hipStream_t s, double* relres, double* op_bytes) {
+int cg_run(Problem& P, const T* W, int ldw, int r, int ld, double rho, double gamma, T* R, T* X,
+           T* Pd, T* P2, T* Q, T* t, double tol, int maxit, hipStream_t s, double* relres,
+           double* op_bytes) {
   const size_t N = (size_t)P.n * ld;  // padding entries are zero and stay zero
   const double sv[2] = {gamma, rho};
   set_slots(P, S_GAMMA, sv, 2, s);
   const int gridv = grid_for(N, 1024);
-  cg_init<T><<<gridv, kBlock, 0, s>>>(N, R, Pd, P.part.p);
+  cg_init<T><<<gridv, kBlock, 0, s>>>(N, R, Pd, P.part.p, P2, ld);
   cg_init_finish<<<1, kBlock, 0, s>>>(gridv, P.part.p, tol * tol, P.sc.p);
   HIPCHK(hipGetLastError());
   int k = 0;
@@ -325,11 +331,11 @@ int cg_run(Problem& P, const T* W, int r, int ld, double rho, double gamma, T* R
     for (int i = 0; i < steps; ++i, ++k) {
       const int par = k & 1;
       int np = 0;
-      P.prof.run(0, bytes_cg_op(P, r, sizeof(T)), s, [&] { np = op_cg<T>(P, W, r, ld, Pd, Q, t, par, s); });
+      P.prof.run(0, bytes_cg_op(P, r, sizeof(T)), s, [&] { np = op_cg<T>(P, W, ldw, r, ld, Pd, P2, Q, t, par, s); });
       cg_alpha_finish<<<1, kBlock, 0, s>>>(np, P.part.p, P.sc.p, par);
       cg_update<T><<<gridv, kBlock, 0, s>>>(N, X, R, Pd, Q, P.sc.p, par, P.part.p);
       cg_update_finish<<<1, kBlock, 0, s>>>(gridv, P.part.p, P.sc.p, par);
-      cg_direction<T><<<gridv, kBlock, 0, s>>>(N, R, Pd, P.sc.p, par);
+      cg_direction<T><<<gridv, kBlock, 0, s>>>(N, R, Pd, P.sc.p, par, P2, ld);
     }
     HIPCHK(hipGetLastError());
     read_slots(P, 0, h, kRead, s);
@@ -351,11 +357,11 @@ template void op_forward<double>(Problem&, const double*, const double*, int, in
 template void op_forward<float>(Problem&, const float*, const float*, int, int, float*, double, hipStream_t);
 template void op_adjoint<double>(Problem&, const double*, double, const double*, int, int, double*, int, double, hipStream_t);
 template void op_adjoint<float>(Problem&, const float*, double, const float*, int, int, float*, int, double, hipStream_t);
-template int op_cg<double>(Problem&, const double*, int, int, const double*, double*, double*, int, hipStream_t);
-template int op_cg<float>(Problem&, const float*, int, int, const float*, float*, float*, int, hipStream_t);
+template int op_cg<double>(Problem&, const double*, int, int, int, const double*, const double*, double*, double*, int, hipStream_t);
+template int op_cg<float>(Problem&, const float*, int, int, int, const float*, const float*, float*, float*, int, hipStream_t);
 template void dot_to_slot<double, double>(Problem&, size_t, const double*, const double*, double, int, hipStream_t);
 template void dot_to_slot<float, float>(Problem&, size_t, const float*, const float*, double, int, hipStream_t);
-template int cg_run<double>(Problem&, const double*, int, int, double, double, double*, double*, double*, double*, double*, double, int, hipStream_t, double*, double*);
-template int cg_run<float>(Problem&, const float*, int, int, double, double, float*, float*, float*, float*, float*, double, int, hipStream_t, double*, double*);
+template int cg_run<double>(Problem&, const double*, int, int, int, double, double, double*, double*, double*, double*, double*, double*, double, int, hipStream_t, double*, double*);
+template int cg_run<float>(Problem&, const float*, int, int, int, double, double, float*, float*, float*, float*, float*, float*, double, int, hipStream_t, double*, double*);
 
 }  // namespace lorads

@@ -169,7 +169,10 @@ void op_adjoint(Problem& P, const T* w, double c_scale, const T* V, int r, int l
 // records the CG step length in sc (see cg_update).  t: m-vector scratch.
 template <typename T>
 // Q = M_W(Pd) (+ block partials of <Pd, Q> in P.part; returns their count)
-int op_cg(Problem& P, const T* W, int r, int ld, const T* Pd, T* Q, T* t, int parity, hipStream_t s);
+// W with row stride ldw; the direction Pd (stride ld), or its copy P2 in the
+// rows of W (stride ldw) when P2 is given
+int op_cg(Problem& P, const T* W, int ldw, int r, int ld, const T* Pd, const T* P2, T* Q, T* t,
+          int parity, hipStream_t s);
 // p1 = A(U D^T + D U^T) and p2 = A(D D^T) in FP64 (the exact line search)
 void op_forward_pair(Problem& P, const double* U, const double* D, int r, double* p1, double* p2,
                      hipStream_t s);
@@ -206,7 +209,8 @@ inline int grid_for(size_t N, int cap = 2048) {
 // CG on M_W D = R from D = X (X holds x0 = 0 normally; R holds R0 - M x0).
 // Buffers dense n x r of type T.  Returns iterations; *relres = ||R||/||R0||.
 template <typename T>
-int cg_run(Problem& P, const T* W, int r, int ld, double rho, double gamma, T* R, T* X, T* Pd,
-           T* Q, T* t, double tol, int maxit, hipStream_t s, double* relres, double* op_bytes);
+int cg_run(Problem& P, const T* W, int ldw, int r, int ld, double rho, double gamma, T* R, T* X,
+           T* Pd, T* P2, T* Q, T* t, double tol, int maxit, hipStream_t s, double* relres,
+           double* op_bytes);
 
 }  // namespace lorads

@@ -313,14 +313,21 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
 // ===========================================================================
 // CG work buffers in the CG layout (leading dimension ld = cg_ld(P, r), zero
 // padding that no kernel writes)
+// For PAIR problems W holds rows [W_t | P_t] (stride ldw = 2 ld) so that the
+// CG operator reads both factors of a partner from one line; P2 points at the
+// direction's half.
 template <typename T>
 struct CgBufs {
   DevBuf<T> R, X, Pd, Q, W, t;
-  int ld = 0;
-  void alloc(size_t N, int m, int ld_, hipStream_t s) {
+  int ld = 0, ldw = 0;
+  T* P2 = nullptr;
+  void alloc(int n, int m, int ld_, bool interleave, hipStream_t s) {
     ld = ld_;
-    R.alloc(N); X.alloc(N); Pd.alloc(N); Q.alloc(N); W.alloc(N); t.alloc(m);
+    ldw = interleave ? 2 * ld : ld;
+    const size_t N = (size_t)n * ld;
+    R.alloc(N); X.alloc(N); Pd.alloc(N); Q.alloc(N); W.alloc((size_t)n * ldw); t.alloc(m);
     R.zero(s); X.zero(s); Pd.zero(s); Q.zero(s); W.zero(s);
+    P2 = interleave ? W.p + ld : nullptr;
   }
 };
 
@@ -339,11 +346,11 @@ static int half_step(Problem& P, const double* W, double* out, int r, double rho
     op_adjoint<double>(P, P.wbuf.p, 1.0, W, r, r, R64.p, ld, -1.0, s);
     convert_kernel<double, float><<<gridN(N), kBlock, 0, s>>>(N, R64.p, B.R.p);
   }
-  copy_rows<double, T><<<gridN((size_t)P.n * r), kBlock, 0, s>>>(P.n, r, W, r, B.W.p, ld);
+  copy_rows<double, T><<<gridN((size_t)P.n * r), kBlock, 0, s>>>(P.n, r, W, r, B.W.p, B.ldw);
   HIPCHK(hipMemsetAsync(B.X.p, 0, N * sizeof(T), s));
   double rel;
-  const int it = cg_run<T>(P, B.W.p, r, ld, rho, gamma, B.R.p, B.X.p, B.Pd.p, B.Q.p, B.t.p, tol,
-                           maxit, s, &rel, &info.op_bytes);
+  const int it = cg_run<T>(P, B.W.p, B.ldw, r, ld, rho, gamma, B.R.p, B.X.p, B.Pd.p, B.P2, B.Q.p,
+                           B.t.p, tol, maxit, s, &rel, &info.op_bytes);
   add_rows<double, T><<<gridN((size_t)P.n * r), kBlock, 0, s>>>(P.n, r, W, r, B.X.p, ld, out);
   HIPCHK(hipGetLastError());
   return it;
@@ -366,7 +373,7 @@ static void phase2_t(Problem& P, const lorads_options& o, double rho, SolveInfo&
     R64.zero(s);
   }
   CgBufs<T> B;
-  B.alloc(Nc, m, ldc, s);
+  B.alloc(n, m, ldc, P.structure == LORADS_STRUCT_PAIR, s);
   const int maxit = (int)std::min<long long>((long long)N, o.cg_maxit);
   const double floor = (std::is_same<T, double>::value) ? o.cg_tol_floor : std::max(o.cg_tol_floor, 1e-6);
   double kkt = INFINITY, pinf = INFINITY, dres = INFINITY, gamma = gamma_of(P, o, rho);
