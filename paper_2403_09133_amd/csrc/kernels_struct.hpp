@@ -376,4 +376,122 @@ __global__ void __launch_bounds__(kBlock) kpair_rows(
   if (MODE == 1) publish_partial(block_sum(pq, sh), part);
 }
 
+// ===========================================================================
+// PAIR CG operator on the CG layout (rows padded to 64 bytes, W and the
+// direction interleaved: row p = [W_p | P_p], stride ldw = 2 ld, zero padding).
+// A lane holds VW = 16 / sizeof(T) contiguous columns loaded as one 16-byte
+// vector, so a constraint occupies G = pow2(ceil(r / VW)) lanes (4 for r <= 16
+// in FP32) and its inner product needs log2 G lane moves; a wave serves 64 / G
+// constraints per step.  Otherwise as kpair_rows MODE 1 (incident lists staged
+// per wave in LDS, fixed-order sums, block partials of <P, Q>).
+// ===========================================================================
+template <typename T, int G>
+__global__ void __launch_bounds__(kBlock) kpair_cg_vec(
+    int n, const int* __restrict__ inc_ptr, const int* __restrict__ inc_nb,
+    const int* __restrict__ inc_id, const T* __restrict__ pcoef, double pair_coef,
+    const T* __restrict__ WP, int ld, int r, T* __restrict__ Q, double* __restrict__ sc,
+    int parity, double* __restrict__ part) {
+  using A = typename OpAcc<T>::type;
+  constexpr int VW = 16 / (int)sizeof(T);
+  constexpr int NG = 64 / G;
+  constexpr int CH = kPairStage;
+  typedef T vec __attribute__((ext_vector_type(16 / sizeof(T))));
+  __shared__ double sh[kBlock / 64];
+  __shared__ int s_nb[kBlock / 64][CH];
+  __shared__ A s_cf[kBlock / 64][CH];
+  if (sc[S_DONE + parity] != 0.0) return;
+  const int wl = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int grp = wl / G, lane = wl & (G - 1);
+  const int row = blockIdx.x * (kBlock / 64) + wid;
+  const int ldw = 2 * ld;
+  const int c0 = lane * VW;  // first column of this lane (c0 < ld: G * VW <= ld)
+  int* nbw = s_nb[wid];
+  A* cfw = s_cf[wid];
+  double pq = 0.0;
+  if (row < n) {  // wave-uniform
+    A acc[VW], pt[VW], vt[VW];
+    {
+      const vec w = *reinterpret_cast<const vec*>(WP + row * ldw + c0);
+      const vec p = *reinterpret_cast<const vec*>(WP + row * ldw + ld + c0);
+#pragma unroll
+      for (int v = 0; v < VW; ++v) {
+        vt[v] = (A)w[v];
+        pt[v] = (A)p[v];
+        acc[v] = 0;
+      }
+    }
+    const A a2u = (A)(pair_coef * pair_coef);
+    const int e0 = inc_ptr[row], e1 = inc_ptr[row + 1];
+    for (int base = e0; base < e1; base += CH) {
+      const int cnt = min(CH, e1 - base);
+#pragma unroll
+      for (int q = 0; q < CH / 64; ++q) {
+        const int j = wl + 64 * q;
+        if (j < cnt) {
+          nbw[j] = inc_nb[base + j] * ldw;
+          A a2 = a2u;
+          if (pcoef != nullptr) {
+            const A a = (A)pcoef[inc_id[base + j]];
+            a2 = a * a;
+          }
+          cfw[j] = a2;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int j = grp; j < cnt; j += NG * kUnroll) {
+        int off[kUnroll];
+        A coef[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int ju = j + u * NG;
+          const bool ok = ju < cnt;
+          off[u] = (ok ? nbw[ju] : row * ldw) + c0;
+          coef[u] = ok ? cfw[ju] : (A)0;
+        }
+        vec wv[kUnroll], pv[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          wv[u] = *reinterpret_cast<const vec*>(WP + off[u]);
+          pv[u] = *reinterpret_cast<const vec*>(WP + off[u] + ld);
+        }
+        A d[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          A s = 0;
+#pragma unroll
+          for (int v = 0; v < VW; ++v) s += pt[v] * (A)wv[u][v] + (A)pv[u][v] * vt[v];
+          d[u] = s;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) d[u] = group_sum<G>(d[u]) * coef[u];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+          for (int v = 0; v < VW; ++v) acc[v] += d[u] * (A)wv[u][v];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+#pragma unroll
+    for (int v = 0; v < VW; ++v)
+      for (int o = G; o < 64; o <<= 1) acc[v] += __shfl_xor(acc[v], o, 64);
+    if (grp == 0) {
+      const double gamma = sc[S_GAMMA], rho = sc[S_RHO];
+#pragma unroll
+      for (int v = 0; v < VW; ++v) {
+        const int c = c0 + v;
+        if (c < r) {
+          const T qv = (T)(gamma * (double)pt[v] + rho * (double)acc[v]);
+          Q[row * ld + c] = qv;
+          pq += (double)pt[v] * (double)qv;
+        }
+      }
+    }
+  }
+  publish_partial(block_sum(pq, sh), part);
+}
+
 }  // namespace lorads

@@ -205,10 +205,23 @@ int op_cg(Problem& P, const T* W, int ldw, int r, int ld, const T* Pd, const T* 
     check_pair_offsets(P, ldw);
     const int grid = waves_grid(P.n);
     P.ensure_part(grid);
-    LORADS_DISPATCH_GK(G, r, (kpair_rows<T, G, 1, KC><<<grid, kBlock, 0, s>>>(
-                             P.n, nullptr, nullptr, nullptr, 0.0, P.inc_ptr.p, P.inc_nb.p,
-                             P.inc_id.p, pc<T>(P), P.pair_coef, nullptr, W, Pg, r, ldw, Q, ld,
-                             1.0, sc, parity, P.part.p)));
+    constexpr int VW = 16 / (int)sizeof(T);
+    const int gv = pow2_group((r + VW - 1) / VW);
+    if (P2 && P2 == W + ld && ldw == 2 * ld && ld % VW == 0 && gv * VW <= ld && gv <= 16) {
+      // CG layout: 16-byte column vectors per lane
+      switch (gv) {
+        case 1: kpair_cg_vec<T, 1><<<grid, kBlock, 0, s>>>(P.n, P.inc_ptr.p, P.inc_nb.p, P.inc_id.p, pc<T>(P), P.pair_coef, W, ld, r, Q, sc, parity, P.part.p); break;
+        case 2: kpair_cg_vec<T, 2><<<grid, kBlock, 0, s>>>(P.n, P.inc_ptr.p, P.inc_nb.p, P.inc_id.p, pc<T>(P), P.pair_coef, W, ld, r, Q, sc, parity, P.part.p); break;
+        case 4: kpair_cg_vec<T, 4><<<grid, kBlock, 0, s>>>(P.n, P.inc_ptr.p, P.inc_nb.p, P.inc_id.p, pc<T>(P), P.pair_coef, W, ld, r, Q, sc, parity, P.part.p); break;
+        case 8: kpair_cg_vec<T, 8><<<grid, kBlock, 0, s>>>(P.n, P.inc_ptr.p, P.inc_nb.p, P.inc_id.p, pc<T>(P), P.pair_coef, W, ld, r, Q, sc, parity, P.part.p); break;
+        default: kpair_cg_vec<T, 16><<<grid, kBlock, 0, s>>>(P.n, P.inc_ptr.p, P.inc_nb.p, P.inc_id.p, pc<T>(P), P.pair_coef, W, ld, r, Q, sc, parity, P.part.p); break;
+      }
+    } else {
+      LORADS_DISPATCH_GK(G, r, (kpair_rows<T, G, 1, KC><<<grid, kBlock, 0, s>>>(
+                               P.n, nullptr, nullptr, nullptr, 0.0, P.inc_ptr.p, P.inc_nb.p,
+                               P.inc_id.p, pc<T>(P), P.pair_coef, nullptr, W, Pg, r, ldw, Q, ld,
+                               1.0, sc, parity, P.part.p)));
+    }
     np = grid;
   } else {
     LORADS_DISPATCH_G(G, (k1_generic<T, G, 2><<<rows_grid(P.m, G), kBlock, 0, s>>>(
