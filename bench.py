@@ -144,7 +144,7 @@ def batch_leg(count: int = 512, sample: int = 16):
     t = time.time()
     ctx = Context(probs)
     out["setup_s"] = round(time.time() - t, 2)
-    best, times = ctx.batch_autotune(U0, opts(max_admm_iter=30), (64, 128, 256, 512, 1024))
+    best, times = ctx.batch_autotune(U0, opts(max_admm_iter=30), (64, 128, 192, 256))
     out["autotune"] = {"block": best, "ms_short_run": {k: round(v, 2) for k, v in times.items()}}
     for name, prec in (("fp64", 0), ("fp32", 1)):
         t = time.perf_counter()

@@ -127,7 +127,7 @@ typedef struct {
                               1: require the batched launch (EINVAL otherwise);
                               2: always one problem after the other */
   int32_t batch_block;     /* workgroup size of the batched launch (multiple of
-                              64 up to 1024); 0: the context's tuned value
+                              64 up to 256); 0: the context's tuned value
                               (lorads_batch_autotune), default 256 */
   /* per-problem starting points, host, caller-owned, arrays of nprob pointers
      (NULL or a NULL entry: not given).  init_U[p] is n x r0 row-major; without
@@ -221,7 +221,7 @@ lorads_status lorads_cg_solve(lorads_ctx *ctx, int32_t prob, const void *W, doub
 lorads_status lorads_admm_solve(lorads_ctx *ctx, const lorads_options *opt, lorads_result *res);
 
 /* Autotuner of the batched launch: runs the batched solve once per candidate
- * workgroup size (host array cand[ncand], multiples of 64 up to 1024) with the
+ * workgroup size (host array cand[ncand], multiples of 64 up to 256) with the
  * given options (callers pass a short iteration budget), times each run with
  * HIP events, keeps the fastest in the context for later solves with
  * batch_block = 0 and returns it in *best (times_ms, host, may be NULL:

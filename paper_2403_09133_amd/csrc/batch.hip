@@ -49,15 +49,85 @@ struct Inst {
 
 #define FOR_ROWS(j) for (int j = threadIdx.x; j < I.n; j += blockDim.x)
 #define FOR_CONS(i) for (int i = threadIdx.x; i < I.m; i += blockDim.x)
+// Factor rows are served by groups of kBG lanes (lane l holds columns l and
+// l + kBG; the rank capacity is at most 2 kBG), so the loads of a row are
+// contiguous and a row's inner product is a DPP reduction inside the group.
+constexpr int kBG = 16;
+// workgroup size limit of the batched launch (keeps the kernel's registers
+// free of spills)
+constexpr int kBatchMaxBlock = 256;
+#define FOR_GROUPS(j, cnt) for (int j = (int)threadIdx.x / kBG; j < (cnt); j += (int)blockDim.x / kBG)
+#define FOR_RC(j, c) FOR_GROUPS(j, I.n) for (int c = (int)threadIdx.x % kBG; c < I.r; c += kBG)
+
+// Element passes over the active block visit kBU rows per group at a time and
+// issue every load of those rows before the first store, so a workgroup keeps
+// kBU * blockDim / kBG rows in flight.  Out-of-range rows and columns load from
+// a clamped in-row position and are masked.
+constexpr int kBU = 4;
+struct PassSlots {
+  int q[kBU][2];
+  bool on[kBU][2];
+};
+__device__ __forceinline__ void pass_slots(int it, int n, int r, int ld, PassSlots& S) {
+  const int l = threadIdx.x % kBG, ng = blockDim.x / kBG;
+  const int c0 = min(l, ld - 1), c1 = min(l + kBG, ld - 1);
+#pragma unroll
+  for (int u = 0; u < kBU; ++u) {
+    const int j = it + u * ng;
+    const bool rok = j < n;
+    const int base = (rok ? j : n - 1) * ld;
+    S.q[u][0] = base + c0;
+    S.q[u][1] = base + c1;
+    S.on[u][0] = rok && l < r;
+    S.on[u][1] = rok && l + kBG < r;
+  }
+}
+#define FOR_PASS(it) \
+  for (int it = (int)threadIdx.x / kBG; it < I.n; it += kBU * ((int)blockDim.x / kBG))
+#define FOR_UH(u, h) _Pragma("unroll") for (int u = 0; u < kBU; ++u) _Pragma("unroll") for (int h = 0; h < 2; ++h)
+
+// Row inner products <X_j, Y_j> of the rows of kBU constraints, it + u * ng
+// (ng groups per workgroup), every load issued before the reductions; rows of
+// constraints past m repeat the last constraint's row.
+template <typename T>
+__device__ __forceinline__ void b_row_dots(const Inst<T>& I, int it, const double* X, const double* Y,
+                                           double (&s)[kBU]) {
+  const int l = threadIdx.x % kBG, ng = blockDim.x / kBG;
+  const int c0 = min(l, I.ld - 1), c1 = min(l + kBG, I.ld - 1);
+  int base[kBU];
+#pragma unroll
+  for (int u = 0; u < kBU; ++u) base[u] = I.drow[min(it + u * ng, I.m - 1)] * I.ld;
+  double x[kBU][2], y[kBU][2];
+#pragma unroll
+  for (int u = 0; u < kBU; ++u) {
+    x[u][0] = X[base[u] + c0];
+    x[u][1] = X[base[u] + c1];
+    y[u][0] = Y[base[u] + c0];
+    y[u][1] = Y[base[u] + c1];
+  }
+#pragma unroll
+  for (int u = 0; u < kBU; ++u) {
+    double t = 0.0;
+    if (l < I.r) t += x[u][0] * y[u][0];
+    if (l + kBG < I.r) t += x[u][1] * y[u][1];
+    s[u] = group_sum<kBG>(t);
+  }
+}
+#define FOR_CPASS(it) \
+  for (int it = (int)threadIdx.x / kBG; it < I.m; it += kBU * ((int)blockDim.x / kBG))
 
 // z_i = scale a_i <X_row, Y_row>
 template <typename T>
 __device__ void b_forward(const Inst<T>& I, const double* X, const double* Y, double* z, double scale) {
-  FOR_CONS(i) {
-    const int j = I.drow[i];
-    double s = 0.0;
-    for (int c = 0; c < I.r; ++c) s += X[(size_t)j * I.ld + c] * Y[(size_t)j * I.ld + c];
-    z[i] = scale * I.dcoef[i] * s;
+  const int l = threadIdx.x % kBG, ng = blockDim.x / kBG;
+  FOR_CPASS(it) {
+    double s[kBU];
+    b_row_dots(I, it, X, Y, s);
+#pragma unroll
+    for (int u = 0; u < kBU; ++u) {
+      const int i = it + u * ng;
+      if (l == 0 && i < I.m) z[i] = scale * I.dcoef[i] * s[u];
+    }
   }
 }
 
@@ -65,29 +135,88 @@ __device__ void b_forward(const Inst<T>& I, const double* X, const double* Y, do
 template <typename T>
 __device__ void b_forward_w(const Inst<T>& I, const double* U, double* z, double* w,
                             const double* lam, double rho) {
-  FOR_CONS(i) {
-    const int j = I.drow[i];
-    double s = 0.0;
-    for (int c = 0; c < I.r; ++c) s += U[(size_t)j * I.ld + c] * U[(size_t)j * I.ld + c];
-    s *= I.dcoef[i];
-    z[i] = s;
-    w[i] = lam[i] + rho * (s - I.b[i]);
+  const int l = threadIdx.x % kBG, ng = blockDim.x / kBG;
+  FOR_CPASS(it) {
+    double s[kBU];
+    b_row_dots(I, it, U, U, s);
+#pragma unroll
+    for (int u = 0; u < kBU; ++u) {
+      const int i = it + u * ng;
+      if (l == 0 && i < I.m) {
+        const double v = s[u] * I.dcoef[i];
+        z[i] = v;
+        w[i] = lam[i] + rho * (v - I.b[i]);
+      }
+    }
   }
 }
 
 // out_j = os (cs (C V)_j + (sum_{i on row j} w_i a_i) V_j), w may be null
+// A group serves kBU rows at once: the lanes load up to kBG entries of each
+// row's cost list together, then every step gathers one partner row for each
+// of the kBU rows (entry broadcast inside the group), so kBU partner rows are
+// in flight per step.
 template <typename T>
 __device__ void b_adjoint(const Inst<T>& I, const double* w, double cs, const double* V,
                           double* out, double os) {
-  FOR_ROWS(j) {
-    double d = 0.0;
-    if (w)
-      for (int i = I.dptr[j]; i < I.dptr[j + 1]; ++i) d += w[i] * I.dcoef[i];
-    for (int c = 0; c < I.r; ++c) {
-      double acc = 0.0;
-      if (cs != 0.0)
-        for (int e = I.cptr[j]; e < I.cptr[j + 1]; ++e) acc += cs * I.cval[e] * V[(size_t)I.ccol[e] * I.ld + c];
-      out[(size_t)j * I.ld + c] = os * (acc + d * V[(size_t)j * I.ld + c]);
+  const int l = threadIdx.x % kBG, ng = blockDim.x / kBG;
+  const int c0 = min(l, I.ld - 1), c1 = min(l + kBG, I.ld - 1);
+  FOR_PASS(it) {
+    int j[kBU], e0[kBU], e1[kBU];
+#pragma unroll
+    for (int u = 0; u < kBU; ++u) j[u] = min(it + u * ng, I.n - 1);
+    int span = 0;
+#pragma unroll
+    for (int u = 0; u < kBU; ++u) {
+      e0[u] = cs != 0.0 ? I.cptr[j[u]] : 0;
+      e1[u] = cs != 0.0 ? I.cptr[j[u] + 1] : 0;
+      span = max(span, e1[u] - e0[u]);
+    }
+    double acc[kBU][2] = {};
+    for (int base = 0; base < span; base += kBG) {
+      int col[kBU];
+      double a[kBU];
+#pragma unroll
+      for (int u = 0; u < kBU; ++u) {
+        const int e = e0[u] + base + l;
+        const bool ok = e < e1[u];
+        col[u] = ok ? I.ccol[e] : j[u];
+        a[u] = ok ? cs * I.cval[e] : 0.0;
+      }
+      const int cnt = min(kBG, span - base);
+      for (int t = 0; t < cnt; ++t) {
+        double v[kBU][2], au[kBU];
+#pragma unroll
+        for (int u = 0; u < kBU; ++u) {
+          const int q = __shfl(col[u], t, kBG) * I.ld;
+          v[u][0] = V[q + c0];
+          v[u][1] = V[q + c1];
+        }
+#pragma unroll
+        for (int u = 0; u < kBU; ++u) au[u] = __shfl(a[u], t, kBG);
+#pragma unroll
+        for (int u = 0; u < kBU; ++u) {
+          acc[u][0] += au[u] * v[u][0];
+          acc[u][1] += au[u] * v[u][1];
+        }
+      }
+    }
+    double d[kBU], vj[kBU][2];
+#pragma unroll
+    for (int u = 0; u < kBU; ++u) {
+      double t = 0.0;
+      if (w)
+        for (int i = I.dptr[j[u]] + l; i < I.dptr[j[u] + 1]; i += kBG) t += w[i] * I.dcoef[i];
+      vj[u][0] = V[j[u] * I.ld + c0];
+      vj[u][1] = V[j[u] * I.ld + c1];
+      d[u] = group_sum<kBG>(t);
+    }
+#pragma unroll
+    for (int u = 0; u < kBU; ++u) {
+      if (it + u * ng >= I.n) continue;
+      const int q = j[u] * I.ld;
+      if (l < I.r) out[q + l] = os * (acc[u][0] + d[u] * vj[u][0]);
+      if (l + kBG < I.r) out[q + l + kBG] = os * (acc[u][1] + d[u] * vj[u][1]);
     }
   }
 }
@@ -95,7 +224,13 @@ __device__ void b_adjoint(const Inst<T>& I, const double* w, double cs, const do
 template <typename T>
 __device__ double b_dot(const Inst<T>& I, const double* X, const double* Y) {
   double s = 0.0;
-  FOR_ROWS(j) for (int c = 0; c < I.r; ++c) s += X[(size_t)j * I.ld + c] * Y[(size_t)j * I.ld + c];
+  FOR_PASS(it) {
+    PassSlots S;
+    pass_slots(it, I.n, I.r, I.ld, S);
+    double xv[kBU][2], yv[kBU][2];
+    FOR_UH(u, h) { xv[u][h] = X[S.q[u][h]]; yv[u][h] = Y[S.q[u][h]]; }
+    FOR_UH(u, h) if (S.on[u][h]) s += xv[u][h] * yv[u][h];
+  }
   return wg_sum(s);
 }
 
@@ -109,9 +244,12 @@ __device__ double b_mdot(const Inst<T>& I, const double* x, const double* y) {
 // y = a x + b y over the active block (x may alias y)
 template <typename T, typename TX, typename TY>
 __device__ void b_axpby(const Inst<T>& I, double a, const TX* x, double bb, TY* y) {
-  FOR_ROWS(j) for (int c = 0; c < I.r; ++c) {
-    const size_t q = (size_t)j * I.ld + c;
-    y[q] = (TY)(a * (double)x[q] + bb * (double)y[q]);
+  FOR_PASS(it) {
+    PassSlots S;
+    pass_slots(it, I.n, I.r, I.ld, S);
+    double xv[kBU][2], yv[kBU][2];
+    FOR_UH(u, h) { xv[u][h] = (double)x[S.q[u][h]]; yv[u][h] = (double)y[S.q[u][h]]; }
+    FOR_UH(u, h) if (S.on[u][h]) y[S.q[u][h]] = (TY)(a * xv[u][h] + bb * yv[u][h]);
   }
   __syncthreads();
 }
@@ -187,7 +325,7 @@ __device__ double d_quartic_step(double q1, double q2, double q3, double q4) {
 // the per-instance solver
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(1024) batch_solve_kernel(const BatchDesc* __restrict__ descs,
+__global__ void __launch_bounds__(kBatchMaxBlock) batch_solve_kernel(const BatchDesc* __restrict__ descs,
                                                            BatchArrays A, BatchOpts o) {
   const BatchDesc d = descs[blockIdx.x];
   Inst<T> I;
@@ -338,7 +476,7 @@ __global__ void __launch_bounds__(1024) batch_solve_kernel(const BatchDesc* __re
       const int r_new = min((int)ceil(o.rank_factor * I.r), r_cap);
       const double sigma = 1e-3 * sqrt(b_dot(I, U, U)) / sqrt((double)I.n * I.r);
       const int add = r_new - I.r;
-      FOR_ROWS(j) for (int c = I.r; c < r_new; ++c) {
+      FOR_GROUPS(j, I.n) for (int c = I.r + (int)threadIdx.x % kBG; c < r_new; c += kBG) {
         const uint64_t t = (uint64_t)j * add + (uint64_t)(c - I.r);
         const uint64_t k1 = ((uint64_t)growths << 40) + 2ull * t + 1ull, k2 = k1 + 1ull;
         const uint64_t gg = 0x9E3779B97F4A7C15ull;
@@ -392,18 +530,21 @@ __global__ void __launch_bounds__(1024) batch_solve_kernel(const BatchDesc* __re
         __syncthreads();
         b_adjoint(I, w, 1.0, W, R64, -1.0);
         __syncthreads();
-        FOR_ROWS(j) for (int c = 0; c < I.r; ++c) {
-          const size_t q = (size_t)j * I.ld + c;
-          R[q] = (T)R64[q];
-          Wt[q] = (T)W[q];
-          X[q] = (T)0;
-          Pd[q] = R[q];
-        }
-        __syncthreads();
         double rr = 0.0;
-        FOR_ROWS(j) for (int c = 0; c < I.r; ++c) {
-          const double t = (double)R[(size_t)j * I.ld + c];
-          rr += t * t;
+        FOR_PASS(it) {
+          PassSlots S;
+          pass_slots(it, I.n, I.r, I.ld, S);
+          double rv[kBU][2], wv[kBU][2];
+          FOR_UH(u, h) { rv[u][h] = R64[S.q[u][h]]; wv[u][h] = W[S.q[u][h]]; }
+          FOR_UH(u, h) if (S.on[u][h]) {
+            const int q = S.q[u][h];
+            const T t = (T)rv[u][h];
+            R[q] = t;
+            Wt[q] = (T)wv[u][h];
+            X[q] = (T)0;
+            Pd[q] = t;
+            rr += (double)t * (double)t;
+          }
         }
         rr = wg_sum(rr);
         const double rr0 = rr;
@@ -411,41 +552,65 @@ __global__ void __launch_bounds__(1024) batch_solve_kernel(const BatchDesc* __re
         while (rr0 > 0.0 && it < maxit && rr > tol * tol * rr0) {
           // Q = gamma P + rho dsq <P_j, W_j> W_j
           double pq = 0.0;
-          FOR_ROWS(j) {
-            double dd = 0.0;
-            for (int c = 0; c < I.r; ++c) dd += (double)Pd[(size_t)j * I.ld + c] * (double)Wt[(size_t)j * I.ld + c];
-            dd *= rho * I.dsq[j];
-            for (int c = 0; c < I.r; ++c) {
-              const size_t q = (size_t)j * I.ld + c;
-              const double p = (double)Pd[q];
-              const T qv = (T)(gamma * p + dd * (double)Wt[q]);
-              Q[q] = qv;
-              pq += p * (double)qv;
+          FOR_PASS(it) {
+            PassSlots S;
+            pass_slots(it, I.n, I.r, I.ld, S);
+            const int ng = blockDim.x / kBG;
+            double pv[kBU][2], wv[kBU][2], ds[kBU];
+            FOR_UH(u, h) { pv[u][h] = (double)Pd[S.q[u][h]]; wv[u][h] = (double)Wt[S.q[u][h]]; }
+#pragma unroll
+            for (int u = 0; u < kBU; ++u) {
+              const int j = min(it + u * ng, I.n - 1);
+              double dd = 0.0;
+#pragma unroll
+              for (int h = 0; h < 2; ++h)
+                if (S.on[u][h]) dd += pv[u][h] * wv[u][h];
+              ds[u] = group_sum<kBG>(dd) * rho * I.dsq[j];
+            }
+            FOR_UH(u, h) if (S.on[u][h]) {
+              const T qv = (T)(gamma * pv[u][h] + ds[u] * wv[u][h]);
+              Q[S.q[u][h]] = qv;
+              pq += pv[u][h] * (double)qv;
             }
           }
           pq = wg_sum(pq);
           if (!(pq > 0.0)) break;
           const double alpha = rr / pq;
           double rn = 0.0;
-          FOR_ROWS(j) for (int c = 0; c < I.r; ++c) {
-            const size_t q = (size_t)j * I.ld + c;
-            X[q] = (T)((double)X[q] + alpha * (double)Pd[q]);
-            const T rv = (T)((double)R[q] - alpha * (double)Q[q]);
-            R[q] = rv;
-            rn += (double)rv * (double)rv;
+          FOR_PASS(it) {
+            PassSlots S;
+            pass_slots(it, I.n, I.r, I.ld, S);
+            double xv[kBU][2], pv[kBU][2], rv[kBU][2], qv[kBU][2];
+            FOR_UH(u, h) {
+              const int q = S.q[u][h];
+              xv[u][h] = (double)X[q];
+              pv[u][h] = (double)Pd[q];
+              rv[u][h] = (double)R[q];
+              qv[u][h] = (double)Q[q];
+            }
+            FOR_UH(u, h) if (S.on[u][h]) {
+              const int q = S.q[u][h];
+              X[q] = (T)(xv[u][h] + alpha * pv[u][h]);
+              const T rt = (T)(rv[u][h] - alpha * qv[u][h]);
+              R[q] = rt;
+              rn += (double)rt * (double)rt;
+            }
           }
           rn = wg_sum(rn);
           const double beta = rn / rr;
           rr = rn;
-          FOR_ROWS(j) for (int c = 0; c < I.r; ++c) {
-            const size_t q = (size_t)j * I.ld + c;
-            Pd[q] = (T)((double)R[q] + beta * (double)Pd[q]);
+          FOR_PASS(it) {
+            PassSlots S;
+            pass_slots(it, I.n, I.r, I.ld, S);
+            double pv[kBU][2], rv[kBU][2];
+            FOR_UH(u, h) { pv[u][h] = (double)Pd[S.q[u][h]]; rv[u][h] = (double)R[S.q[u][h]]; }
+            FOR_UH(u, h) if (S.on[u][h]) Pd[S.q[u][h]] = (T)(rv[u][h] + beta * pv[u][h]);
           }
           __syncthreads();
           ++it;
         }
         cg_total += it;
-        FOR_ROWS(j) for (int c = 0; c < I.r; ++c) {
+        FOR_RC(j, c) {
           const size_t q = (size_t)j * I.ld + c;
           out[q] = W[q] + (double)X[q];
         }
@@ -614,7 +779,8 @@ void batch_solve(std::vector<std::unique_ptr<Problem>>& probs, Batch& B, const l
   const size_t esz = f32 ? sizeof(float) : sizeof(double);
   for (DevBuf<char>* buf : {&B.X, &B.R, &B.P, &B.Q, &B.W}) buf->alloc(F * esz);
   a.X = B.X.p; a.R = B.R.p; a.P = B.P.p; a.Q = B.Q.p; a.W = B.W.p;
-  if (block < 64 || block > 1024 || block % 64) fail(LORADS_EINVAL, "batch block size must be a multiple of 64 in [64, 1024]");
+  if (block < 64 || block > kBatchMaxBlock || block % 64)
+    fail(LORADS_EINVAL, "batch block size must be a multiple of 64 in [64, 256]");
   if (f32)
     batch_solve_kernel<float><<<np, block, 0, s>>>(B.desc.p, a, bo);
   else

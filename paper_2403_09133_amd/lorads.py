@@ -304,7 +304,7 @@ class Context:
         return out
 
     def batch_autotune(self, init_U: Sequence[np.ndarray], options: Options_,
-                       candidates: Sequence[int] = (64, 128, 256, 512, 1024)):
+                       candidates: Sequence[int] = (64, 128, 192, 256)):
         """Time the batched launch per workgroup size; the context keeps the
         fastest.  Returns (best, {size: ms})."""
         lib = load()
