@@ -79,6 +79,16 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;  // valid in thread 0
 }
 
+// Position of element i of a row-major (stride ld) array inside rows of stride
+// 2 ld (32-bit division whenever the index fits).
+__device__ __forceinline__ size_t interleaved_index(size_t i, int ld) {
+  if (i <= 0xffffffffu) {
+    const unsigned iu = (unsigned)i, lu = (unsigned)ld;
+    return (size_t)(iu / lu) * 2u * lu + iu % lu;
+  }
+  return (i / ld) * 2 * ld + i % ld;
+}
+
 // Grid reductions are two-stage: every block stores its partial (plain store,
 // thread 0 holds the block's value) and a one-block finishing kernel sums the
 // partials in index order.  The kernel boundary makes the partials visible
@@ -89,9 +99,20 @@ __device__ __forceinline__ void publish_partial(double partial, double* part) {
 
 // Sum of part[0..n) by the whole block (strided per thread, then the block
 // tree): a fixed order for a given n and block size.  Result in thread 0.
+// A thread issues the loads of eight of its strided elements before adding
+// them in index order, so a long partial array costs few memory round trips.
 __device__ __forceinline__ double block_sum_parts(const double* part, int n, double* sh) {
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
+  const int bs = blockDim.x;
+  int i = threadIdx.x;
+  for (; i + 7 * bs < n; i += 8 * bs) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[i + u * bs];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; i < n; i += bs) s += part[i];
   return block_sum(s, sh);
 }
 
@@ -250,7 +271,7 @@ __global__ void __launch_bounds__(kBlock) cg_init(size_t N, const T* __restrict_
   for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock) {
     const T v = R[i];
     P[i] = v;
-    if (P2) P2[(i / ld) * 2 * ld + i % ld] = v;
+    if (P2) P2[interleaved_index(i, ld)] = v;
     s += (double)v * (double)v;
   }
   publish_partial(block_sum(s, sh), part);
@@ -327,7 +348,7 @@ __global__ void __launch_bounds__(kBlock) cg_direction(size_t N, const T* __rest
   for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock) {
     const T v = (T)((double)R[i] + beta * (double)P[i]);
     P[i] = v;
-    if (P2) P2[(i / ld) * 2 * ld + i % ld] = v;
+    if (P2) P2[interleaved_index(i, ld)] = v;
   }
 }
 

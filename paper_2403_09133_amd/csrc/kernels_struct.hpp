@@ -13,6 +13,9 @@ constexpr int kMaxCols = 4;  // factor columns per lane held in registers (r <= 
 #endif
 constexpr int kUnroll = LORADS_UNROLL;  // constraints gathered per step (memory-level parallelism)
 constexpr int kPairStage = 256;         // PAIR incident entries staged in LDS per wave and pass
+// word 3 of a raw buffer resource on gfx9 parts (32-bit data format, no
+// swizzle, no index stride)
+constexpr int kBufferRsrcWord3 = 0x00020000;
 
 // ===========================================================================
 // K1 forward map, shared MODE convention:
@@ -384,6 +387,11 @@ __global__ void __launch_bounds__(kBlock) kpair_rows(
 // in FP32) and its inner product needs log2 G lane moves; a wave serves 64 / G
 // constraints per step.  Otherwise as kpair_rows MODE 1 (incident lists staged
 // per wave in LDS, fixed-order sums, block partials of <P, Q>).
+// Partner rows are read with buffer loads: the staged entry is the partner's
+// byte offset (32-bit), the direction half sits at a scalar offset of ld
+// elements, and reads past the buffer return zero.  The staged list of a chunk
+// is padded to a whole number of steps with entries (own row, coefficient 0),
+// so the step loop runs without lane guards.
 // ===========================================================================
 template <typename T, int G>
 __global__ void __launch_bounds__(kBlock) kpair_cg_vec(
@@ -395,6 +403,8 @@ __global__ void __launch_bounds__(kBlock) kpair_cg_vec(
   constexpr int VW = 16 / (int)sizeof(T);
   constexpr int NG = 64 / G;
   constexpr int CH = kPairStage;
+  constexpr int STEP = NG * kUnroll;  // entries per step of a wave (divides CH)
+  static_assert(CH % STEP == 0, "staging chunk must hold whole steps");
   typedef T vec __attribute__((ext_vector_type(16 / sizeof(T))));
   __shared__ double sh[kBlock / 64];
   __shared__ int s_nb[kBlock / 64][CH];
@@ -405,6 +415,10 @@ __global__ void __launch_bounds__(kBlock) kpair_cg_vec(
   const int row = blockIdx.x * (kBlock / 64) + wid;
   const int ldw = 2 * ld;
   const int c0 = lane * VW;  // first column of this lane (c0 < ld: G * VW <= ld)
+  const int rowb = ldw * (int)sizeof(T);  // bytes per row
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)WP, 0, n * rowb, kBufferRsrcWord3);
+  const int pofs = ld * (int)sizeof(T);  // direction half of a row
   int* nbw = s_nb[wid];
   A* cfw = s_cf[wid];
   double pq = 0.0;
@@ -421,47 +435,57 @@ __global__ void __launch_bounds__(kBlock) kpair_cg_vec(
       }
     }
     const A a2u = (A)(pair_coef * pair_coef);
+    const int own = row * rowb;
     const int e0 = inc_ptr[row], e1 = inc_ptr[row + 1];
     for (int base = e0; base < e1; base += CH) {
       const int cnt = min(CH, e1 - base);
+      const int cntp = (cnt + STEP - 1) / STEP * STEP;
 #pragma unroll
       for (int q = 0; q < CH / 64; ++q) {
         const int j = wl + 64 * q;
-        if (j < cnt) {
-          nbw[j] = inc_nb[base + j] * ldw;
-          A a2 = a2u;
-          if (pcoef != nullptr) {
-            const A a = (A)pcoef[inc_id[base + j]];
-            a2 = a * a;
+        if (j < cntp) {
+          int off = own;
+          A a2 = 0;
+          if (j < cnt) {
+            off = inc_nb[base + j] * rowb;
+            a2 = a2u;
+            if (pcoef != nullptr) {
+              const A a = (A)pcoef[inc_id[base + j]];
+              a2 = a * a;
+            }
           }
+          nbw[j] = off;
           cfw[j] = a2;
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      for (int j = grp; j < cnt; j += NG * kUnroll) {
+      for (int j = grp; j < cntp; j += STEP) {
         int off[kUnroll];
         A coef[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-          const int ju = j + u * NG;
-          const bool ok = ju < cnt;
-          off[u] = (ok ? nbw[ju] : row * ldw) + c0;
-          coef[u] = ok ? cfw[ju] : (A)0;
+          off[u] = nbw[j + u * NG] + c0 * (int)sizeof(T);
+          coef[u] = cfw[j + u * NG];
         }
         vec wv[kUnroll], pv[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-          wv[u] = *reinterpret_cast<const vec*>(WP + off[u]);
-          pv[u] = *reinterpret_cast<const vec*>(WP + off[u] + ld);
+          wv[u] = __builtin_bit_cast(vec, __builtin_amdgcn_raw_buffer_load_b128(rs, off[u], 0, 0));
+          pv[u] = __builtin_bit_cast(vec, __builtin_amdgcn_raw_buffer_load_b128(rs, off[u], pofs, 0));
         }
         A d[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-          A s = 0;
+          // one fused multiply-add chain over the lane's columns
+          A s = pt[0] * (A)wv[u][0];
+          s = fma((A)pv[u][0], vt[0], s);
 #pragma unroll
-          for (int v = 0; v < VW; ++v) s += pt[v] * (A)wv[u][v] + (A)pv[u][v] * vt[v];
+          for (int v = 1; v < VW; ++v) {
+            s = fma(pt[v], (A)wv[u][v], s);
+            s = fma((A)pv[u][v], vt[v], s);
+          }
           d[u] = s;
         }
 #pragma unroll

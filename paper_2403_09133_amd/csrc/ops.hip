@@ -207,7 +207,8 @@ int op_cg(Problem& P, const T* W, int ldw, int r, int ld, const T* Pd, const T* 
     P.ensure_part(grid);
     constexpr int VW = 16 / (int)sizeof(T);
     const int gv = pow2_group((r + VW - 1) / VW);
-    if (P2 && P2 == W + ld && ldw == 2 * ld && ld % VW == 0 && gv * VW <= ld && gv <= 16) {
+    if (P2 && P2 == W + ld && ldw == 2 * ld && ld % VW == 0 && gv * VW <= ld && gv <= 16 &&
+        (size_t)P.n * ldw * sizeof(T) < ((size_t)1 << 31)) {
       // CG layout: 16-byte column vectors per lane
       switch (gv) {
         case 1: kpair_cg_vec<T, 1><<<grid, kBlock, 0, s>>>(P.n, P.inc_ptr.p, P.inc_nb.p, P.inc_id.p, pc<T>(P), P.pair_coef, W, ld, r, Q, sc, parity, P.part.p); break;
