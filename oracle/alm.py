@@ -156,7 +156,9 @@ def alm(prob, U0, lam0, opts, rho0=None):
         U, z, it, conv = lbfgs_inner(prob, U, lam, rho, tol, cap, opts.lbfgs_mem, nrm["c_fro"])
         inner_total += it
         v = float(np.linalg.norm(z - prob.b)) / (1.0 + nrm["b_inf"])
-        if not conv and r < r_cap and it >= cap:
+        # a hard inner solve raises the rank only while Phase I goes on: once
+        # the infeasibility meets the switching tolerance the phase ends
+        if not conv and r < r_cap and it >= cap and v > opts.switch_tol:
             r_new = min(int(math.ceil(opts.rank_factor * r)), r_cap)
             U = grow_rank(U, r_new, growths, opts.seed)
             growths += 1

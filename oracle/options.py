@@ -18,8 +18,9 @@ Readings where the paper is silent (the GPU library implements the same rules):
     ||grad||_F / (1 + ||C||_F) <= max(0.1 v, 1e-8); multipliers updated when the
     infeasibility v fell below 0.25 of its last value at an update, otherwise
     rho *= 10; rho0 = 1/max(1, ||b||_inf);
-  * rank growth: an inner solve that reaches 1000 iterations stops, the rank
-    becomes min(ceil(1.5 r), floor(sqrt(2m)), n), new columns are
+  * rank growth: an inner solve that reaches 1000 iterations stops; unless the
+    infeasibility already meets the switching tolerance (Phase I then ends), the
+    rank becomes min(ceil(1.5 r), floor(sqrt(2m)), n), new columns are
     N(0, (1e-3 ||U||_F / sqrt(n r))^2) from the counter-based SplitMix64 stream.
 """
 from __future__ import annotations

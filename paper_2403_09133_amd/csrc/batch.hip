@@ -472,7 +472,7 @@ __global__ void __launch_bounds__(kBatchMaxBlock) batch_solve_kernel(const Batch
     }
     inner_total += it;
     v = b_norm_zb(I, z) / (1.0 + I.b_inf);
-    if (!conv && I.r < r_cap && it >= cap) {
+    if (!conv && I.r < r_cap && it >= cap && v > o.switch_tol) {
       const int r_new = min((int)ceil(o.rank_factor * I.r), r_cap);
       const double sigma = 1e-3 * sqrt(b_dot(I, U, U)) / sqrt((double)I.n * I.r);
       const int add = r_new - I.r;

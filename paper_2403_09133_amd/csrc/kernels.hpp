@@ -367,6 +367,23 @@ __global__ void __launch_bounds__(kBlock) dot_kernel(size_t N, const TX* __restr
   publish_partial(block_sum(s, sh), part);
 }
 
+// per-block partials of <X, Y> over the first r columns of n rows stored with
+// stride ld: element i of the compact order is visited by the thread that
+// visits it in dot_kernel over n r elements, so for the same grid the partials
+// (and the finished dot) equal those of the compact layout bit for bit
+[[maybe_unused]] static __global__ void __launch_bounds__(kBlock) dot_rows_kernel(unsigned N, int r, int ld,
+                                                          const double* __restrict__ X,
+                                                          const double* __restrict__ Y,
+                                                          double* __restrict__ part) {
+  __shared__ double sh[kBlock / 64];
+  double s = 0.0;
+  for (unsigned i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
+    const size_t q = (size_t)(i / (unsigned)r) * ld + i % (unsigned)r;
+    s += X[q] * Y[q];
+  }
+  publish_partial(block_sum(s, sh), part);
+}
+
 // Several dots over m-vectors for the quartic line search, in one pass
 // (per-block partials, array t at part + t * gridDim.x):
 //   out[0] = p2.p2, [1] = p1.p2, [2] = p1.p1, [3] = p0.p2, [4] = p0.p1,

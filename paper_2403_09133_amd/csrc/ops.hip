@@ -122,19 +122,19 @@ static void op_forward_w_impl(Problem& P, const double* U, const double* V, int 
 }
 
 // p1 = A(U D^T + D U^T), p2 = A(D D^T) (FP64): one pass for PAIR, two forward maps otherwise
-void op_forward_pair(Problem& P, const double* U, const double* D, int r, double* p1, double* p2,
-                     hipStream_t s) {
+void op_forward_pair(Problem& P, const double* U, const double* D, int r, int ld, double* p1,
+                     double* p2, hipStream_t s) {
   if (P.structure != LORADS_STRUCT_PAIR) {
-    op_forward<double>(P, U, D, r, r, p1, 2.0, s);
-    op_forward<double>(P, D, D, r, r, p2, 1.0, s);
+    op_forward<double>(P, U, D, r, ld, p1, 2.0, s);
+    op_forward<double>(P, D, D, r, ld, p2, 1.0, s);
     return;
   }
   P.prof.run(3, bytes_forward(P, r, 8) + 8.0 * P.m, s, [&] {
-    check_pair_offsets(P, r);
+    check_pair_offsets(P, ld);
     const int G = lane_group(r);
     LORADS_DISPATCH_GK(G, r, (k1_pair<double, G, 3, KC><<<rows_grid(P.nfchunks, G), kBlock, 0, s>>>(
                              P.nfchunks, P.fchunk_row.p, P.fchunk_start.p, P.rptr.p, P.pk.p,
-                             P.pcoef.p, P.pair_coef, U, D, r, r, p1, 1.0, nullptr, nullptr, 0.0,
+                             P.pcoef.p, P.pair_coef, U, D, r, ld, p1, 1.0, nullptr, nullptr, 0.0,
                              p2, nullptr, 0)));
     HIPCHK(hipGetLastError());
   });
@@ -299,6 +299,20 @@ void dot_to_slot(Problem& P, size_t N, const TX* X, const TY* Y, double scale, i
                  hipStream_t s) {
   const int grid = grid_for(N, kRedBlocks);
   dot_kernel<TX, TY><<<grid, kBlock, 0, s>>>(N, X, Y, P.part.p);
+  finish_slots<<<1, kBlock, 0, s>>>(grid, 1, P.part.p, scale, P.sc.p, slot);
+  HIPCHK(hipGetLastError());
+}
+
+void dot_rows_to_slot(Problem& P, int n, int r, int ld, const double* X, const double* Y,
+                      double scale, int slot, hipStream_t s) {
+  const size_t N = (size_t)n * r;
+  if (ld == r || N >= ((size_t)1 << 32)) {
+    if (ld != r) fail(LORADS_EINVAL, "padded factor too large for the row-strided dot");
+    dot_to_slot<double, double>(P, N, X, Y, scale, slot, s);
+    return;
+  }
+  const int grid = grid_for(N, kRedBlocks);
+  dot_rows_kernel<<<grid, kBlock, 0, s>>>((unsigned)N, r, ld, X, Y, P.part.p);
   finish_slots<<<1, kBlock, 0, s>>>(grid, 1, P.part.p, scale, P.sc.p, slot);
   HIPCHK(hipGetLastError());
 }

@@ -173,9 +173,10 @@ template <typename T>
 // rows of W (stride ldw) when P2 is given
 int op_cg(Problem& P, const T* W, int ldw, int r, int ld, const T* Pd, const T* P2, T* Q, T* t,
           int parity, hipStream_t s);
-// p1 = A(U D^T + D U^T) and p2 = A(D D^T) in FP64 (the exact line search)
-void op_forward_pair(Problem& P, const double* U, const double* D, int r, double* p1, double* p2,
-                     hipStream_t s);
+// p1 = A(U D^T + D U^T) and p2 = A(D D^T) in FP64 (the exact line search),
+// U and D with row stride ld
+void op_forward_pair(Problem& P, const double* U, const double* D, int r, int ld, double* p1,
+                     double* p2, hipStream_t s);
 // leading dimension of the CG work buffers: PAIR problems pad rows to a
 // multiple of 64 bytes (zero padding), so every row the CG operator gathers
 // sits in whole, aligned 64-byte sectors; other structures use r
@@ -198,6 +199,10 @@ void linesearch_slots(Problem& P, const double* z, const double* p1, const doubl
                       const double* lam, int slot, hipStream_t s);
 template <typename TX, typename TY>
 void dot_to_slot(Problem& P, size_t N, const TX* X, const TY* Y, double scale, int slot, hipStream_t s);
+// the same for n x r factors stored with row stride ld (bit-identical to the
+// compact dot_to_slot over n r elements)
+void dot_rows_to_slot(Problem& P, int n, int r, int ld, const double* X, const double* Y,
+                      double scale, int slot, hipStream_t s);
 
 inline int grid_for(size_t N, int cap = 2048) {
   size_t g = (N + kBlock - 1) / kBlock;

@@ -89,32 +89,68 @@ double gamma_of(const Problem& P, const lorads_options& o, double rho) {
 //   L(U) = <C, U U^T> + lam^T (A(U U^T) - b) + rho/2 ||A(U U^T) - b||^2
 //   grad = 2 (C + A*(lam + rho (A(U U^T) - b))) U
 // ===========================================================================
+// Factor-shaped work arrays have row stride ld: for PAIR problems rows are
+// padded to whole 64-byte sectors (zero padding, the layout of the CG work
+// buffers), so a gathered row of U or D is one aligned cache line; other
+// structures use ld = r.  Zero padding is kept by every update (the vector
+// updates are linear and the operators write columns < r only).
 struct AlmState {
-  int n, m, r;
+  int n, m, r, ld;
   DevBuf<double> G, Gn, D, Q, CD, p1, p2, Sn, Yn;
   std::vector<DevBuf<double>> S, Y;
   std::vector<double> rhoh;  // 1 / <S, Y>
   int head = 0, count = 0;
 };
 
-static void alm_alloc(AlmState& A, int n, int m, int r, int mem) {
-  A.n = n; A.m = m; A.r = r;
-  const size_t N = (size_t)n * r;
-  A.G.alloc(N); A.Gn.alloc(N); A.D.alloc(N); A.Q.alloc(N); A.CD.alloc(N);
-  A.Sn.alloc(N); A.Yn.alloc(N);
+static int alm_ld(const Problem& P, int r) {
+  return P.structure == LORADS_STRUCT_PAIR ? cg_ld(P, r, (int)sizeof(double)) : r;
+}
+
+static void alm_alloc(AlmState& A, int n, int m, int r, int ld, int mem, hipStream_t s) {
+  A.n = n; A.m = m; A.r = r; A.ld = ld;
+  const size_t N = (size_t)n * ld;
+  for (DevBuf<double>* b : {&A.G, &A.Gn, &A.D, &A.Q, &A.CD, &A.Sn, &A.Yn}) {
+    b->alloc(N);
+    if (ld != r) b->zero(s);
+  }
   A.p1.alloc(m); A.p2.alloc(m);
   A.S.resize(mem); A.Y.resize(mem); A.rhoh.assign(mem, 0.0);
-  for (int i = 0; i < mem; ++i) { A.S[i].alloc(N); A.Y[i].alloc(N); }
+  for (int i = 0; i < mem; ++i) {
+    A.S[i].alloc(N);
+    A.Y[i].alloc(N);
+    if (ld != r) { A.S[i].zero(s); A.Y[i].zero(s); }
+  }
   A.head = A.count = 0;
 }
 
 // G = 2 (C + A*(lam + rho (z - b))) U with z = A(U U^T) recomputed
 static void alm_gradient(Problem& P, AlmState& A, const double* U, double* G, double rho,
                          hipStream_t s, double& bytes) {
-  op_forward_w(P, U, U, A.r, A.r, P.zbuf.p, P.wbuf.p, P.lam.p, rho, s);
-  op_adjoint<double>(P, P.wbuf.p, 1.0, U, A.r, A.r, G, A.r, 2.0, s);
+  op_forward_w(P, U, U, A.r, A.ld, P.zbuf.p, P.wbuf.p, P.lam.p, rho, s);
+  op_adjoint<double>(P, P.wbuf.p, 1.0, U, A.r, A.ld, G, A.ld, 2.0, s);
   bytes += bytes_forward(P, A.r, 8) + bytes_adjoint(P, A.r, 8, true);
 }
+
+// Phase I's copy of U in the working layout (the master P.U stays n x r)
+struct AlmFactor {
+  DevBuf<double> buf;
+  double* U = nullptr;
+  int ld = 0;
+  void load(Problem& P, int r, int ld_, hipStream_t s) {
+    ld = ld_;
+    if (ld == r) { U = P.U.p; return; }
+    buf.alloc((size_t)P.n * ld);
+    buf.zero(s);
+    copy_rows<double, double><<<gridN((size_t)P.n * r), kBlock, 0, s>>>(P.n, r, P.U.p, r, buf.p, ld);
+    HIPCHK(hipGetLastError());
+    U = buf.p;
+  }
+  void store(Problem& P, int r, hipStream_t s) {
+    if (ld == r) return;
+    copy_rows<double, double><<<gridN((size_t)P.n * r), kBlock, 0, s>>>(P.n, r, buf.p, ld, P.U.p, r);
+    HIPCHK(hipGetLastError());
+  }
+};
 
 static double host_norm_zb(Problem& P, hipStream_t s) {
   // ||z - b||_2 via dual_update with rho = 0 (lam unchanged)
@@ -131,9 +167,15 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
   const double c_fro = P.c_fro;
   double rho = o.rho0 > 0 ? o.rho0 : 1.0 / std::max(1.0, P.b_inf);
   AlmState A;
-  alm_alloc(A, n, m, r, o.lbfgs_mem);
-  double* U = P.U.p;
-  op_forward<double>(P, U, U, r, r, P.zbuf.p, 1.0, s);
+  AlmFactor F;
+  F.load(P, r, alm_ld(P, r), s);
+  alm_alloc(A, n, m, r, F.ld, o.lbfgs_mem, s);
+  double* U = F.U;
+  // factor dots in the compact summation order whatever the row stride
+  auto adot = [&](const double* X, const double* Y, double scale, int slot, hipStream_t st) {
+    dot_rows_to_slot(P, n, r, F.ld, X, Y, scale, slot, st);
+  };
+  op_forward<double>(P, U, U, r, F.ld, P.zbuf.p, 1.0, s);
   info.op_bytes += bytes_forward(P, r, 8);
   double v = host_norm_zb(P, s) / (1.0 + P.b_inf);
   double v_ref = INFINITY;
@@ -145,17 +187,17 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
   bool warm_pending = info.warm;
   DevBuf<double> U_start;
   if (warm_pending) {
-    U_start.alloc((size_t)n * r);
-    HIPCHK(hipMemcpyAsync(U_start.p, U, (size_t)n * r * sizeof(double), hipMemcpyDeviceToDevice, s));
+    U_start.alloc((size_t)n * F.ld);
+    HIPCHK(hipMemcpyAsync(U_start.p, U, (size_t)n * F.ld * sizeof(double), hipMemcpyDeviceToDevice, s));
   }
   while (v > o.switch_tol && outer < o.alm_outer_max) {
     const int cap = (r < r_cap) ? o.rank_grow_iters : o.alm_inner_max;
     const double tol = std::max(o.alm_inner_rel * v, o.alm_inner_floor);
-    const size_t N = (size_t)n * r;
+    const size_t N = (size_t)n * F.ld;
     // ---------------- inner L-BFGS ----------------
     A.head = A.count = 0;
     alm_gradient(P, A, U, A.G.p, rho, s, info.op_bytes);
-    dot_to_slot<double, double>(P, N, A.G.p, A.G.p, 1.0, S_GEN, s);
+    adot(A.G.p, A.G.p, 1.0, S_GEN, s);
     read_slots(P, S_GEN, h, 1, s);
     double gnorm2 = h[0];  // ||G||^2 of the current gradient
     int it = 0;
@@ -172,7 +214,7 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
       // alphas live in slots S_GEN+16+t
       for (size_t t = 0; t < order.size(); ++t) {
         const int k = order[t];
-        dot_to_slot<double, double>(P, N, A.S[k].p, A.Q.p, A.rhoh[k], S_GEN + 16 + (int)t, s);
+        adot(A.S[k].p, A.Q.p, A.rhoh[k], S_GEN + 16 + (int)t, s);
         axpby_dev<double><<<gridN(N), kBlock, 0, s>>>(N, P.sc.p, S_GEN + 16 + (int)t, -1.0,
                                                       A.Y[k].p, 1.0, A.Q.p);
       }
@@ -180,15 +222,15 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
       if (A.count > 0) {
         const int k = order[0];
         // q *= <S_k, Y_k> / <Y_k, Y_k>
-        dot_to_slot<double, double>(P, N, A.S[k].p, A.Y[k].p, 1.0, S_GEN + 1, s);
-        dot_to_slot<double, double>(P, N, A.Y[k].p, A.Y[k].p, 1.0, S_GEN + 2, s);
+        adot(A.S[k].p, A.Y[k].p, 1.0, S_GEN + 1, s);
+        adot(A.Y[k].p, A.Y[k].p, 1.0, S_GEN + 2, s);
         axpby_slots<double><<<gridN(N), kBlock, 0, s>>>(N, P.sc.p, S_GEN + 1, S_GEN + 2, 1, A.Q.p,
                                                        0.0, A.Q.p);
       }
       for (int t = (int)order.size() - 1; t >= 0; --t) {
         const int k = order[t];
         // beta = rho_k <Y_k, q>;  q += (alpha_t - beta) S_k
-        dot_to_slot<double, double>(P, N, A.Y[k].p, A.Q.p, A.rhoh[k], S_GEN + 6, s);
+        adot(A.Y[k].p, A.Q.p, A.rhoh[k], S_GEN + 6, s);
         axpby_slots<double><<<gridN(N), kBlock, 0, s>>>(N, P.sc.p, S_GEN + 16 + t, S_GEN + 6, 0,
                                                        A.S[k].p, 1.0, A.Q.p);
       }
@@ -200,13 +242,13 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
       double alpha = 0.0;
       bool checked = false;
       for (int attempt = 0; attempt < 3; ++attempt) {
-        op_forward_pair(P, U, A.D.p, r, A.p1.p, A.p2.p, s);
-        op_adjoint<double>(P, (const double*)nullptr, 1.0, A.D.p, r, r, A.CD.p, r, 1.0, s);
+        op_forward_pair(P, U, A.D.p, r, F.ld, A.p1.p, A.p2.p, s);
+        op_adjoint<double>(P, (const double*)nullptr, 1.0, A.D.p, r, F.ld, A.CD.p, F.ld, 1.0, s);
         info.op_bytes += 2 * bytes_forward(P, r, 8) + bytes_adjoint(P, r, 8, true);
-        dot_to_slot<double, double>(P, N, A.CD.p, U, 2.0, S_GEN + 1, s);
-        dot_to_slot<double, double>(P, N, A.CD.p, A.D.p, 1.0, S_GEN + 2, s);
+        adot(A.CD.p, U, 2.0, S_GEN + 1, s);
+        adot(A.CD.p, A.D.p, 1.0, S_GEN + 2, s);
         linesearch_slots(P, P.zbuf.p, A.p1.p, A.p2.p, P.lam.p, S_GEN + 3, s);
-        if (!checked) dot_to_slot<double, double>(P, N, A.G.p, A.D.p, 1.0, S_GEN + 10, s);
+        if (!checked) adot(A.G.p, A.D.p, 1.0, S_GEN + 10, s);
         read_slots(P, S_GEN + 1, h, checked ? 9 : 10, s);
         if (!checked) {
           checked = true;
@@ -237,8 +279,8 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
       alm_gradient(P, A, U, A.Gn.p, rho, s, info.op_bytes);
       axpby<double, double><<<gridN(N), kBlock, 0, s>>>(N, 1.0, A.Gn.p, 0.0, A.Yn.p);
       axpby<double, double><<<gridN(N), kBlock, 0, s>>>(N, -1.0, A.G.p, 1.0, A.Yn.p);
-      dot_to_slot<double, double>(P, N, A.Sn.p, A.Yn.p, 1.0, S_GEN, s);
-      dot_to_slot<double, double>(P, N, A.Gn.p, A.Gn.p, 1.0, S_GEN + 1, s);
+      adot(A.Sn.p, A.Yn.p, 1.0, S_GEN, s);
+      adot(A.Gn.p, A.Gn.p, 1.0, S_GEN + 1, s);
       read_slots(P, S_GEN, h, 2, s);
       gnorm2 = h[1];
       if (h[0] > 0.0) {
@@ -261,21 +303,24 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
     if (warm_pending) {
       warm_pending = false;
       if (!(v < v_start)) {
-        HIPCHK(hipMemcpyAsync(U, U_start.p, (size_t)n * r * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(U, U_start.p, (size_t)n * F.ld * sizeof(double), hipMemcpyDeviceToDevice, s));
         P.lam.zero(s);
         rho = rho_start;
         info.warm_fallback = 1;
-        op_forward<double>(P, U, U, r, r, P.zbuf.p, 1.0, s);
+        op_forward<double>(P, U, U, r, F.ld, P.zbuf.p, 1.0, s);
         info.op_bytes += bytes_forward(P, r, 8);
         v = host_norm_zb(P, s) / (1.0 + P.b_inf);
         continue;
       }
     }
-    if (!conv && r < r_cap && it >= cap) {
+    // a hard inner solve raises the rank only while Phase I goes on: once the
+    // infeasibility meets the switching tolerance the phase ends
+    if (!conv && r < r_cap && it >= cap && v > o.switch_tol) {
       const int r_new = std::min((int)std::ceil(o.rank_factor * r), r_cap);
-      dot_to_slot<double, double>(P, N, U, U, 1.0, S_GEN, s);
+      adot(U, U, 1.0, S_GEN, s);
       read_slots(P, S_GEN, h, 1, s);
       const double sigma = 1e-3 * std::sqrt(h[0]) / std::sqrt((double)n * r);
+      F.store(P, r, s);
       DevBuf<double> Unew;
       Unew.alloc((size_t)n * r_new);
       grow_rank_kernel<<<gridN((size_t)n * r_new), kBlock, 0, s>>>(n, r, r_new, U, Unew.p, sigma,
@@ -283,12 +328,13 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
       HIPCHK(hipGetLastError());
       HIPCHK(hipStreamSynchronize(s));
       P.U = std::move(Unew);
-      U = P.U.p;
       r = r_new;
       P.rank = r;
-      alm_alloc(A, n, m, r, o.lbfgs_mem);
+      F.load(P, r, alm_ld(P, r), s);
+      U = F.U;
+      alm_alloc(A, n, m, r, F.ld, o.lbfgs_mem, s);
       ++growths;
-      op_forward<double>(P, U, U, r, r, P.zbuf.p, 1.0, s);
+      op_forward<double>(P, U, U, r, F.ld, P.zbuf.p, 1.0, s);
       info.op_bytes += bytes_forward(P, r, 8);
       v = host_norm_zb(P, s) / (1.0 + P.b_inf);
       continue;
@@ -301,6 +347,7 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
     }
     ++outer;
   }
+  F.store(P, r, s);
   info.alm_outer = outer;
   info.alm_inner = inner_total;
   info.growths = growths;

@@ -133,3 +133,25 @@ def test_rank_growth_keeps_columns():
     G = alm.grow_rank(U, 5, 0, 9)
     assert G.shape == (4, 5) and np.array_equal(G[:, :3], U)
     assert np.all(np.abs(G[:, 3:]) < 1e-2 * np.linalg.norm(U))
+
+
+@pytest.mark.parametrize("v_after", [0.0, 10.0])
+def test_rank_growth_only_while_phase_one_continues(monkeypatch, v_after):
+    """An inner solve that stops at the iteration cap raises the rank only when
+    the infeasibility after it is still above the switching tolerance."""
+    p = sdpgen.mc_planted(12, 10, 2, 3, count=60)
+    U0 = np.random.default_rng(1).standard_normal((p.n, 3))
+    opts = Options(switch_tol=1e-3, rank_grow_iters=5, alm_outer_max=1)
+
+    def capped(prob, U, lam, rho, tol, cap, mem, c_fro):
+        # the cap is reached; the infeasibility afterwards is v_after (1 + ||b||_inf)
+        z = prob.b.copy()
+        z[0] += v_after * (1.0 + np.max(np.abs(prob.b)))
+        return U, z, cap, False
+
+    monkeypatch.setattr(alm, "lbfgs_inner", capped)
+    out = alm.alm(p, U0, np.zeros(p.m), opts)
+    if v_after == 0.0:
+        assert out["growths"] == 0 and out["rank"] == 3
+    else:
+        assert out["growths"] >= 1 and out["rank"] > 3
