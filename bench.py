@@ -234,12 +234,19 @@ def ops_profile(key: str, reps: int):
         ctx.cg_solve(V, out, X.zero_(), 2.0, 1.5, 0.0, 20)
         torch.cuda.synchronize()
         print(f"[bench] ops rep {i} done", file=sys.stderr, flush=True)
-    a = torch.empty(64 << 20, dtype=torch.float32, device=dev)
+    calibration_copy()
+    ctx.close()
+
+
+def calibration_copy():
+    """One 256 MiB device-to-device copy: its FETCH_SIZE / WRITE_SIZE readings
+    against the known size give the scale of the byte counters."""
+    import torch
+    a = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
     b = torch.ones_like(a)
     a.copy_(b)
     torch.cuda.synchronize()
     print(f"[bench] copy of {a.numel() * 4} bytes done", file=sys.stderr, flush=True)
-    ctx.close()
 
 
 def main():
@@ -255,6 +262,8 @@ def main():
     ap.add_argument("--ops-profile", type=int, default=0, metavar="REPS",
                     help="only run REPS applications of each operator at the workload's size (FP32, "
                          "r0 columns) and a 256 MiB device copy, for hardware-counter runs")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with a 256 MiB device copy (byte-counter calibration in counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the method's batch and single-instance paths are "
@@ -348,6 +357,8 @@ def main():
                                    admm_iters=r64["admm_iters"], cg_iters=r64["cg_iters"])
         extra["fp32_vs_fp64_obj_rel"] = abs(last["obj"] - r64["obj"]) / max(1.0, abs(r64["obj"]))
     ctx.close()
+    if args.copy_calibration:
+        calibration_copy()
 
     line = {
         "metric": "A(UV^T)+A^*(y)V as HBM GB/s; time-to-1e-6 KKT residual, FP32/batched vs FP64",

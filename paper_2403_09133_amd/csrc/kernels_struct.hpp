@@ -238,6 +238,12 @@ __global__ void __launch_bounds__(kBlock) k3_diag(int n, const T* __restrict__ d
 //     i.e. (gamma I + rho A* A(. V^T) V) applied to Pm; block partials of <Pm, Q>.
 //     Each constraint's inner product is formed by both of its rows, so no
 //     per-constraint buffer is written or gathered.
+//   MODE 2 (gradient form of MODE 0 with V = U, uniform a): the multiplier-side
+//     weight of each entry is formed in place, w = lam + rho (a <U_t, U_p> - b),
+//     from lam and b stored per incident entry (streamed, not gathered); the
+//     entry's inner product and w are evaluated exactly as the forward map
+//     (MODE 1 of k1_pair) evaluates them, so out equals MODE 0 fed with that
+//     map's w bit for bit.
 // ===========================================================================
 template <typename T, int G, int MODE, int KC = kMaxCols>
 __global__ void __launch_bounds__(kBlock) kpair_rows(
@@ -246,13 +252,15 @@ __global__ void __launch_bounds__(kBlock) kpair_rows(
     const int* __restrict__ inc_nb, const int* __restrict__ inc_id, const T* __restrict__ pcoef,
     double pair_coef, const T* __restrict__ w, const T* __restrict__ V, const T* __restrict__ Pm,
     int r, int ld, T* __restrict__ out, int ldo, double out_scale, double* __restrict__ sc,
-    int parity, double* __restrict__ part) {
+    int parity, double* __restrict__ part, const double* __restrict__ lam_inc,
+    const double* __restrict__ b_inc, double rho_w) {
   constexpr int NG = 64 / G;
   constexpr int CH = kPairStage;  // incident entries staged per wave and pass
   __shared__ double sh[kBlock / 64];
   __shared__ int s_nb[kBlock / 64][CH];
   using A = typename OpAcc<T>::type;
   __shared__ A s_cf[kBlock / 64][CH];
+  __shared__ double s_bi[MODE == 2 ? kBlock / 64 : 1][MODE == 2 ? CH : 1];
   if (MODE == 1 && sc[S_DONE + parity] != 0.0) return;
   const int wl = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int grp = wl / G, lane = wl & (G - 1);
@@ -267,9 +275,9 @@ __global__ void __launch_bounds__(kBlock) kpair_rows(
       const int c = lane + t * G;
       acc[t] = 0;
       pt[t] = (MODE == 1 && c < r) ? (A)Pm[row * ld + c] : (A)0;
-      vt[t] = (MODE == 1 && c < r) ? (A)V[row * ld + c] : (A)0;
+      vt[t] = (MODE != 0 && c < r) ? (A)V[row * ld + c] : (A)0;
     }
-    if (MODE == 0 && c_scale != 0.0) {
+    if (MODE != 1 && c_scale != 0.0) {
       for (int e = cptr[row] + grp; e < cptr[row + 1]; e += NG) {
         const int k = ccol[e];
         const A a = (A)(c_scale * (double)cval[e]);
@@ -290,7 +298,13 @@ __global__ void __launch_bounds__(kBlock) kpair_rows(
 #pragma unroll
       for (int q = 0; q < CH / 64; ++q) {
         const int j = wl + 64 * q;
-        if (j < cnt) {
+        if (MODE == 2) {
+          if (j < cnt) {
+            nbw[j] = inc_nb[base + j];
+            cfw[j] = (A)lam_inc[base + j];
+            s_bi[wid][j] = b_inc[base + j];
+          }
+        } else if (j < cnt) {
           nbw[j] = inc_nb[base + j];
           double a = pair_coef;
           if (pcoef != nullptr || MODE == 0) {
@@ -324,6 +338,38 @@ __global__ void __launch_bounds__(kBlock) kpair_rows(
             for (int t = 0; t < KC; ++t) {
               const int c = lane + t * G;
               if (c < r) acc[t] += coef[u] * (A)V[p[u] + c];
+            }
+        } else if (MODE == 2) {
+          // coef holds lam of the entry (0 past the list); w and a w as in
+          // the forward map and the adjoint's staging
+          A vp[kUnroll][KC], d[kUnroll];
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            A s = 0;
+#pragma unroll
+            for (int t = 0; t < KC; ++t) {
+              const int c = lane + t * G;
+              vp[u][t] = c < r ? (A)V[p[u] + c] : (A)0;
+              s += vt[t] * vp[u][t] + vp[u][t] * vt[t];
+            }
+            d[u] = s;
+          }
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) d[u] = group_sum<G>(d[u]);
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            const int ju = j + u * NG;
+            const bool ok = ju < cnt;
+            const double val = (double)d[u] * pair_coef;
+            const double wv = (double)coef[u] + rho_w * (val - s_bi[wid][min(ju, CH - 1)]);
+            coef[u] = ok ? (A)(pair_coef * wv) : (A)0;
+          }
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+            for (int t = 0; t < KC; ++t) {
+              const int c = lane + t * G;
+              if (c < r) acc[t] += coef[u] * vp[u][t];
             }
         } else {
           A vp[kUnroll][KC], d[kUnroll];

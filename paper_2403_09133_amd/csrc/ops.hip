@@ -166,7 +166,7 @@ static void op_adjoint_impl(Problem& P, const T* w, double c_scale, const T* V, 
     LORADS_DISPATCH_GK(G, r, (kpair_rows<T, G, 0, KC><<<waves_grid(P.n), kBlock, 0, s>>>(
                              P.n, P.cptr.p, P.ccol.p, cv<T>(P), c_scale, P.inc_ptr.p, P.inc_nb.p,
                              P.inc_id.p, pc<T>(P), P.pair_coef, w, V, nullptr, r, ld, out, ldo,
-                             out_scale, nullptr, 0, nullptr)));
+                             out_scale, nullptr, 0, nullptr, nullptr, nullptr, 0.0)));
   } else {
     LORADS_DISPATCH_G(G, (k2_generic<T, G, 0><<<rows_grid(P.n, G), kBlock, 0, s>>>(
                              P.n, P.cptr.p, P.ccol.p, cv<T>(P), c_scale, P.aptr.p, P.acol.p,
@@ -174,6 +174,33 @@ static void op_adjoint_impl(Problem& P, const T* w, double c_scale, const T* V, 
                              nullptr, 0, nullptr)));
   }
   HIPCHK(hipGetLastError());
+}
+
+bool grad_pair_ready(const Problem& P) {
+  return P.structure == LORADS_STRUCT_PAIR && P.inc_b.n > 0 && P.inc_lam.n == P.inc_b.n;
+}
+
+void refresh_inc_lam(Problem& P, hipStream_t s) {
+  if (P.structure != LORADS_STRUCT_PAIR || P.inc_b.n == 0) return;
+  P.inc_lam.alloc(P.inc_b.n);
+  gather_kernel<double><<<grid_for(P.inc_b.n), kBlock, 0, s>>>((int)P.inc_b.n, P.inc_id.p, P.lam.p,
+                                                               P.inc_lam.p);
+  HIPCHK(hipGetLastError());
+}
+
+void op_grad_pair(Problem& P, const double* U, int r, int ld, double rho, double* out, int ldo,
+                  double out_scale, hipStream_t s) {
+  if (!grad_pair_ready(P)) fail(LORADS_EINVAL, "gradient form needs per-entry lam and b");
+  P.prof.run(2, bytes_adjoint(P, r, 8, true), s, [&] {
+    check_pair_offsets(P, std::max(ld, ldo));
+    const int G = lane_group(r);
+    if (r > 4 * G) fail(LORADS_EINVAL, "rank above 256 is not supported");
+    LORADS_DISPATCH_GK(G, r, (kpair_rows<double, G, 2, KC><<<waves_grid(P.n), kBlock, 0, s>>>(
+                             P.n, P.cptr.p, P.ccol.p, P.cval.p, 1.0, P.inc_ptr.p, P.inc_nb.p,
+                             P.inc_id.p, nullptr, P.pair_coef, nullptr, U, nullptr, r, ld, out, ldo,
+                             out_scale, nullptr, 0, nullptr, P.inc_lam.p, P.inc_b.p, rho)));
+    HIPCHK(hipGetLastError());
+  });
 }
 
 int cg_ld(const Problem& P, int r, int elem_bytes) {
@@ -221,7 +248,7 @@ int op_cg(Problem& P, const T* W, int ldw, int r, int ld, const T* Pd, const T* 
       LORADS_DISPATCH_GK(G, r, (kpair_rows<T, G, 1, KC><<<grid, kBlock, 0, s>>>(
                                P.n, nullptr, nullptr, nullptr, 0.0, P.inc_ptr.p, P.inc_nb.p,
                                P.inc_id.p, pc<T>(P), P.pair_coef, nullptr, W, Pg, r, ldw, Q, ld,
-                               1.0, sc, parity, P.part.p)));
+                               1.0, sc, parity, P.part.p, nullptr, nullptr, 0.0)));
     }
     np = grid;
   } else {

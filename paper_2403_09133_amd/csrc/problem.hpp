@@ -124,6 +124,9 @@ struct Problem {
   DevBuf<int> fchunk_row, fchunk_start;
   int nfchunks = 0;
   DevBuf<int> inc_ptr, inc_nb, inc_id;  // incident lists: row pointers, partner, internal id
+  // uniform coefficient only: b and the current lam per incident entry, so the
+  // gradient form of the adjoint streams them instead of gathering w by id
+  DevBuf<double> inc_b, inc_lam;
 
   // solver scratch
   DevBuf<double> sc;
@@ -177,6 +180,14 @@ int op_cg(Problem& P, const T* W, int ldw, int r, int ld, const T* Pd, const T* 
 // U and D with row stride ld
 void op_forward_pair(Problem& P, const double* U, const double* D, int r, int ld, double* p1,
                      double* p2, hipStream_t s);
+// gradient form for PAIR problems with a uniform coefficient:
+//   out = out_scale (C + A*(lam + rho (A(U U^T) - b))) U
+// with lam and b read per incident entry (refresh_inc_lam after lam changes);
+// bit-identical to op_forward_w followed by op_adjoint
+bool grad_pair_ready(const Problem& P);
+void refresh_inc_lam(Problem& P, hipStream_t s);
+void op_grad_pair(Problem& P, const double* U, int r, int ld, double rho, double* out, int ldo,
+                  double out_scale, hipStream_t s);
 // leading dimension of the CG work buffers: PAIR problems pad rows to a
 // multiple of 64 bytes (zero padding), so every row the CG operator gathers
 // sits in whole, aligned 64-byte sectors; other structures use r

@@ -287,6 +287,11 @@ std::unique_ptr<Problem> ingest(const lorads_problem& p, hipStream_t s) {
     P->inc_ptr.upload(inc_ptr, s);
     P->inc_nb.upload(inc_nb, s);
     P->inc_id.upload(inc_id, s);
+    if (uniform) {
+      std::vector<double> bi(inc_id.size());
+      for (size_t t = 0; t < inc_id.size(); ++t) bi[t] = b_int[inc_id[t]];
+      P->inc_b.upload(bi, s);
+    }
   }
 
   P->kptr.upload(kptr, s);

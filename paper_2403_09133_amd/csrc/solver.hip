@@ -126,8 +126,14 @@ static void alm_alloc(AlmState& A, int n, int m, int r, int ld, int mem, hipStre
 // G = 2 (C + A*(lam + rho (z - b))) U with z = A(U U^T) recomputed
 static void alm_gradient(Problem& P, AlmState& A, const double* U, double* G, double rho,
                          hipStream_t s, double& bytes) {
-  op_forward_w(P, U, U, A.r, A.ld, P.zbuf.p, P.wbuf.p, P.lam.p, rho, s);
-  op_adjoint<double>(P, P.wbuf.p, 1.0, U, A.r, A.ld, G, A.ld, 2.0, s);
+  if (grad_pair_ready(P)) {
+    // z for the line search and the infeasibility; the gradient forms w per entry
+    op_forward<double>(P, U, U, A.r, A.ld, P.zbuf.p, 1.0, s);
+    op_grad_pair(P, U, A.r, A.ld, rho, G, A.ld, 2.0, s);
+  } else {
+    op_forward_w(P, U, U, A.r, A.ld, P.zbuf.p, P.wbuf.p, P.lam.p, rho, s);
+    op_adjoint<double>(P, P.wbuf.p, 1.0, U, A.r, A.ld, G, A.ld, 2.0, s);
+  }
   bytes += bytes_forward(P, A.r, 8) + bytes_adjoint(P, A.r, 8, true);
 }
 
@@ -168,6 +174,7 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
   double rho = o.rho0 > 0 ? o.rho0 : 1.0 / std::max(1.0, P.b_inf);
   AlmState A;
   AlmFactor F;
+  refresh_inc_lam(P, s);
   F.load(P, r, alm_ld(P, r), s);
   alm_alloc(A, n, m, r, F.ld, o.lbfgs_mem, s);
   double* U = F.U;
@@ -305,6 +312,7 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
       if (!(v < v_start)) {
         HIPCHK(hipMemcpyAsync(U, U_start.p, (size_t)n * F.ld * sizeof(double), hipMemcpyDeviceToDevice, s));
         P.lam.zero(s);
+        refresh_inc_lam(P, s);
         rho = rho_start;
         info.warm_fallback = 1;
         op_forward<double>(P, U, U, r, F.ld, P.zbuf.p, 1.0, s);
@@ -341,6 +349,7 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
     }
     if (v <= o.alm_eta * v_ref) {
       dual_update_slot(P, P.zbuf.p, rho, P.lam.p, S_GEN, s);
+      refresh_inc_lam(P, s);
       v_ref = v;
     } else {
       rho *= o.alm_rho_factor;
@@ -385,14 +394,18 @@ static int half_step(Problem& P, const double* W, double* out, int r, double rho
                      SolveInfo& info) {
   const int ld = B.ld;
   const size_t N = (size_t)P.n * ld;  // CG layout
-  op_forward_w(P, W, W, r, r, P.zbuf.p, P.wbuf.p, P.lam.p, rho, s);
-  info.op_bytes += bytes_forward(P, r, 8) + bytes_adjoint(P, r, 8, true);
-  if constexpr (std::is_same<T, double>::value) {
-    op_adjoint<double>(P, P.wbuf.p, 1.0, W, r, r, B.R.p, ld, -1.0, s);
+  double* R = std::is_same<T, double>::value ? reinterpret_cast<double*>(B.R.p) : R64.p;
+  if (grad_pair_ready(P)) {
+    // the gradient form needs no forward map here (z is recomputed after the step)
+    op_grad_pair(P, W, r, r, rho, R, ld, -1.0, s);
+    info.op_bytes += bytes_adjoint(P, r, 8, true);
   } else {
-    op_adjoint<double>(P, P.wbuf.p, 1.0, W, r, r, R64.p, ld, -1.0, s);
-    convert_kernel<double, float><<<gridN(N), kBlock, 0, s>>>(N, R64.p, B.R.p);
+    op_forward_w(P, W, W, r, r, P.zbuf.p, P.wbuf.p, P.lam.p, rho, s);
+    op_adjoint<double>(P, P.wbuf.p, 1.0, W, r, r, R, ld, -1.0, s);
+    info.op_bytes += bytes_forward(P, r, 8) + bytes_adjoint(P, r, 8, true);
   }
+  if constexpr (!std::is_same<T, double>::value)
+    convert_kernel<double, float><<<gridN(N), kBlock, 0, s>>>(N, R64.p, B.R.p);
   copy_rows<double, T><<<gridN((size_t)P.n * r), kBlock, 0, s>>>(P.n, r, W, r, B.W.p, B.ldw);
   HIPCHK(hipMemsetAsync(B.X.p, 0, N * sizeof(T), s));
   double rel;
@@ -421,6 +434,7 @@ static void phase2_t(Problem& P, const lorads_options& o, double rho, SolveInfo&
   }
   CgBufs<T> B;
   B.alloc(n, m, ldc, P.structure == LORADS_STRUCT_PAIR, s);
+  refresh_inc_lam(P, s);
   const int maxit = (int)std::min<long long>((long long)N, o.cg_maxit);
   const double floor = (std::is_same<T, double>::value) ? o.cg_tol_floor : std::max(o.cg_tol_floor, 1e-6);
   double kkt = INFINITY, pinf = INFINITY, dres = INFINITY, gamma = gamma_of(P, o, rho);
@@ -440,6 +454,7 @@ static void phase2_t(Problem& P, const lorads_options& o, double rho, SolveInfo&
     op_forward<double>(P, P.U.p, P.V.p, r, r, P.zbuf.p, 1.0, s);
     info.op_bytes += bytes_forward(P, r, 8);
     dual_update_slot(P, P.zbuf.p, rho, P.lam.p, S_GEN, s);
+    refresh_inc_lam(P, s);
     axpby<double, double><<<gridN(N), kBlock, 0, s>>>(N, 1.0, P.V.p, -1.0, Vold.p);  // V+ - V
     dot_to_slot<double, double>(P, N, Vold.p, Vold.p, 1.0, S_GEN + 1, s);
     HIPCHK(hipGetLastError());
