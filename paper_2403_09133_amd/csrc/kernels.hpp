@@ -384,6 +384,134 @@ __global__ void __launch_bounds__(kBlock) dot_kernel(size_t N, const TX* __restr
   publish_partial(block_sum(s, sh), part);
 }
 
+// ---------------------------------------------------------------------------
+// Fused passes of the L-BFGS two-loop recursion and step.  Each visits the
+// first r columns of n rows (stride ld) in the compact order of
+// dot_rows_kernel (same grid), evaluates the same elementwise expressions as
+// axpby / axpby_dev / axpby_slots / add_kernel, and writes the block partials
+// of its dots to part + t * gridDim.x, so every value equals that of the
+// unfused sequence bit for bit.  Padding columns are not touched (they are
+// zero in every factor-shaped array and stay zero).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ size_t compact_to_row(unsigned i, int r, int ld) {
+  return (size_t)(i / (unsigned)r) * ld + i % (unsigned)r;
+}
+
+// partials of <X_t, Y_t>, t < k <= 3
+[[maybe_unused]] static __global__ void __launch_bounds__(kBlock) dots3_kernel(
+    unsigned N, int r, int ld, const double* __restrict__ X0, const double* __restrict__ Y0,
+    const double* __restrict__ X1, const double* __restrict__ Y1, const double* __restrict__ X2,
+    const double* __restrict__ Y2, int k, double* __restrict__ part) {
+  __shared__ double sh[kBlock / 64];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (unsigned i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
+    const size_t q = compact_to_row(i, r, ld);
+    s0 += X0[q] * Y0[q];
+    if (k > 1) s1 += X1[q] * Y1[q];
+    if (k > 2) s2 += X2[q] * Y2[q];
+  }
+  publish_partial(block_sum(s0, sh), part);
+  if (k > 1) publish_partial(block_sum(s1, sh), part + gridDim.x);
+  if (k > 2) publish_partial(block_sum(s2, sh), part + 2 * gridDim.x);
+}
+
+// first loop: y = (sign sc[slot]) x + 1.0 yin (yin = y, or G before q exists);
+// with scale, then y = (sc[sa] / sc[sb]) y + 0.0 y; partials of <u, y>
+[[maybe_unused]] static __global__ void __launch_bounds__(kBlock) lbfgs_first_kernel(
+    unsigned N, int r, int ld, const double* __restrict__ sc, int slot, double sign,
+    const double* __restrict__ x, const double* yin, double* y, int scale, int sa, int sb,
+    const double* __restrict__ u, double* __restrict__ part) {
+  __shared__ double sh[kBlock / 64];
+  const double a = sign * sc[slot];
+  const double a2 = scale ? sc[sa] / sc[sb] : 0.0;
+  const double b = 1.0;
+  double s = 0.0;
+  for (unsigned i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
+    const size_t q = compact_to_row(i, r, ld);
+    double v = (double)(a * (double)x[q] + b * (double)yin[q]);
+    if (scale) v = (double)(a2 * v + 0.0 * v);
+    y[q] = v;
+    s += u[q] * v;
+  }
+  publish_partial(block_sum(s, sh), part);
+}
+
+// second loop: y = (sc[sa] - sc[sb]) x + 1.0 y (x == null: y unchanged); then
+// either partials of <u, y>, or (d given) d = -1.0 y + 0.0 d and partials of <g, d>
+[[maybe_unused]] static __global__ void __launch_bounds__(kBlock) lbfgs_second_kernel(
+    unsigned N, int r, int ld, const double* __restrict__ sc, int sa, int sb,
+    const double* __restrict__ x, const double* yin, double* y, const double* __restrict__ u,
+    double* __restrict__ d, const double* __restrict__ g, double* __restrict__ part) {
+  __shared__ double sh[kBlock / 64];
+  const double a = x ? sc[sa] - sc[sb] : 0.0;
+  const double b = 1.0;
+  double s = 0.0;
+  for (unsigned i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
+    const size_t q = compact_to_row(i, r, ld);
+    double v = yin[q];
+    if (x) {
+      v = (double)(a * (double)x[q] + b * v);
+      y[q] = v;
+    }
+    // the dot's operands are chosen first so that its multiply-add is one
+    // fused operation, as in dot_rows_kernel
+    double fa, fb;
+    if (d) {
+      const double dv = (double)(-1.0 * v + 0.0 * (double)d[q]);
+      d[q] = dv;
+      fa = g[q];
+      fb = dv;
+    } else {
+      fa = u[q];
+      fb = v;
+    }
+    s += fa * fb;
+  }
+  publish_partial(block_sum(s, sh), part);
+}
+
+// step and curvature pair: Sn = alpha D + 0.0 Sn, U = U + Sn (all N entries)
+[[maybe_unused]] static __global__ void __launch_bounds__(kBlock) lbfgs_step_kernel(
+    size_t N, double alpha, const double* __restrict__ D, double* __restrict__ Sn,
+    double* __restrict__ U) {
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock) {
+    const double sn = (double)(alpha * (double)D[i] + 0.0 * (double)Sn[i]);
+    Sn[i] = sn;
+    U[i] = (double)((double)U[i] + (double)sn);
+  }
+}
+
+// Yn = 1.0 Gn + 0.0 Yn, Yn = -1.0 G + 1.0 Yn; partials of <Sn, Yn> and <Gn, Gn>
+[[maybe_unused]] static __global__ void __launch_bounds__(kBlock) lbfgs_pair_kernel(
+    unsigned N, int r, int ld, const double* __restrict__ Gn, const double* __restrict__ G,
+    double* __restrict__ Yn, const double* __restrict__ Sn, double* __restrict__ part) {
+  __shared__ double sh[kBlock / 64];
+  double s0 = 0.0, s1 = 0.0;
+  for (unsigned i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
+    const size_t q = compact_to_row(i, r, ld);
+    double y = (double)(1.0 * (double)Gn[q] + 0.0 * (double)Yn[q]);
+    y = (double)(-1.0 * (double)G[q] + 1.0 * y);
+    Yn[q] = y;
+    s0 += Sn[q] * y;
+    s1 += Gn[q] * Gn[q];
+  }
+  publish_partial(block_sum(s0, sh), part);
+  publish_partial(block_sum(s1, sh), part + gridDim.x);
+}
+
+// sc[slot_t] = scale_t * sum of partial array t (t < k <= 3), arrays of length np
+[[maybe_unused]] static __global__ void __launch_bounds__(kBlock) finish_multi(
+    int np, int k, const double* __restrict__ part, double s0, double s1, double s2, int q0,
+    int q1, int q2, double* __restrict__ sc) {
+  __shared__ double sh[kBlock / 64];
+  const double sc_[3] = {s0, s1, s2};
+  const int q_[3] = {q0, q1, q2};
+  for (int t = 0; t < k; ++t) {
+    const double v = block_sum_parts(part + (size_t)t * np, np, sh);
+    if (threadIdx.x == 0) sc[q_[t]] = sc_[t] * v;
+  }
+}
+
 // Several dots over m-vectors for the quartic line search, in one pass
 // (per-block partials, array t at part + t * gridDim.x):
 //   out[0] = p2.p2, [1] = p1.p2, [2] = p1.p1, [3] = p0.p2, [4] = p0.p1,

@@ -214,48 +214,69 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
       if (!std::isfinite(gnorm)) fail(LORADS_ENUMERIC, "non-finite gradient in phase I");
       if (gnorm / (1.0 + c_fro) <= tol) { conv = true; break; }
       if (it >= cap) break;
-      // two-loop recursion: q = G; newest to oldest
-      HIPCHK(hipMemcpyAsync(A.Q.p, A.G.p, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+      // two-loop recursion, newest pair first, in fused passes (each pass
+      // updates q and forms the next dot; q = G until the first update).  The
+      // scalars stay on the device: alphas in slots S_GEN+16+t, <S,Y> and
+      // <Y,Y> of the newest pair in S_GEN+1, S_GEN+2, beta in S_GEN+6.  The
+      // last pass forms D = -q and <G, D> (S_GEN+10) for the descent check.
       std::vector<int> order;
       for (int t = 0; t < A.count; ++t) order.push_back((A.head - 1 - t + o.lbfgs_mem) % o.lbfgs_mem);
-      // alphas live in slots S_GEN+16+t
-      for (size_t t = 0; t < order.size(); ++t) {
-        const int k = order[t];
-        adot(A.S[k].p, A.Q.p, A.rhoh[k], S_GEN + 16 + (int)t, s);
-        axpby_dev<double><<<gridN(N), kBlock, 0, s>>>(N, P.sc.p, S_GEN + 16 + (int)t, -1.0,
-                                                      A.Y[k].p, 1.0, A.Q.p);
+      const int mc = (int)order.size();
+      const unsigned Nc = (unsigned)((size_t)n * r);
+      const int rg = grid_for((size_t)n * r, kRedBlocks);
+      double* part = P.part.p;
+      auto finish = [&](int k, double s0, int q0, double s1 = 0.0, int q1 = 0, double s2 = 0.0, int q2 = 0) {
+        finish_multi<<<1, kBlock, 0, s>>>(rg, k, part, s0, s1, s2, q0, q1, q2, P.sc.p);
+      };
+      if (mc > 0) {
+        const int k0 = order[0];
+        dots3_kernel<<<rg, kBlock, 0, s>>>(Nc, r, F.ld, A.S[k0].p, A.G.p, A.S[k0].p, A.Y[k0].p,
+                                           A.Y[k0].p, A.Y[k0].p, 3, part);
+        finish(3, A.rhoh[k0], S_GEN + 16, 1.0, S_GEN + 1, 1.0, S_GEN + 2);
+        for (int t = 0; t < mc; ++t) {
+          // q = -alpha_t Y_t + q; on the last pass q *= <S,Y>/<Y,Y> of the newest pair
+          const bool last = t == mc - 1;
+          const double* u = last ? A.Y[order[mc - 1]].p : A.S[order[t + 1]].p;
+          lbfgs_first_kernel<<<rg, kBlock, 0, s>>>(Nc, r, F.ld, P.sc.p, S_GEN + 16 + t, -1.0,
+                                                   A.Y[order[t]].p, t == 0 ? A.G.p : A.Q.p, A.Q.p,
+                                                   last ? 1 : 0, S_GEN + 1, S_GEN + 2, u, part);
+          if (last) finish(1, A.rhoh[order[mc - 1]], S_GEN + 6);
+          else finish(1, A.rhoh[order[t + 1]], S_GEN + 16 + t + 1);
+        }
+        for (int t = mc - 1; t >= 0; --t) {
+          // q += (alpha_t - beta_t) S_t, then the next beta's dot, or D = -q
+          if (t > 0) {
+            lbfgs_second_kernel<<<rg, kBlock, 0, s>>>(Nc, r, F.ld, P.sc.p, S_GEN + 16 + t, S_GEN + 6,
+                                                      A.S[order[t]].p, A.Q.p, A.Q.p,
+                                                      A.Y[order[t - 1]].p, nullptr, nullptr, part);
+            finish(1, A.rhoh[order[t - 1]], S_GEN + 6);
+          } else {
+            lbfgs_second_kernel<<<rg, kBlock, 0, s>>>(Nc, r, F.ld, P.sc.p, S_GEN + 16, S_GEN + 6,
+                                                      A.S[order[0]].p, A.Q.p, A.Q.p, nullptr,
+                                                      A.D.p, A.G.p, part);
+            finish(1, 1.0, S_GEN + 10);
+          }
+        }
+      } else {
+        lbfgs_second_kernel<<<rg, kBlock, 0, s>>>(Nc, r, F.ld, P.sc.p, 0, 0, nullptr, A.G.p, nullptr,
+                                                  nullptr, A.D.p, A.G.p, part);
+        finish(1, 1.0, S_GEN + 10);
       }
-      // the scalars of the recursion stay on the device (no host round trip)
-      if (A.count > 0) {
-        const int k = order[0];
-        // q *= <S_k, Y_k> / <Y_k, Y_k>
-        adot(A.S[k].p, A.Y[k].p, 1.0, S_GEN + 1, s);
-        adot(A.Y[k].p, A.Y[k].p, 1.0, S_GEN + 2, s);
-        axpby_slots<double><<<gridN(N), kBlock, 0, s>>>(N, P.sc.p, S_GEN + 1, S_GEN + 2, 1, A.Q.p,
-                                                       0.0, A.Q.p);
-      }
-      for (int t = (int)order.size() - 1; t >= 0; --t) {
-        const int k = order[t];
-        // beta = rho_k <Y_k, q>;  q += (alpha_t - beta) S_k
-        adot(A.Y[k].p, A.Q.p, A.rhoh[k], S_GEN + 6, s);
-        axpby_slots<double><<<gridN(N), kBlock, 0, s>>>(N, P.sc.p, S_GEN + 16 + t, S_GEN + 6, 0,
-                                                       A.S[k].p, 1.0, A.Q.p);
-      }
-      // D = -q.  The line search below also returns <G, D>: a direction that is
-      // not a descent direction is replaced by -G (memory cleared) and the
-      // search repeated, as is a quasi-Newton step whose exact minimiser is not
+      HIPCHK(hipGetLastError());
+      // The line search below also returns <G, D>: a direction that is not a
+      // descent direction is replaced by -G (memory cleared) and the search
+      // repeated, as is a quasi-Newton step whose exact minimiser is not
       // positive.  One host read per search.
-      axpby<double, double><<<gridN(N), kBlock, 0, s>>>(N, -1.0, A.Q.p, 0.0, A.D.p);
       double alpha = 0.0;
       bool checked = false;
       for (int attempt = 0; attempt < 3; ++attempt) {
         op_forward_pair(P, U, A.D.p, r, F.ld, A.p1.p, A.p2.p, s);
         op_adjoint<double>(P, (const double*)nullptr, 1.0, A.D.p, r, F.ld, A.CD.p, F.ld, 1.0, s);
         info.op_bytes += 2 * bytes_forward(P, r, 8) + bytes_adjoint(P, r, 8, true);
-        adot(A.CD.p, U, 2.0, S_GEN + 1, s);
-        adot(A.CD.p, A.D.p, 1.0, S_GEN + 2, s);
+        dots3_kernel<<<rg, kBlock, 0, s>>>(Nc, r, F.ld, A.CD.p, U, A.CD.p, A.D.p, nullptr, nullptr,
+                                           2, part);
+        finish(2, 2.0, S_GEN + 1, 1.0, S_GEN + 2);
         linesearch_slots(P, P.zbuf.p, A.p1.p, A.p2.p, P.lam.p, S_GEN + 3, s);
-        if (!checked) adot(A.G.p, A.D.p, 1.0, S_GEN + 10, s);
         read_slots(P, S_GEN + 1, h, checked ? 9 : 10, s);
         if (!checked) {
           checked = true;
@@ -281,13 +302,11 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
       if (!(alpha > 0.0)) break;
       // S = alpha D; U += S; new gradient; Y = G_new - G.  The pair enters the
       // memory only when <S, Y> > 0 (the oldest pair is dropped when full).
-      axpby<double, double><<<gridN(N), kBlock, 0, s>>>(N, alpha, A.D.p, 0.0, A.Sn.p);
-      add_kernel<double, double, double><<<gridN(N), kBlock, 0, s>>>(N, U, A.Sn.p, U);
+      lbfgs_step_kernel<<<gridN(N), kBlock, 0, s>>>(N, alpha, A.D.p, A.Sn.p, U);
       alm_gradient(P, A, U, A.Gn.p, rho, s, info.op_bytes);
-      axpby<double, double><<<gridN(N), kBlock, 0, s>>>(N, 1.0, A.Gn.p, 0.0, A.Yn.p);
-      axpby<double, double><<<gridN(N), kBlock, 0, s>>>(N, -1.0, A.G.p, 1.0, A.Yn.p);
-      adot(A.Sn.p, A.Yn.p, 1.0, S_GEN, s);
-      adot(A.Gn.p, A.Gn.p, 1.0, S_GEN + 1, s);
+      lbfgs_pair_kernel<<<rg, kBlock, 0, s>>>(Nc, r, F.ld, A.Gn.p, A.G.p, A.Yn.p, A.Sn.p, part);
+      finish(2, 1.0, S_GEN, 1.0, S_GEN + 1);
+      HIPCHK(hipGetLastError());
       read_slots(P, S_GEN, h, 2, s);
       gnorm2 = h[1];
       if (h[0] > 0.0) {
