@@ -147,6 +147,12 @@ static void op_adjoint_impl(Problem& P, const T* w, double c_scale, const T* V, 
 template <typename T>
 void op_adjoint(Problem& P, const T* w, double c_scale, const T* V, int r, int ld, T* out,
                 int ldo, double out_scale, hipStream_t s) {
+  // products with the cost matrix alone (w == null) are not timed: the class
+  // covers the adjoint with multiplier weights
+  if (w == nullptr) {
+    op_adjoint_impl<T>(P, w, c_scale, V, r, ld, out, ldo, out_scale, s);
+    return;
+  }
   P.prof.run(2, bytes_adjoint(P, r, sizeof(T), c_scale != 0.0), s,
              [&] { op_adjoint_impl<T>(P, w, c_scale, V, r, ld, out, ldo, out_scale, s); });
 }
@@ -191,7 +197,7 @@ void refresh_inc_lam(Problem& P, hipStream_t s) {
 void op_grad_pair(Problem& P, const double* U, int r, int ld, double rho, double* out, int ldo,
                   double out_scale, hipStream_t s) {
   if (!grad_pair_ready(P)) fail(LORADS_EINVAL, "gradient form needs per-entry lam and b");
-  P.prof.run(2, bytes_adjoint(P, r, 8, true), s, [&] {
+  P.prof.run(2, bytes_grad_pair(P, r), s, [&] {
     check_pair_offsets(P, std::max(ld, ldo));
     const int G = lane_group(r);
     if (r > 4 * G) fail(LORADS_EINVAL, "rank above 256 is not supported");
@@ -284,6 +290,11 @@ double bytes_adjoint(const Problem& P, int r, int s, bool with_c) {
   if (P.structure == LORADS_STRUCT_PAIR)
     return (double)P.m * 8 + (double)P.m * s + 2.0 * nr + cbytes + (P.pcoef.n ? (double)P.m * s : 0.0);
   return (double)P.acol.n * (8 + s) + (double)(P.n + 1) * 4 + (double)P.m * s + 2.0 * nr + cbytes;
+}
+
+double bytes_grad_pair(const Problem& P, int r) {
+  // the gradient form applies both maps: A(U U^T) entry by entry and the adjoint
+  return bytes_forward(P, r, 8) + bytes_adjoint(P, r, 8, true);
 }
 
 double bytes_cg_op(const Problem& P, int r, int s) {

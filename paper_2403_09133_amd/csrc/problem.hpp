@@ -197,6 +197,7 @@ int cg_ld(const Problem& P, int r, int elem_bytes);
 double bytes_forward(const Problem& P, int r, int s);
 double bytes_adjoint(const Problem& P, int r, int s, bool with_c);
 double bytes_cg_op(const Problem& P, int r, int s);
+double bytes_grad_pair(const Problem& P, int r);  // gradient form: forward + adjoint (FP64)
 
 // ---------------------------------------------------------------------------
 // reductions / small helpers

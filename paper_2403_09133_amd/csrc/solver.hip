@@ -130,11 +130,12 @@ static void alm_gradient(Problem& P, AlmState& A, const double* U, double* G, do
     // z for the line search and the infeasibility; the gradient forms w per entry
     op_forward<double>(P, U, U, A.r, A.ld, P.zbuf.p, 1.0, s);
     op_grad_pair(P, U, A.r, A.ld, rho, G, A.ld, 2.0, s);
+    bytes += bytes_forward(P, A.r, 8) + bytes_grad_pair(P, A.r);
   } else {
     op_forward_w(P, U, U, A.r, A.ld, P.zbuf.p, P.wbuf.p, P.lam.p, rho, s);
     op_adjoint<double>(P, P.wbuf.p, 1.0, U, A.r, A.ld, G, A.ld, 2.0, s);
+    bytes += bytes_forward(P, A.r, 8) + bytes_adjoint(P, A.r, 8, true);
   }
-  bytes += bytes_forward(P, A.r, 8) + bytes_adjoint(P, A.r, 8, true);
 }
 
 // Phase I's copy of U in the working layout (the master P.U stays n x r)
@@ -417,7 +418,7 @@ static int half_step(Problem& P, const double* W, double* out, int r, double rho
   if (grad_pair_ready(P)) {
     // the gradient form needs no forward map here (z is recomputed after the step)
     op_grad_pair(P, W, r, r, rho, R, ld, -1.0, s);
-    info.op_bytes += bytes_adjoint(P, r, 8, true);
+    info.op_bytes += bytes_grad_pair(P, r);
   } else {
     op_forward_w(P, W, W, r, r, P.zbuf.p, P.wbuf.p, P.lam.p, rho, s);
     op_adjoint<double>(P, P.wbuf.p, 1.0, W, r, r, R, ld, -1.0, s);
