@@ -38,6 +38,35 @@ __device__ double wg_sum(double v) {
   return result;
 }
 
+// two workgroup sums with one set of barriers (each summed as wg_sum sums it)
+__device__ void wg_sum2(double& a, double& b) {
+  __shared__ double buf[2][16];
+  __shared__ double result[2];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o, 64);
+    b += __shfl_xor(b, o, 64);
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    buf[0][wid] = a;
+    buf[1][wid] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sa = 0.0, sb = 0.0;
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) sa += buf[0][i];
+    for (int i = 0; i < nw; ++i) sb += buf[1][i];
+    result[0] = sa;
+    result[1] = sb;
+  }
+  __syncthreads();
+  a = result[0];
+  b = result[1];
+}
+
 // Instance view: pointers already offset to the instance.
 template <typename T>
 struct Inst {
@@ -131,34 +160,19 @@ __device__ void b_forward(const Inst<T>& I, const double* X, const double* Y, do
   }
 }
 
-// z = A(U U^T), w = lam + rho (z - b)
-template <typename T>
-__device__ void b_forward_w(const Inst<T>& I, const double* U, double* z, double* w,
-                            const double* lam, double rho) {
-  const int l = threadIdx.x % kBG, ng = blockDim.x / kBG;
-  FOR_CPASS(it) {
-    double s[kBU];
-    b_row_dots(I, it, U, U, s);
-#pragma unroll
-    for (int u = 0; u < kBU; ++u) {
-      const int i = it + u * ng;
-      if (l == 0 && i < I.m) {
-        const double v = s[u] * I.dcoef[i];
-        z[i] = v;
-        w[i] = lam[i] + rho * (v - I.b[i]);
-      }
-    }
-  }
-}
-
 // out_j = os (cs (C V)_j + (sum_{i on row j} w_i a_i) V_j), w may be null
 // A group serves kBU rows at once: the lanes load up to kBG entries of each
 // row's cost list together, then every step gathers one partner row for each
 // of the kBU rows (entry broadcast inside the group), so kBU partner rows are
 // in flight per step.
-template <typename T>
+// GRAD: gradient form with V = U: z_i = a_i <U_j, U_j> (the row's inner
+// product summed as b_row_dots sums it) and w_i = lam_i + rho (z_i - b_i) of
+// the row's constraints are formed in the same pass and z is written, so out
+// equals the forward map of w followed by the plain adjoint bit for bit.
+template <typename T, bool GRAD = false>
 __device__ void b_adjoint(const Inst<T>& I, const double* w, double cs, const double* V,
-                          double* out, double os) {
+                          double* out, double os, double* zo = nullptr,
+                          const double* lam = nullptr, double rho = 0.0) {
   const int l = threadIdx.x % kBG, ng = blockDim.x / kBG;
   const int c0 = min(l, I.ld - 1), c1 = min(l + kBG, I.ld - 1);
   FOR_PASS(it) {
@@ -205,10 +219,23 @@ __device__ void b_adjoint(const Inst<T>& I, const double* w, double cs, const do
 #pragma unroll
     for (int u = 0; u < kBU; ++u) {
       double t = 0.0;
-      if (w)
-        for (int i = I.dptr[j[u]] + l; i < I.dptr[j[u] + 1]; i += kBG) t += w[i] * I.dcoef[i];
       vj[u][0] = V[j[u] * I.ld + c0];
       vj[u][1] = V[j[u] * I.ld + c1];
+      if (GRAD) {
+        double q = 0.0;
+        if (l < I.r) q += vj[u][0] * vj[u][0];
+        if (l + kBG < I.r) q += vj[u][1] * vj[u][1];
+        const double srow = group_sum<kBG>(q);
+        const bool live = it + u * ng < I.n;
+        for (int i = I.dptr[j[u]] + l; i < I.dptr[j[u] + 1]; i += kBG) {
+          const double v = srow * I.dcoef[i];
+          const double wv = lam[i] + rho * (v - I.b[i]);
+          if (live) zo[i] = v;
+          t += wv * I.dcoef[i];
+        }
+      } else if (w) {
+        for (int i = I.dptr[j[u]] + l; i < I.dptr[j[u] + 1]; i += kBG) t += w[i] * I.dcoef[i];
+      }
       d[u] = group_sum<kBG>(t);
     }
 #pragma unroll
@@ -252,6 +279,25 @@ __device__ void b_axpby(const Inst<T>& I, double a, const TX* x, double bb, TY* 
     FOR_UH(u, h) if (S.on[u][h]) y[S.q[u][h]] = (TY)(a * xv[u][h] + bb * yv[u][h]);
   }
   __syncthreads();
+}
+
+// y = a x + b y, then <y, y>, in one pass: the arithmetic and summation order
+// of b_axpby followed by b_dot(y, y)
+template <typename T>
+__device__ double b_axpby_norm2(const Inst<T>& I, double a, const double* x, double bb, double* y) {
+  double s = 0.0;
+  FOR_PASS(it) {
+    PassSlots S;
+    pass_slots(it, I.n, I.r, I.ld, S);
+    double xv[kBU][2], yv[kBU][2];
+    FOR_UH(u, h) { xv[u][h] = x[S.q[u][h]]; yv[u][h] = y[S.q[u][h]]; }
+    FOR_UH(u, h) if (S.on[u][h]) {
+      const double v = (double)(a * xv[u][h] + bb * yv[u][h]);
+      y[S.q[u][h]] = v;
+      s += v * v;
+    }
+  }
+  return wg_sum(s);
 }
 
 template <typename T>
@@ -351,7 +397,6 @@ __global__ void __launch_bounds__(kBatchMaxBlock) batch_solve_kernel(const Batch
   double* CD = A.CD + d.fac_off;
   double* R64 = A.R64 + d.fac_off;
   double* z = A.z + d.con_off;
-  double* w = A.w + d.con_off;
   double* lam = A.lam + d.con_off;
   double* p1 = A.p1 + d.con_off;
   double* p2 = A.p2 + d.con_off;
@@ -380,9 +425,7 @@ __global__ void __launch_bounds__(kBatchMaxBlock) batch_solve_kernel(const Batch
     int head = 0, count = 0;
     for (int t = 0; t < mem; ++t) slot_of[t] = t;
     // gradient G = 2 (C + A*(lam + rho (z - b))) U
-    b_forward_w(I, U, z, w, lam, rho);
-    __syncthreads();
-    b_adjoint(I, w, 1.0, U, G, 2.0);
+    b_adjoint<T, true>(I, nullptr, 1.0, U, G, 2.0, z, lam, rho);
     __syncthreads();
     int it = 0;
     bool conv = false;
@@ -446,9 +489,7 @@ __global__ void __launch_bounds__(kBatchMaxBlock) batch_solve_kernel(const Batch
       if (!(alpha > 0.0)) break;
       b_axpby(I, alpha, D, 0.0, Sn);
       b_axpby(I, 1.0, Sn, 1.0, U);
-      b_forward_w(I, U, z, w, lam, rho);
-      __syncthreads();
-      b_adjoint(I, w, 1.0, U, Gn, 2.0);
+      b_adjoint<T, true>(I, nullptr, 1.0, U, Gn, 2.0, z, lam, rho);
       __syncthreads();
       b_axpby(I, 1.0, Gn, 0.0, Yn);
       b_axpby(I, -1.0, G, 1.0, Yn);
@@ -520,60 +561,96 @@ __global__ void __launch_bounds__(kBatchMaxBlock) batch_solve_kernel(const Batch
     res.status = LORADS_MAXITER;
     while (k < o.max_admm_iter) {
       const double tol = fmin(o.cg_tol_max, fmax(floor_tol, o.cg_tol_kkt * kkt));
-      b_axpby(I, 1.0, V, 0.0, Vold);
-      const double vnorm2 = b_dot(I, Vold, Vold);
+      const double vnorm2 = b_axpby_norm2(I, 1.0, V, 0.0, Vold);
       for (int half = 0; half < 2; ++half) {
         const double* W = half == 0 ? V : U;
         double* out = half == 0 ? U : V;
         // R = -(C + A*(lam + rho (A(W W^T) - b))) W, CG on M_W D = R from D = 0
-        b_forward_w(I, W, z, w, lam, rho);
+        b_adjoint<T, true>(I, nullptr, 1.0, W, R64, -1.0, z, lam, rho);
         __syncthreads();
-        b_adjoint(I, w, 1.0, W, R64, -1.0);
-        __syncthreads();
-        double rr = 0.0;
+        // CG set-up, and the first operator application Q = M(P) with P = R in
+        // the same pass (row-local); its <P, Q> is used if the loop runs
+        double rr = 0.0, pq0 = 0.0;
         FOR_PASS(it) {
           PassSlots S;
           pass_slots(it, I.n, I.r, I.ld, S);
-          double rv[kBU][2], wv[kBU][2];
+          const int ng = blockDim.x / kBG;
+          double rv[kBU][2], wv[kBU][2], pv[kBU][2], wt[kBU][2], ds[kBU];
           FOR_UH(u, h) { rv[u][h] = R64[S.q[u][h]]; wv[u][h] = W[S.q[u][h]]; }
-          FOR_UH(u, h) if (S.on[u][h]) {
+          FOR_UH(u, h) {
             const int q = S.q[u][h];
             const T t = (T)rv[u][h];
-            R[q] = t;
-            Wt[q] = (T)wv[u][h];
-            X[q] = (T)0;
-            Pd[q] = t;
-            rr += (double)t * (double)t;
+            const T tw = (T)wv[u][h];
+            pv[u][h] = (double)t;
+            wt[u][h] = (double)tw;
+            if (S.on[u][h]) {
+              R[q] = t;
+              Wt[q] = tw;
+              X[q] = (T)0;
+              Pd[q] = t;
+              rr += (double)t * (double)t;
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < kBU; ++u) {
+            const int j = min(it + u * ng, I.n - 1);
+            double dd = 0.0;
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+              if (S.on[u][h]) dd += pv[u][h] * wt[u][h];
+            ds[u] = group_sum<kBG>(dd) * rho * I.dsq[j];
+          }
+          FOR_UH(u, h) if (S.on[u][h]) {
+            const T qv = (T)(gamma * pv[u][h] + ds[u] * wt[u][h]);
+            Q[S.q[u][h]] = qv;
+            pq0 += pv[u][h] * (double)qv;
           }
         }
-        rr = wg_sum(rr);
+        wg_sum2(rr, pq0);
         const double rr0 = rr;
-        int it = 0;
-        while (rr0 > 0.0 && it < maxit && rr > tol * tol * rr0) {
-          // Q = gamma P + rho dsq <P_j, W_j> W_j
-          double pq = 0.0;
-          FOR_PASS(it) {
-            PassSlots S;
-            pass_slots(it, I.n, I.r, I.ld, S);
-            const int ng = blockDim.x / kBG;
-            double pv[kBU][2], wv[kBU][2], ds[kBU];
-            FOR_UH(u, h) { pv[u][h] = (double)Pd[S.q[u][h]]; wv[u][h] = (double)Wt[S.q[u][h]]; }
+        int cgi = 0;
+        double beta = 0.0;
+        while (rr0 > 0.0 && cgi < maxit && rr > tol * tol * rr0) {
+          // from the second iteration on, the direction P = R + beta P is formed
+          // in the same pass (row-local), then Q = gamma P + rho dsq <P_j, W_j> W_j
+          double pq = pq0;
+          if (cgi > 0) {
+            pq = 0.0;
+            FOR_PASS(it) {
+              PassSlots S;
+              pass_slots(it, I.n, I.r, I.ld, S);
+              const int ng = blockDim.x / kBG;
+              double pv[kBU][2], wv[kBU][2], ds[kBU];
+              {
+                double rv[kBU][2];
+                FOR_UH(u, h) {
+                  pv[u][h] = (double)Pd[S.q[u][h]];
+                  rv[u][h] = (double)R[S.q[u][h]];
+                  wv[u][h] = (double)Wt[S.q[u][h]];
+                }
+                FOR_UH(u, h) {
+                  const T pt = (T)(rv[u][h] + beta * pv[u][h]);
+                  if (S.on[u][h]) Pd[S.q[u][h]] = pt;
+                  pv[u][h] = (double)pt;
+                }
+              }
 #pragma unroll
-            for (int u = 0; u < kBU; ++u) {
-              const int j = min(it + u * ng, I.n - 1);
-              double dd = 0.0;
+              for (int u = 0; u < kBU; ++u) {
+                const int j = min(it + u * ng, I.n - 1);
+                double dd = 0.0;
 #pragma unroll
-              for (int h = 0; h < 2; ++h)
-                if (S.on[u][h]) dd += pv[u][h] * wv[u][h];
-              ds[u] = group_sum<kBG>(dd) * rho * I.dsq[j];
+                for (int h = 0; h < 2; ++h)
+                  if (S.on[u][h]) dd += pv[u][h] * wv[u][h];
+                ds[u] = group_sum<kBG>(dd) * rho * I.dsq[j];
+              }
+              FOR_UH(u, h) if (S.on[u][h]) {
+                const T qv = (T)(gamma * pv[u][h] + ds[u] * wv[u][h]);
+                Q[S.q[u][h]] = qv;
+                pq += pv[u][h] * (double)qv;
+              }
             }
-            FOR_UH(u, h) if (S.on[u][h]) {
-              const T qv = (T)(gamma * pv[u][h] + ds[u] * wv[u][h]);
-              Q[S.q[u][h]] = qv;
-              pq += pv[u][h] * (double)qv;
-            }
+            pq = wg_sum(pq);
           }
-          pq = wg_sum(pq);
           if (!(pq > 0.0)) break;
           const double alpha = rr / pq;
           double rn = 0.0;
@@ -597,19 +674,11 @@ __global__ void __launch_bounds__(kBatchMaxBlock) batch_solve_kernel(const Batch
             }
           }
           rn = wg_sum(rn);
-          const double beta = rn / rr;
+          beta = rn / rr;
           rr = rn;
-          FOR_PASS(it) {
-            PassSlots S;
-            pass_slots(it, I.n, I.r, I.ld, S);
-            double pv[kBU][2], rv[kBU][2];
-            FOR_UH(u, h) { pv[u][h] = (double)Pd[S.q[u][h]]; rv[u][h] = (double)R[S.q[u][h]]; }
-            FOR_UH(u, h) if (S.on[u][h]) Pd[S.q[u][h]] = (T)(rv[u][h] + beta * pv[u][h]);
-          }
-          __syncthreads();
-          ++it;
+          ++cgi;
         }
-        cg_total += it;
+        cg_total += cgi;
         FOR_RC(j, c) {
           const size_t q = (size_t)j * I.ld + c;
           out[q] = W[q] + (double)X[q];
@@ -626,8 +695,7 @@ __global__ void __launch_bounds__(kBatchMaxBlock) batch_solve_kernel(const Batch
         s += dz * dz;
       }
       s = wg_sum(s);
-      b_axpby(I, 1.0, V, -1.0, Vold);
-      const double dv2 = b_dot(I, Vold, Vold);
+      const double dv2 = b_axpby_norm2(I, 1.0, V, -1.0, Vold);
       pinf = sqrt(s) / (1.0 + I.b_inf);
       dres = gamma * sqrt(dv2) / (1.0 + sqrt(vnorm2));
       if (!(pinf == pinf) || !(dres == dres)) { res.status = LORADS_ENUMERIC; break; }
@@ -711,7 +779,7 @@ void Batch::build(const std::vector<std::unique_ptr<Problem>>& probs, hipStream_
   }
   const size_t F = (size_t)fac;
   for (DevBuf<double>* buf : {&U, &V, &Vold, &G, &Gn, &D, &Sn, &Yn, &CD, &R64}) buf->alloc(F);
-  z.alloc(con); w.alloc(con); lam.alloc(con); p1.alloc(con); p2.alloc(con);
+  z.alloc(con); lam.alloc(con); p1.alloc(con); p2.alloc(con);
   res.alloc(np);
   desc.alloc(np);
   HIPCHK(hipStreamSynchronize(s));
@@ -768,7 +836,7 @@ void batch_solve(std::vector<std::unique_ptr<Problem>>& probs, Batch& B, const l
   a.dcoef = B.dcoef.p; a.dsq = B.dsq.p; a.b = B.b.p;
   a.U = B.U.p; a.V = B.V.p; a.Vold = B.Vold.p; a.G = B.G.p; a.Gn = B.Gn.p; a.D = B.D.p;
   a.Sn = B.Sn.p; a.Yn = B.Yn.p; a.CD = B.CD.p; a.R64 = B.R64.p;
-  a.z = B.z.p; a.w = B.w.p; a.lam = B.lam.p; a.p1 = B.p1.p; a.p2 = B.p2.p;
+  a.z = B.z.p; a.lam = B.lam.p; a.p1 = B.p1.p; a.p2 = B.p2.p;
   a.res = B.res.p;
   a.fac_total = B.fac_total;
   const size_t F = (size_t)B.fac_total;

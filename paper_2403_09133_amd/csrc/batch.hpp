@@ -35,7 +35,7 @@ struct BatchArrays {
   const int *cptr, *ccol, *dptr, *drow;
   const double *cval, *dcoef, *dsq, *b;
   double *U, *V, *Vold, *G, *Gn, *D, *Sn, *Yn, *CD, *R64, *S, *Y;
-  double *z, *w, *lam, *p1, *p2;
+  double *z, *lam, *p1, *p2;
   void *X, *R, *P, *Q, *W;  // CG vectors in the CG precision
   BatchResult* res;
   long long fac_total;
@@ -48,7 +48,7 @@ struct Batch {
   DevBuf<int> cptr, ccol, dptr, drow;
   DevBuf<double> cval, dcoef, dsq, b;
   DevBuf<double> U, V, Vold, G, Gn, D, Sn, Yn, CD, R64, S, Y;
-  DevBuf<double> z, w, lam, p1, p2;
+  DevBuf<double> z, lam, p1, p2;
   DevBuf<char> X, R, P, Q, W;
   DevBuf<BatchResult> res;
   DevBuf<BatchDesc> desc;
