@@ -153,6 +153,105 @@ __global__ void __launch_bounds__(kBlock) k1_pair(
   }
 }
 
+// FP64 forward maps (MODE 0, 1 and 3 of k1_pair) with two columns per lane
+// loaded as one 16-byte vector: GV = G / 2 lanes per constraint, so a wave
+// keeps twice the constraints of the one-column form in flight.  The sums are
+// those of the one-column form bit for bit: a lane adds its two columns' terms
+// (columns 2l and 2l + 1, exactly the first level of the G-lane tree), then the
+// remaining levels run over GV lanes, and every term is evaluated by the same
+// expression.  Needs rows aligned to 16 bytes (ld even) and r <= 2 GV.
+template <int GV, int MODE>
+__global__ void __launch_bounds__(kBlock) k1_pair_v2(
+    int nchunks, const int* __restrict__ chunk_row, const int* __restrict__ chunk_start,
+    const int* __restrict__ rptr, const int* __restrict__ pk, const double* __restrict__ pcoef,
+    double pair_coef, const double* __restrict__ U, const double* __restrict__ V, int r, int ld,
+    double* __restrict__ z, double scale, const double* __restrict__ lam,
+    const double* __restrict__ b, double rho, double* __restrict__ w) {
+  constexpr bool kStage = GV >= 4;
+  constexpr bool kTwo = (MODE == 1 || MODE == 3);
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  __shared__ double sz[kStage ? (kBlock / GV) * kPairChunk : 1];
+  __shared__ double sw[(kStage && kTwo) ? (kBlock / GV) * kPairChunk : 1];
+  const int chunk = (blockIdx.x * kBlock + threadIdx.x) / GV;
+  const int lane = threadIdx.x & (GV - 1);
+  const int gslot = (threadIdx.x / GV) * kPairChunk;
+  if (chunk >= nchunks) return;
+  const int row = chunk_row[chunk];
+  const int i0 = chunk_start[chunk], i1 = min(i0 + kPairChunk, rptr[row + 1]);
+  const int c0 = 2 * lane;
+  const bool on0 = c0 < r, on1 = c0 + 1 < r;
+  const d2 uj = *reinterpret_cast<const d2*>(U + row * ld + c0);
+  const d2 vj = *reinterpret_cast<const d2*>(V + row * ld + c0);
+  const double mult = MODE == 0 ? scale : 1.0;
+  for (int i = i0; i < i1; i += kUnroll) {
+    const int cnt = min(kUnroll, i1 - i);
+    int k[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) k[u] = u < cnt ? pk[i + u] : row;
+    d2 vk[kUnroll], uk[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      vk[u] = *reinterpret_cast<const d2*>(V + k[u] * ld + c0);
+      uk[u] = *reinterpret_cast<const d2*>(U + k[u] * ld + c0);
+    }
+    double d[kUnroll], d2s[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      double s0 = 0.0, s1 = 0.0, q0 = 0.0, q1 = 0.0;
+      if (on0) {
+        s0 += uj[0] * vk[u][0] + uk[u][0] * vj[0];
+        if (MODE == 3) q0 += vj[0] * vk[u][0];
+      }
+      if (on1) {
+        s1 += uj[1] * vk[u][1] + uk[u][1] * vj[1];
+        if (MODE == 3) q1 += vj[1] * vk[u][1];
+      }
+      d[u] = s0 + s1;
+      d2s[u] = q0 + q1;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) d[u] = group_sum<GV>(d[u]);
+    if (MODE == 3) {
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) d2s[u] = group_sum<GV>(d2s[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (lane == (u & (GV - 1)) && u < cnt) {
+        const int id = i + u;
+        const double val = d[u] * (pcoef ? pcoef[id] : pair_coef);
+        double zv, wv = 0.0;
+        if (MODE == 1) {
+          zv = val;
+          wv = lam[id] + rho * (val - b[id]);
+        } else if (MODE == 3) {
+          const double a = pcoef ? pcoef[id] : pair_coef;
+          zv = 2.0 * val;
+          wv = 2.0 * a * d2s[u];
+        } else {
+          zv = mult * val;
+        }
+        if (kStage) {
+          sz[gslot + (id - i0)] = zv;
+          if (kTwo) sw[gslot + (id - i0)] = wv;
+        } else {
+          z[id] = zv;
+          if (kTwo) w[id] = wv;
+        }
+      }
+    }
+  }
+  if (kStage) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int q = lane; q < i1 - i0; q += GV) {
+      z[i0 + q] = sz[gslot + q];
+      if (kTwo) w[i0 + q] = sw[gslot + q];
+    }
+  }
+}
+
 // ===========================================================================
 // K2 DIAG: out_j = out_scale (c_scale (C V)_j + (sum_{i on row j} w_i a_i) V_j)
 // ===========================================================================

@@ -60,6 +60,25 @@ static int rows_grid(int rows, int G) {
   return (int)std::max<long long>(1, (threads + kBlock - 1) / kBlock);
 }
 
+// The two-columns-per-lane FP64 forward maps (k1_pair_v2) serve factors with
+// 16-byte aligned rows; their results equal the one-column form's bit for bit.
+static bool pair_v2_ok(const Problem& P, const void* U, const void* V, int r, int ld) {
+  const int G = lane_group(r);
+  return P.structure == LORADS_STRUCT_PAIR && G >= 2 && G <= 32 && r <= G && ld % 2 == 0 &&
+         (reinterpret_cast<uintptr_t>(U) % 16) == 0 && (reinterpret_cast<uintptr_t>(V) % 16) == 0;
+}
+
+#define LORADS_DISPATCH_V2(G, CALL)                      \
+  do {                                                   \
+    switch (G) {                                         \
+      case 2: { constexpr int GV = 1; CALL; } break;     \
+      case 4: { constexpr int GV = 2; CALL; } break;     \
+      case 8: { constexpr int GV = 4; CALL; } break;     \
+      case 16: { constexpr int GV = 8; CALL; } break;    \
+      default: { constexpr int GV = 16; CALL; } break;   \
+    }                                                    \
+  } while (0)
+
 // ---------------------------------------------------------------------------
 template <typename T>
 static void op_forward_impl(Problem& P, const T* U, const T* V, int r, int ld, T* z, double scale,
@@ -69,6 +88,13 @@ static void op_forward_impl(Problem& P, const T* U, const T* V, int r, int ld, T
     LORADS_DISPATCH_G(G, (k1_diag<T, G, 0><<<rows_grid(P.m, G), kBlock, 0, s>>>(
                              P.m, P.drow.p, dc<T>(P), U, V, r, ld, z, scale, nullptr, nullptr,
                              0.0, nullptr, nullptr, 0)));
+  } else if (P.structure == LORADS_STRUCT_PAIR && std::is_same<T, double>::value &&
+             pair_v2_ok(P, U, V, r, ld)) {
+    check_pair_offsets(P, ld);
+    LORADS_DISPATCH_V2(G, (k1_pair_v2<GV, 0><<<rows_grid(P.nfchunks, GV), kBlock, 0, s>>>(
+                              P.nfchunks, P.fchunk_row.p, P.fchunk_start.p, P.rptr.p, P.pk.p,
+                              P.pcoef.p, P.pair_coef, (const double*)U, (const double*)V, r, ld,
+                              (double*)z, scale, nullptr, nullptr, 0.0, nullptr)));
   } else if (P.structure == LORADS_STRUCT_PAIR) {
     check_pair_offsets(P, ld);
     LORADS_DISPATCH_GK(G, r, (k1_pair<T, G, 0, KC><<<rows_grid(P.nfchunks, G), kBlock, 0, s>>>(
@@ -107,6 +133,11 @@ static void op_forward_w_impl(Problem& P, const double* U, const double* V, int 
     LORADS_DISPATCH_G(G, (k1_diag<double, G, 1><<<rows_grid(P.m, G), kBlock, 0, s>>>(
                              P.m, P.drow.p, P.dcoef.p, U, V, r, ld, z, 1.0, lam, P.b.p, rho, w,
                              nullptr, 0)));
+  } else if (pair_v2_ok(P, U, V, r, ld)) {
+    check_pair_offsets(P, ld);
+    LORADS_DISPATCH_V2(G, (k1_pair_v2<GV, 1><<<rows_grid(P.nfchunks, GV), kBlock, 0, s>>>(
+                              P.nfchunks, P.fchunk_row.p, P.fchunk_start.p, P.rptr.p, P.pk.p,
+                              P.pcoef.p, P.pair_coef, U, V, r, ld, z, 1.0, lam, P.b.p, rho, w)));
   } else if (P.structure == LORADS_STRUCT_PAIR) {
     check_pair_offsets(P, ld);
     LORADS_DISPATCH_GK(G, r, (k1_pair<double, G, 1, KC><<<rows_grid(P.nfchunks, G), kBlock, 0, s>>>(
@@ -132,10 +163,17 @@ void op_forward_pair(Problem& P, const double* U, const double* D, int r, int ld
   P.prof.run(3, bytes_forward(P, r, 8) + 8.0 * P.m, s, [&] {
     check_pair_offsets(P, ld);
     const int G = lane_group(r);
-    LORADS_DISPATCH_GK(G, r, (k1_pair<double, G, 3, KC><<<rows_grid(P.nfchunks, G), kBlock, 0, s>>>(
-                             P.nfchunks, P.fchunk_row.p, P.fchunk_start.p, P.rptr.p, P.pk.p,
-                             P.pcoef.p, P.pair_coef, U, D, r, ld, p1, 1.0, nullptr, nullptr, 0.0,
-                             p2, nullptr, 0)));
+    if (pair_v2_ok(P, U, D, r, ld)) {
+      LORADS_DISPATCH_V2(G, (k1_pair_v2<GV, 3><<<rows_grid(P.nfchunks, GV), kBlock, 0, s>>>(
+                                P.nfchunks, P.fchunk_row.p, P.fchunk_start.p, P.rptr.p, P.pk.p,
+                                P.pcoef.p, P.pair_coef, U, D, r, ld, p1, 1.0, nullptr, nullptr,
+                                0.0, p2)));
+    } else {
+      LORADS_DISPATCH_GK(G, r, (k1_pair<double, G, 3, KC><<<rows_grid(P.nfchunks, G), kBlock, 0, s>>>(
+                               P.nfchunks, P.fchunk_row.p, P.fchunk_start.p, P.rptr.p, P.pk.p,
+                               P.pcoef.p, P.pair_coef, U, D, r, ld, p1, 1.0, nullptr, nullptr, 0.0,
+                               p2, nullptr, 0)));
+    }
     HIPCHK(hipGetLastError());
   });
 }
