@@ -525,6 +525,122 @@ __global__ void __launch_bounds__(kBlock) kpair_rows(
 }
 
 // ===========================================================================
+// Gradient form (MODE 2 of kpair_rows) with two columns per lane in 16-byte
+// loads and two rows per wave: each half-wave serves one row with NG groups of
+// GV = G / 2 lanes, so a group takes the same entries in the same order as a
+// G-lane group of the one-column form, the within-entry sums follow the same
+// tree (a lane adds its two columns first) and the cross-group sums pair the
+// same groups.  The output equals MODE 2's bit for bit.
+// ===========================================================================
+template <int GV>
+__global__ void __launch_bounds__(kBlock) kpair_grad_v2(
+    int n, const int* __restrict__ cptr, const int* __restrict__ ccol,
+    const double* __restrict__ cval, double c_scale, const int* __restrict__ inc_ptr,
+    const int* __restrict__ inc_nb, double pair_coef, const double* __restrict__ V, int r,
+    int ld, double* __restrict__ out, int ldo, double out_scale,
+    const double* __restrict__ lam_inc, const double* __restrict__ b_inc, double rho_w) {
+  constexpr int HW = 32;              // lanes per row
+  constexpr int NG = HW / GV;         // groups per row
+  constexpr int CH = kPairStage / 2;  // entries staged per row and pass (a multiple of NG kUnroll)
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  __shared__ int s_nb[kBlock / HW][CH];
+  __shared__ double s_cf[kBlock / HW][CH];
+  __shared__ double s_bi[kBlock / HW][CH];
+  const int hl = threadIdx.x & (HW - 1), hid = threadIdx.x / HW;
+  const int grp = hl / GV, lane = hl & (GV - 1);
+  const int row = blockIdx.x * (kBlock / HW) + hid;
+  int* nbw = s_nb[hid];
+  double* cfw = s_cf[hid];
+  double* biw = s_bi[hid];
+  if (row < n) {  // uniform over the half-wave
+    const int c0 = 2 * lane;
+    const bool on0 = c0 < r, on1 = c0 + 1 < r;
+    double vt0 = 0.0, vt1 = 0.0;
+    {
+      const d2 v = *reinterpret_cast<const d2*>(V + row * ld + c0);
+      if (on0) vt0 = v[0];
+      if (on1) vt1 = v[1];
+    }
+    double acc0 = 0.0, acc1 = 0.0;
+    if (c_scale != 0.0) {
+      for (int e = cptr[row] + grp; e < cptr[row + 1]; e += NG) {
+        const int k = ccol[e];
+        const double a = c_scale * cval[e];
+        if (on0) acc0 += a * V[k * ld + c0];
+        if (on1) acc1 += a * V[k * ld + c0 + 1];
+      }
+    }
+    const int e0 = inc_ptr[row], e1 = inc_ptr[row + 1];
+    for (int base = e0; base < e1; base += CH) {
+      const int cnt = min(CH, e1 - base);
+#pragma unroll
+      for (int q = 0; q < CH / HW; ++q) {
+        const int j = hl + HW * q;
+        if (j < cnt) {
+          nbw[j] = inc_nb[base + j];
+          cfw[j] = lam_inc[base + j];
+          biw[j] = b_inc[base + j];
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int j = grp; j < cnt; j += NG * kUnroll) {
+        int p[kUnroll];
+        double coef[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int ju = j + u * NG;
+          const bool ok = ju < cnt;
+          p[u] = (ok ? nbw[ju] : row) * ld;
+          coef[u] = ok ? cfw[ju] : 0.0;
+        }
+        double vp0[kUnroll], vp1[kUnroll], d[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const d2 v = *reinterpret_cast<const d2*>(V + p[u] + c0);
+          vp0[u] = on0 ? v[0] : 0.0;
+          vp1[u] = on1 ? v[1] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          double s0 = 0.0, s1 = 0.0;
+          s0 += vt0 * vp0[u] + vp0[u] * vt0;
+          s1 += vt1 * vp1[u] + vp1[u] * vt1;
+          d[u] = s0 + s1;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) d[u] = group_sum<GV>(d[u]);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int ju = j + u * NG;
+          const bool ok = ju < cnt;
+          const double val = d[u] * pair_coef;
+          const double wv = coef[u] + rho_w * (val - biw[min(ju, CH - 1)]);
+          coef[u] = ok ? pair_coef * wv : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          if (on0) acc0 += coef[u] * vp0[u];
+          if (on1) acc1 += coef[u] * vp1[u];
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    for (int o = GV; o < HW; o <<= 1) {
+      acc0 += __shfl_xor(acc0, o, 64);
+      acc1 += __shfl_xor(acc1, o, 64);
+    }
+    if (grp == 0) {
+      if (on0) out[row * ldo + c0] = out_scale * acc0;
+      if (on1) out[row * ldo + c0 + 1] = out_scale * acc1;
+    }
+  }
+}
+
+// ===========================================================================
 // PAIR CG operator on the CG layout (rows padded to 64 bytes, W and the
 // direction interleaved: row p = [W_p | P_p], stride ldw = 2 ld, zero padding).
 // A lane holds VW = 16 / sizeof(T) contiguous columns loaded as one 16-byte

@@ -239,10 +239,18 @@ void op_grad_pair(Problem& P, const double* U, int r, int ld, double rho, double
     check_pair_offsets(P, std::max(ld, ldo));
     const int G = lane_group(r);
     if (r > 4 * G) fail(LORADS_EINVAL, "rank above 256 is not supported");
-    LORADS_DISPATCH_GK(G, r, (kpair_rows<double, G, 2, KC><<<waves_grid(P.n), kBlock, 0, s>>>(
-                             P.n, P.cptr.p, P.ccol.p, P.cval.p, 1.0, P.inc_ptr.p, P.inc_nb.p,
-                             P.inc_id.p, nullptr, P.pair_coef, nullptr, U, nullptr, r, ld, out, ldo,
-                             out_scale, nullptr, 0, nullptr, P.inc_lam.p, P.inc_b.p, rho)));
+    if (pair_v2_ok(P, U, U, r, ld)) {
+      const int grid = std::max(1, (P.n + kBlock / 32 - 1) / (kBlock / 32));  // two rows per wave
+      LORADS_DISPATCH_V2(G, (kpair_grad_v2<GV><<<grid, kBlock, 0, s>>>(
+                                P.n, P.cptr.p, P.ccol.p, P.cval.p, 1.0, P.inc_ptr.p, P.inc_nb.p,
+                                P.pair_coef, U, r, ld, out, ldo, out_scale, P.inc_lam.p, P.inc_b.p,
+                                rho)));
+    } else {
+      LORADS_DISPATCH_GK(G, r, (kpair_rows<double, G, 2, KC><<<waves_grid(P.n), kBlock, 0, s>>>(
+                               P.n, P.cptr.p, P.ccol.p, P.cval.p, 1.0, P.inc_ptr.p, P.inc_nb.p,
+                               P.inc_id.p, nullptr, P.pair_coef, nullptr, U, nullptr, r, ld, out, ldo,
+                               out_scale, nullptr, 0, nullptr, P.inc_lam.p, P.inc_b.p, rho)));
+    }
     HIPCHK(hipGetLastError());
   });
 }
