@@ -432,11 +432,16 @@ int cg_run(Problem& P, const T* W, int ldw, int r, int ld, double rho, double ga
   cg_init_finish<<<1, kBlock, 0, s>>>(gridv, P.part.p, tol * tol, P.sc.p);
   HIPCHK(hipGetLastError());
   int k = 0;
-  int chunk = 2;
+  // Launch schedule (results do not depend on it: iterations queued after the
+  // device-side convergence flag is set return at once).  The first chunk is
+  // the previous solve's iteration count; later chunks aim at the iteration
+  // where the residual, decaying at its observed rate, meets the tolerance.
+  int chunk = P.cg_last_iters > 0 ? std::min(P.cg_last_iters, 32) : 2;
   constexpr int kRead = S_ITERS + 1;  // slots 0 .. S_ITERS
   double h[kRead];
   int iters = 0;
   bool done = false;
+  double rr_prev = -1.0;
   while (!done && k < maxit) {
     const int steps = std::min(chunk, maxit - k);
     const int iters_before = iters;
@@ -455,8 +460,19 @@ int cg_run(Problem& P, const T* W, int ldw, int r, int ld, double rho, double ga
     // launches after convergence returned at once: time only the live ones
     if (P.prof.on) P.prof.resolve(0, iters - iters_before);
     done = h[S_DONE + (k & 1)] != 0.0;
-    chunk = std::min(chunk * 2, 32);
+    const double rr = h[S_RR + (k & 1)], rr0 = h[S_RR0];
+    const double rr_ref = rr_prev > 0.0 ? rr_prev : rr0;
+    const int ran = iters - iters_before;
+    int next = std::min(chunk * 2, 32);
+    if (!done && ran > 0 && rr > 0.0 && rr < rr_ref) {
+      const double per_it = std::log(rr / rr_ref) / ran;  // log decay per iteration (< 0)
+      const double need = std::log(tol * tol * rr0 / rr) / per_it;
+      if (std::isfinite(need)) next = std::max(1, std::min(32, (int)std::ceil(need)));
+    }
+    rr_prev = rr;
+    chunk = next;
   }
+  P.cg_last_iters = k > 0 ? (int)h[S_ITERS] : P.cg_last_iters;
   read_slots(P, 0, h, kRead, s);
   iters = (int)h[S_ITERS];
   if (relres) *relres = h[S_RR0] > 0 ? std::sqrt(h[S_RR + (k & 1)] / h[S_RR0]) : 0.0;

@@ -143,6 +143,7 @@ struct Problem {
   DevBuf<float> tbuff;
 
   KernelProfile prof;
+  int cg_last_iters = 0;  // iterations of the last CG solve (launch schedule only)
 
   // The partial-sum buffer is sized once at setup (kernels may still read it,
   // so it is never reallocated); launches that would need more are refused.
