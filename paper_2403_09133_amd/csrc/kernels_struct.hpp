@@ -531,6 +531,14 @@ __global__ void __launch_bounds__(kBlock) kpair_rows(
 // G-lane group of the one-column form, the within-entry sums follow the same
 // tree (a lane adds its two columns first) and the cross-group sums pair the
 // same groups.  The output equals MODE 2's bit for bit.
+//
+// z (optional): the forward map A(V V^T) as a by-product.  Each entry's inner
+// product is the forward map's expression in the forward map's order, so the
+// value is the forward map's bit for bit; a row writes the entries of its
+// upper part (partners above the row), which in the incident list follow the
+// lower ones and are the row-view constraints rptr[row] .. rptr[row + 1] in
+// order.  The values are collected in the entries' LDS slots and written as
+// one contiguous run per staged pass.
 // ===========================================================================
 template <int GV>
 __global__ void __launch_bounds__(kBlock) kpair_grad_v2(
@@ -538,7 +546,8 @@ __global__ void __launch_bounds__(kBlock) kpair_grad_v2(
     const double* __restrict__ cval, double c_scale, const int* __restrict__ inc_ptr,
     const int* __restrict__ inc_nb, double pair_coef, const double* __restrict__ V, int r,
     int ld, double* __restrict__ out, int ldo, double out_scale,
-    const double* __restrict__ lam_inc, const double* __restrict__ b_inc, double rho_w) {
+    const double* __restrict__ lam_inc, const double* __restrict__ b_inc, double rho_w,
+    const int* __restrict__ rptr, double* __restrict__ z) {
   constexpr int HW = 32;              // lanes per row
   constexpr int NG = HW / GV;         // groups per row
   constexpr int CH = kPairStage / 2;  // entries staged per row and pass (a multiple of NG kUnroll)
@@ -571,6 +580,9 @@ __global__ void __launch_bounds__(kBlock) kpair_grad_v2(
       }
     }
     const int e0 = inc_ptr[row], e1 = inc_ptr[row + 1];
+    // z: the upper part starts at list position zlow and maps to rptr[row] on
+    const int zrow = z ? rptr[row] : 0;
+    const int zlow = z ? (e1 - e0) - (rptr[row + 1] - zrow) : 0;
     for (int base = e0; base < e1; base += CH) {
       const int cnt = min(CH, e1 - base);
 #pragma unroll
@@ -618,6 +630,8 @@ __global__ void __launch_bounds__(kBlock) kpair_grad_v2(
           const double val = d[u] * pair_coef;
           const double wv = coef[u] + rho_w * (val - biw[min(ju, CH - 1)]);
           coef[u] = ok ? pair_coef * wv : 0.0;
+          // the entry's lam slot (already read by the whole group) takes z
+          if (z && ok && lane == (u & (GV - 1))) cfw[ju] = val;
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
@@ -628,6 +642,15 @@ __global__ void __launch_bounds__(kBlock) kpair_grad_v2(
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (z) {
+        // slots read by the lanes that stage them next
+        const int off = base - e0 - zlow;  // z index of slot q: zrow + off + q
+#pragma unroll
+        for (int q = 0; q < CH / HW; ++q) {
+          const int j = hl + HW * q;
+          if (j < cnt && off + j >= 0) z[zrow + off + j] = cfw[j];
+        }
+      }
     }
     for (int o = GV; o < HW; o <<= 1) {
       acc0 += __shfl_xor(acc0, o, 64);

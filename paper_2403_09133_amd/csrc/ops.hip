@@ -233,18 +233,23 @@ void refresh_inc_lam(Problem& P, hipStream_t s) {
 }
 
 void op_grad_pair(Problem& P, const double* U, int r, int ld, double rho, double* out, int ldo,
-                  double out_scale, hipStream_t s) {
+                  double out_scale, hipStream_t s, double* z) {
   if (!grad_pair_ready(P)) fail(LORADS_EINVAL, "gradient form needs per-entry lam and b");
+  const bool v2 = pair_v2_ok(P, U, U, r, ld);
+  if (z && !(v2 && P.inc_upper_view)) {
+    op_forward<double>(P, U, U, r, ld, z, 1.0, s);
+    z = nullptr;
+  }
   P.prof.run(2, bytes_grad_pair(P, r), s, [&] {
     check_pair_offsets(P, std::max(ld, ldo));
     const int G = lane_group(r);
     if (r > 4 * G) fail(LORADS_EINVAL, "rank above 256 is not supported");
-    if (pair_v2_ok(P, U, U, r, ld)) {
+    if (v2) {
       const int grid = std::max(1, (P.n + kBlock / 32 - 1) / (kBlock / 32));  // two rows per wave
       LORADS_DISPATCH_V2(G, (kpair_grad_v2<GV><<<grid, kBlock, 0, s>>>(
                                 P.n, P.cptr.p, P.ccol.p, P.cval.p, 1.0, P.inc_ptr.p, P.inc_nb.p,
                                 P.pair_coef, U, r, ld, out, ldo, out_scale, P.inc_lam.p, P.inc_b.p,
-                                rho)));
+                                rho, P.rptr.p, z)));
     } else {
       LORADS_DISPATCH_GK(G, r, (kpair_rows<double, G, 2, KC><<<waves_grid(P.n), kBlock, 0, s>>>(
                                P.n, P.cptr.p, P.ccol.p, P.cval.p, 1.0, P.inc_ptr.p, P.inc_nb.p,

@@ -127,6 +127,9 @@ struct Problem {
   // uniform coefficient only: b and the current lam per incident entry, so the
   // gradient form of the adjoint streams them instead of gathering w by id
   DevBuf<double> inc_b, inc_lam;
+  // every row's incident entries with partners above the row are, in list
+  // order, the view-R constraints rptr[row] .. rptr[row + 1] (checked at setup)
+  bool inc_upper_view = false;
 
   // solver scratch
   DevBuf<double> sc;
@@ -184,11 +187,13 @@ void op_forward_pair(Problem& P, const double* U, const double* D, int r, int ld
 // gradient form for PAIR problems with a uniform coefficient:
 //   out = out_scale (C + A*(lam + rho (A(U U^T) - b))) U
 // with lam and b read per incident entry (refresh_inc_lam after lam changes);
-// bit-identical to op_forward_w followed by op_adjoint
+// bit-identical to op_forward_w followed by op_adjoint.  z (optional) receives
+// A(U U^T), bit-identical to op_forward with scale 1 (the gradient kernel
+// writes it when it can, otherwise a forward map runs first)
 bool grad_pair_ready(const Problem& P);
 void refresh_inc_lam(Problem& P, hipStream_t s);
 void op_grad_pair(Problem& P, const double* U, int r, int ld, double rho, double* out, int ldo,
-                  double out_scale, hipStream_t s);
+                  double out_scale, hipStream_t s, double* z = nullptr);
 // leading dimension of the CG work buffers: PAIR problems pad rows to a
 // multiple of 64 bytes (zero padding), so every row the CG operator gathers
 // sits in whole, aligned 64-byte sectors; other structures use r

@@ -292,6 +292,15 @@ std::unique_ptr<Problem> ingest(const lorads_problem& p, hipStream_t s) {
       for (size_t t = 0; t < inc_id.size(); ++t) bi[t] = b_int[inc_id[t]];
       P->inc_b.upload(bi, s);
     }
+    bool upper_view = true;
+    for (int j = 0; j < n && upper_view; ++j) {
+      const int nup = rptr[j + 1] - rptr[j];
+      const int lo = inc_ptr[j + 1] - nup;
+      if (lo < inc_ptr[j]) { upper_view = false; break; }
+      for (int q = 0; q < nup; ++q)
+        if (inc_id[lo + q] != rptr[j] + q) { upper_view = false; break; }
+    }
+    P->inc_upper_view = upper_view;
   }
 
   P->kptr.upload(kptr, s);

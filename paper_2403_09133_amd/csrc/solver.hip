@@ -127,10 +127,10 @@ static void alm_alloc(AlmState& A, int n, int m, int r, int ld, int mem, hipStre
 static void alm_gradient(Problem& P, AlmState& A, const double* U, double* G, double rho,
                          hipStream_t s, double& bytes) {
   if (grad_pair_ready(P)) {
-    // z for the line search and the infeasibility; the gradient forms w per entry
-    op_forward<double>(P, U, U, A.r, A.ld, P.zbuf.p, 1.0, s);
-    op_grad_pair(P, U, A.r, A.ld, rho, G, A.ld, 2.0, s);
-    bytes += bytes_forward(P, A.r, 8) + bytes_grad_pair(P, A.r);
+    // the gradient forms w per entry and returns z = A(U U^T) for the line
+    // search and the infeasibility
+    op_grad_pair(P, U, A.r, A.ld, rho, G, A.ld, 2.0, s, P.zbuf.p);
+    bytes += bytes_grad_pair(P, A.r);
   } else {
     op_forward_w(P, U, U, A.r, A.ld, P.zbuf.p, P.wbuf.p, P.lam.p, rho, s);
     op_adjoint<double>(P, P.wbuf.p, 1.0, U, A.r, A.ld, G, A.ld, 2.0, s);
