@@ -112,6 +112,14 @@ __device__ __forceinline__ double block_sum_parts(const double* part, int n, dou
 #pragma unroll
     for (int u = 0; u < 8; ++u) s += v[u];
   }
+  if (i + 3 * bs < n) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = part[i + u * bs];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s += v[u];
+    i += 4 * bs;
+  }
   for (; i < n; i += bs) s += part[i];
   return block_sum(s, sh);
 }
@@ -315,14 +323,23 @@ __global__ void __launch_bounds__(kBlock) cg_update(size_t N, T* __restrict__ X,
   if (!skip) publish_partial(block_sum(s, sh), part);
 }
 
-// ||R||^2 of the update -> next parity slot, beta, iteration count and the
+// P = R + beta P (skipped once converged).  Every block sums the np partials
+// of ||R||^2 left by cg_update (block_sum_parts: one fixed order), so all
+// blocks hold the same beta = ||R_new||^2 / ||R||^2.  Block 0 also records
+// ||R_new||^2 in the next parity slot, beta, the iteration count and the
 // convergence flag; a converged or broken-down solve carries its flag forward.
-[[maybe_unused]] static __global__ void __launch_bounds__(kBlock) cg_update_finish(int np, const double* __restrict__ part,
-                                                           double* __restrict__ sc, int parity) {
+// Block 0 writes only slots of the next parity, which no block here reads.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) cg_direction(size_t N, const T* __restrict__ R,
+                                                       T* __restrict__ P,
+                                                       double* __restrict__ sc,
+                                                       int parity, T* __restrict__ P2, int ld,
+                                                       int np, const double* __restrict__ part) {
   __shared__ double sh[kBlock / 64];
+  __shared__ double s_beta;
   const int q = parity ^ 1;
   if (sc[S_DONE + parity] != 0.0 || sc[S_BRK] != 0.0) {
-    if (threadIdx.x == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
       sc[S_DONE + q] = 1.0;
       sc[S_RR + q] = sc[S_RR + parity];
     }
@@ -330,21 +347,17 @@ __global__ void __launch_bounds__(kBlock) cg_update(size_t N, T* __restrict__ X,
   }
   const double rr = block_sum_parts(part, np, sh);
   if (threadIdx.x == 0) {
-    sc[S_BETA] = rr / sc[S_RR + parity];
-    sc[S_RR + q] = rr;
-    sc[S_ITERS] += 1.0;
-    sc[S_DONE + q] = (rr <= sc[S_TOL2] * sc[S_RR0]) ? 1.0 : 0.0;
+    const double b = rr / sc[S_RR + parity];
+    s_beta = b;
+    if (blockIdx.x == 0) {
+      sc[S_BETA] = b;
+      sc[S_RR + q] = rr;
+      sc[S_ITERS] += 1.0;
+      sc[S_DONE + q] = (rr <= sc[S_TOL2] * sc[S_RR0]) ? 1.0 : 0.0;
+    }
   }
-}
-
-// P = R + beta P (skipped once converged).
-template <typename T>
-__global__ void __launch_bounds__(kBlock) cg_direction(size_t N, const T* __restrict__ R,
-                                                       T* __restrict__ P,
-                                                       const double* __restrict__ sc,
-                                                       int parity, T* __restrict__ P2, int ld) {
-  if (sc[S_DONE + parity] != 0.0 || sc[S_BRK] != 0.0) return;
-  const double beta = sc[S_BETA];
+  __syncthreads();
+  const double beta = s_beta;
   for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock) {
     const T v = (T)((double)R[i] + beta * (double)P[i]);
     P[i] = v;
@@ -512,22 +525,22 @@ __device__ __forceinline__ size_t compact_to_row(unsigned i, int r, int ld) {
   }
 }
 
-// Several dots over m-vectors for the quartic line search, in one pass
-// (per-block partials, array t at part + t * gridDim.x):
-//   out[0] = p2.p2, [1] = p1.p2, [2] = p1.p1, [3] = p0.p2, [4] = p0.p1,
+// Several dots over m-vectors for the quartic line search, in one pass: block
+// bid of nblk (stride nblk blocks) leaves partials at part + t * nblk + bid:
+//   [0] = p2.p2, [1] = p1.p2, [2] = p1.p1, [3] = p0.p2, [4] = p0.p1,
 //   [5] = lam.p1, [6] = lam.p2,   with p0 = z - b.
-[[maybe_unused]] static __global__ void __launch_bounds__(kBlock) linesearch_dots(int m, const double* __restrict__ z,
-                                                          const double* __restrict__ b,
-                                                          const double* __restrict__ p1,
-                                                          const double* __restrict__ p2,
-                                                          const double* __restrict__ lam,
-                                                          double* __restrict__ part) {
-  __shared__ double sh[kBlock / 64];
+__device__ __forceinline__ void linesearch_partials(int bid, int nblk, int m,
+                                                    const double* __restrict__ z,
+                                                    const double* __restrict__ b,
+                                                    const double* __restrict__ p1,
+                                                    const double* __restrict__ p2,
+                                                    const double* __restrict__ lam,
+                                                    double* __restrict__ part, double* sh) {
   double s[7] = {0, 0, 0, 0, 0, 0, 0};
   // four of a thread's strided elements are loaded before they are summed in
   // index order (same sums as one element at a time, four times the loads in flight)
-  const int stride = gridDim.x * kBlock;
-  int i = blockIdx.x * kBlock + threadIdx.x;
+  const int stride = nblk * kBlock;
+  int i = bid * kBlock + threadIdx.x;
   for (; i + 3 * stride < m; i += 4 * stride) {
     double zz[4], bb[4], q1[4], q2[4], ll[4];
 #pragma unroll
@@ -553,7 +566,50 @@ __device__ __forceinline__ size_t compact_to_row(unsigned i, int r, int ld) {
   }
   for (int t = 0; t < 7; ++t) {
     const double bs = block_sum(s[t], sh);
-    if (threadIdx.x == 0) part[(size_t)t * gridDim.x + blockIdx.x] = bs;
+    if (threadIdx.x == 0) part[(size_t)t * nblk + bid] = bs;
+  }
+}
+
+// All sums of the exact line search in one launch: blocks below rg form the
+// partials of <CD, U> and <CD, D> over the first r columns of n rows (stride
+// ld; the element order and grouping of dots3_kernel with rg blocks) at
+// part_f + t * rg, blocks below gl the m-vector sums of linesearch_partials
+// with gl blocks at part_m.
+[[maybe_unused]] static __global__ void __launch_bounds__(kBlock) linesearch_all(
+    unsigned N, int r, int ld, const double* __restrict__ CD, const double* __restrict__ U,
+    const double* __restrict__ D, int rg, double* __restrict__ part_f, int m,
+    const double* __restrict__ z, const double* __restrict__ b, const double* __restrict__ p1,
+    const double* __restrict__ p2, const double* __restrict__ lam, int gl,
+    double* __restrict__ part_m) {
+  __shared__ double sh[kBlock / 64];
+  const int bid = blockIdx.x;
+  if (bid < rg) {  // uniform over the block
+    double s0 = 0.0, s1 = 0.0;
+    for (unsigned i = bid * kBlock + threadIdx.x; i < N; i += rg * kBlock) {
+      const size_t q = compact_to_row(i, r, ld);
+      s0 += CD[q] * U[q];
+      s1 += CD[q] * D[q];
+    }
+    const double b0 = block_sum(s0, sh);
+    if (threadIdx.x == 0) part_f[bid] = b0;
+    const double b1 = block_sum(s1, sh);
+    if (threadIdx.x == 0) part_f[rg + bid] = b1;
+  }
+  if (bid < gl) linesearch_partials(bid, gl, m, z, b, p1, p2, lam, part_m, sh);
+}
+
+// sc[slot] = 2 <CD, U>, sc[slot + 1] = <CD, D>, sc[slot + 2 + t] = line-search sum t
+[[maybe_unused]] static __global__ void __launch_bounds__(kBlock) linesearch_finish(
+    int rg, const double* __restrict__ part_f, int gl, const double* __restrict__ part_m,
+    double* __restrict__ sc, int slot) {
+  __shared__ double sh[kBlock / 64];
+  const double v0 = block_sum_parts(part_f, rg, sh);
+  if (threadIdx.x == 0) sc[slot] = 2.0 * v0;
+  const double v1 = block_sum_parts(part_f + rg, rg, sh);
+  if (threadIdx.x == 0) sc[slot + 1] = 1.0 * v1;
+  for (int t = 0; t < 7; ++t) {
+    const double v = block_sum_parts(part_m + (size_t)t * gl, gl, sh);
+    if (threadIdx.x == 0) sc[slot + 2 + t] = 1.0 * v;
   }
 }
 

@@ -413,11 +413,18 @@ void dual_update_slot(Problem& P, const double* z, double rho, double* lam, int 
   HIPCHK(hipGetLastError());
 }
 
-void linesearch_slots(Problem& P, const double* z, const double* p1, const double* p2,
+void linesearch_slots(Problem& P, int n, int r, int ld, const double* CD, const double* U,
+                      const double* D, const double* z, const double* p1, const double* p2,
                       const double* lam, int slot, hipStream_t s) {
-  const int grid = grid_for(P.m, kRedBlocks);
-  linesearch_dots<<<grid, kBlock, 0, s>>>(P.m, z, P.b.p, p1, p2, lam, P.part.p);
-  finish_slots<<<1, kBlock, 0, s>>>(grid, 7, P.part.p, 1.0, P.sc.p, slot);
+  const size_t N = (size_t)n * r;
+  if (N >= ((size_t)1 << 32)) fail(LORADS_EINVAL, "factor too large for the line-search dots");
+  const int rg = grid_for(N, kRedBlocks), gl = grid_for(P.m, kRedBlocks);
+  P.ensure_part((size_t)2 * rg + (size_t)7 * gl);
+  double* part_f = P.part.p;
+  double* part_m = P.part.p + 2 * rg;
+  linesearch_all<<<std::max(rg, gl), kBlock, 0, s>>>((unsigned)N, r, ld, CD, U, D, rg, part_f, P.m, z,
+                                                     P.b.p, p1, p2, lam, gl, part_m);
+  linesearch_finish<<<1, kBlock, 0, s>>>(rg, part_f, gl, part_m, P.sc.p, slot);
   HIPCHK(hipGetLastError());
 }
 
@@ -456,8 +463,7 @@ int cg_run(Problem& P, const T* W, int ldw, int r, int ld, double rho, double ga
       P.prof.run(0, bytes_cg_op(P, r, sizeof(T)), s, [&] { np = op_cg<T>(P, W, ldw, r, ld, Pd, P2, Q, t, par, s); });
       cg_alpha_finish<<<1, kBlock, 0, s>>>(np, P.part.p, P.sc.p, par);
       cg_update<T><<<gridv, kBlock, 0, s>>>(N, X, R, Pd, Q, P.sc.p, par, P.part.p);
-      cg_update_finish<<<1, kBlock, 0, s>>>(gridv, P.part.p, P.sc.p, par);
-      cg_direction<T><<<gridv, kBlock, 0, s>>>(N, R, Pd, P.sc.p, par, P2, ld);
+      cg_direction<T><<<gridv, kBlock, 0, s>>>(N, R, Pd, P.sc.p, par, P2, ld, gridv, P.part.p);
     }
     HIPCHK(hipGetLastError());
     read_slots(P, 0, h, kRead, s);

@@ -212,8 +212,11 @@ void set_slots(Problem& P, int slot, const double* vals, int count, hipStream_t 
 void read_slots(Problem& P, int slot, double* vals, int count, hipStream_t s);  // synchronises
 // lam += rho (z - b) and sc[slot] = ||z - b||^2 (rho = 0: norm only)
 void dual_update_slot(Problem& P, const double* z, double rho, double* lam, int slot, hipStream_t s);
-// the seven m-vector inner products of the quartic line search -> sc[slot .. slot+6]
-void linesearch_slots(Problem& P, const double* z, const double* p1, const double* p2,
+// the sums of the quartic line search in one pass: sc[slot] = 2 <CD, U>,
+// sc[slot + 1] = <CD, D> (first r columns of n rows of stride ld) and the seven
+// m-vector inner products of p0 = z - b, p1, p2 and lam -> sc[slot + 2 .. slot + 8]
+void linesearch_slots(Problem& P, int n, int r, int ld, const double* CD, const double* U,
+                      const double* D, const double* z, const double* p1, const double* p2,
                       const double* lam, int slot, hipStream_t s);
 template <typename TX, typename TY>
 void dot_to_slot(Problem& P, size_t N, const TX* X, const TY* Y, double scale, int slot, hipStream_t s);

@@ -274,10 +274,8 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
         op_forward_pair(P, U, A.D.p, r, F.ld, A.p1.p, A.p2.p, s);
         op_adjoint<double>(P, (const double*)nullptr, 1.0, A.D.p, r, F.ld, A.CD.p, F.ld, 1.0, s);
         info.op_bytes += 2 * bytes_forward(P, r, 8) + bytes_adjoint(P, r, 8, true);
-        dots3_kernel<<<rg, kBlock, 0, s>>>(Nc, r, F.ld, A.CD.p, U, A.CD.p, A.D.p, nullptr, nullptr,
-                                           2, part);
-        finish(2, 2.0, S_GEN + 1, 1.0, S_GEN + 2);
-        linesearch_slots(P, P.zbuf.p, A.p1.p, A.p2.p, P.lam.p, S_GEN + 3, s);
+        linesearch_slots(P, n, r, F.ld, A.CD.p, U, A.D.p, P.zbuf.p, A.p1.p, A.p2.p, P.lam.p,
+                         S_GEN + 1, s);
         read_slots(P, S_GEN + 1, h, checked ? 9 : 10, s);
         if (!checked) {
           checked = true;
