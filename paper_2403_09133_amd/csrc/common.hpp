@@ -91,6 +91,12 @@ enum Slot : int {
 constexpr int kBlock = 256;        // threads per block of the row / element kernels
 constexpr int kRedBlocks = 512;    // grid of the fixed-grid reductions
 constexpr int kMaxPart = 8192;     // capacity of a partial-sum buffer
+// L-BFGS passes: two alternating regions of three partial arrays, the line
+// search's nine arrays, then the descent check's array above them
+constexpr int kLbfgsPartStride = 2048;
+static_assert(3 * kRedBlocks <= kLbfgsPartStride, "L-BFGS partial region too small");
+static_assert(9 * kRedBlocks <= 3 * kLbfgsPartStride, "line-search partials reach the descent-check array");
+static_assert(4 * kLbfgsPartStride <= kMaxPart, "partial-sum buffer too small");
 constexpr int kPairChunk = 32;     // PAIR forward map: constraints per work item
 
 inline int pow2_group(int r) {

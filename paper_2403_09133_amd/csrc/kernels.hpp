@@ -428,15 +428,57 @@ __device__ __forceinline__ size_t compact_to_row(unsigned i, int r, int ld) {
   if (k > 2) publish_partial(block_sum(s2, sh), part + 2 * gridDim.x);
 }
 
+// The previous pass's sums, finished by every block of the next pass instead
+// of a one-block finishing launch: sum t (t < k <= 3) of the np partials at
+// part + t * np, times s[t], belongs in slot q[t].
+struct PrevSums {
+  const double* part;
+  int np, k;
+  double s[3];
+  int q[3];
+};
+
+// Every block sums the partials with finish_multi's code (one fixed order), so
+// all blocks hold the same values; block 0 stores them in their slots for
+// later passes and the host.  The values are returned in vals (LDS).
+__device__ __forceinline__ void prev_finish(const PrevSums& p, double* __restrict__ sc,
+                                            double* vals, double* sh) {
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    if (t < p.k) {
+      const double v = block_sum_parts(p.part + (size_t)t * p.np, p.np, sh);
+      if (threadIdx.x == 0) {
+        const double val = p.s[t] * v;
+        vals[t] = val;
+        if (blockIdx.x == 0) sc[p.q[t]] = val;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// a slot's value: the previous pass's sum when it produces that slot (block 0
+// may be writing it during this launch), else the stored value
+__device__ __forceinline__ double slot_value(const PrevSums& p, const double* vals,
+                                             const double* __restrict__ sc, int slot) {
+  double v = sc[slot];
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+    if (t < p.k && p.q[t] == slot) v = vals[t];
+  return v;
+}
+
 // first loop: y = (sign sc[slot]) x + 1.0 yin (yin = y, or G before q exists);
 // with scale, then y = (sc[sa] / sc[sb]) y + 0.0 y; partials of <u, y>
 [[maybe_unused]] static __global__ void __launch_bounds__(kBlock) lbfgs_first_kernel(
-    unsigned N, int r, int ld, const double* __restrict__ sc, int slot, double sign,
+    unsigned N, int r, int ld, double* __restrict__ sc, int slot, double sign,
     const double* __restrict__ x, const double* yin, double* y, int scale, int sa, int sb,
-    const double* __restrict__ u, double* __restrict__ part) {
+    const double* __restrict__ u, double* __restrict__ part, PrevSums prev) {
   __shared__ double sh[kBlock / 64];
-  const double a = sign * sc[slot];
-  const double a2 = scale ? sc[sa] / sc[sb] : 0.0;
+  __shared__ double vals[3];
+  prev_finish(prev, sc, vals, sh);
+  const double a = sign * slot_value(prev, vals, sc, slot);
+  const double a2 = scale ? slot_value(prev, vals, sc, sa) / slot_value(prev, vals, sc, sb) : 0.0;
   const double b = 1.0;
   double s = 0.0;
   for (unsigned i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
@@ -452,11 +494,14 @@ __device__ __forceinline__ size_t compact_to_row(unsigned i, int r, int ld) {
 // second loop: y = (sc[sa] - sc[sb]) x + 1.0 y (x == null: y unchanged); then
 // either partials of <u, y>, or (d given) d = -1.0 y + 0.0 d and partials of <g, d>
 [[maybe_unused]] static __global__ void __launch_bounds__(kBlock) lbfgs_second_kernel(
-    unsigned N, int r, int ld, const double* __restrict__ sc, int sa, int sb,
+    unsigned N, int r, int ld, double* __restrict__ sc, int sa, int sb,
     const double* __restrict__ x, const double* yin, double* y, const double* __restrict__ u,
-    double* __restrict__ d, const double* __restrict__ g, double* __restrict__ part) {
+    double* __restrict__ d, const double* __restrict__ g, double* __restrict__ part,
+    PrevSums prev) {
   __shared__ double sh[kBlock / 64];
-  const double a = x ? sc[sa] - sc[sb] : 0.0;
+  __shared__ double vals[3];
+  prev_finish(prev, sc, vals, sh);
+  const double a = x ? slot_value(prev, vals, sc, sa) - slot_value(prev, vals, sc, sb) : 0.0;
   const double b = 1.0;
   double s = 0.0;
   for (unsigned i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
@@ -598,11 +643,16 @@ __device__ __forceinline__ void linesearch_partials(int bid, int nblk, int m,
   if (bid < gl) linesearch_partials(bid, gl, m, z, b, p1, p2, lam, part_m, sh);
 }
 
-// sc[slot] = 2 <CD, U>, sc[slot + 1] = <CD, D>, sc[slot + 2 + t] = line-search sum t
+// sc[slot] = 2 <CD, U>, sc[slot + 1] = <CD, D>, sc[slot + 2 + t] = line-search
+// sum t; with part_gd, also sc[slot + 9] = the sum of its rg partials
 [[maybe_unused]] static __global__ void __launch_bounds__(kBlock) linesearch_finish(
     int rg, const double* __restrict__ part_f, int gl, const double* __restrict__ part_m,
-    double* __restrict__ sc, int slot) {
+    const double* __restrict__ part_gd, double* __restrict__ sc, int slot) {
   __shared__ double sh[kBlock / 64];
+  if (part_gd) {
+    const double v = block_sum_parts(part_gd, rg, sh);
+    if (threadIdx.x == 0) sc[slot + 9] = 1.0 * v;
+  }
   const double v0 = block_sum_parts(part_f, rg, sh);
   if (threadIdx.x == 0) sc[slot] = 2.0 * v0;
   const double v1 = block_sum_parts(part_f + rg, rg, sh);

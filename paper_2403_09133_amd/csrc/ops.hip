@@ -415,7 +415,7 @@ void dual_update_slot(Problem& P, const double* z, double rho, double* lam, int 
 
 void linesearch_slots(Problem& P, int n, int r, int ld, const double* CD, const double* U,
                       const double* D, const double* z, const double* p1, const double* p2,
-                      const double* lam, int slot, hipStream_t s) {
+                      const double* lam, int slot, hipStream_t s, const double* part_gd) {
   const size_t N = (size_t)n * r;
   if (N >= ((size_t)1 << 32)) fail(LORADS_EINVAL, "factor too large for the line-search dots");
   const int rg = grid_for(N, kRedBlocks), gl = grid_for(P.m, kRedBlocks);
@@ -424,7 +424,9 @@ void linesearch_slots(Problem& P, int n, int r, int ld, const double* CD, const 
   double* part_m = P.part.p + 2 * rg;
   linesearch_all<<<std::max(rg, gl), kBlock, 0, s>>>((unsigned)N, r, ld, CD, U, D, rg, part_f, P.m, z,
                                                      P.b.p, p1, p2, lam, gl, part_m);
-  linesearch_finish<<<1, kBlock, 0, s>>>(rg, part_f, gl, part_m, P.sc.p, slot);
+  if (part_gd && part_gd < part_m + (size_t)7 * gl)
+    fail(LORADS_EINVAL, "descent-check partials overlap the line-search partials");
+  linesearch_finish<<<1, kBlock, 0, s>>>(rg, part_f, gl, part_m, part_gd, P.sc.p, slot);
   HIPCHK(hipGetLastError());
 }
 

@@ -214,10 +214,12 @@ void read_slots(Problem& P, int slot, double* vals, int count, hipStream_t s);  
 void dual_update_slot(Problem& P, const double* z, double rho, double* lam, int slot, hipStream_t s);
 // the sums of the quartic line search in one pass: sc[slot] = 2 <CD, U>,
 // sc[slot + 1] = <CD, D> (first r columns of n rows of stride ld) and the seven
-// m-vector inner products of p0 = z - b, p1, p2 and lam -> sc[slot + 2 .. slot + 8]
+// m-vector inner products of p0 = z - b, p1, p2 and lam -> sc[slot + 2 .. slot + 8];
+// part_gd (optional, above the line-search partials in P.part): partials of a
+// dot over the same factor grid, summed into sc[slot + 9]
 void linesearch_slots(Problem& P, int n, int r, int ld, const double* CD, const double* U,
                       const double* D, const double* z, const double* p1, const double* p2,
-                      const double* lam, int slot, hipStream_t s);
+                      const double* lam, int slot, hipStream_t s, const double* part_gd = nullptr);
 template <typename TX, typename TY>
 void dot_to_slot(Problem& P, size_t N, const TX* X, const TY* Y, double scale, int slot, hipStream_t s);
 // the same for n x r factors stored with row stride ld (bit-identical to the

@@ -229,39 +229,53 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
       auto finish = [&](int k, double s0, int q0, double s1 = 0.0, int q1 = 0, double s2 = 0.0, int q2 = 0) {
         finish_multi<<<1, kBlock, 0, s>>>(rg, k, part, s0, s1, s2, q0, q1, q2, P.sc.p);
       };
+      // Each pass finishes the previous pass's sums itself (PrevSums), so the
+      // passes write their partials to two alternating regions of P.part; the
+      // last pass's <G, D> partials go above the line-search partials and are
+      // summed by the line search's finishing launch.
+      double* pbuf[2] = {part, part + kLbfgsPartStride};
+      double* part_gd = part + 3 * kLbfgsPartStride;
+      P.ensure_part((size_t)4 * kLbfgsPartStride);
+      int cur = 0;
+      PrevSums prev{};
+      auto chain = [&](int k, double s0, int q0, double s1 = 0.0, int q1 = 0, double s2 = 0.0,
+                       int q2 = 0) {
+        prev = PrevSums{pbuf[cur], rg, k, {s0, s1, s2}, {q0, q1, q2}};
+        cur ^= 1;
+      };
       if (mc > 0) {
         const int k0 = order[0];
         dots3_kernel<<<rg, kBlock, 0, s>>>(Nc, r, F.ld, A.S[k0].p, A.G.p, A.S[k0].p, A.Y[k0].p,
-                                           A.Y[k0].p, A.Y[k0].p, 3, part);
-        finish(3, A.rhoh[k0], S_GEN + 16, 1.0, S_GEN + 1, 1.0, S_GEN + 2);
+                                           A.Y[k0].p, A.Y[k0].p, 3, pbuf[cur]);
+        chain(3, A.rhoh[k0], S_GEN + 16, 1.0, S_GEN + 1, 1.0, S_GEN + 2);
         for (int t = 0; t < mc; ++t) {
           // q = -alpha_t Y_t + q; on the last pass q *= <S,Y>/<Y,Y> of the newest pair
           const bool last = t == mc - 1;
           const double* u = last ? A.Y[order[mc - 1]].p : A.S[order[t + 1]].p;
           lbfgs_first_kernel<<<rg, kBlock, 0, s>>>(Nc, r, F.ld, P.sc.p, S_GEN + 16 + t, -1.0,
                                                    A.Y[order[t]].p, t == 0 ? A.G.p : A.Q.p, A.Q.p,
-                                                   last ? 1 : 0, S_GEN + 1, S_GEN + 2, u, part);
-          if (last) finish(1, A.rhoh[order[mc - 1]], S_GEN + 6);
-          else finish(1, A.rhoh[order[t + 1]], S_GEN + 16 + t + 1);
+                                                   last ? 1 : 0, S_GEN + 1, S_GEN + 2, u, pbuf[cur],
+                                                   prev);
+          if (last) chain(1, A.rhoh[order[mc - 1]], S_GEN + 6);
+          else chain(1, A.rhoh[order[t + 1]], S_GEN + 16 + t + 1);
         }
         for (int t = mc - 1; t >= 0; --t) {
           // q += (alpha_t - beta_t) S_t, then the next beta's dot, or D = -q
           if (t > 0) {
             lbfgs_second_kernel<<<rg, kBlock, 0, s>>>(Nc, r, F.ld, P.sc.p, S_GEN + 16 + t, S_GEN + 6,
                                                       A.S[order[t]].p, A.Q.p, A.Q.p,
-                                                      A.Y[order[t - 1]].p, nullptr, nullptr, part);
-            finish(1, A.rhoh[order[t - 1]], S_GEN + 6);
+                                                      A.Y[order[t - 1]].p, nullptr, nullptr,
+                                                      pbuf[cur], prev);
+            chain(1, A.rhoh[order[t - 1]], S_GEN + 6);
           } else {
             lbfgs_second_kernel<<<rg, kBlock, 0, s>>>(Nc, r, F.ld, P.sc.p, S_GEN + 16, S_GEN + 6,
                                                       A.S[order[0]].p, A.Q.p, A.Q.p, nullptr,
-                                                      A.D.p, A.G.p, part);
-            finish(1, 1.0, S_GEN + 10);
+                                                      A.D.p, A.G.p, part_gd, prev);
           }
         }
       } else {
         lbfgs_second_kernel<<<rg, kBlock, 0, s>>>(Nc, r, F.ld, P.sc.p, 0, 0, nullptr, A.G.p, nullptr,
-                                                  nullptr, A.D.p, A.G.p, part);
-        finish(1, 1.0, S_GEN + 10);
+                                                  nullptr, A.D.p, A.G.p, part_gd, prev);
       }
       HIPCHK(hipGetLastError());
       // The line search below also returns <G, D>: a direction that is not a
@@ -275,7 +289,7 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
         op_adjoint<double>(P, (const double*)nullptr, 1.0, A.D.p, r, F.ld, A.CD.p, F.ld, 1.0, s);
         info.op_bytes += 2 * bytes_forward(P, r, 8) + bytes_adjoint(P, r, 8, true);
         linesearch_slots(P, n, r, F.ld, A.CD.p, U, A.D.p, P.zbuf.p, A.p1.p, A.p2.p, P.lam.p,
-                         S_GEN + 1, s);
+                         S_GEN + 1, s, part_gd);
         read_slots(P, S_GEN + 1, h, checked ? 9 : 10, s);
         if (!checked) {
           checked = true;
