@@ -85,7 +85,8 @@ enum Slot : int {
   S_RHO = 11,
   S_PQ = 12,
   S_GEN = 16,  // 16..63 general-purpose reduction outputs
-  S_COUNT = 64
+  S_PAIRS = 64,  // 64..80: <S, Y> of each L-BFGS pair buffer (memory <= 16, plus one)
+  S_COUNT = 96
 };
 
 constexpr int kBlock = 256;        // threads per block of the row / element kernels

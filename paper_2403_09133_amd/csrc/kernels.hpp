@@ -430,12 +430,15 @@ __device__ __forceinline__ size_t compact_to_row(unsigned i, int r, int ld) {
 
 // The previous pass's sums, finished by every block of the next pass instead
 // of a one-block finishing launch: sum t (t < k <= 3) of the np partials at
-// part + t * np, times s[t], belongs in slot q[t].
+// part + t * np, times its scale, belongs in slot q[t].  The scale is s[t], or
+// 1 / sc[dv[t]] when dv[t] >= 0 (the reciprocal of a stored sum, rounded as a
+// division on the host would round it).
 struct PrevSums {
   const double* part;
   int np, k;
   double s[3];
   int q[3];
+  int dv[3];
 };
 
 // Every block sums the partials with finish_multi's code (one fixed order), so
@@ -448,7 +451,8 @@ __device__ __forceinline__ void prev_finish(const PrevSums& p, double* __restric
     if (t < p.k) {
       const double v = block_sum_parts(p.part + (size_t)t * p.np, p.np, sh);
       if (threadIdx.x == 0) {
-        const double val = p.s[t] * v;
+        const double scale = p.dv[t] >= 0 ? 1.0 / sc[p.dv[t]] : p.s[t];
+        const double val = scale * v;
         vals[t] = val;
         if (blockIdx.x == 0) sc[p.q[t]] = val;
       }
@@ -555,6 +559,21 @@ __device__ __forceinline__ double slot_value(const PrevSums& p, const double* va
   }
   publish_partial(block_sum(s0, sh), part);
   publish_partial(block_sum(s1, sh), part + gridDim.x);
+}
+
+// the curvature pair's sums: sc[q_sy] = sc[q_mirror] = <Sn, Yn> (array 0),
+// sc[q_gg] = ||Gn||^2 (array 1), arrays of length np
+[[maybe_unused]] static __global__ void __launch_bounds__(kBlock) pair_finish(
+    int np, const double* __restrict__ part, double* __restrict__ sc, int q_sy, int q_mirror,
+    int q_gg) {
+  __shared__ double sh[kBlock / 64];
+  const double v0 = block_sum_parts(part, np, sh);
+  if (threadIdx.x == 0) {
+    sc[q_sy] = 1.0 * v0;
+    sc[q_mirror] = 1.0 * v0;
+  }
+  const double v1 = block_sum_parts(part + np, np, sh);
+  if (threadIdx.x == 0) sc[q_gg] = 1.0 * v1;
 }
 
 // sc[slot_t] = scale_t * sum of partial array t (t < k <= 3), arrays of length np

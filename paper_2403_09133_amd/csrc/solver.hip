@@ -98,7 +98,9 @@ struct AlmState {
   int n, m, r, ld;
   DevBuf<double> G, Gn, D, Q, CD, p1, p2, Sn, Yn;
   std::vector<DevBuf<double>> S, Y;
-  std::vector<double> rhoh;  // 1 / <S, Y>
+  // slot of sc holding <S, Y> of each pair buffer (it travels with the buffer)
+  std::vector<int> sy;
+  int sy_n = 0;
   int head = 0, count = 0;
 };
 
@@ -114,7 +116,10 @@ static void alm_alloc(AlmState& A, int n, int m, int r, int ld, int mem, hipStre
     if (ld != r) b->zero(s);
   }
   A.p1.alloc(m); A.p2.alloc(m);
-  A.S.resize(mem); A.Y.resize(mem); A.rhoh.assign(mem, 0.0);
+  A.S.resize(mem); A.Y.resize(mem);
+  A.sy.resize(mem);
+  for (int i = 0; i < mem; ++i) A.sy[i] = S_PAIRS + i;
+  A.sy_n = S_PAIRS + mem;
   for (int i = 0; i < mem; ++i) {
     A.S[i].alloc(N);
     A.Y[i].alloc(N);
@@ -210,44 +215,39 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
     double gnorm2 = h[0];  // ||G||^2 of the current gradient
     int it = 0;
     bool conv = false;
-    while (true) {
-      const double gnorm = std::sqrt(gnorm2);
-      if (!std::isfinite(gnorm)) fail(LORADS_ENUMERIC, "non-finite gradient in phase I");
-      if (gnorm / (1.0 + c_fro) <= tol) { conv = true; break; }
-      if (it >= cap) break;
-      // two-loop recursion, newest pair first, in fused passes (each pass
-      // updates q and forms the next dot; q = G until the first update).  The
-      // scalars stay on the device: alphas in slots S_GEN+16+t, <S,Y> and
-      // <Y,Y> of the newest pair in S_GEN+1, S_GEN+2, beta in S_GEN+6.  The
-      // last pass forms D = -q and <G, D> (S_GEN+10) for the descent check.
+    const unsigned Nc = (unsigned)((size_t)n * r);
+    const int rg = grid_for((size_t)n * r, kRedBlocks);
+    const int mem = o.lbfgs_mem;
+    double* part = P.part.p;
+    // Each pass of the two-loop finishes the previous pass's sums itself
+    // (PrevSums), so the passes write their partials to two alternating
+    // regions of P.part; the last pass's <G, D> partials go above the
+    // line-search partials and are summed by the line search's finishing
+    // launch.  1 / <S, Y> of a pair is formed on the device from the pair's
+    // own slot, exactly as the host would form it.
+    double* pbuf[2] = {part, part + kLbfgsPartStride};
+    double* part_gd = part + 3 * kLbfgsPartStride;
+    P.ensure_part((size_t)4 * kLbfgsPartStride);
+    // two-loop recursion, newest pair first, in fused passes (each pass
+    // updates q and forms the next dot; q = G until the first update).  The
+    // scalars stay on the device: alphas in slots S_GEN+16+t, <S,Y> and
+    // <Y,Y> of the newest pair in S_GEN+1, S_GEN+2, beta in S_GEN+6.  The
+    // last pass forms D = -q and <G, D> (S_GEN+10) for the descent check.
+    auto two_loop = [&]() {
       std::vector<int> order;
-      for (int t = 0; t < A.count; ++t) order.push_back((A.head - 1 - t + o.lbfgs_mem) % o.lbfgs_mem);
+      for (int t = 0; t < A.count; ++t) order.push_back((A.head - 1 - t + mem) % mem);
       const int mc = (int)order.size();
-      const unsigned Nc = (unsigned)((size_t)n * r);
-      const int rg = grid_for((size_t)n * r, kRedBlocks);
-      double* part = P.part.p;
-      auto finish = [&](int k, double s0, int q0, double s1 = 0.0, int q1 = 0, double s2 = 0.0, int q2 = 0) {
-        finish_multi<<<1, kBlock, 0, s>>>(rg, k, part, s0, s1, s2, q0, q1, q2, P.sc.p);
-      };
-      // Each pass finishes the previous pass's sums itself (PrevSums), so the
-      // passes write their partials to two alternating regions of P.part; the
-      // last pass's <G, D> partials go above the line-search partials and are
-      // summed by the line search's finishing launch.
-      double* pbuf[2] = {part, part + kLbfgsPartStride};
-      double* part_gd = part + 3 * kLbfgsPartStride;
-      P.ensure_part((size_t)4 * kLbfgsPartStride);
       int cur = 0;
       PrevSums prev{};
-      auto chain = [&](int k, double s0, int q0, double s1 = 0.0, int q1 = 0, double s2 = 0.0,
-                       int q2 = 0) {
-        prev = PrevSums{pbuf[cur], rg, k, {s0, s1, s2}, {q0, q1, q2}};
+      auto chain = [&](int k, int dv0, int q0, int q1 = 0, int q2 = 0) {
+        prev = PrevSums{pbuf[cur], rg, k, {1.0, 1.0, 1.0}, {q0, q1, q2}, {dv0, -1, -1}};
         cur ^= 1;
       };
       if (mc > 0) {
         const int k0 = order[0];
         dots3_kernel<<<rg, kBlock, 0, s>>>(Nc, r, F.ld, A.S[k0].p, A.G.p, A.S[k0].p, A.Y[k0].p,
                                            A.Y[k0].p, A.Y[k0].p, 3, pbuf[cur]);
-        chain(3, A.rhoh[k0], S_GEN + 16, 1.0, S_GEN + 1, 1.0, S_GEN + 2);
+        chain(3, A.sy[k0], S_GEN + 16, S_GEN + 1, S_GEN + 2);
         for (int t = 0; t < mc; ++t) {
           // q = -alpha_t Y_t + q; on the last pass q *= <S,Y>/<Y,Y> of the newest pair
           const bool last = t == mc - 1;
@@ -256,8 +256,8 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
                                                    A.Y[order[t]].p, t == 0 ? A.G.p : A.Q.p, A.Q.p,
                                                    last ? 1 : 0, S_GEN + 1, S_GEN + 2, u, pbuf[cur],
                                                    prev);
-          if (last) chain(1, A.rhoh[order[mc - 1]], S_GEN + 6);
-          else chain(1, A.rhoh[order[t + 1]], S_GEN + 16 + t + 1);
+          if (last) chain(1, A.sy[order[mc - 1]], S_GEN + 6);
+          else chain(1, A.sy[order[t + 1]], S_GEN + 16 + t + 1);
         }
         for (int t = mc - 1; t >= 0; --t) {
           // q += (alpha_t - beta_t) S_t, then the next beta's dot, or D = -q
@@ -266,7 +266,7 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
                                                       A.S[order[t]].p, A.Q.p, A.Q.p,
                                                       A.Y[order[t - 1]].p, nullptr, nullptr,
                                                       pbuf[cur], prev);
-            chain(1, A.rhoh[order[t - 1]], S_GEN + 6);
+            chain(1, A.sy[order[t - 1]], S_GEN + 6);
           } else {
             lbfgs_second_kernel<<<rg, kBlock, 0, s>>>(Nc, r, F.ld, P.sc.p, S_GEN + 16, S_GEN + 6,
                                                       A.S[order[0]].p, A.Q.p, A.Q.p, nullptr,
@@ -278,19 +278,69 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
                                                   nullptr, A.D.p, A.G.p, part_gd, prev);
       }
       HIPCHK(hipGetLastError());
-      // The line search below also returns <G, D>: a direction that is not a
+    };
+    // the exact line search's maps and sums; one host read (slots S_GEN+1 ..
+    // S_GEN+nread)
+    auto line_search = [&](int nread) {
+      op_forward_pair(P, U, A.D.p, r, F.ld, A.p1.p, A.p2.p, s);
+      op_adjoint<double>(P, (const double*)nullptr, 1.0, A.D.p, r, F.ld, A.CD.p, F.ld, 1.0, s);
+      info.op_bytes += 2 * bytes_forward(P, r, 8) + bytes_adjoint(P, r, 8, true);
+      linesearch_slots(P, n, r, F.ld, A.CD.p, U, A.D.p, P.zbuf.p, A.p1.p, A.p2.p, P.lam.p,
+                       S_GEN + 1, s, part_gd);
+      read_slots(P, S_GEN + 1, h, nread, s);
+    };
+    // A step's curvature pair enters the memory at once, before its <S, Y>
+    // is known on the host, so the next direction and line search are queued
+    // without waiting for it.  The host reads <S, Y> and ||G||^2 (slots
+    // S_GEN+11, S_GEN+12) with the line search's sums: a pair with
+    // <S, Y> <= 0 is taken out again (the buffers it displaced are untouched
+    // until the next step) and the direction recomputed, so the iterates are
+    // those of the plain order.
+    bool pending = false;
+    int undo_head = 0, undo_count = 0;
+    // applies the pending pair's test; true when the pair was taken out
+    auto resolve = [&](double sy, double gg) {
+      pending = false;
+      gnorm2 = gg;
+      if (sy > 0.0) return false;
+      A.head = undo_head;
+      A.count = undo_count;
+      std::swap(A.S[undo_head], A.Sn);
+      std::swap(A.Y[undo_head], A.Yn);
+      std::swap(A.sy[undo_head], A.sy_n);
+      return true;
+    };
+    // top-of-iteration test: true when the inner loop ends here
+    auto stop_test = [&]() {
+      const double gnorm = std::sqrt(gnorm2);
+      if (!std::isfinite(gnorm)) fail(LORADS_ENUMERIC, "non-finite gradient in phase I");
+      if (gnorm / (1.0 + c_fro) <= tol) { conv = true; return true; }
+      return it >= cap;
+    };
+    while (true) {
+      if (pending && it >= cap) {
+        read_slots(P, S_GEN + 11, h, 2, s);
+        resolve(h[0], h[1]);
+      }
+      if (!pending && stop_test()) break;
+      two_loop();
+      line_search(12);
+      if (pending) {
+        const bool out = resolve(h[10], h[11]);
+        if (stop_test()) break;
+        if (out) {
+          two_loop();
+          line_search(10);
+        }
+      }
+      // The line search also returns <G, D>: a direction that is not a
       // descent direction is replaced by -G (memory cleared) and the search
       // repeated, as is a quasi-Newton step whose exact minimiser is not
-      // positive.  One host read per search.
+      // positive.
       double alpha = 0.0;
       bool checked = false;
       for (int attempt = 0; attempt < 3; ++attempt) {
-        op_forward_pair(P, U, A.D.p, r, F.ld, A.p1.p, A.p2.p, s);
-        op_adjoint<double>(P, (const double*)nullptr, 1.0, A.D.p, r, F.ld, A.CD.p, F.ld, 1.0, s);
-        info.op_bytes += 2 * bytes_forward(P, r, 8) + bytes_adjoint(P, r, 8, true);
-        linesearch_slots(P, n, r, F.ld, A.CD.p, U, A.D.p, P.zbuf.p, A.p1.p, A.p2.p, P.lam.p,
-                         S_GEN + 1, s, part_gd);
-        read_slots(P, S_GEN + 1, h, checked ? 9 : 10, s);
+        if (attempt > 0) line_search(checked ? 9 : 10);
         if (!checked) {
           checked = true;
           if (!(h[9] < 0.0)) {
@@ -313,23 +363,23 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
         A.head = A.count = 0;
       }
       if (!(alpha > 0.0)) break;
-      // S = alpha D; U += S; new gradient; Y = G_new - G.  The pair enters the
-      // memory only when <S, Y> > 0 (the oldest pair is dropped when full).
+      // S = alpha D; U += S; new gradient; Y = G_new - G; <S, Y> into the
+      // pair's own slot (and S_GEN+11), ||G_new||^2 into S_GEN+12.  The pair
+      // enters the memory now (the oldest pair is dropped when full) and
+      // leaves it again at the next read if <S, Y> <= 0.
       lbfgs_step_kernel<<<gridN(N), kBlock, 0, s>>>(N, alpha, A.D.p, A.Sn.p, U);
       alm_gradient(P, A, U, A.Gn.p, rho, s, info.op_bytes);
       lbfgs_pair_kernel<<<rg, kBlock, 0, s>>>(Nc, r, F.ld, A.Gn.p, A.G.p, A.Yn.p, A.Sn.p, part);
-      finish(2, 1.0, S_GEN, 1.0, S_GEN + 1);
+      pair_finish<<<1, kBlock, 0, s>>>(rg, part, P.sc.p, A.sy_n, S_GEN + 11, S_GEN + 12);
       HIPCHK(hipGetLastError());
-      read_slots(P, S_GEN, h, 2, s);
-      gnorm2 = h[1];
-      if (h[0] > 0.0) {
-        const int slot = A.head;
-        std::swap(A.S[slot], A.Sn);
-        std::swap(A.Y[slot], A.Yn);
-        A.rhoh[slot] = 1.0 / h[0];
-        A.head = (A.head + 1) % o.lbfgs_mem;
-        A.count = std::min(A.count + 1, o.lbfgs_mem);
-      }
+      undo_head = A.head;
+      undo_count = A.count;
+      std::swap(A.S[A.head], A.Sn);
+      std::swap(A.Y[A.head], A.Yn);
+      std::swap(A.sy[A.head], A.sy_n);
+      A.head = (A.head + 1) % mem;
+      A.count = std::min(A.count + 1, mem);
+      pending = true;
       std::swap(A.G, A.Gn);
       ++it;
     }
