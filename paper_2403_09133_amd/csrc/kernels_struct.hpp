@@ -12,6 +12,12 @@ constexpr int kMaxCols = 4;  // factor columns per lane held in registers (r <= 
 #define LORADS_UNROLL 4
 #endif
 constexpr int kUnroll = LORADS_UNROLL;  // constraints gathered per step (memory-level parallelism)
+#ifndef LORADS_GRAD_UNROLL
+#define LORADS_GRAD_UNROLL 4
+#endif
+// entries gathered per group and step in the FP64 gradient form (a group's
+// entries are summed in list order whatever the value)
+constexpr int kGU = LORADS_GRAD_UNROLL;
 constexpr int kPairStage = 256;         // PAIR incident entries staged in LDS per wave and pass
 // word 3 of a raw buffer resource on gfx9 parts (32-bit data format, no
 // swizzle, no index stride)
@@ -550,7 +556,7 @@ __global__ void __launch_bounds__(kBlock) kpair_grad_v2(
     const int* __restrict__ rptr, double* __restrict__ z) {
   constexpr int HW = 32;              // lanes per row
   constexpr int NG = HW / GV;         // groups per row
-  constexpr int CH = kPairStage / 2;  // entries staged per row and pass (a multiple of NG kUnroll)
+  constexpr int CH = kPairStage / 2;  // entries staged per row and pass (a multiple of NG kGU)
   typedef double d2 __attribute__((ext_vector_type(2)));
   __shared__ int s_nb[kBlock / HW][CH];
   __shared__ double s_cf[kBlock / HW][CH];
@@ -597,34 +603,34 @@ __global__ void __launch_bounds__(kBlock) kpair_grad_v2(
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      for (int j = grp; j < cnt; j += NG * kUnroll) {
-        int p[kUnroll];
-        double coef[kUnroll];
+      for (int j = grp; j < cnt; j += NG * kGU) {
+        int p[kGU];
+        double coef[kGU];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < kGU; ++u) {
           const int ju = j + u * NG;
           const bool ok = ju < cnt;
           p[u] = (ok ? nbw[ju] : row) * ld;
           coef[u] = ok ? cfw[ju] : 0.0;
         }
-        double vp0[kUnroll], vp1[kUnroll], d[kUnroll];
+        double vp0[kGU], vp1[kGU], d[kGU];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < kGU; ++u) {
           const d2 v = *reinterpret_cast<const d2*>(V + p[u] + c0);
           vp0[u] = on0 ? v[0] : 0.0;
           vp1[u] = on1 ? v[1] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < kGU; ++u) {
           double s0 = 0.0, s1 = 0.0;
           s0 += vt0 * vp0[u] + vp0[u] * vt0;
           s1 += vt1 * vp1[u] + vp1[u] * vt1;
           d[u] = s0 + s1;
         }
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) d[u] = group_sum<GV>(d[u]);
+        for (int u = 0; u < kGU; ++u) d[u] = group_sum<GV>(d[u]);
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < kGU; ++u) {
           const int ju = j + u * NG;
           const bool ok = ju < cnt;
           const double val = d[u] * pair_coef;
@@ -634,7 +640,7 @@ __global__ void __launch_bounds__(kBlock) kpair_grad_v2(
           if (z && ok && lane == (u & (GV - 1))) cfw[ju] = val;
         }
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < kGU; ++u) {
           if (on0) acc0 += coef[u] * vp0[u];
           if (on1) acc1 += coef[u] * vp1[u];
         }
