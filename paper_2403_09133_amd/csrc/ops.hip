@@ -60,12 +60,16 @@ static int rows_grid(int rows, int G) {
   return (int)std::max<long long>(1, (threads + kBlock - 1) / kBlock);
 }
 
-// The two-columns-per-lane FP64 forward maps (k1_pair_v2) serve factors with
-// 16-byte aligned rows; their results equal the one-column form's bit for bit.
+// The two-columns-per-lane FP64 forms (k1_pair_v2, kpair_grad_v2) serve
+// factors with 16-byte aligned rows of at least G entries: every lane loads
+// its two columns unguarded, so all G columns a group covers must lie inside
+// the row (ld >= G), or the last row's loads would run past the buffer.  Their
+// results equal the one-column form's bit for bit.
 static bool pair_v2_ok(const Problem& P, const void* U, const void* V, int r, int ld) {
   const int G = lane_group(r);
-  return P.structure == LORADS_STRUCT_PAIR && G >= 2 && G <= 32 && r <= G && ld % 2 == 0 &&
-         (reinterpret_cast<uintptr_t>(U) % 16) == 0 && (reinterpret_cast<uintptr_t>(V) % 16) == 0;
+  return P.structure == LORADS_STRUCT_PAIR && G >= 2 && G <= 32 && r <= G && ld >= G &&
+         ld % 2 == 0 && (reinterpret_cast<uintptr_t>(U) % 16) == 0 &&
+         (reinterpret_cast<uintptr_t>(V) % 16) == 0;
 }
 
 #define LORADS_DISPATCH_V2(G, CALL)                      \
