@@ -112,11 +112,15 @@ def test_forward_adjoint_f32(device, name):
     assert np.linalg.norm(ga - refa) <= 1e-6 * np.linalg.norm(refa)
 
 
-def test_leading_dimension(device):
+# (r, ld): odd stride; even stride shorter than the 16-column lane group
+# (the two-column form must not be used: its last row would read past the
+# buffer); padded rows with nonzero padding on the two-column form (16 and 8
+# columns), whose masks must keep the padding out of every sum
+@pytest.mark.parametrize("r,ld", [(9, 13), (9, 10), (15, 16), (6, 8)])
+def test_leading_dimension(device, r, ld):
     import torch
     from paper_2403_09133_amd import Context
     p = PROBS["pair_mc_perm"]
-    r, ld = 9, 13
     big = torch.tensor(_rand(p.n, ld, 8), device=device)
     U = big[:, :r]
     ref = oracle.operators.forward(p, U.cpu().numpy(), U.cpu().numpy())
