@@ -1,4 +1,6 @@
 // Operator dispatch (generic / DIAG / PAIR layouts) and the device-resident CG.
+#include <hip/hip_ext.h>
+
 #include "kernels.hpp"
 #include "kernels_struct.hpp"
 #include "problem.hpp"
@@ -272,13 +274,23 @@ int cg_ld(const Problem& P, int r, int elem_bytes) {
 
 template <typename T>
 int op_cg(Problem& P, const T* W, int ldw, int r, int ld, const T* Pd, const T* P2, T* Q, T* t,
-          int parity, hipStream_t s) {
+          int parity, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   const int G = lane_group(r);
   if (r > 4 * G) fail(LORADS_EINVAL, "rank above 256 is not supported");
   double* sc = P.sc.p;
   int np = 0;  // block partials of <P, Q> written to P.part
   if (P.structure != LORADS_STRUCT_PAIR && (ld != r || ldw != r || P2))
     fail(LORADS_EINVAL, "CG buffers must be compact");
+  // PAIR on the CG layout: one kernel with 16-byte column vectors per lane
+  constexpr int VW = 16 / (int)sizeof(T);
+  const int gv = pow2_group((r + VW - 1) / VW);
+  const bool vec = P.structure == LORADS_STRUCT_PAIR && P2 && P2 == W + ld && ldw == 2 * ld &&
+                   ld % VW == 0 && gv * VW <= ld && gv <= 16 &&
+                   (size_t)P.n * ldw * sizeof(T) < ((size_t)1 << 31);
+  // events: attached to that kernel's launch (its own start and end), else
+  // recorded around the operator's launches
+  const bool ext = ev0 != nullptr && vec;
+  if (ev0 && !ext) HIPCHK(hipEventRecord(ev0, s));
   if (P.structure == LORADS_STRUCT_DIAG) {
     const int grid = rows_grid(P.n, G);
     P.ensure_part(grid);
@@ -293,18 +305,26 @@ int op_cg(Problem& P, const T* W, int ldw, int r, int ld, const T* Pd, const T* 
     check_pair_offsets(P, ldw);
     const int grid = waves_grid(P.n);
     P.ensure_part(grid);
-    constexpr int VW = 16 / (int)sizeof(T);
-    const int gv = pow2_group((r + VW - 1) / VW);
-    if (P2 && P2 == W + ld && ldw == 2 * ld && ld % VW == 0 && gv * VW <= ld && gv <= 16 &&
-        (size_t)P.n * ldw * sizeof(T) < ((size_t)1 << 31)) {
-      // CG layout: 16-byte column vectors per lane
+    if (vec) {
+#define LORADS_CG_VEC(GG)                                                                          \
+  do {                                                                                             \
+    if (ext)                                                                                       \
+      hipExtLaunchKernelGGL(kpair_cg_vec<T, GG>, dim3(grid), dim3(kBlock), 0, s, ev0, ev1, 0u,      \
+                            P.n, P.inc_ptr.p, P.inc_nb.p, P.inc_id.p, pc<T>(P), P.pair_coef, W, ld, \
+                            r, Q, sc, parity, P.part.p);                                           \
+    else                                                                                           \
+      kpair_cg_vec<T, GG><<<grid, kBlock, 0, s>>>(P.n, P.inc_ptr.p, P.inc_nb.p, P.inc_id.p,        \
+                                                  pc<T>(P), P.pair_coef, W, ld, r, Q, sc, parity,   \
+                                                  P.part.p);                                       \
+  } while (0)
       switch (gv) {
-        case 1: kpair_cg_vec<T, 1><<<grid, kBlock, 0, s>>>(P.n, P.inc_ptr.p, P.inc_nb.p, P.inc_id.p, pc<T>(P), P.pair_coef, W, ld, r, Q, sc, parity, P.part.p); break;
-        case 2: kpair_cg_vec<T, 2><<<grid, kBlock, 0, s>>>(P.n, P.inc_ptr.p, P.inc_nb.p, P.inc_id.p, pc<T>(P), P.pair_coef, W, ld, r, Q, sc, parity, P.part.p); break;
-        case 4: kpair_cg_vec<T, 4><<<grid, kBlock, 0, s>>>(P.n, P.inc_ptr.p, P.inc_nb.p, P.inc_id.p, pc<T>(P), P.pair_coef, W, ld, r, Q, sc, parity, P.part.p); break;
-        case 8: kpair_cg_vec<T, 8><<<grid, kBlock, 0, s>>>(P.n, P.inc_ptr.p, P.inc_nb.p, P.inc_id.p, pc<T>(P), P.pair_coef, W, ld, r, Q, sc, parity, P.part.p); break;
-        default: kpair_cg_vec<T, 16><<<grid, kBlock, 0, s>>>(P.n, P.inc_ptr.p, P.inc_nb.p, P.inc_id.p, pc<T>(P), P.pair_coef, W, ld, r, Q, sc, parity, P.part.p); break;
+        case 1: LORADS_CG_VEC(1); break;
+        case 2: LORADS_CG_VEC(2); break;
+        case 4: LORADS_CG_VEC(4); break;
+        case 8: LORADS_CG_VEC(8); break;
+        default: LORADS_CG_VEC(16); break;
       }
+#undef LORADS_CG_VEC
     } else {
       LORADS_DISPATCH_GK(G, r, (kpair_rows<T, G, 1, KC><<<grid, kBlock, 0, s>>>(
                                P.n, nullptr, nullptr, nullptr, 0.0, P.inc_ptr.p, P.inc_nb.p,
@@ -324,6 +344,7 @@ int op_cg(Problem& P, const T* W, int ldw, int r, int ld, const T* Pd, const T* 
     np = grid;
   }
   HIPCHK(hipGetLastError());
+  if (ev1 && !ext) HIPCHK(hipEventRecord(ev1, s));
   return np;
 }
 
@@ -466,7 +487,9 @@ int cg_run(Problem& P, const T* W, int ldw, int r, int ld, double rho, double ga
     for (int i = 0; i < steps; ++i, ++k) {
       const int par = k & 1;
       int np = 0;
-      P.prof.run(0, bytes_cg_op(P, r, sizeof(T)), s, [&] { np = op_cg<T>(P, W, ldw, r, ld, Pd, P2, Q, t, par, s); });
+      P.prof.run_ext(0, bytes_cg_op(P, r, sizeof(T)), [&](hipEvent_t e0, hipEvent_t e1) {
+        np = op_cg<T>(P, W, ldw, r, ld, Pd, P2, Q, t, par, s, e0, e1);
+      });
       cg_alpha_finish<<<1, kBlock, 0, s>>>(np, P.part.p, P.sc.p, par);
       cg_update<T><<<gridv, kBlock, 0, s>>>(N, X, R, Pd, Q, P.sc.p, par, P.part.p);
       cg_direction<T><<<gridv, kBlock, 0, s>>>(N, R, Pd, P.sc.p, par, P2, ld, gridv, P.part.p);
@@ -502,8 +525,8 @@ template void op_forward<double>(Problem&, const double*, const double*, int, in
 template void op_forward<float>(Problem&, const float*, const float*, int, int, float*, double, hipStream_t);
 template void op_adjoint<double>(Problem&, const double*, double, const double*, int, int, double*, int, double, hipStream_t);
 template void op_adjoint<float>(Problem&, const float*, double, const float*, int, int, float*, int, double, hipStream_t);
-template int op_cg<double>(Problem&, const double*, int, int, int, const double*, const double*, double*, double*, int, hipStream_t);
-template int op_cg<float>(Problem&, const float*, int, int, int, const float*, const float*, float*, float*, int, hipStream_t);
+template int op_cg<double>(Problem&, const double*, int, int, int, const double*, const double*, double*, double*, int, hipStream_t, hipEvent_t, hipEvent_t);
+template int op_cg<float>(Problem&, const float*, int, int, int, const float*, const float*, float*, float*, int, hipStream_t, hipEvent_t, hipEvent_t);
 template void dot_to_slot<double, double>(Problem&, size_t, const double*, const double*, double, int, hipStream_t);
 template void dot_to_slot<float, float>(Problem&, size_t, const float*, const float*, double, int, hipStream_t);
 template int cg_run<double>(Problem&, const double*, int, int, int, double, double, double*, double*, double*, double*, double*, double*, double, int, hipStream_t, double*, double*);

@@ -42,6 +42,15 @@ struct KernelProfile {
     HIPCHK(hipEventRecord(e1, s));
     pending[kind].push_back({e0, e1, b});
   }
+  // as run, for launch sites that take the two events themselves (a kernel
+  // launched with start / stop events is timed from its own dispatch)
+  template <typename F>
+  void run_ext(int kind, double b, F&& launch) {
+    if (!on) { launch((hipEvent_t) nullptr, (hipEvent_t) nullptr); return; }
+    hipEvent_t e0 = get(), e1 = get();
+    launch(e0, e1);
+    pending[kind].push_back({e0, e1, b});
+  }
   // accumulate the first `keep` pending pairs of `kind` (all when keep < 0);
   // the caller has synchronised the stream
   void resolve(int kind, long long keep = -1) {
@@ -177,9 +186,11 @@ void op_adjoint(Problem& P, const T* w, double c_scale, const T* V, int r, int l
 template <typename T>
 // Q = M_W(Pd) (+ block partials of <Pd, Q> in P.part; returns their count)
 // W with row stride ldw; the direction Pd (stride ld), or its copy P2 in the
-// rows of W (stride ldw) when P2 is given
+// rows of W (stride ldw) when P2 is given.  ev0 / ev1 (optional): events that
+// receive the operator's start and end (attached to the kernel launch itself
+// where the operator is one kernel, else recorded around its launches)
 int op_cg(Problem& P, const T* W, int ldw, int r, int ld, const T* Pd, const T* P2, T* Q, T* t,
-          int parity, hipStream_t s);
+          int parity, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // p1 = A(U D^T + D U^T) and p2 = A(D D^T) in FP64 (the exact line search),
 // U and D with row stride ld
 void op_forward_pair(Problem& P, const double* U, const double* D, int r, int ld, double* p1,
