@@ -441,7 +441,7 @@ struct PrevSums {
   int dv[3];
 };
 
-// Every block sums the partials with finish_multi's code (one fixed order), so
+// Every block sums the partials with block_sum_parts (one fixed order), so
 // all blocks hold the same values; block 0 stores them in their slots for
 // later passes and the host.  The values are returned in vals (LDS).
 __device__ __forceinline__ void prev_finish(const PrevSums& p, double* __restrict__ sc,
@@ -574,19 +574,6 @@ __device__ __forceinline__ double slot_value(const PrevSums& p, const double* va
   }
   const double v1 = block_sum_parts(part + np, np, sh);
   if (threadIdx.x == 0) sc[q_gg] = 1.0 * v1;
-}
-
-// sc[slot_t] = scale_t * sum of partial array t (t < k <= 3), arrays of length np
-[[maybe_unused]] static __global__ void __launch_bounds__(kBlock) finish_multi(
-    int np, int k, const double* __restrict__ part, double s0, double s1, double s2, int q0,
-    int q1, int q2, double* __restrict__ sc) {
-  __shared__ double sh[kBlock / 64];
-  const double sc_[3] = {s0, s1, s2};
-  const int q_[3] = {q0, q1, q2};
-  for (int t = 0; t < k; ++t) {
-    const double v = block_sum_parts(part + (size_t)t * np, np, sh);
-    if (threadIdx.x == 0) sc[q_[t]] = sc_[t] * v;
-  }
 }
 
 // Several dots over m-vectors for the quartic line search, in one pass: block

@@ -473,13 +473,16 @@ struct CgBufs {
 template <typename T>
 static int half_step(Problem& P, const double* W, double* out, int r, double rho, double gamma,
                      double tol, int maxit, CgBufs<T>& B, DevBuf<double>& R64, hipStream_t s,
-                     SolveInfo& info) {
+                     SolveInfo& info, const double* Wp = nullptr, double* outp = nullptr,
+                     int ldp = 0) {
   const int ld = B.ld;
   const size_t N = (size_t)P.n * ld;  // CG layout
   double* R = std::is_same<T, double>::value ? reinterpret_cast<double*>(B.R.p) : R64.p;
   if (grad_pair_ready(P)) {
-    // the gradient form needs no forward map here (z is recomputed after the step)
-    op_grad_pair(P, W, r, r, rho, R, ld, -1.0, s);
+    // the gradient form needs no forward map here (z is recomputed after the
+    // step); it reads the zero-padded copy of W when there is one
+    if (Wp) op_grad_pair(P, Wp, r, ldp, rho, R, ld, -1.0, s);
+    else op_grad_pair(P, W, r, r, rho, R, ld, -1.0, s);
     info.op_bytes += bytes_grad_pair(P, r);
   } else {
     op_forward_w(P, W, W, r, r, P.zbuf.p, P.wbuf.p, P.lam.p, rho, s);
@@ -494,6 +497,8 @@ static int half_step(Problem& P, const double* W, double* out, int r, double rho
   const int it = cg_run<T>(P, B.W.p, B.ldw, r, ld, rho, gamma, B.R.p, B.X.p, B.Pd.p, B.P2, B.Q.p,
                            B.t.p, tol, maxit, s, &rel, &info.op_bytes);
   add_rows<double, T><<<gridN((size_t)P.n * r), kBlock, 0, s>>>(P.n, r, W, r, B.X.p, ld, out);
+  if (outp)
+    copy_rows<double, double><<<gridN((size_t)P.n * r), kBlock, 0, s>>>(P.n, r, out, r, outp, ldp);
   HIPCHK(hipGetLastError());
   return it;
 }
@@ -517,6 +522,21 @@ static void phase2_t(Problem& P, const lorads_options& o, double rho, SolveInfo&
   CgBufs<T> B;
   B.alloc(n, m, ldc, P.structure == LORADS_STRUCT_PAIR, s);
   refresh_inc_lam(P, s);
+  // PAIR: zero-padded FP64 copies of U and V (rows of whole 64-byte sectors),
+  // kept equal to the masters, for the gradient form and the dual update's
+  // forward map (the same results as on the compact masters)
+  const int ldp = P.structure == LORADS_STRUCT_PAIR ? cg_ld(P, r, (int)sizeof(double)) : r;
+  DevBuf<double> Up, Vp;
+  const bool padded = ldp != r;
+  if (padded) {
+    Up.alloc((size_t)n * ldp);
+    Vp.alloc((size_t)n * ldp);
+    Up.zero(s);
+    Vp.zero(s);
+    copy_rows<double, double><<<gridN(N), kBlock, 0, s>>>(n, r, P.U.p, r, Up.p, ldp);
+    copy_rows<double, double><<<gridN(N), kBlock, 0, s>>>(n, r, P.V.p, r, Vp.p, ldp);
+    HIPCHK(hipGetLastError());
+  }
   const int maxit = (int)std::min<long long>((long long)N, o.cg_maxit);
   const double floor = (std::is_same<T, double>::value) ? o.cg_tol_floor : std::max(o.cg_tol_floor, 1e-6);
   double kkt = INFINITY, pinf = INFINITY, dres = INFINITY, gamma = gamma_of(P, o, rho);
@@ -529,11 +549,14 @@ static void phase2_t(Problem& P, const lorads_options& o, double rho, SolveInfo&
     const double tol = std::min(o.cg_tol_max, std::max(floor, o.cg_tol_kkt * kkt));
     HIPCHK(hipMemcpyAsync(Vold.p, P.V.p, N * sizeof(double), hipMemcpyDeviceToDevice, s));
     dot_to_slot<double, double>(P, N, Vold.p, Vold.p, 1.0, S_GEN + 2, s);
-    const int iu = half_step<T>(P, P.V.p, P.U.p, r, rho, gamma, tol, maxit, B, R64, s, info);
-    const int iv = half_step<T>(P, P.U.p, P.V.p, r, rho, gamma, tol, maxit, B, R64, s, info);
+    const int iu = half_step<T>(P, P.V.p, P.U.p, r, rho, gamma, tol, maxit, B, R64, s, info,
+                                padded ? Vp.p : nullptr, padded ? Up.p : nullptr, ldp);
+    const int iv = half_step<T>(P, P.U.p, P.V.p, r, rho, gamma, tol, maxit, B, R64, s, info,
+                                padded ? Up.p : nullptr, padded ? Vp.p : nullptr, ldp);
     cg_total += iu + iv;
     // z = A(U V^T); lam += rho (z - b); residual norms
-    op_forward<double>(P, P.U.p, P.V.p, r, r, P.zbuf.p, 1.0, s);
+    if (padded) op_forward<double>(P, Up.p, Vp.p, r, ldp, P.zbuf.p, 1.0, s);
+    else op_forward<double>(P, P.U.p, P.V.p, r, r, P.zbuf.p, 1.0, s);
     info.op_bytes += bytes_forward(P, r, 8);
     dual_update_slot(P, P.zbuf.p, rho, P.lam.p, S_GEN, s);
     refresh_inc_lam(P, s);
