@@ -67,7 +67,7 @@ def recorded_traffic(symbol: str):
 # each one runs on the completion workload
 KERNEL_CLASSES = {
     "fused CG operator": "kpair_cg_vec<float, 4>",
-    "forward map A(UV^T)": "k1_pair<double, 16, 0, 1>",
+    "forward map A(UV^T)": "k1_pair_v2<8, 0>",
     "adjoint (C + A*(w))V, gradient form": "kpair_grad_v2<8>",
     "line-search maps A(UD^T+DU^T), A(DD^T)": "k1_pair_v2<8, 3>",
 }

@@ -124,6 +124,33 @@ __device__ __forceinline__ double block_sum_parts(const double* part, int n, dou
   return block_sum(s, sh);
 }
 
+// The value block_sum_parts returns in a block of kBlock = 256 threads,
+// computed by one wave (so the waves of a block can finish several arrays at
+// once): lane l plays threads l, l + 64, l + 128 and l + 192, each summing its
+// strided elements in index order, then each virtual wave's xor tree, then the
+// four wave totals in wave order.  Same operations in the same order, so the
+// same bits; every lane returns the value.
+__device__ __forceinline__ double wave_sum_parts(const double* part, int n) {
+  static_assert(kBlock == 256, "emulates a block of four waves");
+  const int l = threadIdx.x & 63;
+  double w[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    double s = 0.0;
+    for (int i = 64 * v + l; i < n; i += kBlock) s += part[i];
+    w[v] = s;
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) w[v] += __shfl_xor(w[v], o, 64);
+  }
+  double t = 0.0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) t += w[v];
+  return t;
+}
+
 // sc[slot + t] = scale * sum of partial array t (t < k), arrays of length np
 [[maybe_unused]] static __global__ void __launch_bounds__(kBlock) finish_slots(int np, int k, const double* __restrict__ part,
                                                        double scale, double* __restrict__ sc, int slot) {
@@ -563,17 +590,21 @@ __device__ __forceinline__ double slot_value(const PrevSums& p, const double* va
 
 // the curvature pair's sums: sc[q_sy] = sc[q_mirror] = <Sn, Yn> (array 0),
 // sc[q_gg] = ||Gn||^2 (array 1), arrays of length np
+// (waves 0 and 1 each finish one array)
 [[maybe_unused]] static __global__ void __launch_bounds__(kBlock) pair_finish(
     int np, const double* __restrict__ part, double* __restrict__ sc, int q_sy, int q_mirror,
     int q_gg) {
-  __shared__ double sh[kBlock / 64];
-  const double v0 = block_sum_parts(part, np, sh);
-  if (threadIdx.x == 0) {
-    sc[q_sy] = 1.0 * v0;
-    sc[q_mirror] = 1.0 * v0;
+  const int wid = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (wid == 0) {
+    const double v0 = wave_sum_parts(part, np);
+    if (l == 0) {
+      sc[q_sy] = 1.0 * v0;
+      sc[q_mirror] = 1.0 * v0;
+    }
+  } else if (wid == 1) {
+    const double v1 = wave_sum_parts(part + np, np);
+    if (l == 0) sc[q_gg] = 1.0 * v1;
   }
-  const double v1 = block_sum_parts(part + np, np, sh);
-  if (threadIdx.x == 0) sc[q_gg] = 1.0 * v1;
 }
 
 // Several dots over m-vectors for the quartic line search, in one pass: block
@@ -654,18 +685,16 @@ __device__ __forceinline__ void linesearch_partials(int bid, int nblk, int m,
 [[maybe_unused]] static __global__ void __launch_bounds__(kBlock) linesearch_finish(
     int rg, const double* __restrict__ part_f, int gl, const double* __restrict__ part_m,
     const double* __restrict__ part_gd, double* __restrict__ sc, int slot) {
-  __shared__ double sh[kBlock / 64];
-  if (part_gd) {
-    const double v = block_sum_parts(part_gd, rg, sh);
-    if (threadIdx.x == 0) sc[slot + 9] = 1.0 * v;
-  }
-  const double v0 = block_sum_parts(part_f, rg, sh);
-  if (threadIdx.x == 0) sc[slot] = 2.0 * v0;
-  const double v1 = block_sum_parts(part_f + rg, rg, sh);
-  if (threadIdx.x == 0) sc[slot + 1] = 1.0 * v1;
-  for (int t = 0; t < 7; ++t) {
-    const double v = block_sum_parts(part_m + (size_t)t * gl, gl, sh);
-    if (threadIdx.x == 0) sc[slot + 2 + t] = 1.0 * v;
+  // ten sums, wave w finishes sums w, w + 4, w + 8: 0 and 1 over part_f,
+  // 2 .. 8 over part_m, 9 over part_gd
+  const int wid = threadIdx.x >> 6, l = threadIdx.x & 63;
+  for (int a = wid; a < 10; a += kBlock / 64) {
+    if (a == 9 && !part_gd) continue;
+    const double* p = a < 2 ? part_f + (size_t)a * rg
+                            : (a < 9 ? part_m + (size_t)(a - 2) * gl : part_gd);
+    const int n = (a < 2 || a == 9) ? rg : gl;
+    const double v = wave_sum_parts(p, n);
+    if (l == 0) sc[slot + a] = (a == 0 ? 2.0 : 1.0) * v;
   }
 }
 
