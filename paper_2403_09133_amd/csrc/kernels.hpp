@@ -151,6 +151,46 @@ __device__ __forceinline__ double wave_sum_parts(const double* part, int n) {
   return t;
 }
 
+// wave_sum_parts for n <= 2 kBlock in two steps, so that a wave can issue the
+// loads of several arrays before it sums any: load_parts2 fetches a lane's
+// (at most) two elements of each virtual thread, sum_parts2 adds them in
+// index order and finishes as wave_sum_parts does.
+struct Parts2 {
+  double x[4][2];
+};
+__device__ __forceinline__ Parts2 load_parts2(const double* part, int n) {
+  const int l = threadIdx.x & 63;
+  Parts2 q;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = 64 * v + l;
+    q.x[v][0] = i < n ? part[i] : 0.0;
+    q.x[v][1] = i + kBlock < n ? part[i + kBlock] : 0.0;
+  }
+  return q;
+}
+__device__ __forceinline__ double sum_parts2(const Parts2& q, int n) {
+  const int l = threadIdx.x & 63;
+  double w[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = 64 * v + l;
+    double s = 0.0;
+    if (i < n) s += q.x[v][0];
+    if (i + kBlock < n) s += q.x[v][1];
+    w[v] = s;
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) w[v] += __shfl_xor(w[v], o, 64);
+  }
+  double t = 0.0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) t += w[v];
+  return t;
+}
+
 // sc[slot + t] = scale * sum of partial array t (t < k), arrays of length np
 [[maybe_unused]] static __global__ void __launch_bounds__(kBlock) finish_slots(int np, int k, const double* __restrict__ part,
                                                        double scale, double* __restrict__ sc, int slot) {
@@ -685,15 +725,28 @@ __device__ __forceinline__ void linesearch_partials(int bid, int nblk, int m,
 [[maybe_unused]] static __global__ void __launch_bounds__(kBlock) linesearch_finish(
     int rg, const double* __restrict__ part_f, int gl, const double* __restrict__ part_m,
     const double* __restrict__ part_gd, double* __restrict__ sc, int slot) {
-  // ten sums, wave w finishes sums w, w + 4, w + 8: 0 and 1 over part_f,
-  // 2 .. 8 over part_m, 9 over part_gd
+  // ten sums (rg, gl <= 2 kBlock), wave w finishes sums w, w + 4, w + 8: 0 and
+  // 1 over part_f, 2 .. 8 over part_m, 9 over part_gd; a wave loads all of
+  // its arrays before it sums them
   const int wid = threadIdx.x >> 6, l = threadIdx.x & 63;
-  for (int a = wid; a < 10; a += kBlock / 64) {
-    if (a == 9 && !part_gd) continue;
+  constexpr int kW = kBlock / 64;
+  Parts2 q[3];
+  int na[3];
+  bool on[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int a = wid + kW * j;
+    on[j] = a < 9 || (a == 9 && part_gd != nullptr);
     const double* p = a < 2 ? part_f + (size_t)a * rg
                             : (a < 9 ? part_m + (size_t)(a - 2) * gl : part_gd);
-    const int n = (a < 2 || a == 9) ? rg : gl;
-    const double v = wave_sum_parts(p, n);
+    na[j] = (a < 2 || a == 9) ? rg : gl;
+    if (on[j]) q[j] = load_parts2(p, na[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int a = wid + kW * j;
+    if (!on[j]) continue;
+    const double v = sum_parts2(q[j], na[j]);
     if (l == 0) sc[slot + a] = (a == 0 ? 2.0 : 1.0) * v;
   }
 }

@@ -451,6 +451,7 @@ void linesearch_slots(Problem& P, int n, int r, int ld, const double* CD, const 
                                                      P.b.p, p1, p2, lam, gl, part_m);
   if (part_gd && part_gd < part_m + (size_t)7 * gl)
     fail(LORADS_EINVAL, "descent-check partials overlap the line-search partials");
+  if (rg > 2 * kBlock || gl > 2 * kBlock) fail(LORADS_EINVAL, "line-search partials exceed the finishing layout");
   linesearch_finish<<<1, kBlock, 0, s>>>(rg, part_f, gl, part_m, part_gd, P.sc.p, slot);
   HIPCHK(hipGetLastError());
 }
