@@ -63,8 +63,9 @@ __device__ __forceinline__ double group_sum(double v) {
   return v;
 }
 
+// Every reduction kernel runs in blocks of kBlock = 256 threads (4 waves).
 __device__ __forceinline__ double block_sum(double v, double* sh) {
-  // wave reduction then across the 4 waves of a 256-thread block
+  // wave reduction then across the 4 waves of the block
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -73,8 +74,8 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   __syncthreads();
   double t = 0.0;
   if (threadIdx.x == 0) {
-    const int nw = (blockDim.x + 63) >> 6;
-    for (int i = 0; i < nw; ++i) t += sh[i];
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i) t += sh[i];
   }
   return t;  // valid in thread 0
 }
@@ -103,7 +104,7 @@ __device__ __forceinline__ void publish_partial(double partial, double* part) {
 // them in index order, so a long partial array costs few memory round trips.
 __device__ __forceinline__ double block_sum_parts(const double* part, int n, double* sh) {
   double s = 0.0;
-  const int bs = blockDim.x;
+  constexpr int bs = kBlock;
   int i = threadIdx.x;
   for (; i + 7 * bs < n; i += 8 * bs) {
     double v[8];
@@ -547,17 +548,32 @@ __device__ __forceinline__ double slot_value(const PrevSums& p, const double* va
     const double* __restrict__ u, double* __restrict__ part, PrevSums prev) {
   __shared__ double sh[kBlock / 64];
   __shared__ double vals[3];
+  // the first element's operands are loaded while the previous pass's sums
+  // are being finished
+  const unsigned i0 = blockIdx.x * kBlock + threadIdx.x, stride = gridDim.x * kBlock;
+  size_t q0 = 0;
+  double x0 = 0.0, y0 = 0.0, u0 = 0.0;
+  if (i0 < N) {
+    q0 = compact_to_row(i0, r, ld);
+    x0 = x[q0];
+    y0 = yin[q0];
+    u0 = u[q0];
+  }
   prev_finish(prev, sc, vals, sh);
   const double a = sign * slot_value(prev, vals, sc, slot);
   const double a2 = scale ? slot_value(prev, vals, sc, sa) / slot_value(prev, vals, sc, sb) : 0.0;
   const double b = 1.0;
   double s = 0.0;
-  for (unsigned i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
-    const size_t q = compact_to_row(i, r, ld);
-    double v = (double)(a * (double)x[q] + b * (double)yin[q]);
+  auto step = [&](size_t q, double xv, double yv, double uv) {
+    double v = (double)(a * xv + b * yv);
     if (scale) v = (double)(a2 * v + 0.0 * v);
     y[q] = v;
-    s += u[q] * v;
+    s += uv * v;
+  };
+  if (i0 < N) step(q0, x0, y0, u0);
+  for (unsigned i = i0 + stride; i < N; i += stride) {
+    const size_t q = compact_to_row(i, r, ld);
+    step(q, x[q], yin[q], u[q]);
   }
   publish_partial(block_sum(s, sh), part);
 }
@@ -571,30 +587,50 @@ __device__ __forceinline__ double slot_value(const PrevSums& p, const double* va
     PrevSums prev) {
   __shared__ double sh[kBlock / 64];
   __shared__ double vals[3];
+  // the first element's operands are loaded while the previous pass's sums
+  // are being finished (o: u's element, or g's when d is formed)
+  const unsigned i0 = blockIdx.x * kBlock + threadIdx.x, stride = gridDim.x * kBlock;
+  size_t q0 = 0;
+  double x0 = 0.0, y0 = 0.0, d0 = 0.0, o0 = 0.0;
+  if (i0 < N) {
+    q0 = compact_to_row(i0, r, ld);
+    y0 = yin[q0];
+    if (x) x0 = x[q0];
+    if (d) {
+      d0 = d[q0];
+      o0 = g[q0];
+    } else {
+      o0 = u[q0];
+    }
+  }
   prev_finish(prev, sc, vals, sh);
   const double a = x ? slot_value(prev, vals, sc, sa) - slot_value(prev, vals, sc, sb) : 0.0;
   const double b = 1.0;
   double s = 0.0;
-  for (unsigned i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
-    const size_t q = compact_to_row(i, r, ld);
-    double v = yin[q];
+  auto step = [&](size_t q, double xv, double yv, double dv0, double ov) {
+    double v = yv;
     if (x) {
-      v = (double)(a * (double)x[q] + b * v);
+      v = (double)(a * xv + b * v);
       y[q] = v;
     }
     // the dot's operands are chosen first so that its multiply-add is one
     // fused operation, as in dot_rows_kernel
     double fa, fb;
     if (d) {
-      const double dv = (double)(-1.0 * v + 0.0 * (double)d[q]);
+      const double dv = (double)(-1.0 * v + 0.0 * dv0);
       d[q] = dv;
-      fa = g[q];
+      fa = ov;
       fb = dv;
     } else {
-      fa = u[q];
+      fa = ov;
       fb = v;
     }
     s += fa * fb;
+  };
+  if (i0 < N) step(q0, x0, y0, d0, o0);
+  for (unsigned i = i0 + stride; i < N; i += stride) {
+    const size_t q = compact_to_row(i, r, ld);
+    step(q, x ? x[q] : 0.0, yin[q], d ? d[q] : 0.0, d ? g[q] : u[q]);
   }
   publish_partial(block_sum(s, sh), part);
 }
