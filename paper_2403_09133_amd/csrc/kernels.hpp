@@ -377,16 +377,27 @@ __global__ void __launch_bounds__(kBlock) cg_update(size_t N, T* __restrict__ X,
                                                     const double* __restrict__ sc, int parity,
                                                     double* __restrict__ part) {
   __shared__ double sh[kBlock / 64];
+  // the first element is loaded before the flags and the step length arrive
+  const size_t i0 = (size_t)blockIdx.x * kBlock + threadIdx.x, stride = (size_t)gridDim.x * kBlock;
+  T x0 = 0, r0 = 0, p0 = 0, q0 = 0;
+  if (i0 < N) {
+    x0 = X[i0];
+    r0 = R[i0];
+    p0 = P[i0];
+    q0 = Q[i0];
+  }
   const bool skip = sc[S_DONE + parity] != 0.0 || sc[S_BRK] != 0.0;
   double s = 0.0;
   if (!skip) {
     const double alpha = sc[S_ALPHA];
-    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock) {
-      X[i] = (T)((double)X[i] + alpha * (double)P[i]);
-      const T rv = (T)((double)R[i] - alpha * (double)Q[i]);
+    auto step = [&](size_t i, T xv, T rv0, T pv, T qv) {
+      X[i] = (T)((double)xv + alpha * (double)pv);
+      const T rv = (T)((double)rv0 - alpha * (double)qv);
       R[i] = rv;
       s += (double)rv * (double)rv;
-    }
+    };
+    if (i0 < N) step(i0, x0, r0, p0, q0);
+    for (size_t i = i0 + stride; i < N; i += stride) step(i, X[i], R[i], P[i], Q[i]);
   }
   if (!skip) publish_partial(block_sum(s, sh), part);
 }
@@ -406,6 +417,13 @@ __global__ void __launch_bounds__(kBlock) cg_direction(size_t N, const T* __rest
   __shared__ double sh[kBlock / 64];
   __shared__ double s_beta;
   const int q = parity ^ 1;
+  // the first element is loaded while beta is being formed
+  const size_t i0 = (size_t)blockIdx.x * kBlock + threadIdx.x, stride = (size_t)gridDim.x * kBlock;
+  T r0 = 0, p0 = 0;
+  if (i0 < N) {
+    r0 = R[i0];
+    p0 = P[i0];
+  }
   if (sc[S_DONE + parity] != 0.0 || sc[S_BRK] != 0.0) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       sc[S_DONE + q] = 1.0;
@@ -426,11 +444,13 @@ __global__ void __launch_bounds__(kBlock) cg_direction(size_t N, const T* __rest
   }
   __syncthreads();
   const double beta = s_beta;
-  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock) {
-    const T v = (T)((double)R[i] + beta * (double)P[i]);
+  auto step = [&](size_t i, T rv, T pv) {
+    const T v = (T)((double)rv + beta * (double)pv);
     P[i] = v;
     if (P2) P2[interleaved_index(i, ld)] = v;
-  }
+  };
+  if (i0 < N) step(i0, r0, p0);
+  for (size_t i = i0 + stride; i < N; i += stride) step(i, R[i], P[i]);
 }
 
 // ===========================================================================
