@@ -192,6 +192,24 @@ __device__ __forceinline__ double sum_parts2(const Parts2& q, int n) {
   return t;
 }
 
+// block_sum_parts for n <= kWideParts kBlock with all of a thread's loads
+// issued before its additions (one memory round trip; the same additions in
+// the same order, so the same value)
+constexpr int kWideParts = 24;
+__device__ __forceinline__ double block_sum_parts_wide(const double* part, int n, double* sh) {
+  double v[kWideParts];
+#pragma unroll
+  for (int u = 0; u < kWideParts; ++u) {
+    const int i = threadIdx.x + u * kBlock;
+    v[u] = i < n ? part[i] : 0.0;
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int u = 0; u < kWideParts; ++u)
+    if ((int)threadIdx.x + u * kBlock < n) s += v[u];
+  return block_sum(s, sh);
+}
+
 // sc[slot + t] = scale * sum of partial array t (t < k), arrays of length np
 [[maybe_unused]] static __global__ void __launch_bounds__(kBlock) finish_slots(int np, int k, const double* __restrict__ part,
                                                        double scale, double* __restrict__ sc, int slot) {
@@ -208,7 +226,8 @@ __device__ __forceinline__ double sum_parts2(const Parts2& q, int n) {
                                                           double* __restrict__ sc, int parity) {
   __shared__ double sh[kBlock / 64];
   if (sc[S_DONE + parity] != 0.0) return;
-  const double s = block_sum_parts(part, np, sh);
+  const double s = np <= kWideParts * kBlock ? block_sum_parts_wide(part, np, sh)
+                                             : block_sum_parts(part, np, sh);
   if (threadIdx.x == 0) {
     sc[S_PQ] = s;
     if (!(s > 0.0)) {
