@@ -771,21 +771,25 @@ __device__ __forceinline__ void linesearch_partials(int bid, int nblk, int m,
 // partials of <CD, U> and <CD, D> over the first r columns of n rows (stride
 // ld; the element order and grouping of dots3_kernel with rg blocks) at
 // part_f + t * rg, blocks below gl the m-vector sums of linesearch_partials
-// with gl blocks at part_m.
+// with gl blocks at part_m.  With cdiag (a diagonal C by row), each element
+// of C D is formed here as the PAIR adjoint's C part forms it (c D + 0: the
+// product, then the other lane groups' zero sums) instead of read from CD.
 [[maybe_unused]] static __global__ void __launch_bounds__(kBlock) linesearch_all(
     unsigned N, int r, int ld, const double* __restrict__ CD, const double* __restrict__ U,
     const double* __restrict__ D, int rg, double* __restrict__ part_f, int m,
     const double* __restrict__ z, const double* __restrict__ b, const double* __restrict__ p1,
     const double* __restrict__ p2, const double* __restrict__ lam, int gl,
-    double* __restrict__ part_m) {
+    double* __restrict__ part_m, const double* __restrict__ cdiag) {
   __shared__ double sh[kBlock / 64];
   const int bid = blockIdx.x;
   if (bid < rg) {  // uniform over the block
     double s0 = 0.0, s1 = 0.0;
     for (unsigned i = bid * kBlock + threadIdx.x; i < N; i += rg * kBlock) {
       const size_t q = compact_to_row(i, r, ld);
-      s0 += CD[q] * U[q];
-      s1 += CD[q] * D[q];
+      const double dq = D[q];
+      const double cd = cdiag ? cdiag[i / (unsigned)r] * dq + 0.0 : CD[q];
+      s0 += cd * U[q];
+      s1 += cd * dq;
     }
     const double b0 = block_sum(s0, sh);
     if (threadIdx.x == 0) part_f[bid] = b0;

@@ -368,6 +368,10 @@ double bytes_adjoint(const Problem& P, int r, int s, bool with_c) {
   return (double)P.acol.n * (8 + s) + (double)(P.n + 1) * 4 + (double)P.m * s + 2.0 * nr + cbytes;
 }
 
+double bytes_cprod(const Problem& P, int r, int s) {
+  return (double)P.cval.n * (4 + s) + (double)(P.n + 1) * 4 + 2.0 * (double)P.n * r * s;
+}
+
 double bytes_grad_pair(const Problem& P, int r) {
   // the gradient form applies both maps: A(U U^T) entry by entry and the adjoint
   return bytes_forward(P, r, 8) + bytes_adjoint(P, r, 8, true);
@@ -440,7 +444,8 @@ void dual_update_slot(Problem& P, const double* z, double rho, double* lam, int 
 
 void linesearch_slots(Problem& P, int n, int r, int ld, const double* CD, const double* U,
                       const double* D, const double* z, const double* p1, const double* p2,
-                      const double* lam, int slot, hipStream_t s, const double* part_gd) {
+                      const double* lam, int slot, hipStream_t s, const double* part_gd,
+                      const double* cdiag) {
   const size_t N = (size_t)n * r;
   if (N >= ((size_t)1 << 32)) fail(LORADS_EINVAL, "factor too large for the line-search dots");
   const int rg = grid_for(N, kRedBlocks), gl = grid_for(P.m, kRedBlocks);
@@ -448,7 +453,7 @@ void linesearch_slots(Problem& P, int n, int r, int ld, const double* CD, const 
   double* part_f = P.part.p;
   double* part_m = P.part.p + 2 * rg;
   linesearch_all<<<std::max(rg, gl), kBlock, 0, s>>>((unsigned)N, r, ld, CD, U, D, rg, part_f, P.m, z,
-                                                     P.b.p, p1, p2, lam, gl, part_m);
+                                                     P.b.p, p1, p2, lam, gl, part_m, cdiag);
   if (part_gd && part_gd < part_m + (size_t)7 * gl)
     fail(LORADS_EINVAL, "descent-check partials overlap the line-search partials");
   if (rg > 2 * kBlock || gl > 2 * kBlock) fail(LORADS_EINVAL, "line-search partials exceed the finishing layout");

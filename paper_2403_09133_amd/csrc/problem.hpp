@@ -109,6 +109,7 @@ struct Problem {
   // cost matrix C, row-CSR of the full symmetric matrix
   DevBuf<int> cptr, ccol;
   DevBuf<double> cval;
+  DevBuf<double> cdiag;  // diagonal C only: C_jj by row (zero where absent), else empty
   DevBuf<float> cvalf;
 
   // DIAG structure: constraint i (internal order) sits on row drow[i] with
@@ -215,6 +216,7 @@ double bytes_forward(const Problem& P, int r, int s);
 double bytes_adjoint(const Problem& P, int r, int s, bool with_c);
 double bytes_cg_op(const Problem& P, int r, int s);
 double bytes_grad_pair(const Problem& P, int r);  // gradient form: forward + adjoint (FP64)
+double bytes_cprod(const Problem& P, int r, int s);  // C V alone: C's entries, V and the output
 
 // ---------------------------------------------------------------------------
 // reductions / small helpers
@@ -228,9 +230,12 @@ void dual_update_slot(Problem& P, const double* z, double rho, double* lam, int 
 // m-vector inner products of p0 = z - b, p1, p2 and lam -> sc[slot + 2 .. slot + 8];
 // part_gd (optional, above the line-search partials in P.part): partials of a
 // dot over the same factor grid, summed into sc[slot + 9]
+// cdiag (optional, PAIR): C's diagonal by row; then C D is formed in the pass
+// as the PAIR adjoint's C part rounds it, and CD is not read
 void linesearch_slots(Problem& P, int n, int r, int ld, const double* CD, const double* U,
                       const double* D, const double* z, const double* p1, const double* p2,
-                      const double* lam, int slot, hipStream_t s, const double* part_gd = nullptr);
+                      const double* lam, int slot, hipStream_t s, const double* part_gd = nullptr,
+                      const double* cdiag = nullptr);
 template <typename TX, typename TY>
 void dot_to_slot(Problem& P, size_t N, const TX* X, const TY* Y, double scale, int slot, hipStream_t s);
 // the same for n x r factors stored with row stride ld (bit-identical to the

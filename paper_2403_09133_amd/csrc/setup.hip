@@ -209,6 +209,19 @@ std::unique_ptr<Problem> ingest(const lorads_problem& p, hipStream_t s) {
       std::vector<float> cf(cval.begin(), cval.end());
       P->cvalf.upload(cf, s);
     }
+    // a diagonal C (at most one entry per row, on the diagonal): its entries
+    // by row, so (C D)_j = c_j D_j can be formed where it is used
+    bool cdiag = true;
+    for (int j = 0; j < n && cdiag; ++j) {
+      const int cnt = cptr[j + 1] - cptr[j];
+      if (cnt > 1 || (cnt == 1 && ccol[cptr[j]] != j)) cdiag = false;
+    }
+    if (cdiag) {
+      std::vector<double> cd(n, 0.0);
+      for (int j = 0; j < n; ++j)
+        if (cptr[j + 1] > cptr[j]) cd[j] = cval[cptr[j]];
+      P->cdiag.upload(cd, s);
+    }
   }
 
   // ---------------- DIAG layout ----------------

@@ -281,12 +281,17 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
     };
     // the exact line search's maps and sums; one host read (slots S_GEN+1 ..
     // S_GEN+nread)
+    // PAIR with a diagonal C: C D is formed inside the sums pass
+    const double* cdiag =
+        (P.structure == LORADS_STRUCT_PAIR && P.cdiag.n > 0) ? P.cdiag.p : nullptr;
     auto line_search = [&](int nread) {
       op_forward_pair(P, U, A.D.p, r, F.ld, A.p1.p, A.p2.p, s);
-      op_adjoint<double>(P, (const double*)nullptr, 1.0, A.D.p, r, F.ld, A.CD.p, F.ld, 1.0, s);
-      info.op_bytes += 2 * bytes_forward(P, r, 8) + bytes_adjoint(P, r, 8, true);
+      if (!cdiag)
+        op_adjoint<double>(P, (const double*)nullptr, 1.0, A.D.p, r, F.ld, A.CD.p, F.ld, 1.0, s);
+      // the two maps, and C D (a product with C alone)
+      info.op_bytes += 2 * bytes_forward(P, r, 8) + bytes_cprod(P, r, 8);
       linesearch_slots(P, n, r, F.ld, A.CD.p, U, A.D.p, P.zbuf.p, A.p1.p, A.p2.p, P.lam.p,
-                       S_GEN + 1, s, part_gd);
+                       S_GEN + 1, s, part_gd, cdiag);
       read_slots(P, S_GEN + 1, h, nread, s);
     };
     // A step's curvature pair enters the memory at once, before its <S, Y>
