@@ -15,11 +15,29 @@ from oracle.options import Options, paper_defaults
 pytestmark = pytest.mark.gpu
 
 
+def _mc_offdiag_c():
+    # completion constraints (PAIR structure) with a cost that is not diagonal:
+    # I/2 plus small symmetric couplings between nearby rows (still positive
+    # definite), so the line search forms C D with the general product
+    p = sdpgen.mc_planted(40, 30, 2, 7, count=700)
+    rng = np.random.default_rng(11)
+    rows = rng.integers(0, p.n - 6, 80)
+    cols = rows + 1 + rng.integers(0, 5, 80)
+    pairs = sorted(set(zip(rows.tolist(), cols.tolist())))
+    cr = np.array([a for a, _ in pairs], dtype=p.c_row.dtype)
+    cc = np.array([b for _, b in pairs], dtype=p.c_col.dtype)
+    p.c_row = np.concatenate([p.c_row, cr])
+    p.c_col = np.concatenate([p.c_col, cc])
+    p.c_val = np.concatenate([p.c_val, 0.04 * rng.standard_normal(len(pairs))])
+    return p
+
+
 def _cases():
     return {
         "maxcut_er200": (sdpgen.config_instance("maxcut_er200"), 8),
         "maxcut_torus12": (sdpgen.maxcut_torus(12, 12, 5, "pm1"), 8),
         "mc_60x50": (sdpgen.mc_planted(60, 50, 2, 5, count=1500), None),
+        "mc_offdiag_c": (_mc_offdiag_c(), None),
         "generic_10x8": (sdpgen.generic_random(10, 8, 5), 6),
     }
 
