@@ -210,6 +210,18 @@ __device__ __forceinline__ double block_sum_parts_wide(const double* part, int n
   return block_sum(s, sh);
 }
 
+// Copies count (<= 64) slot values to host-mapped words 1 .. count, then,
+// after a system-scope fence, the sequence number to word 0; the host waits
+// for that number instead of for the stream.
+[[maybe_unused]] static __global__ void __launch_bounds__(64) publish_slots(
+    const double* __restrict__ src, int count, double* dst, long long seq) {
+  const int i = threadIdx.x;
+  if (i < count) dst[1 + i] = src[i];
+  __threadfence_system();
+  __syncthreads();
+  if (i == 0) __atomic_store_n(reinterpret_cast<long long*>(dst), seq, __ATOMIC_RELEASE);
+}
+
 // sc[slot + t] = scale * sum of partial array t (t < k), arrays of length np
 [[maybe_unused]] static __global__ void __launch_bounds__(kBlock) finish_slots(int np, int k, const double* __restrict__ part,
                                                        double scale, double* __restrict__ sc, int slot) {

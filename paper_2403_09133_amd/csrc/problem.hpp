@@ -58,6 +58,7 @@ struct KernelProfile {
     const size_t k = keep < 0 ? v.size() : std::min<size_t>(v.size(), (size_t)keep);
     for (size_t i = 0; i < k; ++i) {
       float t = 0.f;
+      HIPCHK(hipEventSynchronize(v[i].b));  // complete already: the host has seen later work end
       HIPCHK(hipEventElapsedTime(&t, v[i].a, v[i].b));
       ms[kind] += t;
       bytes[kind] += v[i].bytes;
@@ -88,6 +89,26 @@ struct KernelProfile {
 // (b, z, w, lambda) live on the device.  `perm[i]` is the caller's id of
 // internal constraint i; when the caller's order is kept perm_identity is set
 // and no permutation is ever applied.
+// Pinned, device-mapped host words that read_slots has the device publish
+// into: word 0 a sequence number written last, words 1 .. 64 slot values.
+struct HostSlots {
+  double* h = nullptr;  // host address
+  double* d = nullptr;  // device address of the same memory
+  long long seq = 0;
+  HostSlots() = default;
+  HostSlots(const HostSlots&) = delete;
+  HostSlots& operator=(const HostSlots&) = delete;
+  ~HostSlots() {
+    if (h) (void)hipHostFree(h);
+  }
+  void init() {
+    if (h) return;
+    HIPCHK(hipHostMalloc((void**)&h, 65 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent));
+    HIPCHK(hipHostGetDevicePointer((void**)&d, h, 0));
+    *(volatile long long*)h = 0;
+  }
+};
+
 struct Problem {
   int n = 0, m = 0;
   int structure = LORADS_STRUCT_GENERIC;
@@ -143,6 +164,7 @@ struct Problem {
 
   // solver scratch
   DevBuf<double> sc;
+  HostSlots hs;
   DevBuf<double> part;
   size_t part_cap = 0;
 
