@@ -410,7 +410,8 @@ void set_slots(Problem& P, int slot, const double* vals, int count, hipStream_t 
 #define LORADS_HOST_PUBLISH 1
 #endif
 void read_slots(Problem& P, int slot, double* vals, int count, hipStream_t s) {
-  if (LORADS_HOST_PUBLISH && P.hs.h && count <= 64) {
+  if (LORADS_HOST_PUBLISH && !P.hs.h) P.hs.init();  // first read of this problem
+  if (LORADS_HOST_PUBLISH && count <= 64) {
     // the device writes the values and then a fresh sequence number into
     // pinned host words; the host spins on the number for a short while, then
     // waits for the stream (which also reports a failed launch)

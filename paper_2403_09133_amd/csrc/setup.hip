@@ -329,7 +329,6 @@ std::unique_ptr<Problem> ingest(const lorads_problem& p, hipStream_t s) {
 
   P->sc.alloc(S_COUNT);
   P->sc.zero(s);
-  P->hs.init();
   // one partial per block of the widest row kernel (64 lanes per row)
   // (the PAIR adjoint runs one block per row)
   P->part_cap = std::max<size_t>(kMaxPart, (size_t)n + 64);
