@@ -266,8 +266,8 @@ def main():
                     help="end with a 256 MiB device copy (byte-counter calibration in counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU: the method's batch and single-instance paths are "
-              "measured per GPU, no multi-GPU run exists in this build (use --gpus 1)", file=sys.stderr)
+        print("bench.py runs on one GPU: the single-instance and batched paths are measured "
+              "on one GPU and there is no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import torch
