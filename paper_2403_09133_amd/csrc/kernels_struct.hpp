@@ -681,12 +681,13 @@ __global__ void __launch_bounds__(kBlock) kpair_grad_v2(
 // byte offset (32-bit), the direction half sits at a scalar offset of ld
 // elements, and reads past the buffer return zero.  The staged list of a chunk
 // is padded to a whole number of steps with entries (own row, coefficient 0),
-// so the step loop runs without lane guards.  The launch bound asks for 7
-// waves per SIMD (at most 72 VGPRs; the unbounded allocation gives 6), which
-// measured 3% faster on the completion solves.
+// so the step loop runs without lane guards.  The FP32 form's launch bound
+// asks for 7 waves per SIMD (at most 72 VGPRs; the unbounded allocation gives
+// 6), which measured 3% faster on the completion solves; the FP64 form keeps
+// its natural allocation (7 waves would spill).
 // ===========================================================================
 template <typename T, int G>
-__global__ void __launch_bounds__(kBlock, 7) kpair_cg_vec(
+__global__ void __launch_bounds__(kBlock, (sizeof(T) == 4 ? 7 : 1)) kpair_cg_vec(
     int n, const int* __restrict__ inc_ptr, const int* __restrict__ inc_nb,
     const int* __restrict__ inc_id, const T* __restrict__ pcoef, double pair_coef,
     const T* __restrict__ WP, int ld, int r, T* __restrict__ Q, double* __restrict__ sc,
