@@ -584,11 +584,10 @@ __device__ __forceinline__ void prev_finish(const PrevSums& p, double* __restric
 // may be writing it during this launch), else the stored value
 __device__ __forceinline__ double slot_value(const PrevSums& p, const double* vals,
                                              const double* __restrict__ sc, int slot) {
-  double v = sc[slot];
 #pragma unroll
   for (int t = 0; t < 3; ++t)
-    if (t < p.k && p.q[t] == slot) v = vals[t];
-  return v;
+    if (t < p.k && p.q[t] == slot) return vals[t];
+  return sc[slot];  // not written during this launch
 }
 
 // first loop: y = (sign sc[slot]) x + 1.0 yin (yin = y, or G before q exists);
