@@ -127,3 +127,29 @@ def test_iteration_cap_status(device):
     with Context(p) as ctx:
         res = ctx.admm_solve([U0], _lib_opts(p, U0.shape[1], max_admm_iter=1))[0]
     assert res["status"] == lorads.LORADS_MAXITER and res["admm_iters"] == 1
+
+
+@pytest.mark.parametrize("name", ["mc_60x50", "maxcut_er200"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solve_bitwise_reproducible(device, name, precision):
+    # every reduction has a fixed order and the launch schedule does not enter
+    # the arithmetic, so a solve repeated in the same context or in a new one
+    # returns the same bits
+    from paper_2403_09133_amd import Context
+    p, r0 = CASES[name]
+    r0 = r0 or sdpgen.rank_rule_2lnm(p.m)
+    U0 = sdpgen.random_init_U(p.n, r0, 3)
+    runs = []
+    with Context(p) as ctx:
+        for _ in range(2):
+            res = ctx.admm_solve([U0], _lib_opts(p, r0, precision=precision))[0]
+            runs.append((res, ctx.get_solution(0, res["rank"])))
+    with Context(p) as ctx:
+        res = ctx.admm_solve([U0], _lib_opts(p, r0, precision=precision))[0]
+        runs.append((res, ctx.get_solution(0, res["rank"])))
+    ref, (U, V, lam) = runs[0]
+    for res, (U2, V2, lam2) in runs[1:]:
+        for key in ("status", "rank", "alm_outer", "alm_inner", "admm_iters", "cg_iters"):
+            assert res[key] == ref[key], key
+        assert res["obj"] == ref["obj"] and res["kkt"] == ref["kkt"]
+        assert np.array_equal(U2, U) and np.array_equal(V2, V) and np.array_equal(lam2, lam)
