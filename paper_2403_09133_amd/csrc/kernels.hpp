@@ -701,34 +701,42 @@ __device__ __forceinline__ double slot_value(const PrevSums& p, const double* va
     unsigned N, int r, int ld, const double* __restrict__ Gn, const double* __restrict__ G,
     double* __restrict__ Yn, const double* __restrict__ Sn, double* __restrict__ part) {
   __shared__ double sh[kBlock / 64];
-  double s0 = 0.0, s1 = 0.0;
+  // also the three sums the next two-loop starts from when this pair is the
+  // newest in memory (those of dots3_kernel over Sn, Gn and Yn: same products,
+  // same order, same grid); arrays: <Sn, Gn>, <Sn, Yn>, <Yn, Yn>, ||Gn||^2
+  double s_sy = 0.0, s_gg = 0.0, s_sg = 0.0, s_yy = 0.0;
   for (unsigned i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
     const size_t q = compact_to_row(i, r, ld);
-    double y = (double)(1.0 * (double)Gn[q] + 0.0 * (double)Yn[q]);
+    const double gv = Gn[q], sv = Sn[q];
+    double y = (double)(1.0 * gv + 0.0 * (double)Yn[q]);
     y = (double)(-1.0 * (double)G[q] + 1.0 * y);
     Yn[q] = y;
-    s0 += Sn[q] * y;
-    s1 += Gn[q] * Gn[q];
+    s_sy += sv * y;
+    s_gg += gv * gv;
+    s_sg += sv * gv;
+    s_yy += y * y;
   }
-  publish_partial(block_sum(s0, sh), part);
-  publish_partial(block_sum(s1, sh), part + gridDim.x);
+  publish_partial(block_sum(s_sg, sh), part);
+  publish_partial(block_sum(s_sy, sh), part + gridDim.x);
+  publish_partial(block_sum(s_yy, sh), part + 2 * gridDim.x);
+  publish_partial(block_sum(s_gg, sh), part + 3 * gridDim.x);
 }
 
-// the curvature pair's sums: sc[q_sy] = sc[q_mirror] = <Sn, Yn> (array 0),
-// sc[q_gg] = ||Gn||^2 (array 1), arrays of length np
+// the curvature pair's sums: sc[q_sy] = sc[q_mirror] = <Sn, Yn> (array 1),
+// sc[q_gg] = ||Gn||^2 (array 3), arrays of length np
 // (waves 0 and 1 each finish one array)
 [[maybe_unused]] static __global__ void __launch_bounds__(kBlock) pair_finish(
     int np, const double* __restrict__ part, double* __restrict__ sc, int q_sy, int q_mirror,
     int q_gg) {
   const int wid = threadIdx.x >> 6, l = threadIdx.x & 63;
   if (wid == 0) {
-    const double v0 = wave_sum_parts(part, np);
+    const double v0 = wave_sum_parts(part + np, np);
     if (l == 0) {
       sc[q_sy] = 1.0 * v0;
       sc[q_mirror] = 1.0 * v0;
     }
   } else if (wid == 1) {
-    const double v1 = wave_sum_parts(part + np, np);
+    const double v1 = wave_sum_parts(part + 3 * (size_t)np, np);
     if (l == 0) sc[q_gg] = 1.0 * v1;
   }
 }

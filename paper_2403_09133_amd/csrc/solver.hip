@@ -227,6 +227,11 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
     // own slot, exactly as the host would form it.
     double* pbuf[2] = {part, part + kLbfgsPartStride};
     double* part_gd = part + 3 * kLbfgsPartStride;
+    // the pair kernel's four sums (read by its finish and, while its pair is
+    // the newest in memory, by the next two-loop's first pass)
+    double* part_pair = pbuf[1];
+    static_assert(4 * kRedBlocks <= kLbfgsPartStride, "pair sums exceed their region");
+    bool fresh_pair = false;
     P.ensure_part((size_t)4 * kLbfgsPartStride);
     // two-loop recursion, newest pair first, in fused passes (each pass
     // updates q and forms the next dot; q = G until the first update).  The
@@ -245,9 +250,17 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
       };
       if (mc > 0) {
         const int k0 = order[0];
-        dots3_kernel<<<rg, kBlock, 0, s>>>(Nc, r, F.ld, A.S[k0].p, A.G.p, A.S[k0].p, A.Y[k0].p,
-                                           A.Y[k0].p, A.Y[k0].p, 3, pbuf[cur]);
-        chain(3, A.sy[k0], S_GEN + 16, S_GEN + 1, S_GEN + 2);
+        if (fresh_pair) {
+          // the newest pair and G came from the last step: its pair kernel left
+          // the three starting sums in part_pair (cur stays 0: the first pass
+          // writes pbuf[0])
+          prev = PrevSums{part_pair, rg, 3, {1.0, 1.0, 1.0}, {S_GEN + 16, S_GEN + 1, S_GEN + 2},
+                          {A.sy[k0], -1, -1}};
+        } else {
+          dots3_kernel<<<rg, kBlock, 0, s>>>(Nc, r, F.ld, A.S[k0].p, A.G.p, A.S[k0].p, A.Y[k0].p,
+                                             A.Y[k0].p, A.Y[k0].p, 3, pbuf[cur]);
+          chain(3, A.sy[k0], S_GEN + 16, S_GEN + 1, S_GEN + 2);
+        }
         for (int t = 0; t < mc; ++t) {
           // q = -alpha_t Y_t + q; on the last pass q *= <S,Y>/<Y,Y> of the newest pair
           const bool last = t == mc - 1;
@@ -308,6 +321,7 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
       pending = false;
       gnorm2 = gg;
       if (sy > 0.0) return false;
+      fresh_pair = false;
       A.head = undo_head;
       A.count = undo_count;
       std::swap(A.S[undo_head], A.Sn);
@@ -374,8 +388,9 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
       // leaves it again at the next read if <S, Y> <= 0.
       lbfgs_step_kernel<<<gridN(N), kBlock, 0, s>>>(N, alpha, A.D.p, A.Sn.p, U);
       alm_gradient(P, A, U, A.Gn.p, rho, s, info.op_bytes);
-      lbfgs_pair_kernel<<<rg, kBlock, 0, s>>>(Nc, r, F.ld, A.Gn.p, A.G.p, A.Yn.p, A.Sn.p, part);
-      pair_finish<<<1, kBlock, 0, s>>>(rg, part, P.sc.p, A.sy_n, S_GEN + 11, S_GEN + 12);
+      lbfgs_pair_kernel<<<rg, kBlock, 0, s>>>(Nc, r, F.ld, A.Gn.p, A.G.p, A.Yn.p, A.Sn.p,
+                                              part_pair);
+      pair_finish<<<1, kBlock, 0, s>>>(rg, part_pair, P.sc.p, A.sy_n, S_GEN + 11, S_GEN + 12);
       HIPCHK(hipGetLastError());
       undo_head = A.head;
       undo_count = A.count;
@@ -385,6 +400,7 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
       A.head = (A.head + 1) % mem;
       A.count = std::min(A.count + 1, mem);
       pending = true;
+      fresh_pair = true;
       std::swap(A.G, A.Gn);
       ++it;
     }
