@@ -104,8 +104,14 @@ struct AlmState {
   int head = 0, count = 0;
 };
 
+// FP64 factor rows of PAIR problems: whole 64-byte sectors, and at least the
+// lane group G (up to 32) so the two-column kernels apply (r = 17..24 gets 32
+// columns rather than 24)
 static int alm_ld(const Problem& P, int r) {
-  return P.structure == LORADS_STRUCT_PAIR ? cg_ld(P, r, (int)sizeof(double)) : r;
+  if (P.structure != LORADS_STRUCT_PAIR) return r;
+  const int ld = cg_ld(P, r, (int)sizeof(double));
+  const int G = lane_group(r);
+  return G <= 32 ? std::max(ld, G) : ld;
 }
 
 static void alm_alloc(AlmState& A, int n, int m, int r, int ld, int mem, hipStream_t s) {
@@ -546,7 +552,7 @@ static void phase2_t(Problem& P, const lorads_options& o, double rho, SolveInfo&
   // PAIR: zero-padded FP64 copies of U and V (rows of whole 64-byte sectors),
   // kept equal to the masters, for the gradient form and the dual update's
   // forward map (the same results as on the compact masters)
-  const int ldp = P.structure == LORADS_STRUCT_PAIR ? cg_ld(P, r, (int)sizeof(double)) : r;
+  const int ldp = alm_ld(P, r);
   DevBuf<double> Up, Vp;
   const bool padded = ldp != r;
   if (padded) {
