@@ -820,9 +820,14 @@ __device__ __forceinline__ void linesearch_partials(int bid, int nblk, int m,
 
 // sc[slot] = 2 <CD, U>, sc[slot + 1] = <CD, D>, sc[slot + 2 + t] = line-search
 // sum t; with part_gd, also sc[slot + 9] = the sum of its rg partials
+//
+// host (optional): also publish slots slot .. slot + npub - 1 (npub <= 64) to
+// host-mapped words 1 .. npub and then seq to word 0, as publish_slots does
+// (sums not formed here are copied from sc, written by earlier launches).
 [[maybe_unused]] static __global__ void __launch_bounds__(kBlock) linesearch_finish(
     int rg, const double* __restrict__ part_f, int gl, const double* __restrict__ part_m,
-    const double* __restrict__ part_gd, double* __restrict__ sc, int slot) {
+    const double* __restrict__ part_gd, double* __restrict__ sc, int slot, double* host,
+    long long seq, int npub) {
   // ten sums (rg, gl <= 2 kBlock), wave w finishes sums w, w + 4, w + 8: 0 and
   // 1 over part_f, 2 .. 8 over part_m, 9 over part_gd; a wave loads all of
   // its arrays before it sums them
@@ -845,7 +850,18 @@ __device__ __forceinline__ void linesearch_partials(int bid, int nblk, int m,
     const int a = wid + kW * j;
     if (!on[j]) continue;
     const double v = sum_parts2(q[j], na[j]);
-    if (l == 0) sc[slot + a] = (a == 0 ? 2.0 : 1.0) * v;
+    if (l == 0) {
+      const double val = (a == 0 ? 2.0 : 1.0) * v;
+      sc[slot + a] = val;
+      if (host && a < npub) host[1 + a] = val;
+    }
+  }
+  if (host) {
+    const int t = threadIdx.x;
+    if (t < npub && (t >= 10 || (t == 9 && part_gd == nullptr))) host[1 + t] = sc[slot + t];
+    __threadfence_system();
+    __syncthreads();
+    if (t == 0) __atomic_store_n(reinterpret_cast<long long*>(host), seq, __ATOMIC_RELEASE);
   }
 }
 

@@ -409,35 +409,44 @@ void set_slots(Problem& P, int slot, const double* vals, int count, hipStream_t 
 #ifndef LORADS_HOST_PUBLISH
 #define LORADS_HOST_PUBLISH 1
 #endif
+// Waits until the device has published sequence number seq (a kernel wrote
+// the values to the pinned words, then seq after a system-scope fence) and
+// copies count values out: the host spins on the number for a short while,
+// then waits for the stream (which also reports a failed launch).
+static void wait_published(Problem& P, long long seq, double* vals, int count, hipStream_t s) {
+  volatile long long* flag = reinterpret_cast<volatile long long*>(P.hs.h);
+  const auto t0 = std::chrono::steady_clock::now();
+  bool seen = false;
+  for (unsigned spin = 1; !(seen = (*flag == seq)); ++spin) {
+    if ((spin & 1023) == 0 &&
+        std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(2000))
+      break;
+  }
+  if (!seen) {
+    HIPCHK(hipStreamSynchronize(s));
+    if (*flag != seq) fail(LORADS_EDEVICE, "device did not publish the solver scalars");
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
+  const volatile double* hv = P.hs.h + 1;
+  for (int i = 0; i < count; ++i) vals[i] = hv[i];
+  if (P.prof.on) {  // the stream has passed these timings: finished forward / adjoint
+    P.prof.resolve(1);
+    P.prof.resolve(2);
+  }
+}
+
 void read_slots(Problem& P, int slot, double* vals, int count, hipStream_t s) {
   if (LORADS_HOST_PUBLISH && !P.hs.h) P.hs.init();  // first read of this problem
   if (LORADS_HOST_PUBLISH && count <= 64) {
-    // the device writes the values and then a fresh sequence number into
-    // pinned host words; the host spins on the number for a short while, then
-    // waits for the stream (which also reports a failed launch)
     const long long seq = ++P.hs.seq;
     publish_slots<<<1, 64, 0, s>>>(P.sc.p + slot, count, P.hs.d, seq);
     HIPCHK(hipGetLastError());
-    volatile long long* flag = reinterpret_cast<volatile long long*>(P.hs.h);
-    const auto t0 = std::chrono::steady_clock::now();
-    bool seen = false;
-    for (unsigned spin = 1; !(seen = (*flag == seq)); ++spin) {
-      if ((spin & 1023) == 0 &&
-          std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(2000))
-        break;
-    }
-    if (!seen) {
-      HIPCHK(hipStreamSynchronize(s));
-      if (*flag != seq) fail(LORADS_EDEVICE, "device did not publish the solver scalars");
-    }
-    std::atomic_thread_fence(std::memory_order_acquire);
-    const volatile double* hv = P.hs.h + 1;
-    for (int i = 0; i < count; ++i) vals[i] = hv[i];
-  } else {
-    HIPCHK(hipMemcpyAsync(vals, P.sc.p + slot, count * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    wait_published(P, seq, vals, count, s);
+    return;
   }
-  if (P.prof.on) {  // the stream has passed these timings: finished forward / adjoint
+  HIPCHK(hipMemcpyAsync(vals, P.sc.p + slot, count * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (P.prof.on) {  // the stream is idle: finished forward / adjoint timings
     P.prof.resolve(1);
     P.prof.resolve(2);
   }
@@ -476,7 +485,7 @@ void dual_update_slot(Problem& P, const double* z, double rho, double* lam, int 
 void linesearch_slots(Problem& P, int n, int r, int ld, const double* CD, const double* U,
                       const double* D, const double* z, const double* p1, const double* p2,
                       const double* lam, int slot, hipStream_t s, const double* part_gd,
-                      const double* cdiag) {
+                      const double* cdiag, double* vals, int nread) {
   const size_t N = (size_t)n * r;
   if (N >= ((size_t)1 << 32)) fail(LORADS_EINVAL, "factor too large for the line-search dots");
   const int rg = grid_for(N, kRedBlocks), gl = grid_for(P.m, kRedBlocks);
@@ -488,8 +497,16 @@ void linesearch_slots(Problem& P, int n, int r, int ld, const double* CD, const 
   if (part_gd && part_gd < part_m + (size_t)7 * gl)
     fail(LORADS_EINVAL, "descent-check partials overlap the line-search partials");
   if (rg > 2 * kBlock || gl > 2 * kBlock) fail(LORADS_EINVAL, "line-search partials exceed the finishing layout");
-  linesearch_finish<<<1, kBlock, 0, s>>>(rg, part_f, gl, part_m, part_gd, P.sc.p, slot);
+  // with vals, the finishing launch also publishes slot .. slot + nread - 1
+  // to the host and the call returns them (no separate read launch)
+  if (vals && LORADS_HOST_PUBLISH && !P.hs.h) P.hs.init();
+  const bool pub = vals && LORADS_HOST_PUBLISH && nread <= 64;
+  const long long seq = pub ? ++P.hs.seq : 0;
+  linesearch_finish<<<1, kBlock, 0, s>>>(rg, part_f, gl, part_m, part_gd, P.sc.p, slot,
+                                         pub ? P.hs.d : nullptr, seq, nread);
   HIPCHK(hipGetLastError());
+  if (pub) wait_published(P, seq, vals, nread, s);
+  else if (vals) read_slots(P, slot, vals, nread, s);
 }
 
 // ---------------------------------------------------------------------------

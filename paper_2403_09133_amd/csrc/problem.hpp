@@ -254,10 +254,12 @@ void dual_update_slot(Problem& P, const double* z, double rho, double* lam, int 
 // dot over the same factor grid, summed into sc[slot + 9]
 // cdiag (optional, PAIR): C's diagonal by row; then C D is formed in the pass
 // as the PAIR adjoint's C part rounds it, and CD is not read
+// vals (optional): also read slot .. slot + nread - 1 back to the host (the
+// finishing launch publishes them; synchronises like read_slots)
 void linesearch_slots(Problem& P, int n, int r, int ld, const double* CD, const double* U,
                       const double* D, const double* z, const double* p1, const double* p2,
                       const double* lam, int slot, hipStream_t s, const double* part_gd = nullptr,
-                      const double* cdiag = nullptr);
+                      const double* cdiag = nullptr, double* vals = nullptr, int nread = 0);
 template <typename TX, typename TY>
 void dot_to_slot(Problem& P, size_t N, const TX* X, const TY* Y, double scale, int slot, hipStream_t s);
 // the same for n x r factors stored with row stride ld (bit-identical to the

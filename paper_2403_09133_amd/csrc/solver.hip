@@ -310,8 +310,7 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
       // the two maps, and C D (a product with C alone)
       info.op_bytes += 2 * bytes_forward(P, r, 8) + bytes_cprod(P, r, 8);
       linesearch_slots(P, n, r, F.ld, A.CD.p, U, A.D.p, P.zbuf.p, A.p1.p, A.p2.p, P.lam.p,
-                       S_GEN + 1, s, part_gd, cdiag);
-      read_slots(P, S_GEN + 1, h, nread, s);
+                       S_GEN + 1, s, part_gd, cdiag, h, nread);
     };
     // A step's curvature pair enters the memory at once, before its <S, Y>
     // is known on the host, so the next direction and line search are queued
