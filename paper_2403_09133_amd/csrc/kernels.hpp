@@ -954,6 +954,14 @@ __global__ void __launch_bounds__(kBlock) scatter_kernel(int m, const int* __res
                                                          const T* __restrict__ src, T* __restrict__ dst) {
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < m; i += gridDim.x * kBlock) dst[idx[i]] = src[i];
 }
+// lb[2 t] = lam[id[t]] (the multiplier half of the interleaved [lam, b]
+// entries of the incident lists)
+[[maybe_unused]] static __global__ void __launch_bounds__(kBlock) gather_lam_lb(
+    int E, const int* __restrict__ id, const double* __restrict__ lam, double* __restrict__ lb) {
+  for (int t = blockIdx.x * kBlock + threadIdx.x; t < E; t += gridDim.x * kBlock)
+    lb[2 * (size_t)t] = lam[id[t]];
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) gather_kernel(int m, const int* __restrict__ idx,
                                                         const T* __restrict__ src, T* __restrict__ dst) {

@@ -357,8 +357,7 @@ __global__ void __launch_bounds__(kBlock) kpair_rows(
     const int* __restrict__ inc_nb, const int* __restrict__ inc_id, const T* __restrict__ pcoef,
     double pair_coef, const T* __restrict__ w, const T* __restrict__ V, const T* __restrict__ Pm,
     int r, int ld, T* __restrict__ out, int ldo, double out_scale, double* __restrict__ sc,
-    int parity, double* __restrict__ part, const double* __restrict__ lam_inc,
-    const double* __restrict__ b_inc, double rho_w) {
+    int parity, double* __restrict__ part, const double* __restrict__ lb_inc, double rho_w) {
   constexpr int NG = 64 / G;
   constexpr int CH = kPairStage;  // incident entries staged per wave and pass
   __shared__ double sh[kBlock / 64];
@@ -406,8 +405,8 @@ __global__ void __launch_bounds__(kBlock) kpair_rows(
         if (MODE == 2) {
           if (j < cnt) {
             nbw[j] = inc_nb[base + j];
-            cfw[j] = (A)lam_inc[base + j];
-            s_bi[wid][j] = b_inc[base + j];
+            cfw[j] = (A)lb_inc[2 * (size_t)(base + j)];
+            s_bi[wid][j] = lb_inc[2 * (size_t)(base + j) + 1];
           }
         } else if (j < cnt) {
           nbw[j] = inc_nb[base + j];
@@ -552,7 +551,7 @@ __global__ void __launch_bounds__(kBlock) kpair_grad_v2(
     const double* __restrict__ cval, double c_scale, const int* __restrict__ inc_ptr,
     const int* __restrict__ inc_nb, double pair_coef, const double* __restrict__ V, int r,
     int ld, double* __restrict__ out, int ldo, double out_scale,
-    const double* __restrict__ lam_inc, const double* __restrict__ b_inc, double rho_w,
+    const double* __restrict__ lb_inc, double rho_w,
     const int* __restrict__ rptr, double* __restrict__ z) {
   constexpr int HW = 32;              // lanes per row
   constexpr int NG = HW / GV;         // groups per row
@@ -596,8 +595,9 @@ __global__ void __launch_bounds__(kBlock) kpair_grad_v2(
         const int j = hl + HW * q;
         if (j < cnt) {
           nbw[j] = inc_nb[base + j];
-          cfw[j] = lam_inc[base + j];
-          biw[j] = b_inc[base + j];
+          const d2 lb = *reinterpret_cast<const d2*>(lb_inc + 2 * (size_t)(base + j));
+          cfw[j] = lb[0];
+          biw[j] = lb[1];
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

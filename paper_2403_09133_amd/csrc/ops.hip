@@ -219,7 +219,7 @@ static void op_adjoint_impl(Problem& P, const T* w, double c_scale, const T* V, 
     LORADS_DISPATCH_GK(G, r, (kpair_rows<T, G, 0, KC><<<waves_grid(P.n), kBlock, 0, s>>>(
                              P.n, P.cptr.p, P.ccol.p, cv<T>(P), c_scale, P.inc_ptr.p, P.inc_nb.p,
                              P.inc_id.p, pc<T>(P), P.pair_coef, w, V, nullptr, r, ld, out, ldo,
-                             out_scale, nullptr, 0, nullptr, nullptr, nullptr, 0.0)));
+                             out_scale, nullptr, 0, nullptr, nullptr, 0.0)));
   } else {
     LORADS_DISPATCH_G(G, (k2_generic<T, G, 0><<<rows_grid(P.n, G), kBlock, 0, s>>>(
                              P.n, P.cptr.p, P.ccol.p, cv<T>(P), c_scale, P.aptr.p, P.acol.p,
@@ -230,15 +230,15 @@ static void op_adjoint_impl(Problem& P, const T* w, double c_scale, const T* V, 
 }
 
 bool grad_pair_ready(const Problem& P) {
-  return P.structure == LORADS_STRUCT_PAIR && P.inc_b.n > 0 && P.inc_lam.n == P.inc_b.n;
+  return P.structure == LORADS_STRUCT_PAIR && P.inc_lb.n > 0 && P.inc_lb_lam;
 }
 
 void refresh_inc_lam(Problem& P, hipStream_t s) {
-  if (P.structure != LORADS_STRUCT_PAIR || P.inc_b.n == 0) return;
-  P.inc_lam.alloc(P.inc_b.n);
-  gather_kernel<double><<<grid_for(P.inc_b.n), kBlock, 0, s>>>((int)P.inc_b.n, P.inc_id.p, P.lam.p,
-                                                               P.inc_lam.p);
+  if (P.structure != LORADS_STRUCT_PAIR || P.inc_lb.n == 0) return;
+  const int E = (int)(P.inc_lb.n / 2);
+  gather_lam_lb<<<grid_for(E), kBlock, 0, s>>>(E, P.inc_id.p, P.lam.p, P.inc_lb.p);
   HIPCHK(hipGetLastError());
+  P.inc_lb_lam = true;
 }
 
 void op_grad_pair(Problem& P, const double* U, int r, int ld, double rho, double* out, int ldo,
@@ -257,13 +257,13 @@ void op_grad_pair(Problem& P, const double* U, int r, int ld, double rho, double
       const int grid = std::max(1, (P.n + kBlock / 32 - 1) / (kBlock / 32));  // two rows per wave
       LORADS_DISPATCH_V2(G, (kpair_grad_v2<GV><<<grid, kBlock, 0, s>>>(
                                 P.n, P.cptr.p, P.ccol.p, P.cval.p, 1.0, P.inc_ptr.p, P.inc_nb.p,
-                                P.pair_coef, U, r, ld, out, ldo, out_scale, P.inc_lam.p, P.inc_b.p,
-                                rho, P.rptr.p, z)));
+                                P.pair_coef, U, r, ld, out, ldo, out_scale, P.inc_lb.p, rho,
+                                P.rptr.p, z)));
     } else {
       LORADS_DISPATCH_GK(G, r, (kpair_rows<double, G, 2, KC><<<waves_grid(P.n), kBlock, 0, s>>>(
                                P.n, P.cptr.p, P.ccol.p, P.cval.p, 1.0, P.inc_ptr.p, P.inc_nb.p,
                                P.inc_id.p, nullptr, P.pair_coef, nullptr, U, nullptr, r, ld, out, ldo,
-                               out_scale, nullptr, 0, nullptr, P.inc_lam.p, P.inc_b.p, rho)));
+                               out_scale, nullptr, 0, nullptr, P.inc_lb.p, rho)));
     }
     HIPCHK(hipGetLastError());
   });
@@ -332,7 +332,7 @@ int op_cg(Problem& P, const T* W, int ldw, int r, int ld, const T* Pd, const T* 
       LORADS_DISPATCH_GK(G, r, (kpair_rows<T, G, 1, KC><<<grid, kBlock, 0, s>>>(
                                P.n, nullptr, nullptr, nullptr, 0.0, P.inc_ptr.p, P.inc_nb.p,
                                P.inc_id.p, pc<T>(P), P.pair_coef, nullptr, W, Pg, r, ldw, Q, ld,
-                               1.0, sc, parity, P.part.p, nullptr, nullptr, 0.0)));
+                               1.0, sc, parity, P.part.p, nullptr, 0.0)));
     }
     np = grid;
   } else {

@@ -155,9 +155,11 @@ struct Problem {
   DevBuf<int> fchunk_row, fchunk_start;
   int nfchunks = 0;
   DevBuf<int> inc_ptr, inc_nb, inc_id;  // incident lists: row pointers, partner, internal id
-  // uniform coefficient only: b and the current lam per incident entry, so the
-  // gradient form of the adjoint streams them instead of gathering w by id
-  DevBuf<double> inc_b, inc_lam;
+  // uniform coefficient only: [lam, b] per incident entry (interleaved, 16
+  // bytes), so the gradient form streams them instead of gathering w by id;
+  // lam is filled by refresh_inc_lam
+  DevBuf<double> inc_lb;
+  bool inc_lb_lam = false;
   // every row's incident entries with partners above the row are, in list
   // order, the view-R constraints rptr[row] .. rptr[row + 1] (checked at setup)
   bool inc_upper_view = false;

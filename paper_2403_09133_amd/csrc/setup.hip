@@ -301,9 +301,9 @@ std::unique_ptr<Problem> ingest(const lorads_problem& p, hipStream_t s) {
     P->inc_nb.upload(inc_nb, s);
     P->inc_id.upload(inc_id, s);
     if (uniform) {
-      std::vector<double> bi(inc_id.size());
-      for (size_t t = 0; t < inc_id.size(); ++t) bi[t] = b_int[inc_id[t]];
-      P->inc_b.upload(bi, s);
+      std::vector<double> lb(2 * inc_id.size(), 0.0);
+      for (size_t t = 0; t < inc_id.size(); ++t) lb[2 * t + 1] = b_int[inc_id[t]];
+      P->inc_lb.upload(lb, s);
     }
     bool upper_view = true;
     for (int j = 0; j < n && upper_view; ++j) {
