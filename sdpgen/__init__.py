@@ -338,3 +338,42 @@ def config_instance(name: str) -> Problem:
     if name == "mc_20000":
         return mc_paper_sample(40000, 1005)
     raise KeyError(name)
+
+
+# ----------------------------------------------------------------------------
+# Lovasz theta SDPs: min <-J, X> s.t. tr X = 1, X_ij = 0 on the graph's edges,
+# X PSD; the optimal value is -theta(G) (a general-structure family with a
+# dense cost)
+# ----------------------------------------------------------------------------
+
+def lovasz_theta(n: int, edges) -> Problem:
+    ei = np.array([min(a, b) for a, b in edges], dtype=np.int64)
+    ej = np.array([max(a, b) for a, b in edges], dtype=np.int64)
+    ir, ic = np.triu_indices(n)
+    c_row, c_col, c_val = ir, ic, np.full(ir.size, -1.0)
+    m = 1 + ei.size
+    con = np.concatenate([np.zeros(n, dtype=np.int64), 1 + np.arange(ei.size)])
+    row = np.concatenate([np.arange(n), ei])
+    col = np.concatenate([np.arange(n), ej])
+    # an off-diagonal triplet counts twice in <A_i, X>: 0.5 gives X_ij itself
+    val = np.concatenate([np.ones(n), np.full(ei.size, 0.5)])
+    b = np.zeros(m)
+    b[0] = 1.0
+    return Problem(n=n, m=m, c_row=c_row, c_col=c_col, c_val=c_val, a_con=con,
+                   a_row=row, a_col=col, a_val=val, b=b, kind="generic",
+                   meta={"graph_edges": len(edges)})
+
+
+def cycle_edges(n: int):
+    return [(i, (i + 1) % n) for i in range(n)]
+
+
+def complete_edges(n: int):
+    return [(i, j) for i in range(n) for j in range(i + 1, n)]
+
+
+def petersen_edges():
+    outer = [(i, (i + 1) % 5) for i in range(5)]
+    spokes = [(i, i + 5) for i in range(5)]
+    inner = [(5 + i, 5 + (i + 2) % 5) for i in range(5)]
+    return outer + spokes + inner

@@ -153,3 +153,18 @@ def test_solve_bitwise_reproducible(device, name, precision):
             assert res[key] == ref[key], key
         assert res["obj"] == ref["obj"] and res["kkt"] == ref["kkt"]
         assert np.array_equal(U2, U) and np.array_equal(V2, V) and np.array_equal(lam2, lam)
+
+
+@pytest.mark.parametrize("name", ["C5", "C7", "K6", "empty6", "petersen"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solve_lovasz_theta(device, name, precision):
+    # general structure with a dense cost (C = -J): the closed-form theta
+    from paper_2403_09133_amd import Context
+    from tests.test_oracle_theta import theta_instance
+    p, r0, theta = theta_instance(name)
+    U0 = sdpgen.random_init_U(p.n, r0, 3)
+    with Context(p) as ctx:
+        res = ctx.admm_solve([U0], _lib_opts(p, r0, precision=precision))[0]
+    assert res["status"] == 0, res
+    assert res["kkt"] < 1e-6
+    assert abs(-res["obj"] - theta) <= 5e-6 * theta, (res["obj"], theta)
