@@ -1,0 +1,116 @@
+"""GPU parity at the full sizes of the benchmarked configurations.
+
+The completion instance of the headline run (n_X = 20000, m = 4,605,170,
+r = 15) and the two MaxCut instances of the FP32-CG configuration (the
+100 x 100 torus and G(20000, 60000)): the forward map and the adjoint are
+compared with the oracle element by element (the oracle forms them in a few
+seconds at these sizes), in FP64 to the operator tests' bounds and in FP32 to
+the FP32 bounds; the CG entry point, which runs the solver's CG layout and
+kernels, is compared after a fixed number of iterations with the oracle's
+textbook CG on the same system.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import sdpgen
+
+pytestmark = pytest.mark.gpu
+
+_CACHE = {}
+
+
+def _problem(name):
+    if name not in _CACHE:
+        _CACHE[name] = sdpgen.config_instance(name)
+    return _CACHE[name]
+
+
+def _rank(p):
+    return 15 if p.kind == "mc" else int(math.ceil(math.log2(p.n)))
+
+
+def _abs_bound_forward(p, U, V):
+    pa = sdpgen.Problem(n=p.n, m=p.m, c_row=p.c_row, c_col=p.c_col, c_val=p.c_val, a_con=p.a_con,
+                        a_row=p.a_row, a_col=p.a_col, a_val=np.abs(p.a_val), b=p.b)
+    return oracle.operators.forward(pa, np.abs(U), np.abs(V))
+
+
+@pytest.mark.parametrize("name", ["mc_10000", "maxcut_torus100", "maxcut_gnm20000"])
+def test_fullsize_forward_adjoint_f64(device, name):
+    import torch
+    from paper_2403_09133_amd import Context
+    p = _problem(name)
+    r = _rank(p)
+    rng = np.random.default_rng(21)
+    U, V = rng.standard_normal((p.n, r)), rng.standard_normal((p.n, r))
+    w = rng.standard_normal(p.m)
+    refz = oracle.operators.forward(p, U, V)
+    refa = oracle.operators.adjoint(p, w, 1.0, V)
+    with Context(p) as ctx:
+        Ud, Vd, wd = (torch.tensor(a, device=device) for a in (U, V, w))
+        z = torch.zeros(p.m, dtype=torch.float64, device=device)
+        out = torch.zeros_like(Vd)
+        ctx.apply_A(Ud, Vd, z)
+        ctx.apply_AT_V(wd, Vd, out)
+        torch.cuda.synchronize()
+        gz, ga = z.cpu().numpy(), out.cpu().numpy()
+    assert np.linalg.norm(gz - refz) <= 1e-12 * np.linalg.norm(refz)
+    assert np.all(np.abs(gz - refz) <= 1e-12 * _abs_bound_forward(p, U, V) + 1e-300)
+    assert np.linalg.norm(ga - refa) <= 1e-12 * np.linalg.norm(refa)
+
+
+@pytest.mark.parametrize("name", ["mc_10000", "maxcut_gnm20000"])
+def test_fullsize_forward_adjoint_f32(device, name):
+    import torch
+    from paper_2403_09133_amd import Context
+    p = _problem(name)
+    r = _rank(p)
+    rng = np.random.default_rng(22)
+    U32 = rng.standard_normal((p.n, r)).astype(np.float32)
+    V32 = rng.standard_normal((p.n, r)).astype(np.float32)
+    w32 = rng.standard_normal(p.m).astype(np.float32)
+    U, V, w = (a.astype(np.float64) for a in (U32, V32, w32))
+    refz = oracle.operators.forward(p, U, V)
+    refa = oracle.operators.adjoint(p, w, 1.0, V)
+    with Context(p) as ctx:
+        Ud, Vd, wd = (torch.tensor(a, device=device) for a in (U32, V32, w32))
+        z = torch.zeros(p.m, dtype=torch.float32, device=device)
+        out = torch.zeros_like(Vd)
+        ctx.apply_A(Ud, Vd, z)
+        ctx.apply_AT_V(wd, Vd, out)
+        torch.cuda.synchronize()
+        gz, ga = z.cpu().numpy().astype(np.float64), out.cpu().numpy().astype(np.float64)
+    bound = _abs_bound_forward(p, U, V)
+    assert np.all(np.abs(gz - refz) <= 6e-8 * np.abs(refz) + 1.2e-7 * bound + 1e-30)
+    assert np.linalg.norm(ga - refa) <= 1e-6 * np.linalg.norm(refa)
+
+
+@pytest.mark.parametrize("name", ["mc_10000", "maxcut_torus100"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_fullsize_cg_iterations(device, name, dtype):
+    import torch
+    from paper_2403_09133_amd import Context
+    p = _problem(name)
+    r = _rank(p)
+    rng = np.random.default_rng(23)
+    W = rng.standard_normal((p.n, r)) / math.sqrt(r)
+    R = rng.standard_normal((p.n, r))
+    if dtype == "f32":
+        W, R = (a.astype(np.float32).astype(np.float64) for a in (W, R))
+    rho, gamma, K = 2.0, 1.5, 5
+    apply_M = oracle.cg.cg_operator(p, W, rho, gamma)
+    Xref, itref, _, _ = oracle.cg.cg(apply_M, R, 1e-14, K)
+    assert itref == K
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    with Context(p) as ctx:
+        Wd = torch.tensor(W, dtype=tdt, device=device)
+        Rd = torch.tensor(R, dtype=tdt, device=device)
+        Xd = torch.zeros_like(Wd)
+        info = ctx.cg_solve(Wd, Rd, Xd, rho, gamma, 1e-14, K)
+        X = Xd.cpu().numpy().astype(np.float64)
+    assert info["iters"] == K
+    tol = 1e-10 if dtype == "f64" else 1e-4
+    assert np.linalg.norm(X - Xref) <= tol * np.linalg.norm(Xref)
