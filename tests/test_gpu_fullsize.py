@@ -38,8 +38,11 @@ def _abs_bound_forward(p, U, V):
     return oracle.operators.forward(pa, np.abs(U), np.abs(V))
 
 
-@pytest.mark.parametrize("name", ["mc_10000", "maxcut_torus100", "maxcut_gnm20000"])
-def test_fullsize_forward_adjoint_f64(device, name):
+# ld 16: factors in rows of 16 columns (the solver's padded FP64 layout, on
+# which the completion forward map runs its two-columns-per-lane kernel)
+@pytest.mark.parametrize("name,ld", [("mc_10000", None), ("mc_10000", 16), ("maxcut_torus100", None),
+                                     ("maxcut_gnm20000", None)])
+def test_fullsize_forward_adjoint_f64(device, name, ld):
     import torch
     from paper_2403_09133_amd import Context
     p = _problem(name)
@@ -49,10 +52,18 @@ def test_fullsize_forward_adjoint_f64(device, name):
     w = rng.standard_normal(p.m)
     refz = oracle.operators.forward(p, U, V)
     refa = oracle.operators.adjoint(p, w, 1.0, V)
+
+    def dev(a):
+        if ld is None or a.ndim == 1:
+            return torch.tensor(a, device=device)
+        big = torch.zeros((a.shape[0], ld), dtype=torch.float64, device=device)
+        big[:, :a.shape[1]] = torch.tensor(a, device=device)
+        return big[:, :a.shape[1]]
+
     with Context(p) as ctx:
-        Ud, Vd, wd = (torch.tensor(a, device=device) for a in (U, V, w))
+        Ud, Vd, wd = (dev(a) for a in (U, V, w))
         z = torch.zeros(p.m, dtype=torch.float64, device=device)
-        out = torch.zeros_like(Vd)
+        out = dev(np.zeros((p.n, r)))  # the adjoint writes with V's row stride
         ctx.apply_A(Ud, Vd, z)
         ctx.apply_AT_V(wd, Vd, out)
         torch.cuda.synchronize()
