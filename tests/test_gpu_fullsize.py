@@ -166,3 +166,31 @@ def test_fullsize_batch_sampled(device):
                 s1 = one.admm_solve([U0[i]], opts(batch_mode=2))[0]
             assert s1["status"] == 0, (i, s1)
             assert abs(s1["obj"] - r["obj"]) <= 1e-5 * abs(s1["obj"]), (i, s1["obj"], r["obj"])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_fullsize_headline_solve(device, precision):
+    """The headline solve (completion, n_X = 20000, m = 4,605,170) with the
+    benchmarked options and start, FP64 and FP32-CG: it meets eq. (stop); the
+    oracle recomputes the objective, the primal infeasibility and the gap
+    (Appendix B) from the returned factors and multipliers at full size, and
+    the planted matrix is recovered."""
+    from paper_2403_09133_amd import Context, lorads
+    from paper_2403_09133_amd.params import initial_rank, solver_options
+    p = _problem("mc_10000")
+    r0 = initial_rank(p.kind, p.n, p.m)
+    U0 = sdpgen.random_init_U(p.n, r0, 3)
+    with Context(p) as ctx:
+        res = ctx.admm_solve([U0], solver_options(p.kind, p.n, r0, precision))[0]
+        U, V, lam = ctx.get_solution(0, res["rank"])
+    assert res["status"] == lorads.LORADS_OK and res["kkt"] < 1e-6, res
+    Uh = 0.5 * (U + V)
+    nrm = oracle.operators.norms(p)
+    obj = oracle.operators.cost_inner(p, Uh, Uh)
+    pinf = float(np.linalg.norm(oracle.operators.forward(p, Uh, Uh) - p.b)) / (1.0 + nrm["b_1"])
+    by = float(p.b @ -lam)
+    gap = (obj - by) / (1.0 + abs(obj) + abs(by))
+    assert abs(obj - res["obj"]) <= 1e-10 * abs(obj), (obj, res["obj"])
+    assert abs(pinf - res["pinf"]) <= 1e-9, (pinf, res["pinf"])
+    assert abs(gap - res["gap"]) <= 1e-9, (gap, res["gap"])
+    assert oracle.metrics.mc_recovery_error(p, Uh) < 1e-6
