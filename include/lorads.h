@@ -120,7 +120,11 @@ typedef struct {
   int32_t phase1;          /* 1: run the warm start; 0: start ADMM at init_U */
   int32_t verbose;         /* 0 silent, 1 per-phase summary, 2 per iteration */
   int32_t profile;         /* 1: time the operator launches with HIP events
-                              (fields prof_* of the result) */
+                              (fields prof_* of the result); 2: time only the
+                              fused CG operator (class 0), whose launches carry
+                              their own start / stop events, so the other
+                              launches run without event records between them;
+                              other values: EINVAL */
   int32_t batch_mode;      /* 0: batched persistent launch when the context holds
                               >= 2 problems, all with diagonal constraints
                               (MaxCut), else one problem after the other;

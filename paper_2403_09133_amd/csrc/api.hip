@@ -295,7 +295,7 @@ lorads_status lorads_admm_solve(lorads_ctx* ctx, const lorads_options* opt, lora
     const lorads_options& o = *opt;
     if (o.precision != LORADS_F64 && o.precision != LORADS_F32) fail(LORADS_EINVAL, "precision");
     if (!(o.eps > 0) || o.max_admm_iter < 0 || o.lbfgs_mem < 1 || o.lbfgs_mem > 16 ||
-        o.rho_every < 1)
+        o.rho_every < 1 || o.profile < 0 || o.profile > 2)
       fail(LORADS_EINVAL, "invalid options");
     if (!o.init_U) fail(LORADS_EINVAL, "init_U is required (the random start is an input)");
     for (size_t pi = 0; pi < ctx->probs.size(); ++pi) {
@@ -348,6 +348,7 @@ lorads_status lorads_admm_solve(lorads_ctx* ctx, const lorads_options* opt, lora
       info.warm = o.warm_check && o.init_lambda && o.init_lambda[pi];
       P.prof.reset();
       P.prof.on = o.profile != 0;
+      P.prof.kinds = o.profile == 2 ? 1u : ~0u;
       double rho;
       if (o.phase1) {
         phase1(P, o, info, s);

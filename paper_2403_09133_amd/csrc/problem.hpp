@@ -16,6 +16,7 @@ namespace lorads {
 constexpr int kProfKinds = 4;
 struct KernelProfile {
   bool on = false;
+  unsigned kinds = ~0u;  // bit k: time class k
   struct Pair { hipEvent_t a, b; double bytes; };
   std::vector<hipEvent_t> all, free_;
   std::vector<Pair> pending[kProfKinds];
@@ -35,7 +36,7 @@ struct KernelProfile {
   }
   template <typename F>
   void run(int kind, double b, hipStream_t s, F&& launch) {
-    if (!on) { launch(); return; }
+    if (!on || !((kinds >> kind) & 1u)) { launch(); return; }
     hipEvent_t e0 = get(), e1 = get();
     HIPCHK(hipEventRecord(e0, s));
     launch();
@@ -46,7 +47,7 @@ struct KernelProfile {
   // launched with start / stop events is timed from its own dispatch)
   template <typename F>
   void run_ext(int kind, double b, F&& launch) {
-    if (!on) { launch((hipEvent_t) nullptr, (hipEvent_t) nullptr); return; }
+    if (!on || !((kinds >> kind) & 1u)) { launch((hipEvent_t) nullptr, (hipEvent_t) nullptr); return; }
     hipEvent_t e0 = get(), e1 = get();
     launch(e0, e1);
     pending[kind].push_back({e0, e1, b});

@@ -155,6 +155,28 @@ def test_solve_bitwise_reproducible(device, name, precision):
         assert np.array_equal(U2, U) and np.array_equal(V2, V) and np.array_equal(lam2, lam)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_profile_levels(device, precision):
+    # profile 1 times every kernel class, profile 2 only the fused CG operator;
+    # the timing does not enter the arithmetic; other levels are rejected
+    from paper_2403_09133_amd import Context
+    from paper_2403_09133_amd.lorads import LoradsError
+    p, r0 = CASES["mc_60x50"]
+    r0 = r0 or sdpgen.rank_rule_2lnm(p.m)
+    U0 = sdpgen.random_init_U(p.n, r0, 3)
+    with Context(p) as ctx:
+        out = [ctx.admm_solve([U0], _lib_opts(p, r0, precision=precision, profile=k))[0] for k in (0, 1, 2)]
+        with pytest.raises(LoradsError):
+            ctx.admm_solve([U0], _lib_opts(p, r0, precision=precision, profile=3))
+    for res in out[1:]:
+        for key in ("rank", "alm_inner", "admm_iters", "cg_iters", "obj", "kkt"):
+            assert res[key] == out[0][key], key
+    assert out[0]["prof_launches"] == [0, 0, 0, 0]
+    assert out[1]["prof_launches"][0] > 0 and sum(out[1]["prof_launches"][1:]) > 0
+    assert out[2]["prof_launches"][0] == out[1]["prof_launches"][0]
+    assert out[2]["prof_launches"][1:] == [0, 0, 0] and out[2]["prof_ms"][0] > 0
+
+
 @pytest.mark.parametrize("name", ["C5", "C7", "K6", "empty6", "petersen"])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_solve_lovasz_theta(device, name, precision):
