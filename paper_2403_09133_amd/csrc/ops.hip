@@ -549,10 +549,12 @@ int cg_run(Problem& P, const T* W, int ldw, int r, int ld, double rho, double ga
       cg_direction<T><<<gridv, kBlock, 0, s>>>(N, R, Pd, P.sc.p, par, P2, ld, gridv, P.part.p);
     }
     HIPCHK(hipGetLastError());
+    // earlier chunks' timings are read while the device runs this one
+    if (P.prof.on) P.prof.settle(0);
     read_slots(P, 0, h, kRead, s);
     iters = (int)h[S_ITERS];
     // launches after convergence returned at once: time only the live ones
-    if (P.prof.on) P.prof.resolve(0, iters - iters_before);
+    if (P.prof.on) P.prof.mark(0, iters - iters_before);
     done = h[S_DONE + (k & 1)] != 0.0;
     const double rr = h[S_RR + (k & 1)], rr0 = h[S_RR0];
     const double rr_ref = rr_prev > 0.0 ? rr_prev : rr0;

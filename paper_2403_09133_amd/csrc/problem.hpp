@@ -52,21 +52,43 @@ struct KernelProfile {
     launch(e0, e1);
     pending[kind].push_back({e0, e1, b});
   }
-  // accumulate the first `keep` pending pairs of `kind` (all when keep < 0);
-  // the caller has synchronised the stream
-  void resolve(int kind, long long keep = -1) {
+  // the first `marked` pending pairs of each kind have finished and the first
+  // `live` of them are counted; settle() reads them later, so that a launch
+  // site can have the host read them while the device runs newer work
+  size_t marked[kProfKinds] = {0, 0, 0, 0}, live[kProfKinds] = {0, 0, 0, 0};
+  // the pairs of `kind` not yet marked have finished (the caller has seen
+  // later work on the stream end); count the first `keep` of them (all when
+  // keep < 0)
+  void mark(int kind, long long keep = -1) {
     auto& v = pending[kind];
-    const size_t k = keep < 0 ? v.size() : std::min<size_t>(v.size(), (size_t)keep);
-    for (size_t i = 0; i < k; ++i) {
+    const size_t fresh = v.size() - marked[kind];
+    const size_t k = keep < 0 ? fresh : std::min<size_t>(fresh, (size_t)keep);
+    if (k > 0) {
+      // counted pairs form a prefix: settle a batch that ends uncounted first
+      if (live[kind] != marked[kind]) settle(kind);
+      live[kind] = marked[kind] + k;
+    }
+    marked[kind] = v.size();
+  }
+  // accumulate the counted marked pairs and return every marked pair's events
+  void settle(int kind) {
+    auto& v = pending[kind];
+    for (size_t i = 0; i < live[kind]; ++i) {
       float t = 0.f;
-      HIPCHK(hipEventSynchronize(v[i].b));  // complete already: the host has seen later work end
+      HIPCHK(hipEventSynchronize(v[i].b));  // complete already
       HIPCHK(hipEventElapsedTime(&t, v[i].a, v[i].b));
       ms[kind] += t;
       bytes[kind] += v[i].bytes;
       count[kind] += 1;
     }
-    for (auto& pr : v) { free_.push_back(pr.a); free_.push_back(pr.b); }
-    v.clear();
+    for (size_t i = 0; i < marked[kind]; ++i) { free_.push_back(v[i].a); free_.push_back(v[i].b); }
+    v.erase(v.begin(), v.begin() + (long)marked[kind]);
+    marked[kind] = live[kind] = 0;
+  }
+  // mark and settle at once; the caller has synchronised the stream
+  void resolve(int kind, long long keep = -1) {
+    mark(kind, keep);
+    settle(kind);
   }
   void resolve_all() {
     for (int k = 0; k < kProfKinds; ++k) resolve(k);
@@ -75,6 +97,7 @@ struct KernelProfile {
     for (int k = 0; k < kProfKinds; ++k) {
       for (auto& pr : pending[k]) { free_.push_back(pr.a); free_.push_back(pr.b); }
       pending[k].clear();
+      marked[k] = live[k] = 0;
       ms[k] = bytes[k] = 0;
       count[k] = 0;
     }

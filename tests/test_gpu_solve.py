@@ -174,6 +174,9 @@ def test_profile_levels(device, precision):
     assert out[0]["prof_launches"] == [0, 0, 0, 0]
     assert out[1]["prof_launches"][0] > 0 and sum(out[1]["prof_launches"][1:]) > 0
     assert out[2]["prof_launches"][0] == out[1]["prof_launches"][0]
+    # one live CG operator launch per CG iteration; launches queued after a
+    # CG solve converged are not counted
+    assert out[1]["prof_launches"][0] == out[1]["cg_iters"]
     assert out[2]["prof_launches"][1:] == [0, 0, 0] and out[2]["prof_ms"][0] > 0
 
 
