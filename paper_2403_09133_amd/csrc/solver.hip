@@ -436,10 +436,12 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
       adot(U, U, 1.0, S_GEN, s);
       read_slots(P, S_GEN, h, 1, s);
       const double sigma = 1e-3 * std::sqrt(h[0]) / std::sqrt((double)n * r);
+      // the kernel reads the compact n x r master that F.store has just
+      // written (the working copy U may have padded rows)
       F.store(P, r, s);
       DevBuf<double> Unew;
       Unew.alloc((size_t)n * r_new);
-      grow_rank_kernel<<<gridN((size_t)n * r_new), kBlock, 0, s>>>(n, r, r_new, U, Unew.p, sigma,
+      grow_rank_kernel<<<gridN((size_t)n * r_new), kBlock, 0, s>>>(n, r, r_new, P.U.p, Unew.p, sigma,
                                                                    o.seed, (uint64_t)growths);
       HIPCHK(hipGetLastError());
       HIPCHK(hipStreamSynchronize(s));
