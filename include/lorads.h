@@ -90,8 +90,10 @@ typedef struct {
                               factor; U, V, lambda, right-hand sides, dual
                               updates, decisions and residuals stay FP64 */
   double eps;              /* final tolerance on eq. (stop), default 1e-6 */
-  double switch_tol;       /* phase-I exit on primal infeasibility (paper:
-                              1e-2 MaxCut, 1e-3 otherwise) */
+  double switch_tol;       /* phase-I exit on primal infeasibility, default 1e-3
+                              (Section 5.1: 1e-3 for most instances; its 1e-2
+                              for MaxCut goes with a stop on primal
+                              infeasibility alone, not with eq. (stop)) */
   double h;                /* rho factor at the phase switch (paper) */
   double rho_growth;       /* 1.2 (paper) */
   int32_t rho_every;       /* 5 (paper) */
@@ -109,7 +111,13 @@ typedef struct {
   int32_t rank_grow_iters; /* an inner solve reaching this count grows the rank, 1000 */
   double rank_factor;      /* 1.5 (paper) */
   int32_t r0;              /* initial rank (> 0 required unless init_U given) */
-  int32_t r_max;           /* rank cap; 0: min(floor(sqrt(2m)), n) */
+  int32_t r_max;           /* rank cap: min(r_max, n, 256), or with r_max = 0
+                              min(floor(sqrt(2m)), n, 256) (floor(sqrt(2m)) is
+                              the Barvinok-Pataki bound of Section 2; 256 is the
+                              largest rank the operator kernels take).  The
+                              batched launch caps ranks at 32 as well (its lane
+                              group holds one factor row); a solve never raises
+                              the rank above its cap */
   double alm_inner_rel;    /* inner stop ||grad||/(1+||C||_F) <= max(rel v, floor) */
   double alm_inner_floor;
   double alm_eta;          /* multiplier update when v <= eta * v_at_last_update */

@@ -45,15 +45,20 @@ def appendix_b(prob, U, lam):
     )
 
 
-def mc_recovery_error(prob, U):
+def mc_recovery_error(prob, U, block: int = 1024):
     """||U1 U2^T - M||_F / ||M||_F with M = L R^T (the off-diagonal block of
-    X = U U^T estimates M under the halved completion scaling)."""
+    X = U U^T estimates M under the halved completion scaling).
+
+    The definition written out: the difference U1 U2^T - L R^T is formed
+    entry by entry, a block of rows at a time, and its squared entries summed,
+    so no large quantity is subtracted from another."""
     n1 = prob.meta["n1"]
     L, R = prob.meta["L"], prob.meta["R"]
     U1, U2 = U[:n1], U[n1:]
-    # Frobenius norms through small Gram matrices
-    g11, g22 = U1.T @ U1, U2.T @ U2
-    lu, ru = L.T @ U1, R.T @ U2
-    ll, rr = L.T @ L, R.T @ R
-    e2 = np.sum(g11 * g22) - 2.0 * np.sum(lu * ru) + np.sum(ll * rr)
-    return float(np.sqrt(max(e2, 0.0)) / np.sqrt(np.sum(ll * rr)))
+    num = den = 0.0
+    for j0 in range(0, n1, block):
+        M = L[j0:j0 + block] @ R.T
+        E = U1[j0:j0 + block] @ U2.T - M
+        num += float(np.sum(E * E))
+        den += float(np.sum(M * M))
+    return float(np.sqrt(num / den))
