@@ -1,24 +1,39 @@
 #!/usr/bin/env python
 """Benchmark of the LoRADS hot path on one MI355X.
 
-Workload: the planted rank-5 matrix-completion SDP with M of order 10000 x 10000
-(X of order 20000), 4,605,170 observed entries, C = I/2, solved by the
-two-phase method (warm start + ADMM with CG subproblems) to KKT residual 1e-6,
-CG in FP32 with FP64 right-hand sides, dual updates and residuals.
+Headline workload: the planted rank-5 matrix-completion SDP with M of order
+20000 x 20000 (X of order 40000), 15,683,710 observed entries drawn as the
+paper's completion generator draws them (800 d uniform cells, duplicates
+merged), C = I/2, solved by the two-phase method (Burer-Monteiro warm start,
+then ADMM with CG subproblem solves) to KKT residual eq. (stop) <= 1e-6, CG in
+FP32 with FP64 right-hand sides, dual updates and residuals; the initial rank
+round(ln m) = 17.  A second entry repeats it on the completion instance of
+order 10000 (4,605,170 entries, rank 15).
 
 One step = one full two-phase solve from the same random start, the instance
 already resident in HBM (setup is outside the timed region).
 
 value  = algorithmic bytes of every constraint-operator application of the
-         solves (forward map, adjoint product, fused CG operator; indices,
-         coefficients, inputs and outputs counted once) / wall time, in GB/s.
-roofline: the dominant kernel's algorithmic bytes per launch / its mean launch
-         time from HIP events recorded on the solver's stream during the timed
-         steps, against the 8 TB/s HBM peak.
+         solves (forward map, adjoint product, fused CG operator, the gradient
+         form as a forward map plus an adjoint, the line-search pass as the two
+         forward maps it computes; indices, coefficients, inputs and outputs
+         counted once) / wall time of the timed steps, in GB/s.
+roofline: the dominant kernel class of the timed steps (all classes carry HIP
+         events on the solver's stream during the timed steps): algorithmic
+         bytes per launch x launches / summed event time, against the 8 TB/s
+         HBM peak; `traffic` is the measured HBM bytes per launch of that class
+         on this workload (FETCH_SIZE + WRITE_SIZE, profiles/hbm_traffic.json)
+         while the kernel sources are unchanged, else null.
+roofline_fp64: the same for the plain FP64 solve.
+ops_cold_warm: forward map and adjoint product alone at the solve's rank, FP32
+         and FP64, warm (back to back) and cold (a 1 GiB buffer written before
+         each call, flushing the 256 MB Infinity Cache and the L2s).
 cpu_baseline: the FP64 numpy oracle's forward map and adjoint product at the
-         same size on the host, one thread, in the same unit.
+         same size on the host, one thread, in the same unit; beside it the
+         oracle's end-to-end time to eq. (stop) <= 1e-6 on the MaxCut instance
+         of order 200.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
 from __future__ import annotations
 
@@ -26,6 +41,7 @@ import argparse
 import json
 import math
 import os
+import platform
 import sys
 import time
 
@@ -41,6 +57,38 @@ KERNEL_SOURCES = ["paper_2403_09133_amd/csrc/kernels_struct.hpp", "paper_2403_09
                   "paper_2403_09133_amd/csrc/ops.hip", "paper_2403_09133_amd/csrc/common.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 
+# kernel classes timed by the library (lorads_result.prof_*)
+CLASSES = ["fused CG operator", "forward map A(UV^T)", "adjoint (C + A*(w))V", "line search A(UD^T+DU^T), A(DD^T)"]
+
+
+def pow2_group(k: int) -> int:
+    g = 1
+    while g < k and g < 64:
+        g <<= 1
+    return g
+
+
+def class_kernels(structure: str, r: int, cg_dtype: str) -> list:
+    """The kernel each class runs for a structure and rank (the names rocprofv3
+    reports), so that a line names what was timed."""
+    G = pow2_group(r)
+    if structure == "pair":
+        # the CG layout pads rows to 64 bytes; the vector form needs its lane
+        # group's columns inside the row
+        esz = 4 if cg_dtype == "float" else 8
+        vw = 16 // esz
+        ld = (r + 64 // esz - 1) // (64 // esz) * (64 // esz)
+        gv = pow2_group((r + vw - 1) // vw)
+        cg = f"kpair_cg_vec<{cg_dtype}, {gv}>" if gv * vw <= ld and gv <= 16 else f"kpair_rows<{cg_dtype}, {G}, 1>"
+        GV = max(1, G // 2)
+        return [cg, f"k1_pair_v2<{GV}, 0>", f"kpair_grad_v2<{GV}>", f"k1_pair_ls<{GV}>"]
+    if structure == "diag":
+        # the line search's two maps run as forward maps (counted in that class)
+        return [f"k3_diag<{cg_dtype}, {G}>", f"k1_diag<double, {G}, 0|1>", f"k2_diag<double, {G}, 0>",
+                "(none: two forward maps)"]
+    return [f"k1_generic<{cg_dtype}, {G}, 2> + k2_generic<{cg_dtype}, {G}, 1>", f"k1_generic<double, {G}, 1>",
+            f"k2_generic<double, {G}, 0>", f"k1_generic<double, {G}, 0>"]
+
 
 def kernel_sources_hash() -> str:
     import hashlib
@@ -51,32 +99,27 @@ def kernel_sources_hash() -> str:
     return h.hexdigest()
 
 
-def recorded_traffic(symbol: str):
-    """HBM bytes per launch of `symbol` from the recorded FETCH_SIZE / WRITE_SIZE
-    passes (already scaled by the copy-kernel calibration), or None when no
-    record exists or the kernel sources changed since it was taken."""
+def recorded_traffic(workload: str, precision: str, klass: str):
+    """HBM bytes per launch of a kernel class on a workload, from the recorded
+    FETCH_SIZE / WRITE_SIZE passes (already scaled by the copy-kernel
+    calibration), or None when no record exists for that workload, precision
+    and class, or the kernel sources changed since it was taken."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as fh:
         rec = json.load(fh)
     if rec.get("sources_sha256") != kernel_sources_hash():
         return None
-    ent = rec.get("kernels", {}).get(symbol)
+    ent = rec.get("workloads", {}).get(workload, {}).get(precision, {}).get(klass)
     return None if ent is None else int(round(ent["hbm_bytes_per_launch"]))
-# kernel classes timed by the library (lorads_result.prof_*), with the kernel
-# each one runs on the completion workload
-KERNEL_CLASSES = {
-    "fused CG operator": "kpair_cg_vec<float, 4>",
-    "forward map A(UV^T)": "k1_pair_v2<8, 0>",
-    "adjoint (C + A*(w))V, gradient form": "kpair_grad_v2<8>",
-    "line-search maps A(UD^T+DU^T), A(DD^T)": "k1_pair_v2<8, 3>",
-}
+
+
 WORKLOADS = {
-    # name -> (generator key, precision code, description)
-    "mc_10000": ("mc_10000", 1, "matrix completion 10000x10000, rank 5, |Omega|=4605170, X of order 20000"),
-    "mc_20000": ("mc_20000", 1, "matrix completion 20000x20000, rank 5, 800*d draws deduplicated, X of order 40000"),
-    "maxcut_torus100": ("maxcut_torus100", 1, "MaxCut 100x100 torus, +-1 weights, n=m=10000"),
-    "maxcut_gnm20000": ("maxcut_gnm20000", 1, "MaxCut G(20000, M=60000), unit weights"),
+    # name -> description
+    "mc_20000": "matrix completion 20000x20000, rank 5, 800*d draws deduplicated, X of order 40000",
+    "mc_10000": "matrix completion 10000x10000, rank 5, |Omega|=4605170, X of order 20000",
+    "maxcut_torus100": "MaxCut 100x100 torus, +-1 weights, n=m=10000",
+    "maxcut_gnm20000": "MaxCut G(20000, M=60000), unit weights",
 }
 
 
@@ -90,14 +133,34 @@ def lib_options(p, r0, precision, **kw):
     return solver_options(p.kind, p.n, r0, precision, **kw)
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def host_cpu() -> dict:
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return dict(model=model, nproc=os.cpu_count())
+
+
 def cpu_baseline(p, r: int, budget_s: float = 20.0):
-    """Time the oracle's forward map and adjoint product (FP64, numpy) on the
-    host, single thread, for a bounded number of applications."""
+    """The oracle's forward map and adjoint product (FP64, numpy) on the host,
+    one thread, for a bounded number of applications; plus the oracle's
+    end-to-end solve of the MaxCut instance of order 200 to eq. (stop)."""
     try:
         from threadpoolctl import threadpool_limits
     except Exception:  # pragma: no cover
         threadpool_limits = None
     import oracle
+    import sdpgen
+    from oracle.options import Options, paper_defaults
     rng = np.random.default_rng(0)
     U = rng.standard_normal((p.n, r))
     V = rng.standard_normal((p.n, r))
@@ -113,39 +176,146 @@ def cpu_baseline(p, r: int, budget_s: float = 20.0):
             t = time.perf_counter() - t0
             if t > budget_s / 2 or reps >= 8:
                 break
+        q = sdpgen.config_instance("maxcut_er200")
+        U0 = sdpgen.random_init_U(q.n, 8, 3)
+        t1 = time.perf_counter()
+        out = oracle.lorads.lorads(q, U0, Options(**paper_defaults(q.kind, q.n)), with_metrics=False)
+        t_e2e = time.perf_counter() - t1
     finally:
-        if ctx is not None:
-            ctx.unregister() if hasattr(ctx, "unregister") else None
+        if ctx is not None and hasattr(ctx, "unregister"):
+            ctx.unregister()
     bytes_pair = 2 * (8.0 * p.m + 8.0 * p.m + 2.0 * p.n * r * 8)
     return dict(value=round(reps * bytes_pair / t / 1e9, 4), unit="GB/s", cores=1, kind="oracle",
                 sample=f"{reps} x (A(UV^T) + (C + A*(y))V) at full size, r={r}, FP64 numpy, "
-                       f"{t:.1f} s on the host")
+                       f"{t:.1f} s on the host",
+                host=host_cpu(),
+                oracle_time_to_kkt_s=dict(workload="maxcut_er200 (n = m = 200, r0 = 8), FP64 numpy, 1 thread",
+                                          s=round(t_e2e, 3), admm_iters=int(out["phase2"]["iters"]),
+                                          converged=bool(out["phase2"]["converged"])))
 
 
-def batch_leg(count: int = 512, sample: int = 16):
+def timed_solves(ctx, p, U0, r0, prec, steps, warmup):
+    """`warmup` untimed solves, then `steps` timed ones with every kernel class
+    carrying HIP events (profile level 1)."""
+    import torch
+    for i in range(warmup):
+        res = ctx.admm_solve([U0], lib_options(p, r0, prec))[0]
+        log(f"warmup {i}: {res['t_total']:.3f}s status {res['status']} kkt {res['kkt']:.2e}")
+    results = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        res = ctx.admm_solve([U0], lib_options(p, r0, prec, profile=1))[0]
+        results.append(res)
+        log(f"step {i}: {res['t_total']:.3f}s status {res['status']} kkt {res['kkt']:.2e} "
+            f"obj {res['obj']:.10g} admm {res['admm_iters']} cg {res['cg_iters']} "
+            f"(phase I {res['t_phase1']:.3f}s, II {res['t_phase2']:.3f}s)")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return results, wall
+
+
+def roofline_of(results, workload, structure, prec):
+    """Dominant class over the timed solves and its figures."""
+    K = len(CLASSES)
+    ms = [sum(r["prof_ms"][k] for r in results) for k in range(K)]
+    launches = [sum(r["prof_launches"][k] for r in results) for k in range(K)]
+    kbytes = [sum(r["prof_bytes"][k] for r in results) for k in range(K)]
+    rank = results[-1]["rank"]
+    names = class_kernels(structure, rank, "float" if prec == 1 else "double")
+    kernels = {CLASSES[k]: dict(kernel=names[k], launches=int(launches[k]), total_ms=round(ms[k], 3),
+                                mean_us=round(ms[k] * 1e3 / max(1, launches[k]), 2),
+                                gbs=round(kbytes[k] / (ms[k] * 1e-3) / 1e9, 1) if ms[k] > 0 else None)
+               for k in range(K)}
+    dom = int(np.argmax(ms))
+    achieved = kbytes[dom] / (ms[dom] * 1e-3) / 1e9 if ms[dom] > 0 else 0.0
+    pname = "fp32_cg" if prec == 1 else "fp64"
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4),
+                traffic=recorded_traffic(workload, pname, CLASSES[dom]),
+                kernel=CLASSES[dom], symbol=names[dom], launches=int(launches[dom]),
+                mean_launch_us=round(ms[dom] * 1e3 / max(1, launches[dom]), 2),
+                bytes_per_launch=round(kbytes[dom] / max(1, launches[dom])),
+                timed_in="timed steps (HIP events on the solver's stream)")
+    return roof, kernels
+
+
+def ops_cold_warm(ctx, p, r: int, reps: int = 10, flush_bytes: int = 1 << 30):
+    """Forward map and adjoint product alone, FP32 and FP64, warm (back to
+    back) and cold (a 1 GiB write before each call).  Median of `reps`."""
+    import torch
+    from paper_2403_09133_amd.lorads import F32
+    dev = torch.device("cuda")
+    flush = torch.empty(flush_bytes // 4, dtype=torch.float32, device=dev)
+    out = {}
+    g = torch.Generator().manual_seed(11)
+    for dt in (torch.float32, torch.float64):
+        s = 4 if dt == torch.float32 else 8
+        U = torch.randn(p.n, r, generator=g, dtype=torch.float64).to(dev, dt)
+        V = torch.randn(p.n, r, generator=g, dtype=torch.float64).to(dev, dt)
+        w = torch.randn(p.m, generator=g, dtype=torch.float64).to(dev, dt)
+        z = torch.empty(p.m, dtype=dt, device=dev)
+        o = torch.empty_like(V)
+        if p.kind == "mc":
+            fwd_b = 8.0 * p.m + p.m * s + 2.0 * p.n * r * s
+            adj_b = 8.0 * p.m + p.m * s + 2.0 * p.n * r * s + p.n * (4 + s) + (p.n + 1) * 4
+        else:
+            fwd_b = p.m * (4 + s) + 2.0 * p.n * r * s + p.m * s
+            adj_b = p.m * (4 + 2 * s) + 2.0 * p.n * r * s + p.c_val.size * 2 * (4 + s) + (p.n + 1) * 4
+        ops = {"K1 forward A(UV^T)": (lambda: ctx.apply_A(U, V, z), fwd_b),
+               "K2 adjoint (C + A*(w))V": (lambda: ctx.apply_AT_V(w, V, o), adj_b)}
+        for name, (fn, nbytes) in ops.items():
+            fn()
+            torch.cuda.synchronize()
+            res = {}
+            for mode in ("warm", "cold"):
+                ts = []
+                for _ in range(reps):
+                    if mode == "cold":
+                        flush.fill_(1.0)
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    fn()
+                    e1.record()
+                    e1.synchronize()
+                    ts.append(e0.elapsed_time(e1) * 1e3)
+                us = float(np.median(ts))
+                res[mode] = dict(us=round(us, 2), gbs=round(nbytes / (us * 1e-6) / 1e9, 1),
+                                 frac=round(nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4))
+            out[f"{name} {'fp32' if s == 4 else 'fp64'}"] = dict(bytes=int(nbytes), **res)
+        del U, V, w, z, o
+    del flush
+    torch.cuda.empty_cache()
+    return dict(rank=r, reps=reps, flush="1 GiB fill before each cold call", **out)
+
+
+def batch_leg(count: int = 512, sequential: bool = True):
     """Batched form: `count` MaxCut SDPs, n ~ U{50..2000}, average degree ~ U[3, 20],
     +-1 weights, rank ceil(log2 n) each, in one persistent launch (workgroup size
-    autotuned), FP64 and FP32 CG; against `sample` instances solved one after the
-    other by the single-instance path, extrapolated to `count`."""
+    autotuned on short runs), FP64 and FP32 CG; against the same instances solved
+    one after the other by the single-instance path (measured, FP64)."""
     import sdpgen
     from paper_2403_09133_amd import Context, default_options
+    from paper_2403_09133_amd.params import family_params
     t = time.time()
     probs = sdpgen.batch_maxcut(count, 2000, 50, 2000, 3.0, 20.0, "pm1")
     U0 = [sdpgen.random_init_U(p.n, int(math.ceil(math.log2(p.n))), 2000 + i) for i, p in enumerate(probs)]
     t_gen = time.time() - t
-    from paper_2403_09133_amd.params import family_params
     pd = family_params("maxcut", 1000)
 
     def opts(**kw):
-        return default_options(r0=1, switch_tol=pd["switch_tol"], h=pd["h"], **kw)
+        return default_options(r0=1, **{**pd, **kw})
 
     out = dict(instances=count, sum_n=int(sum(p.n for p in probs)),
                sum_edges=int(sum(len(p.meta["edges"][0]) for p in probs)), gen_s=round(t_gen, 2))
     t = time.time()
     ctx = Context(probs)
     out["setup_s"] = round(time.time() - t, 2)
-    best, times = ctx.batch_autotune(U0, opts(max_admm_iter=30), (64, 128, 192, 256))
-    out["autotune"] = {"block": best, "ms_short_run": {k: round(v, 2) for k, v in times.items()}}
+    t = time.perf_counter()
+    best, times = ctx.batch_autotune(U0, opts(max_admm_iter=10, alm_outer_max=2), (64, 128, 256))
+    out["autotune"] = {"block": best, "s": round(time.perf_counter() - t, 2),
+                       "ms_short_run": {k: round(v, 2) for k, v in times.items()},
+                       "short_run": "2 ALM outer and 10 ADMM iterations per instance"}
     for name, prec in (("fp64", 0), ("fp32", 1)):
         t = time.perf_counter()
         res = ctx.admm_solve(U0, opts(precision=prec, batch_mode=1))
@@ -153,22 +323,23 @@ def batch_leg(count: int = 512, sample: int = 16):
         out[name] = dict(s=round(dt, 4), converged=int(sum(r["status"] == 0 for r in res)),
                          max_admm_iters=int(max(r["admm_iters"] for r in res)),
                          median_admm_iters=float(np.median([r["admm_iters"] for r in res])),
-                         max_kkt=float(max(r["kkt"] for r in res)))
-        print(f"[bench] batch {name}: {dt:.3f}s, {out[name]['converged']}/{count} converged",
-              file=sys.stderr, flush=True)
+                         max_kkt=float(max(r["kkt"] for r in res)), max_rank=int(max(r["rank"] for r in res)))
+        log(f"batch {name}: {dt:.3f}s, {out[name]['converged']}/{count} converged")
     ctx.close()
-    sub = probs[:sample]
-    ctx = Context(sub)
-    t = time.perf_counter()
-    res = ctx.admm_solve(U0[:sample], opts(batch_mode=2))
-    dt = time.perf_counter() - t
-    ctx.close()
-    share = sum(p.n for p in sub) / sum(p.n for p in probs)
-    out["sequential_sample"] = dict(instances=sample, s=round(dt, 3),
-                                    extrapolated_s=round(dt / share, 2),
-                                    note="first instances of the batch solved one after the other "
-                                         "(single-instance path, FP64); extrapolated by their share of sum n")
-    out["speedup_vs_sequential_fp64"] = round(out["sequential_sample"]["extrapolated_s"] / out["fp64"]["s"], 1)
+    if sequential:
+        t = time.perf_counter()
+        conv = 0
+        for i, p in enumerate(probs):
+            with Context(p) as one:
+                r = one.admm_solve([U0[i]], opts(batch_mode=2))[0]
+            conv += r["status"] == 0
+            if i % 64 == 63:
+                log(f"sequential {i + 1}/{count}: {time.perf_counter() - t:.1f}s")
+        dt = time.perf_counter() - t
+        out["sequential_fp64"] = dict(s=round(dt, 3), converged=int(conv),
+                                      note="every instance solved one after the other by the single-instance "
+                                           "path (context setup per instance included)")
+        out["speedup_vs_sequential_fp64"] = round(dt / out["fp64"]["s"], 1)
     return out
 
 
@@ -176,7 +347,7 @@ def learned_leg(count: int = 6):
     """Learned warm start (the shipped MaxCut network) against the cold start on
     `count` held-out graphs shaped like its training set (n ~ U{2000..5000},
     average degree ~ U[4, 16], +-1 weights), FP64 solves to eq. (stop) <= 1e-6
-    from the same random U0: mean time-to-KKT, ADMM iterations and the App. B gap."""
+    from the same random U0: time-to-KKT, ADMM iterations and the App. B gap."""
     from paper_2403_09133_amd import Context, warmstart as W
     from paper_2403_09133_amd.params import solver_options
     ws = W.WarmStart.load()
@@ -193,28 +364,27 @@ def learned_leg(count: int = 6):
             warm = ctx.admm_solve([U0], solver_options("maxcut", p.n, r0),
                                   init_lambda=[pr["lambda0"]])[0]
         rows.append((cold, warm))
-        print(f"[bench] learned leg n={p.n}: cold {cold['t_total']:.2f}s {cold['admm_iters']} it, "
-              f"learned {warm['t_total']:.2f}s {warm['admm_iters']} it", file=sys.stderr, flush=True)
-    mean = lambda k, i: float(np.mean([r[i][k] for r in rows]))
+        log(f"learned leg n={p.n}: cold {cold['t_total']:.2f}s {cold['admm_iters']} it, "
+            f"learned {warm['t_total']:.2f}s {warm['admm_iters']} it")
     col = lambda k, i: [r[i][k] for r in rows]
+    med = lambda k, i: float(np.median(col(k, i)))
     return dict(instances=count, predict_s=round(t_pred, 3),
+                cold_s=[round(v, 3) for v in col("t_total", 0)], learned_s=[round(v, 3) for v in col("t_total", 1)],
                 cold_admm=col("admm_iters", 0), learned_admm=col("admm_iters", 1),
                 cold_gap=[float(f"{g:.2e}") for g in col("gap", 0)],
                 learned_gap=[float(f"{g:.2e}") for g in col("gap", 1)],
-                caution="a solve that meets eq. (stop) after very few ADMM iterations at a large rho can be "
-                        "off by its App. B gap (listed); compare times only together with the gaps",
-                cold_mean_s=round(mean("t_total", 0), 3), learned_mean_s=round(mean("t_total", 1), 3),
-                cold_mean_admm=mean("admm_iters", 0), learned_mean_admm=mean("admm_iters", 1),
+                cold_median_s=round(med("t_total", 0), 3), learned_median_s=round(med("t_total", 1), 3),
                 cold_converged=int(sum(r[0]["status"] == 0 for r in rows)),
                 learned_converged=int(sum(r[1]["status"] == 0 for r in rows)),
-                max_gap=float(max(max(abs(r[0]["gap"]), abs(r[1]["gap"])) for r in rows)),
-                note="held-out evaluation over 48 graphs: profiles/warmstart_maxcut_c5a_eval.md")
+                gaps_above_1e_6=int(sum(abs(r[i]["gap"]) > 1e-6 for r in rows for i in (0, 1))),
+                note="medians with every solve's App. B gap; held-out evaluation: "
+                     "profiles/warmstart_maxcut_c5a_eval.md")
 
 
 def ops_profile(key: str, reps: int):
     """Operator calls only: REPS x (forward map, adjoint product, 20-iteration CG
-    solve) in FP32 at r0 columns, then one 256 MiB device-to-device copy whose
-    known size calibrates the HBM byte counters."""
+    solve) in FP32 at the initial rank, then one 256 MiB device-to-device copy
+    whose known size calibrates the HBM byte counters."""
     import torch
     import sdpgen
     from paper_2403_09133_amd import Context
@@ -233,7 +403,7 @@ def ops_profile(key: str, reps: int):
         ctx.apply_AT_V(z, V, out)
         ctx.cg_solve(V, out, X.zero_(), 2.0, 1.5, 0.0, 20)
         torch.cuda.synchronize()
-        print(f"[bench] ops rep {i} done", file=sys.stderr, flush=True)
+        log(f"ops rep {i} done")
     calibration_copy()
     ctx.close()
 
@@ -246,7 +416,57 @@ def calibration_copy():
     b = torch.ones_like(a)
     a.copy_(b)
     torch.cuda.synchronize()
-    print(f"[bench] copy of {a.numel() * 4} bytes done", file=sys.stderr, flush=True)
+    log(f"copy of {a.numel() * 4} bytes done")
+
+
+def workload_leg(key, steps, warmup, prec, with_fp64=True, with_ops=True):
+    """Timed solves of one workload: the FP32-CG (or given) form with its
+    roofline, the FP64 form with its roofline, and the operators alone."""
+    import torch
+    import sdpgen
+    from paper_2403_09133_amd import Context
+    t = time.time()
+    p = sdpgen.config_instance(key)
+    t_gen = time.time() - t
+    r0 = initial_rank(p)
+    U0 = sdpgen.random_init_U(p.n, r0, 3)
+    log(f"{key}: n={p.n} m={p.m} r0={r0} (generated in {t_gen:.1f}s)")
+    t = time.time()
+    ctx = Context(p)
+    torch.cuda.synchronize()
+    t_setup = time.time() - t
+    info = ctx.problem_info()
+    log(f"setup {t_setup:.2f}s {info}")
+    results, wall = timed_solves(ctx, p, U0, r0, prec, steps, warmup)
+    op_bytes = sum(r["op_bytes"] for r in results)
+    roof, kernels = roofline_of(results, key, info["structure"], prec)
+    last = results[-1]
+    leg = dict(p=p, r0=r0, wall=wall, value=op_bytes / wall / 1e9, roofline=roof, kernels=kernels,
+               setup_s=round(t_setup, 3), structure=info["structure"],
+               solve=dict(status=last["status"], kkt=last["kkt"], obj=last["obj"], pinf=last["pinf"],
+                          dinf=last["dinf"], gap=last["gap"], rank=last["rank"],
+                          admm_iters=last["admm_iters"], cg_iters=last["cg_iters"],
+                          alm_outer=last["alm_outer"], alm_inner=last["alm_inner"],
+                          rank_growths=last["rank_growths"], t_phase1=round(last["t_phase1"], 4),
+                          t_phase2=round(last["t_phase2"], 4)))
+    if p.kind == "mc":
+        from paper_2403_09133_amd.report import completion_recovery_error_sampled
+        U, V, lam = ctx.get_solution(0, last["rank"])
+        leg["mc_recovery_error"] = dict(
+            sampled_1e6_cells=completion_recovery_error_sampled(0.5 * (U + V), p.meta["L"], p.meta["R"]),
+            note="||U1 U2^T - M||_F / ||M||_F on 10^6 uniformly drawn cells")
+    if with_fp64:
+        r64s, wall64 = timed_solves(ctx, p, U0, r0, 0, 1, 0)
+        r64 = r64s[0]
+        roof64, kern64 = roofline_of(r64s, key, info["structure"], 0)
+        leg["fp64"] = dict(s=round(wall64, 4), status=r64["status"], kkt=r64["kkt"], obj=r64["obj"],
+                           admm_iters=r64["admm_iters"], cg_iters=r64["cg_iters"], roofline=roof64,
+                           kernels=kern64)
+        leg["obj_rel_diff_vs_fp64"] = abs(last["obj"] - r64["obj"]) / max(1.0, abs(r64["obj"]))
+    if with_ops:
+        leg["ops_cold_warm"] = ops_cold_warm(ctx, p, last["rank"])
+    ctx.close()
+    return leg
 
 
 def main():
@@ -254,14 +474,19 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="mc_10000", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="mc_20000", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solve")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the second completion workload")
+    ap.add_argument("--no-ops", action="store_true", help="skip the cold / warm operator timings")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form leg")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="skip the one-at-a-time solve of the 512 batched instances")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-warm-start leg")
+    ap.add_argument("--fp64-only", action="store_true", help="time the plain FP64 form in the timed steps")
     ap.add_argument("--ops-profile", type=int, default=0, metavar="REPS",
                     help="only run REPS applications of each operator at the workload's size (FP32, "
-                         "r0 columns) and a 256 MiB device copy, for hardware-counter runs")
+                         "initial rank) and a 256 MiB device copy, for hardware-counter runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a 256 MiB device copy (byte-counter calibration in counter runs)")
     args = ap.parse_args()
@@ -271,137 +496,70 @@ def main():
         sys.exit(2)
 
     import torch
-
-    import sdpgen
-    from paper_2403_09133_amd import Context
-
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
-    key, prec, desc = WORKLOADS[args.workload]
     if args.ops_profile:
-        ops_profile(key, args.ops_profile)
+        ops_profile(args.workload, args.ops_profile)
         return
-    t = time.time()
-    p = sdpgen.config_instance(key)
-    t_gen = time.time() - t
-    r0 = initial_rank(p)
-    U0 = sdpgen.random_init_U(p.n, r0, 3)
-    print(f"[bench] {args.workload}: n={p.n} m={p.m} r0={r0} (generated in {t_gen:.1f}s)", file=sys.stderr, flush=True)
-    t = time.time()
-    ctx = Context(p)
-    torch.cuda.synchronize()
-    t_setup = time.time() - t
-    print(f"[bench] setup {t_setup:.2f}s {ctx.problem_info()}", file=sys.stderr, flush=True)
-
-    for i in range(args.warmup):
-        res = ctx.admm_solve([U0], lib_options(p, r0, prec))[0]
-        print(f"[bench] warmup {i}: {res['t_total']:.3f}s status {res['status']} kkt {res['kkt']:.2e}",
-              file=sys.stderr, flush=True)
-
-    results = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        # profile 2: the CG operator's launches carry their own HIP events; the
-        # other launches run unrecorded (their classes are timed below)
-        res = ctx.admm_solve([U0], lib_options(p, r0, prec, profile=2))[0]
-        results.append(res)
-        print(f"[bench] step {i}: {res['t_total']:.3f}s status {res['status']} kkt {res['kkt']:.2e} "
-              f"obj {res['obj']:.10g} admm {res['admm_iters']} cg {res['cg_iters']}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    op_bytes = sum(r["op_bytes"] for r in results)
-    value = op_bytes / wall / 1e9
-
-    # every kernel class timed on one more solve after the timed region; the
-    # dominant class's figures come from the timed steps (live HIP-event
-    # timings) when it is the one timed there
-    names = list(KERNEL_CLASSES)
-    K = len(names)
-    full = ctx.admm_solve([U0], lib_options(p, r0, prec, profile=1))[0]
-    ms = [full["prof_ms"][k] for k in range(K)]
-    launches = [full["prof_launches"][k] for k in range(K)]
-    kbytes = [full["prof_bytes"][k] for k in range(K)]
-    dom = int(np.argmax(ms))
-    kernels = {names[k]: dict(launches=int(launches[k]), total_ms=round(ms[k], 3),
-                              mean_us=round(ms[k] * 1e3 / max(1, launches[k]), 2),
-                              gbs=round(kbytes[k] / (ms[k] * 1e-3) / 1e9, 1) if ms[k] > 0 else None)
-               for k in range(K)}
-    timed_live = dom == 0
-    if timed_live:
-        ms = [sum(r["prof_ms"][k] for r in results) for k in range(K)]
-        launches = [sum(r["prof_launches"][k] for r in results) for k in range(K)]
-        kbytes = [sum(r["prof_bytes"][k] for r in results) for k in range(K)]
-    else:
-        print(f"[bench] dominant class {names[dom]} is not the one timed in the timed steps; "
-              "its figures come from the extra profiled solve", file=sys.stderr, flush=True)
-    achieved = kbytes[dom] / (ms[dom] * 1e-3) / 1e9 if ms[dom] > 0 else 0.0
-    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4),
-                    traffic=recorded_traffic(KERNEL_CLASSES[names[dom]]),
-                    kernel=names[dom], symbol=KERNEL_CLASSES[names[dom]], launches=int(launches[dom]),
-                    mean_launch_us=round(ms[dom] * 1e3 / max(1, launches[dom]), 2),
-                    bytes_per_launch=round(kbytes[dom] / max(1, launches[dom])),
-                    timed_in="timed steps" if timed_live else "extra profiled solve")
-
-    last = results[-1]
-    extra = dict(
-        time_to_kkt_s={"fp32_cg": round(wall / args.steps, 4)},
-        solve=dict(status=last["status"], kkt=last["kkt"], obj=last["obj"], pinf=last["pinf"],
-                   dinf=last["dinf"], gap=last["gap"], rank=last["rank"], admm_iters=last["admm_iters"],
-                   cg_iters=last["cg_iters"], alm_outer=last["alm_outer"], alm_inner=last["alm_inner"],
-                   t_phase1=round(last["t_phase1"], 4), t_phase2=round(last["t_phase2"], 4)),
-        kernels=kernels, setup_s=round(t_setup, 3),
-    )
-    if p.kind == "mc":
-        from paper_2403_09133_amd.report import (completion_recovery_error,
-                                                 completion_recovery_error_sampled)
-        U, V, lam = ctx.get_solution(0, last["rank"])
-        Uh = 0.5 * (U + V)
-        extra["mc_recovery_error"] = dict(
-            gram_identity=completion_recovery_error(Uh, p.meta["L"], p.meta["R"]),
-            sampled_1e6_cells=completion_recovery_error_sampled(Uh, p.meta["L"], p.meta["R"]),
-            note="||U1 U2^T - M||_F / ||M||_F; the Gram identity resolves about 1e-8, the sample is exact per cell")
-    if not args.no_fp64:
-        t = time.perf_counter()
-        r64 = ctx.admm_solve([U0], lib_options(p, r0, 0))[0]
-        extra["time_to_kkt_s"]["fp64"] = round(time.perf_counter() - t, 4)
-        extra["fp64_solve"] = dict(status=r64["status"], kkt=r64["kkt"], obj=r64["obj"],
-                                   admm_iters=r64["admm_iters"], cg_iters=r64["cg_iters"])
-        extra["fp32_vs_fp64_obj_rel"] = abs(last["obj"] - r64["obj"]) / max(1.0, abs(r64["obj"]))
-    ctx.close()
-    if args.copy_calibration:
-        calibration_copy()
-
+    prec = 0 if args.fp64_only else 1
+    leg = workload_leg(args.workload, args.steps, args.warmup, prec, with_fp64=not args.no_fp64,
+                       with_ops=not args.no_ops)
+    p = leg["p"]
+    tkey = "fp32_cg" if prec == 1 else "fp64"
     line = {
         "metric": "A(UV^T)+A^*(y)V as HBM GB/s; time-to-1e-6 KKT residual, FP32/batched vs FP64",
-        "value": round(value, 2),
+        "value": round(leg["value"], 2),
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "ms_per_step": round(leg["wall"] / args.steps * 1e3, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64" if prec == 1 else "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "description": desc, "n_X": p.n, "m": p.m, "r0": r0,
-                   "kkt_tol": 1e-6},
-        "roofline": roofline,
+        "config": {"workload": args.workload, "description": WORKLOADS[args.workload], "n_X": p.n, "m": p.m,
+                   "r0": leg["r0"], "kkt_tol": 1e-6},
+        "roofline": leg["roofline"],
     }
+    if "fp64" in leg:
+        line["roofline_fp64"] = leg["fp64"]["roofline"]
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(p, r0)
-    line.update(extra)
+        line["cpu_baseline"] = cpu_baseline(p, leg["r0"])
+    line["time_to_kkt_s"] = {tkey: round(leg["wall"] / args.steps, 4)}
+    if "fp64" in leg:
+        line["time_to_kkt_s"]["fp64"] = leg["fp64"]["s"]
+        line["obj_rel_diff_vs_fp64"] = leg["obj_rel_diff_vs_fp64"]
+    line["solve"] = leg["solve"]
+    line["kernels"] = leg["kernels"]
+    if "fp64" in leg:
+        line["fp64_solve"] = {k: v for k, v in leg["fp64"].items() if k != "roofline"}
+    line["setup_s"] = leg["setup_s"]
+    if "mc_recovery_error" in leg:
+        line["mc_recovery_error"] = leg["mc_recovery_error"]
+    if "ops_cold_warm" in leg:
+        line["ops_cold_warm"] = {args.workload: leg["ops_cold_warm"]}
+    if not args.no_secondary and args.workload != "mc_10000":
+        sec = workload_leg("mc_10000", 2, 1, prec, with_fp64=False, with_ops=not args.no_ops)
+        line["secondary"] = {"mc_10000": dict(ms_per_step=round(sec["wall"] / 2 * 1e3, 3),
+                                              value=round(sec["value"], 2), roofline=sec["roofline"],
+                                              solve=sec["solve"], kernels=sec["kernels"])}
+        if "ops_cold_warm" in sec:
+            line.setdefault("ops_cold_warm", {})["mc_10000"] = sec["ops_cold_warm"]
     if not args.no_learned:
         line["learned_warm_start"] = learned_leg()
-        line["time_to_kkt_s"]["learned_fp64_mean"] = line["learned_warm_start"]["learned_mean_s"]
-        line["time_to_kkt_s"]["cold_fp64_mean_same_instances"] = line["learned_warm_start"]["cold_mean_s"]
+        line["time_to_kkt_s"]["learned_fp64_median"] = line["learned_warm_start"]["learned_median_s"]
+        line["time_to_kkt_s"]["cold_fp64_median_same_instances"] = line["learned_warm_start"]["cold_median_s"]
     if not args.no_batch:
-        line["batched_maxcut"] = batch_leg()
+        line["batched_maxcut"] = batch_leg(sequential=not args.no_sequential)
         line["time_to_kkt_s"]["batched_512_fp64"] = line["batched_maxcut"]["fp64"]["s"]
         line["time_to_kkt_s"]["batched_512_fp32"] = line["batched_maxcut"]["fp32"]["s"]
+        if "sequential_fp64" in line["batched_maxcut"]:
+            line["time_to_kkt_s"]["sequential_512_fp64"] = line["batched_maxcut"]["sequential_fp64"]["s"]
+    if args.copy_calibration:
+        calibration_copy()
     print(json.dumps(line), flush=True)
 
 

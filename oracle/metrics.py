@@ -62,3 +62,14 @@ def mc_recovery_error(prob, U, block: int = 1024):
         num += float(np.sum(E * E))
         den += float(np.sum(M * M))
     return float(np.sqrt(num / den))
+
+
+def gram(A, B, block: int = 4096):
+    """G = A^T B for tall factors A (n x ra), B (n x rb): the sum over rows j of
+    the outer products A_j^T B_j, a block of rows at a time."""
+    A = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    G = np.zeros((A.shape[1], B.shape[1]))
+    for j0 in range(0, A.shape[0], block):
+        G += A[j0:j0 + block].T @ B[j0:j0 + block]
+    return G

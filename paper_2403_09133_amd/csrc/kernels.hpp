@@ -790,7 +790,8 @@ __device__ __forceinline__ void linesearch_partials(int bid, int nblk, int m,
 // partials of <CD, U> and <CD, D> over the first r columns of n rows (stride
 // ld; the element order and grouping of dots3_kernel with rg blocks) at
 // part_f + t * rg, blocks below gl the m-vector sums of linesearch_partials
-// with gl blocks at part_m.  With cdiag (a diagonal C by row), each element
+// with gl blocks at part_m (with lsp, those sums from the nls block partials
+// the fused line-search map left, summed in a fixed order).  With cdiag (a diagonal C by row), each element
 // of C D is formed here as the PAIR adjoint's C part forms it (c D + 0: the
 // product, then the other lane groups' zero sums) instead of read from CD.
 [[maybe_unused]] static __global__ void __launch_bounds__(kBlock) linesearch_all(
@@ -798,7 +799,8 @@ __device__ __forceinline__ void linesearch_partials(int bid, int nblk, int m,
     const double* __restrict__ D, int rg, double* __restrict__ part_f, int m,
     const double* __restrict__ z, const double* __restrict__ b, const double* __restrict__ p1,
     const double* __restrict__ p2, const double* __restrict__ lam, int gl,
-    double* __restrict__ part_m, const double* __restrict__ cdiag) {
+    double* __restrict__ part_m, const double* __restrict__ cdiag,
+    const double* __restrict__ lsp, int nls) {
   __shared__ double sh[kBlock / 64];
   const int bid = blockIdx.x;
   if (bid < rg) {  // uniform over the block
@@ -815,7 +817,20 @@ __device__ __forceinline__ void linesearch_partials(int bid, int nblk, int m,
     const double b1 = block_sum(s1, sh);
     if (threadIdx.x == 0) part_f[rg + bid] = b1;
   }
-  if (bid < gl) linesearch_partials(bid, gl, m, z, b, p1, p2, lam, part_m, sh);
+  if (bid < gl) {
+    if (lsp) {
+      // the seven sums already formed per block of the fused line-search map
+      // (nls partials each): block bid adds partials bid, bid + gl, ...
+      for (int t = 0; t < 7; ++t) {
+        double v = 0.0;
+        for (int j = bid + (int)threadIdx.x * gl; j < nls; j += gl * kBlock) v += lsp[(size_t)t * nls + j];
+        const double bs = block_sum(v, sh);
+        if (threadIdx.x == 0) part_m[(size_t)t * gl + bid] = bs;
+      }
+    } else {
+      linesearch_partials(bid, gl, m, z, b, p1, p2, lam, part_m, sh);
+    }
+  }
 }
 
 // sc[slot] = 2 <CD, U>, sc[slot + 1] = <CD, D>, sc[slot + 2 + t] = line-search

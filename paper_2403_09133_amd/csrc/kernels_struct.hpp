@@ -258,6 +258,101 @@ __global__ void __launch_bounds__(kBlock) k1_pair_v2(
   }
 }
 
+// The exact line search of Phase I in one pass (PAIR, FP64, two columns per
+// lane): the loop of k1_pair_v2 MODE 3, which collects a chunk's
+//   p1_i = A(U D^T + D U^T)_i = 2 a (<U_j, D_k> + <U_k, D_j>),
+//   p2_i = A(D D^T)_i = 2 a <D_j, D_k>
+// in the group's LDS slots (the same expressions, so the same values), ends by
+// reading z, b and lam of the chunk's constraints as contiguous runs and adding
+// the seven sums of the quartic (the order of linesearch_partials):
+//   p2.p2, p1.p2, p1.p1, p0.p2, p0.p1, lam.p1, lam.p2,   p0 = z - b.
+// Nothing m-sized is written: each block leaves its seven partials at
+// part[t * gridDim.x + block].  Groups of at least 4 lanes (GV >= 4).
+template <int GV>
+__global__ void __launch_bounds__(kBlock) k1_pair_ls(
+    int nchunks, const int* __restrict__ chunk_row, const int* __restrict__ chunk_start,
+    const int* __restrict__ rptr, const int* __restrict__ pk, const double* __restrict__ pcoef,
+    double pair_coef, const double* __restrict__ U, const double* __restrict__ D, int r, int ld,
+    const double* __restrict__ z, const double* __restrict__ b, const double* __restrict__ lam,
+    double* __restrict__ part) {
+  static_assert(GV >= 4, "the chunk results are staged per group");
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  __shared__ double s1[(kBlock / GV) * kPairChunk];
+  __shared__ double s2[(kBlock / GV) * kPairChunk];
+  __shared__ double sh[kBlock / 64];
+  const int chunk = (blockIdx.x * kBlock + threadIdx.x) / GV;
+  const int lane = threadIdx.x & (GV - 1);
+  const int gslot = (threadIdx.x / GV) * kPairChunk;
+  double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (chunk < nchunks) {
+    const int row = chunk_row[chunk];
+    const int i0 = chunk_start[chunk], i1 = min(i0 + kPairChunk, rptr[row + 1]);
+    const int c0 = 2 * lane;
+    const bool on0 = c0 < r, on1 = c0 + 1 < r;
+    const d2 uj = *reinterpret_cast<const d2*>(U + row * ld + c0);
+    const d2 dj = *reinterpret_cast<const d2*>(D + row * ld + c0);
+    for (int i = i0; i < i1; i += kUnroll) {
+      const int cnt = min(kUnroll, i1 - i);
+      int k[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) k[u] = u < cnt ? pk[i + u] : row;
+      d2 dk[kUnroll], uk[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        dk[u] = *reinterpret_cast<const d2*>(D + k[u] * ld + c0);
+        uk[u] = *reinterpret_cast<const d2*>(U + k[u] * ld + c0);
+      }
+      double d[kUnroll], dd[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        double sa = 0.0, sb = 0.0, qa = 0.0, qb = 0.0;
+        if (on0) {
+          sa += uj[0] * dk[u][0] + uk[u][0] * dj[0];
+          qa += dj[0] * dk[u][0];
+        }
+        if (on1) {
+          sb += uj[1] * dk[u][1] + uk[u][1] * dj[1];
+          qb += dj[1] * dk[u][1];
+        }
+        d[u] = sa + sb;
+        dd[u] = qa + qb;
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) d[u] = group_sum<GV>(d[u]);
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) dd[u] = group_sum<GV>(dd[u]);
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        if (lane == (u & (GV - 1)) && u < cnt) {
+          const int id = i + u;
+          const double a = pcoef ? pcoef[id] : pair_coef;
+          s1[gslot + (id - i0)] = 2.0 * (d[u] * a);
+          s2[gslot + (id - i0)] = 2.0 * a * dd[u];
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int q = lane; q < i1 - i0; q += GV) {
+      const double p1 = s1[gslot + q], p2 = s2[gslot + q];
+      const double p0 = z[i0 + q] - b[i0 + q], l = lam[i0 + q];
+      acc[0] += p2 * p2;
+      acc[1] += p1 * p2;
+      acc[2] += p1 * p1;
+      acc[3] += p0 * p2;
+      acc[4] += p0 * p1;
+      acc[5] += l * p1;
+      acc[6] += l * p2;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 7; ++t) {
+    const double bs = block_sum(acc[t], sh);
+    if (threadIdx.x == 0) part[(size_t)t * gridDim.x + blockIdx.x] = bs;
+  }
+}
+
 // ===========================================================================
 // K2 DIAG: out_j = out_scale (c_scale (C V)_j + (sum_{i on row j} w_i a_i) V_j)
 // ===========================================================================

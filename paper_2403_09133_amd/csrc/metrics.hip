@@ -130,6 +130,37 @@ static double tridiag_min(const std::vector<double>& a, const std::vector<double
   return 0.5 * (lo + hi);
 }
 
+// Residual bound of the smallest Ritz pair: beta_k |s_k|, with s_k the last
+// component of the unit eigenvector of T for theta (inverse iteration on the
+// tridiagonal, shifted just below theta).  The smallest eigenvalue of the
+// operator lies within this bound of a Ritz value.
+static double ritz_residual(const std::vector<double>& a, const std::vector<double>& b, int k,
+                            double theta, double beta) {
+  if (k == 1) return std::fabs(beta);
+  double scale = 0.0;
+  for (int i = 0; i < k; ++i) scale = std::max(scale, std::fabs(a[i]) + 2.0 * (i < k - 1 ? std::fabs(b[i]) : 0.0));
+  const double shift = theta - 1e-13 * std::max(1.0, scale);
+  std::vector<double> x(k, 1.0), d(k), u(k), rhs(k);
+  for (int it = 0; it < 3; ++it) {
+    // Thomas algorithm on (T - shift I) x_new = x
+    for (int i = 0; i < k; ++i) {
+      const double sub = i > 0 ? b[i - 1] : 0.0;
+      double di = a[i] - shift - (i > 0 ? sub * u[i - 1] : 0.0);
+      if (di == 0.0) di = 1e-300;
+      d[i] = di;
+      u[i] = i < k - 1 ? b[i] / di : 0.0;
+      rhs[i] = (x[i] - (i > 0 ? sub * rhs[i - 1] : 0.0)) / di;
+    }
+    for (int i = k - 1; i >= 0; --i) x[i] = rhs[i] - (i < k - 1 ? u[i] * x[i + 1] : 0.0);
+    double nrm = 0.0;
+    for (double v : x) nrm += v * v;
+    nrm = std::sqrt(nrm);
+    if (!(nrm > 0.0) || !std::isfinite(nrm)) return INFINITY;
+    for (double& v : x) v /= nrm;
+  }
+  return std::fabs(beta * x[k - 1]);
+}
+
 double dual_lambda_min(Problem& P, const double* lam, int max_steps, hipStream_t s) {
   const int n = P.n;
   const int kmax = std::max(2, std::min(max_steps, n));
@@ -144,7 +175,7 @@ double dual_lambda_min(Problem& P, const double* lam, int max_steps, hipStream_t
   read_slots(P, S_GEN, h, 1, s);
   axpby<double, double><<<gridn, 256, 0, s>>>(n, 0.0, Qb.p, 1.0 / std::sqrt(h[0]), Qb.p);
   std::vector<double> al, be;
-  double prev = INFINITY, theta = 0.0;
+  double theta = 0.0, anorm = 0.0;
   int k = 0;
   for (; k < kmax; ++k) {
     double* qk = Qb.p + (size_t)k * n;
@@ -164,11 +195,15 @@ double dual_lambda_min(Problem& P, const double* lam, int max_steps, hipStream_t
     al.push_back(ak);
     const double beta = std::sqrt(h[0]);
     theta = tridiag_min(al, be, k + 1);
-    if (k % 10 == 9) {
-      if (std::fabs(theta - prev) <= 1e-11 * std::max(1.0, std::fabs(theta))) { ++k; break; }
-      prev = theta;
+    anorm = std::max(anorm, std::fabs(ak) + beta + (k > 0 ? be[k - 1] : 0.0));
+    // stop once the smallest Ritz value is within 1e-12 of the operator's
+    // scale of an eigenvalue (checked every 5 steps), or on an invariant
+    // subspace
+    if (k % 5 == 4 && ritz_residual(al, be, k + 1, theta, beta) <= 1e-12 * std::max(1.0, anorm)) {
+      ++k;
+      break;
     }
-    if (!(beta > 1e-13 * std::max(1.0, std::fabs(h[1])))) { ++k; break; }
+    if (!(beta > 1e-13 * std::max(1.0, anorm))) { ++k; break; }
     be.push_back(beta);
     if (k + 1 < kmax)
       axpby<double, double><<<gridn, 256, 0, s>>>(n, 1.0 / beta, y.p, 0.0, Qb.p + (size_t)(k + 1) * n);

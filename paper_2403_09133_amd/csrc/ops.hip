@@ -88,6 +88,16 @@ static bool pair_v2_ok(const Problem& P, const void* U, const void* V, int r, in
     }                                                    \
   } while (0)
 
+// groups of G / 2 >= 4 lanes (the fused line search stages per group)
+#define LORADS_DISPATCH_LS(G, CALL)                      \
+  do {                                                   \
+    switch (G) {                                         \
+      case 8: { constexpr int GV = 4; CALL; } break;     \
+      case 16: { constexpr int GV = 8; CALL; } break;    \
+      default: { constexpr int GV = 16; CALL; } break;   \
+    }                                                    \
+  } while (0)
+
 // ---------------------------------------------------------------------------
 template <typename T>
 static void op_forward_impl(Problem& P, const T* U, const T* V, int r, int ld, T* z, double scale,
@@ -185,6 +195,25 @@ void op_forward_pair(Problem& P, const double* U, const double* D, int r, int ld
     }
     HIPCHK(hipGetLastError());
   });
+}
+
+// The fused line-search pass (PAIR, FP64 two-column layout): the seven sums
+// of the quartic as block partials in part (7 * ls_blocks doubles), nothing
+// m-sized written.  Returns false (nothing launched) where the layout does not
+// allow it; the caller then runs op_forward_pair and the m-vector sums.
+bool op_linesearch_pair(Problem& P, const double* U, const double* D, int r, int ld,
+                        const double* z, const double* lam, double* part, hipStream_t s) {
+  const int G = lane_group(r);
+  if (!pair_v2_ok(P, U, D, r, ld) || G < 8) return false;
+  if (rows_grid(P.nfchunks, G / 2) != ls_blocks(P, r)) fail(LORADS_EINVAL, "line-search grid mismatch");
+  check_pair_offsets(P, ld);
+  P.prof.run(3, bytes_linesearch_pair(P, r), s, [&] {
+    LORADS_DISPATCH_LS(G, (k1_pair_ls<GV><<<ls_blocks(P, r), kBlock, 0, s>>>(
+                              P.nfchunks, P.fchunk_row.p, P.fchunk_start.p, P.rptr.p, P.pk.p,
+                              P.pcoef.p, P.pair_coef, U, D, r, ld, z, P.b.p, lam, part)));
+    HIPCHK(hipGetLastError());
+  });
+  return true;
 }
 
 template <typename T>
@@ -362,6 +391,10 @@ double bytes_forward(const Problem& P, int r, int s) {
   return (double)P.a_nnz * (8 + s) + (double)(P.m + 1) * 4 + 2.0 * nr + (double)P.m * s;
 }
 
+double bytes_linesearch_pair(const Problem& P, int r) {
+  return (double)P.m * 8 + 3.0 * P.m * 8 + 2.0 * P.n * r * 8 + (P.pcoef.n ? (double)P.m * 8 : 0.0);
+}
+
 double bytes_adjoint(const Problem& P, int r, int s, bool with_c) {
   const double nr = (double)P.n * r * s;
   const double cbytes = with_c ? (double)P.cval.n * (4 + s) + (double)(P.n + 1) * 4 : 0.0;
@@ -485,7 +518,7 @@ void dual_update_slot(Problem& P, const double* z, double rho, double* lam, int 
 void linesearch_slots(Problem& P, int n, int r, int ld, const double* CD, const double* U,
                       const double* D, const double* z, const double* p1, const double* p2,
                       const double* lam, int slot, hipStream_t s, const double* part_gd,
-                      const double* cdiag, double* vals, int nread) {
+                      const double* cdiag, double* vals, int nread, const double* lsp, int nls) {
   const size_t N = (size_t)n * r;
   if (N >= ((size_t)1 << 32)) fail(LORADS_EINVAL, "factor too large for the line-search dots");
   const int rg = grid_for(N, kRedBlocks), gl = grid_for(P.m, kRedBlocks);
@@ -493,7 +526,7 @@ void linesearch_slots(Problem& P, int n, int r, int ld, const double* CD, const 
   double* part_f = P.part.p;
   double* part_m = P.part.p + 2 * rg;
   linesearch_all<<<std::max(rg, gl), kBlock, 0, s>>>((unsigned)N, r, ld, CD, U, D, rg, part_f, P.m, z,
-                                                     P.b.p, p1, p2, lam, gl, part_m, cdiag);
+                                                     P.b.p, p1, p2, lam, gl, part_m, cdiag, lsp, nls);
   if (part_gd && part_gd < part_m + (size_t)7 * gl)
     fail(LORADS_EINVAL, "descent-check partials overlap the line-search partials");
   if (rg > 2 * kBlock || gl > 2 * kBlock) fail(LORADS_EINVAL, "line-search partials exceed the finishing layout");

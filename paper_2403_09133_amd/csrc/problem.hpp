@@ -244,6 +244,20 @@ int op_cg(Problem& P, const T* W, int ldw, int r, int ld, const T* Pd, const T* 
 // U and D with row stride ld
 void op_forward_pair(Problem& P, const double* U, const double* D, int r, int ld, double* p1,
                      double* p2, hipStream_t s);
+// the fused line-search pass (PAIR): the seven m-vector sums of the quartic
+// (p0 = z - b, p1, p2 and lam, the order of linesearch_slots) as
+// 7 x ls_blocks(P) block partials in part, without writing p1 and p2; false
+// (nothing launched) where the two-column layout does not apply
+bool op_linesearch_pair(Problem& P, const double* U, const double* D, int r, int ld,
+                        const double* z, const double* lam, double* part, hipStream_t s);
+// grid of the fused line-search pass at rank r (one group of G/2 lanes per
+// chunk, 256 threads per block), i.e. its count of block partials
+inline int ls_blocks(const Problem& P, int r) {
+  int g = 1;
+  while (g < r && g < 64) g <<= 1;
+  const long long threads = (long long)P.nfchunks * std::max(1, g / 2);
+  return (int)std::max<long long>(1, (threads + kBlock - 1) / kBlock);
+}
 // gradient form for PAIR problems with a uniform coefficient:
 //   out = out_scale (C + A*(lam + rho (A(U U^T) - b))) U
 // with lam and b read per incident entry (refresh_inc_lam after lam changes);
@@ -265,6 +279,8 @@ double bytes_adjoint(const Problem& P, int r, int s, bool with_c);
 double bytes_cg_op(const Problem& P, int r, int s);
 double bytes_grad_pair(const Problem& P, int r);  // gradient form: forward + adjoint (FP64)
 double bytes_cprod(const Problem& P, int r, int s);  // C V alone: C's entries, V and the output
+// fused line-search pass: indices, z, b and lam once, U and D once (FP64)
+double bytes_linesearch_pair(const Problem& P, int r);
 
 // ---------------------------------------------------------------------------
 // reductions / small helpers
@@ -285,7 +301,8 @@ void dual_update_slot(Problem& P, const double* z, double rho, double* lam, int 
 void linesearch_slots(Problem& P, int n, int r, int ld, const double* CD, const double* U,
                       const double* D, const double* z, const double* p1, const double* p2,
                       const double* lam, int slot, hipStream_t s, const double* part_gd = nullptr,
-                      const double* cdiag = nullptr, double* vals = nullptr, int nread = 0);
+                      const double* cdiag = nullptr, double* vals = nullptr, int nread = 0,
+                      const double* lsp = nullptr, int nls = 0);
 template <typename TX, typename TY>
 void dot_to_slot(Problem& P, size_t N, const TX* X, const TY* Y, double scale, int slot, hipStream_t s);
 // the same for n x r factors stored with row stride ld (bit-identical to the

@@ -97,6 +97,7 @@ double gamma_of(const Problem& P, const lorads_options& o, double rho) {
 struct AlmState {
   int n, m, r, ld;
   DevBuf<double> G, Gn, D, Q, CD, p1, p2, Sn, Yn;
+  DevBuf<double> lsp;  // block partials of the fused line-search pass
   std::vector<DevBuf<double>> S, Y;
   // slot of sc holding <S, Y> of each pair buffer (it travels with the buffer)
   std::vector<int> sy;
@@ -122,6 +123,7 @@ static void alm_alloc(AlmState& A, int n, int m, int r, int ld, int mem, hipStre
     if (ld != r) b->zero(s);
   }
   A.p1.alloc(m); A.p2.alloc(m);
+
   A.S.resize(mem); A.Y.resize(mem);
   A.sy.resize(mem);
   for (int i = 0; i < mem; ++i) A.sy[i] = S_PAIRS + i;
@@ -303,14 +305,19 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
     // PAIR with a diagonal C: C D is formed inside the sums pass
     const double* cdiag =
         (P.structure == LORADS_STRUCT_PAIR && P.cdiag.n > 0) ? P.cdiag.p : nullptr;
+    // PAIR: the two maps and their seven m-vector sums in one pass (nothing
+    // m-sized written); otherwise the maps, then the sums
+    if (A.lsp.n < (size_t)7 * ls_blocks(P, r)) A.lsp.alloc((size_t)7 * ls_blocks(P, r));
     auto line_search = [&](int nread) {
-      op_forward_pair(P, U, A.D.p, r, F.ld, A.p1.p, A.p2.p, s);
+      const bool fused = op_linesearch_pair(P, U, A.D.p, r, F.ld, P.zbuf.p, P.lam.p, A.lsp.p, s);
+      if (!fused) op_forward_pair(P, U, A.D.p, r, F.ld, A.p1.p, A.p2.p, s);
       if (!cdiag)
         op_adjoint<double>(P, (const double*)nullptr, 1.0, A.D.p, r, F.ld, A.CD.p, F.ld, 1.0, s);
       // the two maps, and C D (a product with C alone)
       info.op_bytes += 2 * bytes_forward(P, r, 8) + bytes_cprod(P, r, 8);
       linesearch_slots(P, n, r, F.ld, A.CD.p, U, A.D.p, P.zbuf.p, A.p1.p, A.p2.p, P.lam.p,
-                       S_GEN + 1, s, part_gd, cdiag, h, nread);
+                       S_GEN + 1, s, part_gd, cdiag, h, nread, fused ? A.lsp.p : nullptr,
+                       fused ? ls_blocks(P, r) : 0);
     };
     // A step's curvature pair enters the memory at once, before its <S, Y>
     // is known on the host, so the next direction and line search are queued

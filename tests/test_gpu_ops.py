@@ -203,8 +203,24 @@ def test_gram_mfma(device, shape):
     Bd = torch.tensor(B, device=device)
     G = torch.zeros((ra, rb), dtype=torch.float64, device=device)
     gram(Ad, Bd, G)
-    ref = A.T @ B
+    ref = oracle.metrics.gram(A, B)
     assert np.linalg.norm(G.cpu().numpy() - ref) <= 1e-13 * n * np.linalg.norm(ref) / 10 + 1e-12
+
+
+@pytest.mark.parametrize("d", [1e-3, 0.3])
+def test_recovery_error_path_matches_oracle(device, d):
+    """The library's recovery error (Gram products on the device, expanded
+    norm) against the oracle's entry-by-entry definition, on factors whose
+    error is known: U1 = (1 + d) L + a small perturbation, U2 = R."""
+    from paper_2403_09133_amd.report import completion_recovery_error
+    p = sdpgen.mc_planted(700, 500, 5, 9, count=5000)
+    L, R = p.meta["L"], p.meta["R"]
+    rng = np.random.default_rng(3)
+    U = np.vstack([(1.0 + d) * L, R]) + 1e-4 * rng.standard_normal((p.n, 5))
+    ref = oracle.metrics.mc_recovery_error(p, U)
+    got = completion_recovery_error(U, L, R)
+    assert abs(ref - d) <= 0.05 * d
+    assert abs(got - ref) <= 1e-7 * ref, (got, ref)
 
 
 @pytest.mark.parametrize("name", ["diag_er200", "pair_mc_perm", "generic_small"])

@@ -58,7 +58,7 @@ def _oracle(name):
 def _lib_opts(p, r0, **kw):
     from paper_2403_09133_amd import default_options
     pd = paper_defaults(p.kind, p.n)
-    return default_options(r0=r0, switch_tol=pd["switch_tol"], h=pd["h"], **kw)
+    return default_options(r0=r0, **{**pd, **kw})
 
 
 @pytest.mark.parametrize("name", sorted(CASES))
@@ -193,3 +193,44 @@ def test_solve_lovasz_theta(device, name, precision):
     assert res["status"] == 0, res
     assert res["kkt"] < 1e-6
     assert abs(-res["obj"] - theta) <= 5e-6 * theta, (res["obj"], theta)
+
+
+# Rank growth (Sections 4.3 and 5.1): an inner solve that reaches
+# rank_grow_iters L-BFGS iterations raises the rank by 1.5 (capped), appending
+# columns from the counter-based normal stream.  A low trigger makes the
+# library and the oracle grow on the same iterations.  The completion case
+# starts at r = 5, whose Phase-I rows are padded to 8 columns (11 -> 16 after
+# the second growth), so the grown factor must be built from the compact rows.
+GROWTH = {
+    "mc_60x50": dict(r0=5, r_max=11, rank_grow_iters=4),
+    "maxcut_er200": dict(r0=4, r_max=9, rank_grow_iters=4),
+}
+
+
+@pytest.mark.parametrize("name", sorted(GROWTH))
+def test_rank_growth_matches_oracle(device, name):
+    from paper_2403_09133_amd import Context
+    p, _ = CASES[name]
+    g = GROWTH[name]
+    U0 = sdpgen.random_init_U(p.n, g["r0"], 3)
+    o = Options(**paper_defaults(p.kind, p.n), r_max=g["r_max"], rank_grow_iters=g["rank_grow_iters"])
+    ref = oracle.lorads.lorads(p, U0, o)
+    assert ref["phase1"]["growths"] >= 1 and ref["rank"] > g["r0"]
+    kw = dict(r_max=g["r_max"], rank_grow_iters=g["rank_grow_iters"])
+    with Context(p) as ctx:
+        res = ctx.admm_solve([U0], _lib_opts(p, g["r0"], **kw))[0]
+    assert res["status"] == 0 and res["kkt"] < 1e-6, res
+    assert res["rank_growths"] == ref["phase1"]["growths"]
+    assert res["rank"] == ref["rank"]
+    oobj = ref["metrics"]["obj"]
+    assert abs(res["obj"] - oobj) <= 1e-6 * max(1.0, abs(oobj)), (res["obj"], oobj)
+    if p.kind == "mc":
+        # stable case: the same state after a fixed number of ADMM iterations
+        K = max(1, ref["phase2"]["iters"] // 2)
+        o.max_admm_iter = K
+        refK = oracle.lorads.lorads(p, U0, o)
+        with Context(p) as ctx:
+            rK = ctx.admm_solve([U0], _lib_opts(p, g["r0"], max_admm_iter=K, **kw))[0]
+        assert rK["admm_iters"] == refK["phase2"]["iters"] == K
+        assert abs(rK["kkt"] - refK["phase2"]["kkt"]) <= 1e-5 * refK["phase2"]["kkt"]
+        assert abs(rK["obj"] - refK["metrics"]["obj"]) <= 1e-9 * max(1.0, abs(refK["metrics"]["obj"]))

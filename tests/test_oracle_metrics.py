@@ -7,6 +7,8 @@ block of X = U U^T against M = L R^T):
     d = 1e-3 and d = -0.5);
   * exact recovery gives 0; the error is invariant under U -> U Q (Q orthogonal);
   * brute force: the dense n1 x n2 difference at small sizes.
+Gram products: integer factors, whose products and sums are exact in FP64,
+against the entry-by-entry triple loop.
 Normals (Box-Muller on SplitMix64 uniforms): a Kolmogorov-Smirnov test against
 the standard normal distribution function of scipy (independent code), and the
 first element of a stream rebuilt from the published SplitMix64 outputs.
@@ -75,3 +77,15 @@ def test_normals_first_element_from_published_stream():
     u2 = (o2 >> 11) * 2.0 ** -53
     want = math.sqrt(-2.0 * math.log(u1)) * math.cos(2.0 * math.pi * u2)
     assert oracle.rng.normals(0, 0, 1)[0] == pytest.approx(want, rel=1e-15)
+
+
+@pytest.mark.parametrize("n,ra,rb,block", [(37, 3, 5, 8), (9, 1, 1, 4096), (200, 6, 2, 7)])
+def test_gram_integer_exact(n, ra, rb, block):
+    rng = np.random.default_rng(n)
+    A = rng.integers(-9, 10, (n, ra)).astype(np.float64)
+    B = rng.integers(-9, 10, (n, rb)).astype(np.float64)
+    want = np.zeros((ra, rb))
+    for i in range(ra):
+        for j in range(rb):
+            want[i, j] = sum(A[t, i] * B[t, j] for t in range(n))
+    assert np.array_equal(oracle.metrics.gram(A, B, block=block), want)
