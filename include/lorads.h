@@ -226,6 +226,26 @@ lorads_status lorads_cg_solve(lorads_ctx *ctx, int32_t prob, const void *W, doub
                               double tol, int32_t maxit, int32_t dtype, int32_t *iters,
                               double *relres, void *stream);
 
+/* lorads_cg_solve for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same CG, kernels and results, with the work buffers (the CG-layout copies
+ * of W, R and X, the direction and the operator output; for general
+ * constraints also one m-vector) placed in a static device workspace of
+ * 64 MiB that the library holds on each GPU it runs on until the process ends,
+ * instead of allocated.  The call allocates nothing; lorads_setup records the
+ * workspace of the current device and creates every buffer the call touches.
+ * Arguments, layout, ownership and blocking as lorads_cg_solve.  Errors:
+ * EINVAL when one call needs more than 64 MiB of workspace (about
+ * (6 n ld_cg) elements, ld_cg = r rounded up to 64 bytes for completion
+ * problems, r otherwise), ESTATE when the context was set up on another
+ * device.  Every call on a GPU uses that GPU's one workspace, which keeps the
+ * last call's contents (the call clears what must start at zero): calls that
+ * overlap on one GPU (other threads, other streams, other contexts) race. */
+lorads_status lorads_cg_solve_noalloc(lorads_ctx *ctx, int32_t prob, const void *W, double rho,
+                                      double gamma, const void *R, void *X, int32_t r, int32_t ld,
+                                      double tol, int32_t maxit, int32_t dtype, int32_t *iters,
+                                      double *relres, void *stream);
+
 /* Full two-phase solve (Algorithm 2) of every problem of the context; with
  * nprob > 1 all problems advance together in batched launches.  res: host
  * array of nprob results.  Blocks the host until done.  Returns the worst

@@ -137,7 +137,11 @@ lorads_status lorads_setup(const lorads_problem* probs, int32_t nprob, lorads_ct
         e.msg = "problem " + std::to_string(i) + ": " + e.msg;
         throw;
       }
+      // the pinned words the solver reads its scalars through, made here so
+      // that lorads_cg_solve_noalloc never allocates
+      ctx->probs.back()->hs.init();
     }
+    scratch_register_current_device();
   });
   if (st != LORADS_OK) {
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -283,6 +287,31 @@ lorads_status lorads_cg_solve(lorads_ctx* ctx, int32_t prob, const void* W, doub
     else
       cg_api<float>(P, (const float*)W, rho, gamma, (const float*)R, (float*)X, r, ld, tol, maxit,
                     s, iters, relres, &ok);
+  });
+  if (st == LORADS_OK && !ok) return LORADS_MAXITER;
+  return st;
+}
+
+lorads_status lorads_cg_solve_noalloc(lorads_ctx* ctx, int32_t prob, const void* W, double rho,
+                                      double gamma, const void* R, void* X, int32_t r, int32_t ld,
+                                      double tol, int32_t maxit, int32_t dtype, int32_t* iters,
+                                      double* relres, void* stream) {
+  bool ok = true;
+  lorads_status st = guarded(ctx, [&] {
+    Problem& P = get(ctx, prob);
+    check_factor(W, r, ld);
+    check_factor(R, r, ld);
+    check_factor(X, r, ld);
+    check_dtype(dtype);
+    if (!(rho >= 0.0) || !(gamma > 0.0)) fail(LORADS_EINVAL, "need rho >= 0 and gamma > 0");
+    if (!(tol >= 0.0) || maxit < 0) fail(LORADS_EINVAL, "need tol >= 0 and maxit >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    if (dtype == LORADS_F64)
+      cg_noalloc<double>(P, ctx->device, (const double*)W, rho, gamma, (const double*)R, (double*)X,
+                         r, ld, tol, maxit, s, iters, relres, &ok);
+    else
+      cg_noalloc<float>(P, ctx->device, (const float*)W, rho, gamma, (const float*)R, (float*)X, r,
+                        ld, tol, maxit, s, iters, relres, &ok);
   });
   if (st == LORADS_OK && !ok) return LORADS_MAXITER;
   return st;

@@ -37,4 +37,14 @@ double dual_lambda_min(Problem& P, const double* lam, int max_steps, hipStream_t
 void gram(const double* A, const double* B, int64_t n, int ra, int rb, int lda, int ldb,
           double* G, hipStream_t s);
 
+// The static workspace of lorads_cg_solve_noalloc (noalloc.hip): record its
+// address on the current device (once per device; called by lorads_setup),
+// the bytes one call needs, and the CG of lorads_cg_solve run in it on the
+// device `dev` the context was set up on.
+void scratch_register_current_device();
+size_t cg_noalloc_bytes(const Problem& P, int r, int elem);
+template <typename T>
+void cg_noalloc(Problem& P, int dev, const T* W, double rho, double gamma, const T* R, T* X, int r,
+                int ld, double tol, int maxit, hipStream_t s, int* iters, double* relres, bool* ok);
+
 }  // namespace lorads

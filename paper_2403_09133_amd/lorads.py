@@ -72,7 +72,8 @@ class Result_(C.Structure):
 
 EXPORTED = [
     "lorads_default_options", "lorads_setup", "lorads_problem_info", "lorads_apply_A",
-    "lorads_apply_AT_V", "lorads_cg_solve", "lorads_admm_solve", "lorads_get_solution",
+    "lorads_apply_AT_V", "lorads_cg_solve", "lorads_cg_solve_noalloc", "lorads_admm_solve",
+    "lorads_get_solution",
     "lorads_gram", "lorads_dual_lambda_min", "lorads_destroy", "lorads_last_error",
     "lorads_version", "lorads_batch_autotune",
     "lorads_gnn_param_count", "lorads_gnn_create", "lorads_gnn_set_params",
@@ -103,6 +104,7 @@ def load():
     lib.lorads_apply_AT_V.argtypes = [vp, i32, vp, dbl, vp, i32, i32, vp, i32, vp]
     lib.lorads_cg_solve.argtypes = [vp, i32, vp, dbl, dbl, vp, vp, i32, i32, dbl, i32, i32,
                                     C.POINTER(i32), C.POINTER(dbl), vp]
+    lib.lorads_cg_solve_noalloc.argtypes = lib.lorads_cg_solve.argtypes
     lib.lorads_admm_solve.argtypes = [vp, C.POINTER(Options_), C.POINTER(Result_)]
     lib.lorads_get_solution.argtypes = [vp, i32, vp, vp, vp]
     lib.lorads_gram.argtypes = [vp, vp, i64, i32, i32, i32, i32, vp, vp]
@@ -129,7 +131,7 @@ def load():
     lib.lorads_gnn_destroy.argtypes = [vp]
     lib.lorads_gnn_destroy.restype = None
     for name in ("lorads_setup", "lorads_problem_info", "lorads_apply_A", "lorads_apply_AT_V",
-                 "lorads_cg_solve", "lorads_admm_solve", "lorads_get_solution", "lorads_gram",
+                 "lorads_cg_solve", "lorads_cg_solve_noalloc", "lorads_admm_solve", "lorads_get_solution", "lorads_gram",
                  "lorads_dual_lambda_min", "lorads_batch_autotune", "lorads_gnn_create",
                  "lorads_gnn_set_params", "lorads_gnn_get_params", "lorads_gnn_load_graphs",
                  "lorads_gnn_set_targets", "lorads_gnn_forward", "lorads_gnn_loss_grad",
@@ -270,6 +272,18 @@ class Context:
                                                 _ptr(R), _ptr(X), r, ld, float(tol), int(maxit),
                                                 _dtype_code(W), C.byref(it), C.byref(rel),
                                                 _stream(stream)))
+        return dict(status=st, iters=it.value, relres=rel.value)
+
+    def cg_solve_noalloc(self, W, R, X, rho: float, gamma: float, tol: float, maxit: int,
+                         prob: int = 0, stream=None):
+        """cg_solve with the work buffers in the library's static workspace (no
+        device allocation)."""
+        r, ld = _factor_shape(W)
+        it, rel = C.c_int32(), C.c_double()
+        st = self._check(load().lorads_cg_solve_noalloc(self.h, prob, _ptr(W), float(rho), float(gamma),
+                                                        _ptr(R), _ptr(X), r, ld, float(tol), int(maxit),
+                                                        _dtype_code(W), C.byref(it), C.byref(rel),
+                                                        _stream(stream)))
         return dict(status=st, iters=it.value, relres=rel.value)
 
     def admm_solve(self, init_U: Sequence[np.ndarray], options: Options_,
