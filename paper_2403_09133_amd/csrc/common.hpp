@@ -99,6 +99,9 @@ static_assert(3 * kRedBlocks <= kLbfgsPartStride, "L-BFGS partial region too sma
 static_assert(9 * kRedBlocks <= 3 * kLbfgsPartStride, "line-search partials reach the descent-check array");
 static_assert(4 * kLbfgsPartStride <= kMaxPart, "partial-sum buffer too small");
 constexpr int kPairChunk = 32;     // PAIR forward map: constraints per work item
+// XCDs of the part: consecutive workgroups of a launch are dealt to them in
+// turn, so workgroup b runs on XCD b mod kXcds (each with its own L2)
+constexpr int kXcds = 8;
 
 inline int pow2_group(int r) {
   int g = 1;

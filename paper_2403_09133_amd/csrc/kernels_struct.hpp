@@ -166,10 +166,21 @@ __global__ void __launch_bounds__(kBlock) k1_pair(
 // (columns 2l and 2l + 1, exactly the first level of the G-lane tree), then the
 // remaining levels run over GV lanes, and every term is evaluated by the same
 // expression.  Needs rows aligned to 16 bytes (ld even) and r <= 2 GV.
+// Chunks come from the XCD lists: workgroup b serves list b mod kXcds, whose
+// partners all lie in one block of rows, so the partner rows one XCD gathers
+// stay in its L2.
+__device__ __forceinline__ int xchunk_of(const int* __restrict__ xoff, int GV) {
+  const int x = blockIdx.x % kXcds;
+  const int local = (blockIdx.x / kXcds) * (kBlock / GV) + (int)threadIdx.x / GV;
+  const int c = xoff[x] + local;
+  return c < xoff[x + 1] ? c : -1;
+}
+
 template <int GV, int MODE>
 __global__ void __launch_bounds__(kBlock) k1_pair_v2(
-    int nchunks, const int* __restrict__ chunk_row, const int* __restrict__ chunk_start,
-    const int* __restrict__ rptr, const int* __restrict__ pk, const double* __restrict__ pcoef,
+    const int* __restrict__ xoff, const int* __restrict__ chunk_row,
+    const int* __restrict__ chunk_start, const int* __restrict__ chunk_end,
+    const int* __restrict__ pk, const double* __restrict__ pcoef,
     double pair_coef, const double* __restrict__ U, const double* __restrict__ V, int r, int ld,
     double* __restrict__ z, double scale, const double* __restrict__ lam,
     const double* __restrict__ b, double rho, double* __restrict__ w) {
@@ -178,12 +189,12 @@ __global__ void __launch_bounds__(kBlock) k1_pair_v2(
   typedef double d2 __attribute__((ext_vector_type(2)));
   __shared__ double sz[kStage ? (kBlock / GV) * kPairChunk : 1];
   __shared__ double sw[(kStage && kTwo) ? (kBlock / GV) * kPairChunk : 1];
-  const int chunk = (blockIdx.x * kBlock + threadIdx.x) / GV;
+  const int chunk = xchunk_of(xoff, GV);
   const int lane = threadIdx.x & (GV - 1);
   const int gslot = (threadIdx.x / GV) * kPairChunk;
-  if (chunk >= nchunks) return;
+  if (chunk < 0) return;
   const int row = chunk_row[chunk];
-  const int i0 = chunk_start[chunk], i1 = min(i0 + kPairChunk, rptr[row + 1]);
+  const int i0 = chunk_start[chunk], i1 = chunk_end[chunk];
   const int c0 = 2 * lane;
   const bool on0 = c0 < r, on1 = c0 + 1 < r;
   const d2 uj = *reinterpret_cast<const d2*>(U + row * ld + c0);
@@ -259,7 +270,7 @@ __global__ void __launch_bounds__(kBlock) k1_pair_v2(
 }
 
 // The exact line search of Phase I in one pass (PAIR, FP64, two columns per
-// lane): the loop of k1_pair_v2 MODE 3, which collects a chunk's
+// lane, XCD chunk lists): the loop of k1_pair_v2 MODE 3, which collects a chunk's
 //   p1_i = A(U D^T + D U^T)_i = 2 a (<U_j, D_k> + <U_k, D_j>),
 //   p2_i = A(D D^T)_i = 2 a <D_j, D_k>
 // in the group's LDS slots (the same expressions, so the same values), ends by
@@ -270,8 +281,9 @@ __global__ void __launch_bounds__(kBlock) k1_pair_v2(
 // part[t * gridDim.x + block].  Groups of at least 4 lanes (GV >= 4).
 template <int GV>
 __global__ void __launch_bounds__(kBlock) k1_pair_ls(
-    int nchunks, const int* __restrict__ chunk_row, const int* __restrict__ chunk_start,
-    const int* __restrict__ rptr, const int* __restrict__ pk, const double* __restrict__ pcoef,
+    const int* __restrict__ xoff, const int* __restrict__ chunk_row,
+    const int* __restrict__ chunk_start, const int* __restrict__ chunk_end,
+    const int* __restrict__ pk, const double* __restrict__ pcoef,
     double pair_coef, const double* __restrict__ U, const double* __restrict__ D, int r, int ld,
     const double* __restrict__ z, const double* __restrict__ b, const double* __restrict__ lam,
     double* __restrict__ part) {
@@ -280,13 +292,13 @@ __global__ void __launch_bounds__(kBlock) k1_pair_ls(
   __shared__ double s1[(kBlock / GV) * kPairChunk];
   __shared__ double s2[(kBlock / GV) * kPairChunk];
   __shared__ double sh[kBlock / 64];
-  const int chunk = (blockIdx.x * kBlock + threadIdx.x) / GV;
+  const int chunk = xchunk_of(xoff, GV);
   const int lane = threadIdx.x & (GV - 1);
   const int gslot = (threadIdx.x / GV) * kPairChunk;
   double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  if (chunk < nchunks) {
+  if (chunk >= 0) {
     const int row = chunk_row[chunk];
-    const int i0 = chunk_start[chunk], i1 = min(i0 + kPairChunk, rptr[row + 1]);
+    const int i0 = chunk_start[chunk], i1 = chunk_end[chunk];
     const int c0 = 2 * lane;
     const bool on0 = c0 < r, on1 = c0 + 1 < r;
     const d2 uj = *reinterpret_cast<const d2*>(U + row * ld + c0);

@@ -110,8 +110,8 @@ static void op_forward_impl(Problem& P, const T* U, const T* V, int r, int ld, T
   } else if (P.structure == LORADS_STRUCT_PAIR && std::is_same<T, double>::value &&
              pair_v2_ok(P, U, V, r, ld)) {
     check_pair_offsets(P, ld);
-    LORADS_DISPATCH_V2(G, (k1_pair_v2<GV, 0><<<rows_grid(P.nfchunks, GV), kBlock, 0, s>>>(
-                              P.nfchunks, P.fchunk_row.p, P.fchunk_start.p, P.rptr.p, P.pk.p,
+    LORADS_DISPATCH_V2(G, (k1_pair_v2<GV, 0><<<xchunk_grid(P, GV), kBlock, 0, s>>>(
+                              P.xchunk_off.p, P.xchunk_row.p, P.xchunk_start.p, P.xchunk_end.p, P.pk.p,
                               P.pcoef.p, P.pair_coef, (const double*)U, (const double*)V, r, ld,
                               (double*)z, scale, nullptr, nullptr, 0.0, nullptr)));
   } else if (P.structure == LORADS_STRUCT_PAIR) {
@@ -154,8 +154,8 @@ static void op_forward_w_impl(Problem& P, const double* U, const double* V, int 
                              nullptr, 0)));
   } else if (pair_v2_ok(P, U, V, r, ld)) {
     check_pair_offsets(P, ld);
-    LORADS_DISPATCH_V2(G, (k1_pair_v2<GV, 1><<<rows_grid(P.nfchunks, GV), kBlock, 0, s>>>(
-                              P.nfchunks, P.fchunk_row.p, P.fchunk_start.p, P.rptr.p, P.pk.p,
+    LORADS_DISPATCH_V2(G, (k1_pair_v2<GV, 1><<<xchunk_grid(P, GV), kBlock, 0, s>>>(
+                              P.xchunk_off.p, P.xchunk_row.p, P.xchunk_start.p, P.xchunk_end.p, P.pk.p,
                               P.pcoef.p, P.pair_coef, U, V, r, ld, z, 1.0, lam, P.b.p, rho, w)));
   } else if (P.structure == LORADS_STRUCT_PAIR) {
     check_pair_offsets(P, ld);
@@ -183,9 +183,9 @@ void op_forward_pair(Problem& P, const double* U, const double* D, int r, int ld
     check_pair_offsets(P, ld);
     const int G = lane_group(r);
     if (pair_v2_ok(P, U, D, r, ld)) {
-      LORADS_DISPATCH_V2(G, (k1_pair_v2<GV, 3><<<rows_grid(P.nfchunks, GV), kBlock, 0, s>>>(
-                                P.nfchunks, P.fchunk_row.p, P.fchunk_start.p, P.rptr.p, P.pk.p,
-                                P.pcoef.p, P.pair_coef, U, D, r, ld, p1, 1.0, nullptr, nullptr,
+      LORADS_DISPATCH_V2(G, (k1_pair_v2<GV, 3><<<xchunk_grid(P, GV), kBlock, 0, s>>>(
+                                P.xchunk_off.p, P.xchunk_row.p, P.xchunk_start.p, P.xchunk_end.p,
+                                P.pk.p, P.pcoef.p, P.pair_coef, U, D, r, ld, p1, 1.0, nullptr, nullptr,
                                 0.0, p2)));
     } else {
       LORADS_DISPATCH_GK(G, r, (k1_pair<double, G, 3, KC><<<rows_grid(P.nfchunks, G), kBlock, 0, s>>>(
@@ -205,12 +205,12 @@ bool op_linesearch_pair(Problem& P, const double* U, const double* D, int r, int
                         const double* z, const double* lam, double* part, hipStream_t s) {
   const int G = lane_group(r);
   if (!pair_v2_ok(P, U, D, r, ld) || G < 8) return false;
-  if (rows_grid(P.nfchunks, G / 2) != ls_blocks(P, r)) fail(LORADS_EINVAL, "line-search grid mismatch");
+  if (xchunk_grid(P, G / 2) != ls_blocks(P, r)) fail(LORADS_EINVAL, "line-search grid mismatch");
   check_pair_offsets(P, ld);
   P.prof.run(3, bytes_linesearch_pair(P, r), s, [&] {
     LORADS_DISPATCH_LS(G, (k1_pair_ls<GV><<<ls_blocks(P, r), kBlock, 0, s>>>(
-                              P.nfchunks, P.fchunk_row.p, P.fchunk_start.p, P.rptr.p, P.pk.p,
-                              P.pcoef.p, P.pair_coef, U, D, r, ld, z, P.b.p, lam, part)));
+                              P.xchunk_off.p, P.xchunk_row.p, P.xchunk_start.p, P.xchunk_end.p,
+                              P.pk.p, P.pcoef.p, P.pair_coef, U, D, r, ld, z, P.b.p, lam, part)));
     HIPCHK(hipGetLastError());
   });
   return true;

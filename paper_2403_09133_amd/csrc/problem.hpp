@@ -178,6 +178,11 @@ struct Problem {
   // next chunk's start or the row's end
   DevBuf<int> fchunk_row, fchunk_start;
   int nfchunks = 0;
+  // XCD chunk lists of the two-column FP64 maps (row, first and last + 1
+  // constraint of each chunk; list x at [xchunk_off[x], xchunk_off[x + 1]),
+  // all of its partners in partner block x)
+  DevBuf<int> xchunk_row, xchunk_start, xchunk_end, xchunk_off;
+  int nxchunks = 0, xchunk_maxlen = 0;
   DevBuf<int> inc_ptr, inc_nb, inc_id;  // incident lists: row pointers, partner, internal id
   // uniform coefficient only: [lam, b] per incident entry (interleaved, 16
   // bytes), so the gradient form streams them instead of gathering w by id;
@@ -250,13 +255,19 @@ void op_forward_pair(Problem& P, const double* U, const double* D, int r, int ld
 // (nothing launched) where the two-column layout does not apply
 bool op_linesearch_pair(Problem& P, const double* U, const double* D, int r, int ld,
                         const double* z, const double* lam, double* part, hipStream_t s);
-// grid of the fused line-search pass at rank r (one group of G/2 lanes per
-// chunk, 256 threads per block), i.e. its count of block partials
+// grid of the two-column maps over the XCD chunk lists for groups of GV
+// lanes: kXcds x the blocks the longest list needs (block b serves list
+// b mod kXcds)
+inline int xchunk_grid(const Problem& P, int GV) {
+  const long long per = ((long long)P.xchunk_maxlen * GV + kBlock - 1) / kBlock;
+  return (int)std::max<long long>(kXcds, kXcds * std::max<long long>(1, per));
+}
+// grid of the fused line-search pass at rank r (groups of G/2 lanes), i.e. its
+// count of block partials
 inline int ls_blocks(const Problem& P, int r) {
   int g = 1;
   while (g < r && g < 64) g <<= 1;
-  const long long threads = (long long)P.nfchunks * std::max(1, g / 2);
-  return (int)std::max<long long>(1, (threads + kBlock - 1) / kBlock);
+  return xchunk_grid(P, std::max(1, g / 2));
 }
 // gradient form for PAIR problems with a uniform coefficient:
 //   out = out_scale (C + A*(lam + rho (A(U U^T) - b))) U

@@ -297,6 +297,57 @@ std::unique_ptr<Problem> ingest(const lorads_problem& p, hipStream_t s) {
       P->fchunk_row.upload(crow, s);
       P->fchunk_start.upload(cstart, s);
     }
+    {
+      // XCD chunk lists of the two-column FP64 maps: partner rows are cut into
+      // kXcds blocks of about m / kXcds constraints each (quantiles of the
+      // partner index); list x holds, row after row, the pieces of each row's
+      // run (sorted by partner) whose partners lie in block x, cut into near
+      // equal chunks of at most kPairChunk.  Workgroups b with b mod kXcds = x
+      // serve list x, so an XCD gathers partner rows from one block only.
+      std::vector<long long> cum(n + 1, 0);
+      for (int i = 0; i < m; ++i) ++cum[pk[i] + 1];
+      for (int k = 0; k < n; ++k) cum[k + 1] += cum[k];
+      std::vector<int> kb(kXcds + 1, n);
+      kb[0] = 0;
+      for (int x = 1; x < kXcds; ++x) {
+        const long long want = (long long)m * x / kXcds;
+        kb[x] = (int)(std::lower_bound(cum.begin(), cum.end(), want) - cum.begin());
+        kb[x] = std::max(kb[x], kb[x - 1]);
+      }
+      std::vector<int> xr[kXcds], xs[kXcds], xe[kXcds];
+      for (int j = 0; j < n; ++j) {
+        int i = rptr[j];
+        for (int x = 0; x < kXcds; ++x) {
+          int e = i;
+          while (e < rptr[j + 1] && pk[e] < kb[x + 1]) ++e;
+          const int len = e - i;
+          if (len > 0) {
+            const int pieces = (len + kPairChunk - 1) / kPairChunk;
+            for (int q = 0; q < pieces; ++q) {
+              xr[x].push_back(j);
+              xs[x].push_back(i + (int)((long long)len * q / pieces));
+              xe[x].push_back(i + (int)((long long)len * (q + 1) / pieces));
+            }
+          }
+          i = e;
+        }
+      }
+      std::vector<int> row, start, end, off(kXcds + 1, 0);
+      int maxlen = 0;
+      for (int x = 0; x < kXcds; ++x) {
+        off[x + 1] = off[x] + (int)xr[x].size();
+        maxlen = std::max(maxlen, (int)xr[x].size());
+        row.insert(row.end(), xr[x].begin(), xr[x].end());
+        start.insert(start.end(), xs[x].begin(), xs[x].end());
+        end.insert(end.end(), xe[x].begin(), xe[x].end());
+      }
+      P->xchunk_row.upload(row, s);
+      P->xchunk_start.upload(start, s);
+      P->xchunk_end.upload(end, s);
+      P->xchunk_off.upload(off, s);
+      P->nxchunks = (int)row.size();
+      P->xchunk_maxlen = maxlen;
+    }
     P->inc_ptr.upload(inc_ptr, s);
     P->inc_nb.upload(inc_nb, s);
     P->inc_id.upload(inc_id, s);
