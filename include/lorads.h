@@ -230,7 +230,8 @@ lorads_status lorads_cg_solve(lorads_ctx *ctx, int32_t prob, const void *W, doub
  * HIP graph capture, tight serving loops, harnesses that forbid allocation):
  * the same CG, kernels and results, with the work buffers (the CG-layout copies
  * of W, R and X, the direction and the operator output; for general
- * constraints also one m-vector) placed in a static device workspace of
+ * constraints also one m-vector; for completion factors whose interleaved rows
+ * exceed 4 MiB also 8 n ld_cg partial sums) placed in a static device workspace of
  * 64 MiB that the library holds on each GPU it runs on until the process ends,
  * instead of allocated.  The call allocates nothing; lorads_setup records the
  * workspace of the current device and creates every buffer the call touches.

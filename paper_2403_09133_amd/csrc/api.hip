@@ -239,6 +239,11 @@ void cg_api(Problem& P, const T* W, double rho, double gamma, const T* R, T* X, 
   Wd.alloc((size_t)P.n * ldw); Rd.alloc(N); Xd.alloc(N); Pd.alloc(N); Qd.alloc(N); td.alloc(P.m);
   Wd.zero(s); Rd.zero(s); Xd.zero(s); Pd.zero(s); Qd.zero(s);
   T* P2 = inter ? Wd.p + ldp : nullptr;
+  // per-XCD partials of the split CG operator when the factors exceed one L2
+  DevBuf<char> xparts;
+  const size_t xb = cg_xparts_bytes(P, ldp, (int)sizeof(typename OpAcc<T>::type));
+  if (xb) xparts.alloc(xb);
+  CgXpartsScope xs(P, xb ? xparts.p : nullptr);
   const int g = grid_for(N);
   copy_rows<T, T><<<g, kBlock, 0, s>>>(P.n, r, W, ld, Wd.p, ldw);
   copy_rows<T, T><<<g, kBlock, 0, s>>>(P.n, r, R, ld, Rd.p, ldp);

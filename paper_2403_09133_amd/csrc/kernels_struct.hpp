@@ -918,4 +918,162 @@ __global__ void __launch_bounds__(kBlock, (sizeof(T) == 4 ? 7 : 1)) kpair_cg_vec
   publish_partial(block_sum(pq, sh), part);
 }
 
+// ===========================================================================
+// The PAIR CG operator split by XCD (factor arrays larger than one XCD's L2):
+// workgroup b serves partner block x = b mod kXcds.  A wave takes one row's
+// incident entries whose partners lie in block x (the row's list is sorted by
+// partner, so they are the run inc_xptr[row (kXcds + 1) + x] ..
+// inc_xptr[row (kXcds + 1) + x + 1]) and writes that run's part of
+// rho^-1 (Q - gamma P) for the row, sum_e a^2 (<P_row, W_p> + <P_p, W_row>) W_p,
+// to xparts[(x n + row) ld + c]; an XCD thus gathers the [W | P] rows of one
+// block only.  Otherwise the computation of kpair_cg_vec (same staging,
+// buffer loads and per-group order within the run).  xcg_combine then forms
+// Q = gamma P + rho sum_x xparts[x] in block order and the partials of <P, Q>.
+// ===========================================================================
+template <typename T, int G>
+__global__ void __launch_bounds__(kBlock, (sizeof(T) == 4 ? 7 : 1)) kpair_cg_xvec(
+    int n, const int* __restrict__ inc_xptr, const int* __restrict__ inc_nb,
+    const int* __restrict__ inc_id, const T* __restrict__ pcoef, double pair_coef,
+    const T* __restrict__ WP, int ld, int r, typename OpAcc<T>::type* __restrict__ xparts,
+    const double* __restrict__ sc, int parity) {
+  using A = typename OpAcc<T>::type;
+  constexpr int VW = 16 / (int)sizeof(T);
+  constexpr int NG = 64 / G;
+  constexpr int CH = kPairStage;
+  constexpr int STEP = NG * kUnroll;
+  static_assert(CH % STEP == 0, "staging chunk must hold whole steps");
+  typedef T vec __attribute__((ext_vector_type(16 / sizeof(T))));
+  __shared__ int s_nb[kBlock / 64][CH];
+  __shared__ A s_cf[kBlock / 64][CH];
+  if (sc[S_DONE + parity] != 0.0) return;
+  const int wl = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int grp = wl / G, lane = wl & (G - 1);
+  const int x = blockIdx.x % kXcds;
+  const int row = (blockIdx.x / kXcds) * (kBlock / 64) + wid;
+  if (row >= n) return;  // wave-uniform; no block-wide synchronisation follows
+  const int ldw = 2 * ld;
+  const int c0 = lane * VW;
+  const int rowb = ldw * (int)sizeof(T);
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)WP, 0, n * rowb, kBufferRsrcWord3);
+  const int pofs = ld * (int)sizeof(T);
+  int* nbw = s_nb[wid];
+  A* cfw = s_cf[wid];
+  A acc[VW], pt[VW], vt[VW];
+  {
+    const vec w = *reinterpret_cast<const vec*>(WP + row * ldw + c0);
+    const vec p = *reinterpret_cast<const vec*>(WP + row * ldw + ld + c0);
+#pragma unroll
+    for (int v = 0; v < VW; ++v) {
+      vt[v] = (A)w[v];
+      pt[v] = (A)p[v];
+      acc[v] = 0;
+    }
+  }
+  const A a2u = (A)(pair_coef * pair_coef);
+  const int own = row * rowb;
+  const int e0 = inc_xptr[row * (kXcds + 1) + x], e1 = inc_xptr[row * (kXcds + 1) + x + 1];
+  for (int base = e0; base < e1; base += CH) {
+    const int cnt = min(CH, e1 - base);
+    const int cntp = (cnt + STEP - 1) / STEP * STEP;
+#pragma unroll
+    for (int q = 0; q < CH / 64; ++q) {
+      const int j = wl + 64 * q;
+      if (j < cntp) {
+        int off = own;
+        A a2 = 0;
+        if (j < cnt) {
+          off = inc_nb[base + j] * rowb;
+          a2 = a2u;
+          if (pcoef != nullptr) {
+            const A a = (A)pcoef[inc_id[base + j]];
+            a2 = a * a;
+          }
+        }
+        nbw[j] = off;
+        cfw[j] = a2;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int j = grp; j < cntp; j += STEP) {
+      int off[kUnroll];
+      A coef[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        off[u] = nbw[j + u * NG] + c0 * (int)sizeof(T);
+        coef[u] = cfw[j + u * NG];
+      }
+      vec wv[kUnroll], pv[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        wv[u] = __builtin_bit_cast(vec, __builtin_amdgcn_raw_buffer_load_b128(rs, off[u], 0, 0));
+        pv[u] = __builtin_bit_cast(vec, __builtin_amdgcn_raw_buffer_load_b128(rs, off[u], pofs, 0));
+      }
+      A d[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        A sm = pt[0] * (A)wv[u][0];
+        sm = fma((A)pv[u][0], vt[0], sm);
+#pragma unroll
+        for (int v = 1; v < VW; ++v) {
+          sm = fma(pt[v], (A)wv[u][v], sm);
+          sm = fma((A)pv[u][v], vt[v], sm);
+        }
+        d[u] = sm;
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) d[u] = group_sum<G>(d[u]) * coef[u];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+        for (int v = 0; v < VW; ++v) acc[v] += d[u] * (A)wv[u][v];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+#pragma unroll
+  for (int v = 0; v < VW; ++v)
+    for (int o = G; o < 64; o <<= 1) acc[v] += __shfl_xor(acc[v], o, 64);
+  if (grp == 0) {
+    A* dst = xparts + ((size_t)x * n + row) * ld;
+#pragma unroll
+    for (int v = 0; v < VW; ++v) {
+      const int c = c0 + v;
+      if (c < r) dst[c] = acc[v];
+    }
+  }
+}
+
+// Q = gamma P + rho sum_x xparts[x] (x = 0 .. kXcds - 1 in order) over the
+// first r columns of each row, with the block partials of <P, Q>; P is the
+// direction half of the interleaved rows [W | P] (stride 2 ld).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) xcg_combine(
+    int n, int r, int ld, const typename OpAcc<T>::type* __restrict__ xparts,
+    const T* __restrict__ WP, T* __restrict__ Q, const double* __restrict__ sc, int parity,
+    double* __restrict__ part) {
+  using A = typename OpAcc<T>::type;
+  __shared__ double sh[kBlock / 64];
+  if (sc[S_DONE + parity] != 0.0) return;
+  const double gamma = sc[S_GAMMA], rho = sc[S_RHO];
+  const size_t N = (size_t)n * r, plane = (size_t)n * ld;
+  double pq = 0.0;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock) {
+    const size_t row = i / (unsigned)r;
+    const int c = (int)(i - row * (unsigned)r);
+    const size_t q = row * ld + c;
+    A acc = xparts[q];
+#pragma unroll
+    for (int x = 1; x < kXcds; ++x) acc += xparts[x * plane + q];
+    const A pt = (A)WP[row * 2 * ld + ld + c];
+    const T qv = (T)(gamma * (double)pt + rho * (double)acc);
+    Q[q] = qv;
+    pq += (double)pt * (double)qv;
+  }
+  publish_partial(block_sum(pq, sh), part);
+}
+
 }  // namespace lorads

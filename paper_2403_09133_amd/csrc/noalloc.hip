@@ -2,7 +2,8 @@
 //
 // It runs the CG of lorads_cg_solve (the same kernels, launches and results)
 // with its work buffers (the CG-layout copies of W, R and X, the direction, the
-// operator output and, for general constraints, the per-constraint buffer)
+// operator output, for general constraints the per-constraint buffer, and for
+// factors larger than one XCD's L2 the per-XCD partials of the operator)
 // placed in one static device array of kScratchBytes instead of allocating
 // them.  Each GPU the library runs on holds its own copy of the array until the
 // process ends; lorads_setup records that copy's address for the current
@@ -66,8 +67,10 @@ size_t cg_noalloc_bytes(const Problem& P, int r, int elem) {
   const int ldp = cg_ld(P, r, elem);
   const int ldw = P.structure == LORADS_STRUCT_PAIR ? 2 * ldp : ldp;
   const size_t nt = P.structure == LORADS_STRUCT_GENERIC ? (size_t)P.m : 0;
+  // the CG operator's accumulation type is the element type here (FP32 and
+  // FP64 accumulate in their own precision)
   return round256((size_t)P.n * ldw * elem) + 4 * round256((size_t)P.n * ldp * elem) +
-         round256(nt * elem);
+         round256(nt * elem) + round256(cg_xparts_bytes(P, ldp, elem));
 }
 
 template <typename T>
@@ -90,7 +93,12 @@ void cg_noalloc(Problem& P, int dev, const T* W, double rho, double gamma, const
   T* Xd = reinterpret_cast<T*>(base + bw + bn);
   T* Pd = reinterpret_cast<T*>(base + bw + 2 * bn);
   T* Qd = reinterpret_cast<T*>(base + bw + 3 * bn);
+  const size_t bt = round256((P.structure == LORADS_STRUCT_GENERIC ? (size_t)P.m : 0) * sizeof(T));
   T* td = P.structure == LORADS_STRUCT_GENERIC ? reinterpret_cast<T*>(base + bw + 4 * bn) : nullptr;
+  // per-XCD partials of the split CG operator (large factors only), as
+  // lorads_cg_solve provides them
+  const size_t xb = cg_xparts_bytes(P, ldp, (int)sizeof(T));
+  CgXpartsScope xs(P, xb ? static_cast<void*>(base + bw + 4 * bn + bt) : nullptr);
   // the workspace keeps the last call's contents: clear the buffers (padding
   // columns must be zero) with a fill kernel
   const size_t words = (bw + 4 * bn) / sizeof(T);

@@ -319,9 +319,13 @@ int op_cg(Problem& P, const T* W, int ldw, int r, int ld, const T* Pd, const T* 
   const bool vec = P.structure == LORADS_STRUCT_PAIR && P2 && P2 == W + ld && ldw == 2 * ld &&
                    ld % VW == 0 && gv * VW <= ld && gv <= 16 &&
                    (size_t)P.n * ldw * sizeof(T) < ((size_t)1 << 31);
+  // factor arrays larger than one XCD's L2 (with the caller's partials): the
+  // operator split by partner block, then the combining pass
+  using Acc = typename OpAcc<T>::type;
+  const bool xcd = vec && P.cg_xparts != nullptr && cg_xparts_bytes(P, ld, (int)sizeof(Acc)) > 0;
   // events: attached to that kernel's launch (its own start and end), else
   // recorded around the operator's launches
-  const bool ext = ev0 != nullptr && vec;
+  const bool ext = ev0 != nullptr && vec && !xcd;
   if (ev0 && !ext) HIPCHK(hipEventRecord(ev0, s));
   if (P.structure == LORADS_STRUCT_DIAG) {
     const int grid = rows_grid(P.n, G);
@@ -337,7 +341,24 @@ int op_cg(Problem& P, const T* W, int ldw, int r, int ld, const T* Pd, const T* 
     check_pair_offsets(P, ldw);
     const int grid = waves_grid(P.n);
     P.ensure_part(grid);
-    if (vec) {
+    if (xcd) {
+      Acc* xp = static_cast<Acc*>(P.cg_xparts);
+      const int xgrid = kXcds * ((P.n + kBlock / 64 - 1) / (kBlock / 64));
+#define LORADS_CG_XVEC(GG)                                                                         \
+  kpair_cg_xvec<T, GG><<<xgrid, kBlock, 0, s>>>(P.n, P.inc_xptr.p, P.inc_nb.p, P.inc_id.p,         \
+                                                pc<T>(P), P.pair_coef, W, ld, r, xp, sc, parity)
+      switch (gv) {
+        case 1: LORADS_CG_XVEC(1); break;
+        case 2: LORADS_CG_XVEC(2); break;
+        case 4: LORADS_CG_XVEC(4); break;
+        case 8: LORADS_CG_XVEC(8); break;
+        default: LORADS_CG_XVEC(16); break;
+      }
+#undef LORADS_CG_XVEC
+      const int cgrid = grid_for((size_t)P.n * r, 1024);
+      P.ensure_part(cgrid);
+      xcg_combine<T><<<cgrid, kBlock, 0, s>>>(P.n, r, ld, xp, W, Q, sc, parity, P.part.p);
+    } else if (vec) {
 #define LORADS_CG_VEC(GG)                                                                          \
   do {                                                                                             \
     if (ext)                                                                                       \
@@ -363,7 +384,7 @@ int op_cg(Problem& P, const T* W, int ldw, int r, int ld, const T* Pd, const T* 
                                P.inc_id.p, pc<T>(P), P.pair_coef, nullptr, W, Pg, r, ldw, Q, ld,
                                1.0, sc, parity, P.part.p, nullptr, 0.0)));
     }
-    np = grid;
+    np = xcd ? grid_for((size_t)P.n * r, 1024) : grid;
   } else {
     LORADS_DISPATCH_G(G, (k1_generic<T, G, 2><<<rows_grid(P.m, G), kBlock, 0, s>>>(
                              P.m, P.kptr.p, P.krow.p, P.kcol.p, kv<T>(P), Pd, W, r, r, t, 1.0,

@@ -183,6 +183,13 @@ struct Problem {
   // all of its partners in partner block x)
   DevBuf<int> xchunk_row, xchunk_start, xchunk_end, xchunk_off;
   int nxchunks = 0, xchunk_maxlen = 0;
+  // the incident lists cut by partner block: row t's entries with partners in
+  // block x are inc_xptr[t (kXcds + 1) + x] .. inc_xptr[t (kXcds + 1) + x + 1]
+  DevBuf<int> inc_xptr;
+  // per-XCD partial outputs of the CG operator (kXcds planes of n x ld of the
+  // operator's accumulation type), provided by the caller of a CG run whose
+  // factor array exceeds one XCD's L2 (nullptr: the single-pass operator)
+  void* cg_xparts = nullptr;
   DevBuf<int> inc_ptr, inc_nb, inc_id;  // incident lists: row pointers, partner, internal id
   // uniform coefficient only: [lam, b] per incident entry (interleaved, 16
   // bytes), so the gradient form streams them instead of gathering w by id;
@@ -262,6 +269,19 @@ inline int xchunk_grid(const Problem& P, int GV) {
   const long long per = ((long long)P.xchunk_maxlen * GV + kBlock - 1) / kBlock;
   return (int)std::max<long long>(kXcds, kXcds * std::max<long long>(1, per));
 }
+// the CG operator runs split by XCD when the interleaved [W | P] rows exceed
+// one XCD's L2 (4 MiB): bytes of its per-XCD partials, else 0
+inline size_t cg_xparts_bytes(const Problem& P, int ld, int elem) {
+  if (P.structure != LORADS_STRUCT_PAIR || P.inc_xptr.n == 0) return 0;
+  if ((size_t)P.n * 2 * ld * elem <= ((size_t)4 << 20)) return 0;
+  return (size_t)kXcds * P.n * ld * elem;
+}
+// sets the CG operator's per-XCD partials for the life of a CG run
+struct CgXpartsScope {
+  Problem& P;
+  CgXpartsScope(Problem& P_, void* p) : P(P_) { P.cg_xparts = p; }
+  ~CgXpartsScope() { P.cg_xparts = nullptr; }
+};
 // grid of the fused line-search pass at rank r (groups of G/2 lanes), i.e. its
 // count of block partials
 inline int ls_blocks(const Problem& P, int r) {

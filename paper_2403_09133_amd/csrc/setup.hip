@@ -351,6 +351,29 @@ std::unique_ptr<Problem> ingest(const lorads_problem& p, hipStream_t s) {
     P->inc_ptr.upload(inc_ptr, s);
     P->inc_nb.upload(inc_nb, s);
     P->inc_id.upload(inc_id, s);
+    {
+      // partner blocks of the incident entries (2m / kXcds each) and every
+      // row's runs per block (its list is sorted by partner)
+      std::vector<long long> cum(n + 1, 0);
+      for (size_t t = 0; t < inc_nb.size(); ++t) ++cum[inc_nb[t] + 1];
+      for (int k = 0; k < n; ++k) cum[k + 1] += cum[k];
+      std::vector<int> kb(kXcds + 1, n);
+      kb[0] = 0;
+      for (int x = 1; x < kXcds; ++x) {
+        const long long want = 2LL * m * x / kXcds;
+        kb[x] = std::max(kb[x - 1], (int)(std::lower_bound(cum.begin(), cum.end(), want) - cum.begin()));
+      }
+      std::vector<int> xp((size_t)n * (kXcds + 1));
+      for (int t = 0; t < n; ++t) {
+        int e = inc_ptr[t];
+        for (int x = 0; x < kXcds; ++x) {
+          xp[(size_t)t * (kXcds + 1) + x] = e;
+          while (e < inc_ptr[t + 1] && inc_nb[e] < kb[x + 1]) ++e;
+        }
+        xp[(size_t)t * (kXcds + 1) + kXcds] = inc_ptr[t + 1];
+      }
+      P->inc_xptr.upload(xp, s);
+    }
     if (uniform) {
       std::vector<double> lb(2 * inc_id.size(), 0.0);
       for (size_t t = 0; t < inc_id.size(); ++t) lb[2 * t + 1] = b_int[inc_id[t]];

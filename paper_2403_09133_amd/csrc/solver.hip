@@ -492,15 +492,18 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
 template <typename T>
 struct CgBufs {
   DevBuf<T> R, X, Pd, Q, W, t;
+  DevBuf<char> xparts;  // per-XCD partials of the split CG operator (large factors)
   int ld = 0, ldw = 0;
   T* P2 = nullptr;
-  void alloc(int n, int m, int ld_, bool interleave, hipStream_t s) {
+  void alloc(const Problem& P, int n, int m, int ld_, bool interleave, hipStream_t s) {
     ld = ld_;
     ldw = interleave ? 2 * ld : ld;
     const size_t N = (size_t)n * ld;
     R.alloc(N); X.alloc(N); Pd.alloc(N); Q.alloc(N); W.alloc((size_t)n * ldw); t.alloc(m);
     R.zero(s); X.zero(s); Pd.zero(s); Q.zero(s); W.zero(s);
     P2 = interleave ? W.p + ld : nullptr;
+    const size_t xb = cg_xparts_bytes(P, ld, (int)sizeof(typename OpAcc<T>::type));
+    if (xb) xparts.alloc(xb);
   }
 };
 
@@ -529,8 +532,12 @@ static int half_step(Problem& P, const double* W, double* out, int r, double rho
   copy_rows<double, T><<<gridN((size_t)P.n * r), kBlock, 0, s>>>(P.n, r, W, r, B.W.p, B.ldw);
   HIPCHK(hipMemsetAsync(B.X.p, 0, N * sizeof(T), s));
   double rel;
-  const int it = cg_run<T>(P, B.W.p, B.ldw, r, ld, rho, gamma, B.R.p, B.X.p, B.Pd.p, B.P2, B.Q.p,
-                           B.t.p, tol, maxit, s, &rel, &info.op_bytes);
+  int it;
+  {
+    CgXpartsScope xs(P, B.xparts.n ? B.xparts.p : nullptr);
+    it = cg_run<T>(P, B.W.p, B.ldw, r, ld, rho, gamma, B.R.p, B.X.p, B.Pd.p, B.P2, B.Q.p, B.t.p,
+                   tol, maxit, s, &rel, &info.op_bytes);
+  }
   add_rows<double, T><<<gridN((size_t)P.n * r), kBlock, 0, s>>>(P.n, r, W, r, B.X.p, ld, out);
   if (outp)
     copy_rows<double, double><<<gridN((size_t)P.n * r), kBlock, 0, s>>>(P.n, r, out, r, outp, ldp);
@@ -555,7 +562,7 @@ static void phase2_t(Problem& P, const lorads_options& o, double rho, SolveInfo&
     R64.zero(s);
   }
   CgBufs<T> B;
-  B.alloc(n, m, ldc, P.structure == LORADS_STRUCT_PAIR, s);
+  B.alloc(P, n, m, ldc, P.structure == LORADS_STRUCT_PAIR, s);
   refresh_inc_lam(P, s);
   // PAIR: zero-padded FP64 copies of U and V (rows of whole 64-byte sectors),
   // kept equal to the masters, for the gradient form and the dual update's
