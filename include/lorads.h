@@ -61,8 +61,12 @@ typedef enum { LORADS_F64 = 0, LORADS_F32 = 1 } lorads_dtype;
 typedef enum {
   LORADS_STRUCT_GENERIC = 0, /* any sparse symmetric A_i */
   LORADS_STRUCT_DIAG = 1,    /* every A_i = a_i e_j e_j^T (MaxCut: diag(X) = 1) */
-  LORADS_STRUCT_PAIR = 2     /* every A_i = a_i (e_j e_k^T + e_k e_j^T), j < k
+  LORADS_STRUCT_PAIR = 2,    /* every A_i = a_i (e_j e_k^T + e_k e_j^T), j < k
                                 (matrix completion) */
+  LORADS_STRUCT_RANK1 = 3    /* every A_i = c_i a_i a_i^T with a sparse a_i
+                                (sensor network localization, Section 3; the
+                                balance constraint <1 1^T, X> = 0 of graph
+                                bisection), when not DIAG */
 } lorads_structure;
 
 /* One SDP instance, host memory, caller-owned; lorads_setup copies it. */
@@ -238,8 +242,9 @@ lorads_status lorads_cg_solve(lorads_ctx *ctx, int32_t prob, const void *W, doub
  * Arguments, layout, ownership and blocking as lorads_cg_solve.  Errors:
  * EINVAL when one call needs more than 64 MiB of workspace (about
  * (6 n ld_cg) elements, ld_cg = r rounded up to 64 bytes for completion
- * problems, r otherwise), ESTATE when the context was set up on another
- * device.  Every call on a GPU uses that GPU's one workspace, which keeps the
+ * problems, r otherwise) or for rank-one constraint problems
+ * (LORADS_STRUCT_RANK1, whose work vectors grow with the rank), ESTATE when
+ * the context was set up on another device.  Every call on a GPU uses that GPU's one workspace, which keeps the
  * last call's contents (the call clears what must start at zero): calls that
  * overlap on one GPU (other threads, other streams, other contexts) race. */
 lorads_status lorads_cg_solve_noalloc(lorads_ctx *ctx, int32_t prob, const void *W, double rho,

@@ -82,6 +82,9 @@ void cg_noalloc(Problem& P, int dev, const T* W, double rho, double gamma, const
                             " bytes) exceeds the static workspace of " +
                             std::to_string(kScratchBytes) + " bytes");
   if (!P.hs.h) fail(LORADS_ESTATE, "host words of the problem not set up");
+  if (P.structure == LORADS_STRUCT_RANK1)
+    fail(LORADS_EINVAL, "rank-one constraint problems are not served without allocation "
+                        "(their operator's work vectors grow with the rank)");
   unsigned char* base = scratch_address(dev);
   const int ldp = cg_ld(P, r, (int)sizeof(T));
   const size_t N = (size_t)P.n * ldp;

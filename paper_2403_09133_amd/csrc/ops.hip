@@ -5,6 +5,7 @@
 #include <chrono>
 
 #include "kernels.hpp"
+#include "kernels_rank1.hpp"
 #include "kernels_struct.hpp"
 #include "problem.hpp"
 
@@ -39,6 +40,32 @@ template <> const float* ds<float>(const Problem& P) { return P.dsqf.p; }
 template <typename T> static const T* pc(const Problem& P);
 template <> const double* pc<double>(const Problem& P) { return P.pcoef.p; }
 template <> const float* pc<float>(const Problem& P) { return P.pcoeff.p; }
+template <typename T> static const T* r1v(const Problem& P);
+template <> const double* r1v<double>(const Problem& P) { return P.r1val.p; }
+template <> const float* r1v<float>(const Problem& P) { return P.r1valf.p; }
+template <typename T> static const T* r1t(const Problem& P);
+template <> const double* r1t<double>(const Problem& P) { return P.r1tval.p; }
+template <> const float* r1t<float>(const Problem& P) { return P.r1tvalf.p; }
+
+// RANK1 work vectors at rank r (segment partials of two factors, per-constraint
+// r-vectors and weights), in the operator's accumulation type
+template <typename T>
+struct R1Work {
+  using A = typename OpAcc<T>::type;
+  A *su, *sv, *S, *coef;
+};
+template <typename T>
+static R1Work<T> r1_work(Problem& P, int r) {
+  using A = typename OpAcc<T>::type;
+  const size_t nseg = (size_t)P.r1nseg, m = (size_t)P.m;
+  const size_t need = (2 * nseg * r + m * r + m) * sizeof(double);
+  if (P.r1work_bytes < need) {
+    P.r1work.alloc(need);
+    P.r1work_bytes = need;
+  }
+  A* base = reinterpret_cast<A*>(P.r1work.p);
+  return R1Work<T>{base, base + nseg * r, base + 2 * nseg * r, base + 2 * nseg * r + m * r};
+}
 
 // G as above, plus KC = the factor columns a lane holds: 1 when r <= G
 #define LORADS_DISPATCH_GK(G, r, CALL)                          \
@@ -103,7 +130,15 @@ template <typename T>
 static void op_forward_impl(Problem& P, const T* U, const T* V, int r, int ld, T* z, double scale,
                             hipStream_t s) {
   const int G = lane_group(r);
-  if (P.structure == LORADS_STRUCT_DIAG) {
+  if (P.structure == LORADS_STRUCT_RANK1) {
+    const R1Work<T> wk = r1_work<T>(P, r);
+    LORADS_DISPATCH_G(G, (r1_seg<T, G, 1><<<rows_grid(P.r1nseg, G), kBlock, 0, s>>>(
+                             P.r1nseg, P.r1sstart.p, P.r1idx.p, r1v<T>(P), U, V, r, ld, wk.su,
+                             wk.sv, nullptr, 0)));
+    LORADS_DISPATCH_G(G, (r1_con<T, G, 0><<<rows_grid(P.m, G), kBlock, 0, s>>>(
+                             P.m, P.r1cseg.p, P.r1c.p, wk.su, wk.sv, r, z, scale, nullptr, nullptr,
+                             0.0, nullptr, nullptr, nullptr, nullptr, nullptr, 0)));
+  } else if (P.structure == LORADS_STRUCT_DIAG) {
     LORADS_DISPATCH_G(G, (k1_diag<T, G, 0><<<rows_grid(P.m, G), kBlock, 0, s>>>(
                              P.m, P.drow.p, dc<T>(P), U, V, r, ld, z, scale, nullptr, nullptr,
                              0.0, nullptr, nullptr, 0)));
@@ -148,7 +183,15 @@ void op_forward_w(Problem& P, const double* U, const double* V, int r, int ld, d
 static void op_forward_w_impl(Problem& P, const double* U, const double* V, int r, int ld,
                               double* z, double* w, const double* lam, double rho, hipStream_t s) {
   const int G = lane_group(r);
-  if (P.structure == LORADS_STRUCT_DIAG) {
+  if (P.structure == LORADS_STRUCT_RANK1) {
+    const R1Work<double> wk = r1_work<double>(P, r);
+    LORADS_DISPATCH_G(G, (r1_seg<double, G, 1><<<rows_grid(P.r1nseg, G), kBlock, 0, s>>>(
+                             P.r1nseg, P.r1sstart.p, P.r1idx.p, P.r1val.p, U, V, r, ld, wk.su,
+                             wk.sv, nullptr, 0)));
+    LORADS_DISPATCH_G(G, (r1_con<double, G, 1><<<rows_grid(P.m, G), kBlock, 0, s>>>(
+                             P.m, P.r1cseg.p, P.r1c.p, wk.su, wk.sv, r, z, 1.0, lam, P.b.p, rho, w,
+                             nullptr, nullptr, nullptr, nullptr, 0)));
+  } else if (P.structure == LORADS_STRUCT_DIAG) {
     LORADS_DISPATCH_G(G, (k1_diag<double, G, 1><<<rows_grid(P.m, G), kBlock, 0, s>>>(
                              P.m, P.drow.p, P.dcoef.p, U, V, r, ld, z, 1.0, lam, P.b.p, rho, w,
                              nullptr, 0)));
@@ -238,7 +281,22 @@ static void op_adjoint_impl(Problem& P, const T* w, double c_scale, const T* V, 
                             T* out, int ldo, double out_scale, hipStream_t s) {
   const int G = lane_group(r);
   if (r > 4 * G) fail(LORADS_EINVAL, "rank above 256 is not supported");
-  if (P.structure == LORADS_STRUCT_DIAG) {
+  if (P.structure == LORADS_STRUCT_RANK1) {
+    // S_i = a_i^T V with weight c_i w_i, then the row pass (C alone without w)
+    const R1Work<T> wk = r1_work<T>(P, r);
+    if (w != nullptr) {
+      LORADS_DISPATCH_G(G, (r1_seg<T, G, 0><<<rows_grid(P.r1nseg, G), kBlock, 0, s>>>(
+                               P.r1nseg, P.r1sstart.p, P.r1idx.p, r1v<T>(P), V, V, r, ld, wk.su,
+                               nullptr, nullptr, 0)));
+      LORADS_DISPATCH_G(G, (r1_con<T, G, 2><<<rows_grid(P.m, G), kBlock, 0, s>>>(
+                               P.m, P.r1cseg.p, P.r1c.p, wk.su, nullptr, r, nullptr, 1.0, nullptr,
+                               nullptr, 0.0, nullptr, w, wk.S, wk.coef, nullptr, 0)));
+    }
+    LORADS_DISPATCH_G(G, (r1_rows<T, G, 0><<<rows_grid(P.n, G), kBlock, 0, s>>>(
+                             P.n, P.cptr.p, P.ccol.p, cv<T>(P), c_scale, P.r1tptr.p, P.r1tcon.p,
+                             r1t<T>(P), w != nullptr ? wk.coef : nullptr, wk.S, V, r, ld, out, ldo,
+                             out_scale, nullptr, nullptr, 0, nullptr)));
+  } else if (P.structure == LORADS_STRUCT_DIAG) {
     LORADS_DISPATCH_G(G, (k2_diag<T, G, 0><<<rows_grid(P.n, G), kBlock, 0, s>>>(
                              P.n, P.cptr.p, P.ccol.p, cv<T>(P), c_scale, P.dptr.p, dc<T>(P),
                              nullptr, w, V, r, ld, out, ldo, out_scale, nullptr, nullptr, 0,
@@ -327,7 +385,24 @@ int op_cg(Problem& P, const T* W, int ldw, int r, int ld, const T* Pd, const T* 
   // recorded around the operator's launches
   const bool ext = ev0 != nullptr && vec && !xcd;
   if (ev0 && !ext) HIPCHK(hipEventRecord(ev0, s));
-  if (P.structure == LORADS_STRUCT_DIAG) {
+  if (P.structure == LORADS_STRUCT_RANK1) {
+    // u_i = a_i^T P, S_i = a_i^T W, weight rho c_i^2 <u_i, S_i>; then
+    // Q_t = gamma P_t + sum_i weight_i a_{i,t} S_i
+    if (ld != r || ldw != r || P2) fail(LORADS_EINVAL, "CG buffers must be compact");
+    const R1Work<T> wk = r1_work<T>(P, r);
+    LORADS_DISPATCH_G(G, (r1_seg<T, G, 1><<<rows_grid(P.r1nseg, G), kBlock, 0, s>>>(
+                             P.r1nseg, P.r1sstart.p, P.r1idx.p, r1v<T>(P), Pd, W, r, ld, wk.su,
+                             wk.sv, sc, parity)));
+    LORADS_DISPATCH_G(G, (r1_con<T, G, 3><<<rows_grid(P.m, G), kBlock, 0, s>>>(
+                             P.m, P.r1cseg.p, P.r1c.p, wk.su, wk.sv, r, nullptr, 1.0, nullptr,
+                             nullptr, 0.0, nullptr, nullptr, wk.S, wk.coef, sc, parity)));
+    const int grid = rows_grid(P.n, G);
+    P.ensure_part(grid);
+    LORADS_DISPATCH_G(G, (r1_rows<T, G, 1><<<grid, kBlock, 0, s>>>(
+                             P.n, nullptr, nullptr, nullptr, 0.0, P.r1tptr.p, P.r1tcon.p, r1t<T>(P),
+                             wk.coef, wk.S, W, r, ld, Q, ld, 1.0, Pd, sc, parity, P.part.p)));
+    np = grid;
+  } else if (P.structure == LORADS_STRUCT_DIAG) {
     const int grid = rows_grid(P.n, G);
     P.ensure_part(grid);
     LORADS_DISPATCH_G(G, (k3_diag<T, G><<<grid, kBlock, 0, s>>>(
@@ -409,6 +484,9 @@ double bytes_forward(const Problem& P, int r, int s) {
   if (P.structure == LORADS_STRUCT_DIAG) return (double)P.m * (4 + s) + 2.0 * nr + (double)P.m * s;
   if (P.structure == LORADS_STRUCT_PAIR)
     return (double)P.m * 8 + (double)P.m * s + 2.0 * nr + (P.pcoef.n ? (double)P.m * s : 0.0);
+  if (P.structure == LORADS_STRUCT_RANK1)  // a's entries, segment bounds, c, both factors, z
+    return (double)P.r1idx.n * (4 + s) + (double)(P.r1nseg + P.m + 1) * 4 + (double)P.m * 8 + 2.0 * nr +
+           (double)P.m * s;
   return (double)P.a_nnz * (8 + s) + (double)(P.m + 1) * 4 + 2.0 * nr + (double)P.m * s;
 }
 
@@ -420,6 +498,9 @@ double bytes_adjoint(const Problem& P, int r, int s, bool with_c) {
   const double nr = (double)P.n * r * s;
   const double cbytes = with_c ? (double)P.cval.n * (4 + s) + (double)(P.n + 1) * 4 : 0.0;
   if (P.structure == LORADS_STRUCT_DIAG) return (double)P.m * (4 + 2 * s) + 2.0 * nr + cbytes;
+  if (P.structure == LORADS_STRUCT_RANK1)  // a by constraint and by row, w, c, V, out
+    return 2.0 * (double)P.r1idx.n * (4 + s) + (double)(P.r1nseg + P.m + P.n + 2) * 4 +
+           (double)P.m * (8 + s) + 2.0 * nr + cbytes;
   if (P.structure == LORADS_STRUCT_PAIR)
     return (double)P.m * 8 + (double)P.m * s + 2.0 * nr + cbytes + (P.pcoef.n ? (double)P.m * s : 0.0);
   return (double)P.acol.n * (8 + s) + (double)(P.n + 1) * 4 + (double)P.m * s + 2.0 * nr + cbytes;

@@ -157,6 +157,21 @@ struct Problem {
   DevBuf<double> cdiag;  // diagonal C only: C_jj by row (zero where absent), else empty
   DevBuf<float> cvalf;
 
+  // RANK1 structure: A_i = r1c[i] a_i a_i^T.  a_i's entries (index, value) in
+  // constraint CSR r1ptr / r1idx / r1val, cut into segments of at most
+  // kR1Seg entries (segment s: entries r1sstart[s] .. r1sstart[s + 1] - 1 of
+  // constraint r1scon[s]; constraint i owns segments r1cseg[i] ..
+  // r1cseg[i + 1] - 1); row view: row t meets constraints r1tcon[e] with
+  // a_{i,t} = r1tval[e], e in r1tptr[t] .. r1tptr[t + 1] - 1.  Work vectors
+  // (segment partials, per-constraint r-vectors and coefficients) grow with
+  // the rank on first use.
+  DevBuf<int> r1ptr, r1idx, r1scon, r1sstart, r1cseg, r1tptr, r1tcon;
+  DevBuf<double> r1val, r1c, r1tval;
+  DevBuf<float> r1valf, r1cf, r1tvalf;
+  int r1nseg = 0;
+  DevBuf<char> r1work;
+  size_t r1work_bytes = 0;
+
   // DIAG structure: constraint i (internal order) sits on row drow[i] with
   // coefficient dcoef[i]; rows own contiguous constraint ranges dptr.
   DevBuf<int> drow, dptr;

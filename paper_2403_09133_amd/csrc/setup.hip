@@ -131,6 +131,7 @@ std::unique_ptr<Problem> ingest(const lorads_problem& p, hipStream_t s) {
   for (int i = 0; i < m; ++i) b_int[i] = p.b[perm[i]];
 
   // ---------------- constraint-CSR (internal order) ----------------
+  // (RANK1 is decided after it: it needs each constraint's merged triplets)
   std::vector<int> kcon(p.a_nnz);
   for (int64_t e = 0; e < p.a_nnz; ++e) kcon[e] = iperm[p.a_con[e]];
   std::vector<int> kptr;
@@ -144,6 +145,101 @@ std::unique_ptr<Problem> ingest(const lorads_problem& p, hipStream_t s) {
       krow[q] = p.a_row[e];
       kcol[q] = p.a_col[e];
       kval[q] = p.a_val[e];
+    }
+  }
+  // ---------------- RANK1: every A_i = c_i a_i a_i^T ----------------
+  if (P->structure == LORADS_STRUCT_GENERIC) {
+    std::vector<int> r1ptr(1, 0), r1idx;
+    std::vector<double> r1val, r1c;
+    bool rank1 = true;
+    std::vector<std::pair<int64_t, double>> ent;
+    std::vector<int> sup;
+    std::vector<double> dg, a;
+    for (int i = 0; i < m && rank1; ++i) {
+      // merged triplets of A_i, keyed (row, col) with row <= col
+      ent.clear();
+      for (int q = kptr[i]; q < kptr[i + 1]; ++q) ent.push_back({(int64_t)krow[q] * n + kcol[q], kval[q]});
+      std::sort(ent.begin(), ent.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+      size_t w = 0;
+      for (size_t q = 0; q < ent.size(); ++q) {
+        if (w > 0 && ent[w - 1].first == ent[q].first) ent[w - 1].second += ent[q].second;
+        else ent[w++] = ent[q];
+      }
+      ent.resize(w);
+      sup.clear();
+      for (const auto& e : ent) { sup.push_back((int)(e.first / n)); sup.push_back((int)(e.first % n)); }
+      std::sort(sup.begin(), sup.end());
+      sup.erase(std::unique(sup.begin(), sup.end()), sup.end());
+      const size_t k = sup.size();
+      // every pair of the support must be present: a_j a_k != 0 for nonzero a
+      if (ent.size() != k * (k + 1) / 2) { rank1 = false; break; }
+      auto find = [&](int j, int l) -> double {
+        const int64_t key = (int64_t)std::min(j, l) * n + std::max(j, l);
+        auto it = std::lower_bound(ent.begin(), ent.end(), key,
+                                   [](const auto& x, int64_t v) { return x.first < v; });
+        return (it != ent.end() && it->first == key) ? it->second : 0.0;
+      };
+      dg.assign(k, 0.0);
+      size_t piv = 0;
+      for (size_t t = 0; t < k; ++t) {
+        dg[t] = find(sup[t], sup[t]);
+        if (std::fabs(dg[t]) > std::fabs(dg[piv])) piv = t;
+      }
+      const double c = dg[piv] > 0 ? 1.0 : -1.0;
+      a.assign(k, 0.0);
+      for (size_t t = 0; t < k && rank1; ++t) {
+        if (!(dg[t] * c > 0)) { rank1 = false; break; }
+        a[t] = std::sqrt(dg[t] * c);
+        if (t != piv && c * find(sup[piv], sup[t]) < 0) a[t] = -a[t];
+      }
+      for (size_t t = 0; t < k && rank1; ++t)
+        for (size_t u = t + 1; u < k; ++u) {
+          const double want = c * a[t] * a[u], got = find(sup[t], sup[u]);
+          if (std::fabs(got - want) > 1e-12 * std::max(std::fabs(got), std::fabs(want))) { rank1 = false; break; }
+        }
+      if (!rank1) break;
+      for (size_t t = 0; t < k; ++t) { r1idx.push_back(sup[t]); r1val.push_back(a[t]); }
+      r1ptr.push_back((int)r1idx.size());
+      r1c.push_back(c);
+    }
+    if (rank1) {
+      P->structure = LORADS_STRUCT_RANK1;
+      std::vector<int> scon, sstart, cseg(1, 0);
+      for (int i = 0; i < m; ++i) {
+        for (int e = r1ptr[i]; e < r1ptr[i + 1]; e += kR1Seg) {
+          scon.push_back(i);
+          sstart.push_back(e);
+        }
+        cseg.push_back((int)scon.size());
+      }
+      sstart.push_back(r1ptr[m]);
+      std::vector<int> tkey(r1idx.begin(), r1idx.end()), tptr;
+      csr_counts(tkey, n, tptr);
+      std::vector<int> tcon(r1idx.size());
+      std::vector<double> tval(r1idx.size());
+      std::vector<int> pos(tptr.begin(), tptr.end() - 1);
+      for (int i = 0; i < m; ++i)
+        for (int e = r1ptr[i]; e < r1ptr[i + 1]; ++e) {
+          const int t = pos[r1idx[e]]++;
+          tcon[t] = i;
+          tval[t] = r1val[e];
+        }
+      P->r1ptr.upload(r1ptr, s);
+      P->r1idx.upload(r1idx, s);
+      P->r1val.upload(r1val, s);
+      P->r1c.upload(r1c, s);
+      P->r1scon.upload(scon, s);
+      P->r1sstart.upload(sstart, s);
+      P->r1cseg.upload(cseg, s);
+      P->r1tptr.upload(tptr, s);
+      P->r1tcon.upload(tcon, s);
+      P->r1tval.upload(tval, s);
+      std::vector<float> f1(r1val.begin(), r1val.end()), f2(r1c.begin(), r1c.end()),
+          f3(tval.begin(), tval.end());
+      P->r1valf.upload(f1, s);
+      P->r1cf.upload(f2, s);
+      P->r1tvalf.upload(f3, s);
+      P->r1nseg = (int)scon.size();
     }
   }
   // ---------------- adjoint row-CSR ----------------

@@ -20,7 +20,7 @@ _lib = None
 LORADS_OK, LORADS_MAXITER, LORADS_TIMELIMIT = 0, 1, 2
 LORADS_EINVAL, LORADS_ENOMEM, LORADS_EDEVICE, LORADS_ENUMERIC, LORADS_ESTATE = -1, -2, -3, -4, -5
 F64, F32 = 0, 1
-STRUCT_NAMES = {0: "generic", 1: "diag", 2: "pair"}
+STRUCT_NAMES = {0: "generic", 1: "diag", 2: "pair", 3: "rank1"}
 
 
 class LoradsError(RuntimeError):

@@ -20,6 +20,8 @@ def family_params(kind: str, n: int) -> dict:
         return dict(switch_tol=1e-3, h=10.0, lbfgs_mem=4)
     if kind == "mc":
         return dict(switch_tol=1e-3, h=5.0 if n < 10000 else 2.5, lbfgs_mem=4)
+    if kind == "partition":  # graph partition and bisection: h = 10 (Section 5.1)
+        return dict(switch_tol=1e-3, h=10.0, lbfgs_mem=4)
     return dict(switch_tol=1e-3, h=1.0, lbfgs_mem=4)
 
 

@@ -377,3 +377,92 @@ def petersen_edges():
     spokes = [(i, i + 5) for i in range(5)]
     inner = [(5 + i, 5 + (i + 2) % 5) for i in range(5)]
     return outer + spokes + inner
+
+
+# ----------------------------------------------------------------------------
+# Rank-one constraints: every A_i = a_i a_i^T (Section 3's sensor network
+# localization relaxation; the balance constraint of graph bisection)
+# ----------------------------------------------------------------------------
+
+def _rank_one_triplets(con: int, idx, val):
+    """Upper-triangle triplets of a a^T for a sparse a (indices ascending):
+    diagonal a_k^2, off-diagonal a_j a_k (one triplet stands for both sides)."""
+    idx = np.asarray(idx, dtype=np.int64)
+    val = np.asarray(val, dtype=np.float64)
+    order = np.argsort(idx)
+    idx, val = idx[order], val[order]
+    iu, ju = np.triu_indices(idx.size)
+    return (np.full(iu.size, con, dtype=np.int64), idx[iu], idx[ju], val[iu] * val[ju])
+
+
+def snl(n_sensors: int, n_anchors: int, radius: float, seed: int, d: int = 2) -> Problem:
+    """SDP relaxation of sensor network localization (Section 3) with exact
+    distances: Z of order d + n_sensors, Z[:d, :d] = I written with rank-one
+    constraints (Z_kk = 1 and <(e_k + e_l)(e_k + e_l)^T, Z> = 2), one constraint
+    <(0; e_i - e_j)(0; e_i - e_j)^T, Z> = |x_i - x_j|^2 per sensor pair closer
+    than `radius` and <(a_k; -e_j)(a_k; -e_j)^T, Z> = |a_k - x_j|^2 per
+    anchor-sensor pair closer than `radius`; C = 0.  Sensors and anchors are
+    uniform in [-0.5, 0.5]^d; the true positions are kept in meta."""
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(-0.5, 0.5, (n_sensors, d))
+    A = rng.uniform(-0.5, 0.5, (n_anchors, d))
+    parts, b = [], []
+
+    def add(idx, val, rhs):
+        parts.append(_rank_one_triplets(len(b), idx, val))
+        b.append(rhs)
+
+    for k in range(d):
+        add([k], [1.0], 1.0)
+    for k in range(d):
+        for l in range(k + 1, d):
+            add([k, l], [1.0, 1.0], 2.0)
+    ss = 0
+    for i in range(n_sensors):
+        dist = np.linalg.norm(X[i + 1:] - X[i], axis=1)
+        for j in np.nonzero(dist < radius)[0] + i + 1:
+            add([d + i, d + j], [1.0, -1.0], float(np.sum((X[i] - X[j]) ** 2)))
+            ss += 1
+    sa = 0
+    for k in range(n_anchors):
+        dist = np.linalg.norm(X - A[k], axis=1)
+        for j in np.nonzero(dist < radius)[0]:
+            add(list(range(d)) + [d + j], list(A[k]) + [-1.0], float(np.sum((A[k] - X[j]) ** 2)))
+            sa += 1
+    con, row, col, val = (np.concatenate([p[t] for p in parts]) for t in range(4))
+    n = d + n_sensors
+    return Problem(n=n, m=len(b), c_row=np.zeros(0), c_col=np.zeros(0), c_val=np.zeros(0),
+                   a_con=con, a_row=row, a_col=col, a_val=val, b=np.asarray(b), kind="snl",
+                   meta={"seed": seed, "d": d, "sensors": X, "anchors": A, "sensor_pairs": ss,
+                         "anchor_pairs": sa, "family": f"SNL({n_sensors}, {n_anchors}, r={radius})"})
+
+
+def min_bisection(n: int, ei, ej, w, meta: Optional[dict] = None) -> Problem:
+    """Graph bisection relaxation: min <L/4, X> s.t. diag(X) = 1 and
+    <J / n, X> = 0 (x in {-1, 1}^n with sum x = 0), J / n = a a^T with
+    a = 1 / sqrt(n) the one dense rank-one constraint (scaled like the diagonal
+    ones: ||a|| = 1).  The value bounds the minimum bisection width from below."""
+    ei = np.asarray(ei, dtype=np.int64)
+    ej = np.asarray(ej, dtype=np.int64)
+    w = np.asarray(w, dtype=np.float64)
+    lo, hi = np.minimum(ei, ej), np.maximum(ei, ej)
+    deg = np.bincount(lo, weights=w, minlength=n) + np.bincount(hi, weights=w, minlength=n)
+    c_row = np.concatenate([np.arange(n), lo])
+    c_col = np.concatenate([np.arange(n), hi])
+    c_val = np.concatenate([deg / 4.0, -w / 4.0])
+    ar = np.arange(n)
+    jc, jr, jcol, jv = _rank_one_triplets(n, ar, np.full(n, 1.0 / np.sqrt(n)))
+    md = {"edges": (lo.astype(np.int32), hi.astype(np.int32), w)}
+    if meta:
+        md.update(meta)
+    return Problem(n=n, m=n + 1, c_row=c_row, c_col=c_col, c_val=c_val,
+                   a_con=np.concatenate([ar, jc]), a_row=np.concatenate([ar, jr]),
+                   a_col=np.concatenate([ar, jcol]), a_val=np.concatenate([np.ones(n), jv]),
+                   b=np.concatenate([np.ones(n), [0.0]]), kind="partition", meta=md)
+
+
+def min_bisection_er(n: int, p: float, seed: int, weights: str = "unit") -> Problem:
+    rng = np.random.default_rng(seed)
+    ei, ej = er_gnp_edges(n, p, rng)
+    w = _weights(ei.size, weights, rng)
+    return min_bisection(n, ei, ej, w, {"seed": seed, "family": f"bisection G({n},p={p})"})

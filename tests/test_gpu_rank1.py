@@ -1,0 +1,166 @@
+"""Rank-one constraint problems (A_i = c_i a_i a_i^T) on the RANK1 kernels:
+structure detection, the forward map, the adjoint product and the CG entry
+point against the oracle (FP64 to 1e-12 norm-wise, FP32 to its bounds), and
+solves against the closed forms and the oracle's solves: sensor network
+localization recovers the sensors (Section 3's relaxation with exact
+distances), cycle bisection reaches n (1 - cos(2 pi / n)) / 2, and a random
+graph's bisection matches the oracle's objective."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import sdpgen
+from oracle.options import Options, paper_defaults
+
+pytestmark = pytest.mark.gpu
+
+PROBS = {
+    "snl_200": sdpgen.snl(200, 8, 0.2, 11),
+    # the balance constraint a = 1 has 500 entries: 8 segments of one constraint
+    "bisect_er500": sdpgen.min_bisection_er(500, 0.02, 4, "unit"),
+}
+
+
+def test_structure_detection(device):
+    from paper_2403_09133_amd import Context
+    from tests.test_oracle_theta import theta_instance
+    for name, p in PROBS.items():
+        with Context(p) as ctx:
+            assert ctx.problem_info()["structure"] == "rank1", name
+    # X_ij = 0 and tr X = 1 are not rank one
+    p, _, _ = theta_instance("C5")
+    with Context(p) as ctx:
+        assert ctx.problem_info()["structure"] == "generic"
+
+
+@pytest.mark.parametrize("name", sorted(PROBS))
+@pytest.mark.parametrize("r", [1, 7, 20])
+def test_rank1_operators_f64(device, name, r):
+    import torch
+    from paper_2403_09133_amd import Context
+    p = PROBS[name]
+    rng = np.random.default_rng(r)
+    U, V = rng.standard_normal((p.n, r)), rng.standard_normal((p.n, r))
+    w = rng.standard_normal(p.m)
+    refz = oracle.operators.forward(p, U, V)
+    refa = oracle.operators.adjoint(p, w, 1.0, V)
+    refc = oracle.operators.adjoint(p, np.zeros(p.m), 1.0, V)
+    with Context(p) as ctx:
+        Ud, Vd, wd = (torch.tensor(a, device=device) for a in (U, V, w))
+        z = torch.zeros(p.m, dtype=torch.float64, device=device)
+        out = torch.zeros_like(Vd)
+        outc = torch.zeros_like(Vd)
+        ctx.apply_A(Ud, Vd, z)
+        ctx.apply_AT_V(wd, Vd, out)
+        ctx.apply_AT_V(torch.zeros_like(wd), Vd, outc)
+        torch.cuda.synchronize()
+    assert np.linalg.norm(z.cpu().numpy() - refz) <= 1e-12 * np.linalg.norm(refz)
+    assert np.linalg.norm(out.cpu().numpy() - refa) <= 1e-12 * np.linalg.norm(refa)
+    if np.linalg.norm(refc) > 0:
+        assert np.linalg.norm(outc.cpu().numpy() - refc) <= 1e-12 * np.linalg.norm(refc)
+
+
+@pytest.mark.parametrize("name", sorted(PROBS))
+def test_rank1_operators_f32(device, name):
+    import torch
+    from paper_2403_09133_amd import Context
+    p = PROBS[name]
+    rng = np.random.default_rng(3)
+    U32 = rng.standard_normal((p.n, 9)).astype(np.float32)
+    V32 = rng.standard_normal((p.n, 9)).astype(np.float32)
+    w32 = rng.standard_normal(p.m).astype(np.float32)
+    U, V, w = (a.astype(np.float64) for a in (U32, V32, w32))
+    refz = oracle.operators.forward(p, U, V)
+    refa = oracle.operators.adjoint(p, w, 1.0, V)
+    with Context(p) as ctx:
+        Ud, Vd, wd = (torch.tensor(a, device=device) for a in (U32, V32, w32))
+        z = torch.zeros(p.m, dtype=torch.float32, device=device)
+        out = torch.zeros_like(Vd)
+        ctx.apply_A(Ud, Vd, z)
+        ctx.apply_AT_V(wd, Vd, out)
+        torch.cuda.synchronize()
+    assert np.linalg.norm(z.cpu().numpy() - refz) <= 1e-5 * np.linalg.norm(refz)
+    assert np.linalg.norm(out.cpu().numpy() - refa) <= 1e-5 * np.linalg.norm(refa)
+
+
+@pytest.mark.parametrize("name", sorted(PROBS))
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_rank1_cg(device, name, dtype):
+    import torch
+    from paper_2403_09133_amd import Context
+    p = PROBS[name]
+    r = 6
+    rng = np.random.default_rng(8)
+    W = rng.standard_normal((p.n, r)) / math.sqrt(r)
+    R = rng.standard_normal((p.n, r))
+    if dtype == "f32":
+        W, R = (a.astype(np.float32).astype(np.float64) for a in (W, R))
+    rho, gamma, K = 2.0, 1.5, 6
+    Xref, itref, _, _ = oracle.cg.cg(oracle.cg.cg_operator(p, W, rho, gamma), R, 1e-14, K)
+    assert itref == K
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    with Context(p) as ctx:
+        Wd, Rd = torch.tensor(W, dtype=tdt, device=device), torch.tensor(R, dtype=tdt, device=device)
+        Xd = torch.zeros_like(Wd)
+        info = ctx.cg_solve(Wd, Rd, Xd, rho, gamma, 1e-14, K)
+        X = Xd.cpu().numpy().astype(np.float64)
+    assert info["iters"] == K
+    tol = 1e-10 if dtype == "f64" else 1e-4
+    assert np.linalg.norm(X - Xref) <= tol * np.linalg.norm(Xref)
+
+
+def _lib_opts(p, r0, **kw):
+    from paper_2403_09133_amd import default_options
+    return default_options(r0=r0, **{**paper_defaults(p.kind, p.n), **kw})
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_snl_solve_recovers_sensors(device, precision):
+    from paper_2403_09133_amd import Context
+    p = sdpgen.snl(30, 4, 0.45, 7)
+    r0 = sdpgen.rank_rule_2lnm(p.m)
+    U0 = sdpgen.random_init_U(p.n, r0, 3)
+    with Context(p) as ctx:
+        res = ctx.admm_solve([U0], _lib_opts(p, r0, precision=precision))[0]
+        U, V, lam = ctx.get_solution(0, res["rank"])
+    assert res["status"] == 0 and res["kkt"] < 1e-6, res
+    Uh = 0.5 * (U + V)
+    Z = Uh @ Uh.T
+    assert np.abs(Z[2:, :2] - p.meta["sensors"]).max() <= 1e-5
+    m = oracle.metrics.appendix_b(p, Uh, lam)
+    assert abs(m["pinf"] - res["pinf"]) <= 1e-9 and m["pinf"] <= 1e-6
+
+
+@pytest.mark.parametrize("n", [30, 64])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_cycle_bisection_solve(device, n, precision):
+    from paper_2403_09133_amd import Context
+    e = np.arange(n)
+    p = sdpgen.min_bisection(n, e, (e + 1) % n, np.ones(n))
+    U0 = sdpgen.random_init_U(p.n, 4, 3)
+    with Context(p) as ctx:
+        res = ctx.admm_solve([U0], _lib_opts(p, 4, precision=precision))[0]
+    assert res["status"] == 0 and res["kkt"] < 1e-6, res
+    want = n * (1.0 - math.cos(2.0 * math.pi / n)) / 2.0
+    assert abs(res["obj"] - want) <= 1e-6 * want, (res["obj"], want)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_bisection_matches_oracle(device, precision):
+    from paper_2403_09133_amd import Context
+    p = sdpgen.min_bisection_er(120, 0.06, 9, "unit")
+    r0 = sdpgen.rank_rule_2lnm(p.m)
+    U0 = sdpgen.random_init_U(p.n, r0, 3)
+    ref = oracle.lorads.lorads(p, U0, Options(**paper_defaults(p.kind, p.n)))
+    assert ref["phase2"]["converged"]
+    with Context(p) as ctx:
+        res = ctx.admm_solve([U0], _lib_opts(p, r0, precision=precision))[0]
+        U, V, lam = ctx.get_solution(0, res["rank"])
+    assert res["status"] == 0 and res["kkt"] < 1e-6, res
+    oobj = ref["metrics"]["obj"]
+    assert abs(res["obj"] - oobj) <= 1e-6 * max(1.0, abs(oobj)), (res["obj"], oobj)
+    m = oracle.metrics.appendix_b(p, 0.5 * (U + V), lam)
+    assert abs(m["obj"] - res["obj"]) <= 1e-10 * max(1.0, abs(m["obj"]))
+    assert abs(m["lambda_min"] - res["lambda_min"]) <= 1e-7 * max(1.0, abs(m["lambda_min"]))
