@@ -641,23 +641,18 @@ __device__ __forceinline__ double slot_value(const PrevSums& p, const double* va
   // are being finished (o: u's element, or g's when d is formed)
   const unsigned i0 = blockIdx.x * kBlock + threadIdx.x, stride = gridDim.x * kBlock;
   size_t q0 = 0;
-  double x0 = 0.0, y0 = 0.0, d0 = 0.0, o0 = 0.0;
+  double x0 = 0.0, y0 = 0.0, o0 = 0.0;
   if (i0 < N) {
     q0 = compact_to_row(i0, r, ld);
     y0 = yin[q0];
     if (x) x0 = x[q0];
-    if (d) {
-      d0 = d[q0];
-      o0 = g[q0];
-    } else {
-      o0 = u[q0];
-    }
+    o0 = d ? g[q0] : u[q0];
   }
   prev_finish(prev, sc, vals, sh);
   const double a = x ? slot_value(prev, vals, sc, sa) - slot_value(prev, vals, sc, sb) : 0.0;
   const double b = 1.0;
   double s = 0.0;
-  auto step = [&](size_t q, double xv, double yv, double dv0, double ov) {
+  auto step = [&](size_t q, double xv, double yv, double ov) {
     double v = yv;
     if (x) {
       v = (double)(a * xv + b * v);
@@ -667,7 +662,8 @@ __device__ __forceinline__ double slot_value(const PrevSums& p, const double* va
     // fused operation, as in dot_rows_kernel
     double fa, fb;
     if (d) {
-      const double dv = (double)(-1.0 * v + 0.0 * dv0);
+      // D = -q; D's old contents are not read (a stale NaN must not leak in)
+      const double dv = (double)(-1.0 * v + 0.0);
       d[q] = dv;
       fa = ov;
       fb = dv;
@@ -677,26 +673,26 @@ __device__ __forceinline__ double slot_value(const PrevSums& p, const double* va
     }
     s += fa * fb;
   };
-  if (i0 < N) step(q0, x0, y0, d0, o0);
+  if (i0 < N) step(q0, x0, y0, o0);
   for (unsigned i = i0 + stride; i < N; i += stride) {
     const size_t q = compact_to_row(i, r, ld);
-    step(q, x ? x[q] : 0.0, yin[q], d ? d[q] : 0.0, d ? g[q] : u[q]);
+    step(q, x ? x[q] : 0.0, yin[q], d ? g[q] : u[q]);
   }
   publish_partial(block_sum(s, sh), part);
 }
 
-// step and curvature pair: Sn = alpha D + 0.0 Sn, U = U + Sn (all N entries)
+// step and curvature pair: Sn = alpha D, U = U + Sn (all N entries)
 [[maybe_unused]] static __global__ void __launch_bounds__(kBlock) lbfgs_step_kernel(
     size_t N, double alpha, const double* __restrict__ D, double* __restrict__ Sn,
     double* __restrict__ U) {
   for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock) {
-    const double sn = (double)(alpha * (double)D[i] + 0.0 * (double)Sn[i]);
+    const double sn = (double)(alpha * (double)D[i] + 0.0);  // Sn's old contents unread
     Sn[i] = sn;
     U[i] = (double)((double)U[i] + (double)sn);
   }
 }
 
-// Yn = 1.0 Gn + 0.0 Yn, Yn = -1.0 G + 1.0 Yn; partials of <Sn, Yn> and <Gn, Gn>
+// Yn = Gn - G; partials of <Sn, Yn> and <Gn, Gn>
 [[maybe_unused]] static __global__ void __launch_bounds__(kBlock) lbfgs_pair_kernel(
     unsigned N, int r, int ld, const double* __restrict__ Gn, const double* __restrict__ G,
     double* __restrict__ Yn, const double* __restrict__ Sn, double* __restrict__ part) {
@@ -708,7 +704,7 @@ __device__ __forceinline__ double slot_value(const PrevSums& p, const double* va
   for (unsigned i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
     const size_t q = compact_to_row(i, r, ld);
     const double gv = Gn[q], sv = Sn[q];
-    double y = (double)(1.0 * gv + 0.0 * (double)Yn[q]);
+    double y = (double)(1.0 * gv + 0.0);  // Yn's old contents unread
     y = (double)(-1.0 * (double)G[q] + 1.0 * y);
     Yn[q] = y;
     s_sy += sv * y;
@@ -895,12 +891,13 @@ __device__ __forceinline__ void linesearch_partials(int bid, int nblk, int m,
   publish_partial(block_sum(s, sh), part);
 }
 
-// y = a * x + b * y  (elementwise, mixed types allowed)
+// y = a * x + b * y  (elementwise, mixed types allowed); with b = 0 the old y
+// is not read (uninitialised memory may hold NaN patterns)
 template <typename TX, typename TY>
 __global__ void __launch_bounds__(kBlock) axpby(size_t N, double a, const TX* __restrict__ x,
                                                 double b, TY* __restrict__ y) {
   for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock)
-    y[i] = (TY)(a * (double)x[i] + b * (double)y[i]);
+    y[i] = (TY)(a * (double)x[i] + (b != 0.0 ? b * (double)y[i] : 0.0));
 }
 
 // y = a * x + b * y with a = sc[sa] - sc[sb] (ratio == 0) or sc[sa] / sc[sb]
@@ -912,7 +909,7 @@ __global__ void __launch_bounds__(kBlock) axpby_slots(size_t N, const double* __
                                                       T* __restrict__ y) {
   const double a = ratio ? sc[sa] / sc[sb] : sc[sa] - sc[sb];
   for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock)
-    y[i] = (T)(a * (double)x[i] + b * (double)y[i]);
+    y[i] = (T)(a * (double)x[i] + (b != 0.0 ? b * (double)y[i] : 0.0));
 }
 
 // y = a * x + b * y with a = sign * sc[slot] (device-resident coefficient)
@@ -922,7 +919,7 @@ __global__ void __launch_bounds__(kBlock) axpby_dev(size_t N, const double* __re
                                                     double b, T* __restrict__ y) {
   const double a = sign * sc[slot];
   for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock)
-    y[i] = (T)(a * (double)x[i] + b * (double)y[i]);
+    y[i] = (T)(a * (double)x[i] + (b != 0.0 ? b * (double)y[i] : 0.0));
 }
 
 // z = x + y (z may alias x or y), with conversion

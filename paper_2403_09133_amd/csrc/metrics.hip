@@ -168,6 +168,7 @@ double dual_lambda_min(Problem& P, const double* lam, int max_steps, hipStream_t
   Qb.alloc((size_t)kmax * n);
   y.alloc(n);
   c.alloc(kmax + 1);
+  Qb.zero(s);
   const int gridn = (n + 255) / 256;
   start_vector<<<gridn, 256, 0, s>>>(n, Qb.p);
   dot_to_slot<double, double>(P, n, Qb.p, Qb.p, 1.0, S_GEN, s);

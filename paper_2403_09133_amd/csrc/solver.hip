@@ -118,9 +118,11 @@ static int alm_ld(const Problem& P, int r) {
 static void alm_alloc(AlmState& A, int n, int m, int r, int ld, int mem, hipStream_t s) {
   A.n = n; A.m = m; A.r = r; A.ld = ld;
   const size_t N = (size_t)n * ld;
+  // every array starts zeroed (padding columns must stay zero; no kernel may
+  // meet a stale value)
   for (DevBuf<double>* b : {&A.G, &A.Gn, &A.D, &A.Q, &A.CD, &A.Sn, &A.Yn}) {
     b->alloc(N);
-    if (ld != r) b->zero(s);
+    b->zero(s);
   }
   A.p1.alloc(m); A.p2.alloc(m);
 
@@ -131,7 +133,8 @@ static void alm_alloc(AlmState& A, int n, int m, int r, int ld, int mem, hipStre
   for (int i = 0; i < mem; ++i) {
     A.S[i].alloc(N);
     A.Y[i].alloc(N);
-    if (ld != r) { A.S[i].zero(s); A.Y[i].zero(s); }
+    A.S[i].zero(s);
+    A.Y[i].zero(s);
   }
   A.head = A.count = 0;
 }

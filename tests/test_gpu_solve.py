@@ -234,3 +234,31 @@ def test_rank_growth_matches_oracle(device, name):
         assert rK["admm_iters"] == refK["phase2"]["iters"] == K
         assert abs(rK["kkt"] - refK["phase2"]["kkt"]) <= 1e-5 * refK["phase2"]["kkt"]
         assert abs(rK["obj"] - refK["metrics"]["obj"]) <= 1e-9 * max(1.0, abs(refK["metrics"]["obj"]))
+
+
+def test_solves_ignore_stale_memory(device):
+    """Buffers the library allocates may hold whatever earlier work left in
+    recycled device memory.  A solve must not read such values: a kernel that
+    combined 0 x (old content) once turned NaN patterns left in memory into a
+    NaN search direction.  Here device memory is filled with NaN and released
+    before the solves, whose results must equal those of solves made before."""
+    import torch
+    from paper_2403_09133_amd import Context
+    cases = [(CASES["maxcut_er200"][0], 8), (CASES["generic_10x8"][0], 6),
+             (sdpgen.min_bisection_er(60, 0.1, 3, "unit"), 6)]
+    before = []
+    for p, r0 in cases:
+        U0 = sdpgen.random_init_U(p.n, r0, 3)
+        with Context(p) as ctx:
+            before.append(ctx.admm_solve([U0], _lib_opts(p, r0))[0])
+    torch.cuda.synchronize()
+    junk = torch.full((1 << 29,), float("nan"), dtype=torch.float64, device=device)  # 4 GiB
+    torch.cuda.synchronize()
+    del junk
+    torch.cuda.empty_cache()
+    for (p, r0), ref in zip(cases, before):
+        U0 = sdpgen.random_init_U(p.n, r0, 3)
+        with Context(p) as ctx:
+            res = ctx.admm_solve([U0], _lib_opts(p, r0))[0]
+        assert res["status"] == ref["status"] == 0
+        assert res["obj"] == ref["obj"] and res["admm_iters"] == ref["admm_iters"]
