@@ -1,11 +1,18 @@
 """Learned warm start as shipped (paper_2403_09133_amd/data/gnn_maxcut.npz):
-prediction on graphs of the training range, the fallback rules, and a solve
-started from the predicted multipliers reaching the cold solve's objective."""
+prediction on graphs of the training range and the fallback rules; what the
+network learned (its multipliers against the solved ones, beside the
+degree-only fit); and a solve started from the predicted multipliers, held to
+the cold solve's bar.
+
+What the network does not give: a faster solve.  Over 48 held-out graphs the
+learned start neither shortens the solve nor its iteration count significantly
+(profiles/warmstart_maxcut_c5a_eval.md), so no test claims a speed-up."""
 import math
 
 import numpy as np
 import pytest
 
+import oracle
 import sdpgen
 
 pytestmark = pytest.mark.gpu
@@ -28,7 +35,41 @@ def test_predict_inside_and_outside_training_range():
     assert preds[2]["lambda0"] is None and "training range" in preds[2]["reason"]
 
 
-def test_warm_solve_matches_cold_objective():
+def test_network_beats_degree_fit():
+    """On held-out graphs the predicted multipliers are within 15% (norm-wise)
+    of the solved ones y*, and at most half the error of the best fit of y*
+    on the weighted degree (a * sum_k |w_jk| + b, fitted on these graphs)."""
+    from paper_2403_09133_amd import warmstart as W
+    ws = W.WarmStart.load()
+    probs = W.instances(4, W.HELDOUT_SEED0 + 200)
+    labels = W.make_labels(probs)
+    keep = [i for i, l in enumerate(labels) if l["status"] == 0]
+    assert len(keep) >= 3
+    q = W.evaluate_loss(ws.theta, [probs[i] for i in keep], [labels[i] for i in keep], ws.y_scale)
+    print(f"[test] y_hat error {q['val_y_rel']:.3f}, degree fit {q['val_y_rel_degree_fit']:.3f}", flush=True)
+    assert q["val_y_rel"] <= 0.15
+    assert q["val_y_rel"] <= 0.5 * q["val_y_rel_degree_fit"]
+
+
+def _certified_interval(p, Uh, lam):
+    # MaxCut: the constraints sum to the identity, so y + lambda_min 1 is dual
+    # feasible and b^T y + n min(0, lambda_min) bounds the optimum from below;
+    # the cost of U U^T bounds it from above
+    obj = oracle.operators.cost_inner(p, Uh, Uh)
+    lmin = oracle.metrics.lambda_min(p, lam)
+    return float(p.b @ -lam) + p.n * min(0.0, lmin), obj
+
+
+def test_warm_solve_meets_the_cold_bar():
+    """Cold start, learned start, and learned start under warm_check, from the
+    same random U0: all meet eq. (stop) at 1e-6, the method's stop test.  At a
+    rank below the Barvinok-Pataki bound eq. (stop) certifies a stationary
+    point of the factored problem, whose dual slack can keep a small negative
+    eigenvalue: the Appendix-B dual infeasibility and gap of such a point have
+    been seen at 2.3e-6 and -4.2e-6 on this graph, so they are held to 1e-5
+    (primal infeasibility to 2e-6).  The correctness check is that the two
+    objectives lie in each other's certified interval (both bound the optimum,
+    see test_c2_family_matches_oracle)."""
     from paper_2403_09133_amd import Context, warmstart as W
     from paper_2403_09133_amd.params import solver_options
     ws = W.WarmStart.load()
@@ -38,12 +79,19 @@ def test_warm_solve_matches_cold_objective():
     U0 = W.random_start(p, r0)
     with Context(p) as ctx:
         cold = ctx.admm_solve([U0], solver_options("maxcut", p.n, r0))[0]
+        sc = ctx.get_solution(0, cold["rank"])
         warm = ctx.admm_solve([U0], solver_options("maxcut", p.n, r0), init_lambda=[pr["lambda0"]])[0]
+        sw = ctx.get_solution(0, warm["rank"])
         chk = ctx.admm_solve([U0], solver_options("maxcut", p.n, r0, warm_check=1),
                              init_lambda=[pr["lambda0"]])[0]
     for res in (cold, warm, chk):
-        assert res["kkt"] < 1e-4 and abs(res["gap"]) < 1e-4
-    assert abs(warm["obj"] - cold["obj"]) <= 2e-4 * abs(cold["obj"])
+        assert res["status"] == 0 and res["kkt"] < 1e-6, res
+        assert res["pinf"] <= 2e-6 and res["dinf"] <= 1e-5 and abs(res["gap"]) <= 1e-5, res
+    lo_c, hi_c = _certified_interval(p, 0.5 * (sc[0] + sc[1]), sc[2])
+    lo_w, hi_w = _certified_interval(p, 0.5 * (sw[0] + sw[1]), sw[2])
+    scale = abs(cold["obj"])
+    assert max(lo_c, lo_w) <= min(hi_c, hi_w) + 1e-6 * scale, (lo_c, hi_c, lo_w, hi_w)
+    assert abs(warm["obj"] - cold["obj"]) <= max(hi_c - lo_c, hi_w - lo_w) + 1e-6 * scale
     # with the check on, a rejected learned start continues exactly as the cold start
     if chk["warm_fallback"]:
         assert chk["admm_iters"] == cold["admm_iters"] and chk["obj"] == cold["obj"]
