@@ -88,8 +88,10 @@ def class_kernels(structure: str, r: int, cg_dtype: str, n=None) -> list:
                 cg = f"kpair_cg_vec<{cg_dtype}, {gv}>"
         else:
             cg = f"kpair_rows<{cg_dtype}, {G}, 1>"
-        GV = max(1, G // 2)
-        return [cg, f"k1_pair_v2<{GV}, 0>", f"kpair_grad_v2<{GV}>", f"k1_pair_ls<{GV}>"]
+        # FP64 maps: G / 2 lanes of two columns; 8 lanes of three for r = 17..24
+        X3 = 1 if 16 < r <= 24 else 0
+        GV = 8 if X3 else max(1, G // 2)
+        return [cg, f"k1_pair_v2<{GV}, 0, {X3}>", f"kpair_grad_v2<{GV}, {X3}>", f"k1_pair_ls<{GV}, {X3}>"]
     if structure == "diag":
         # the line search's two maps run as forward maps (counted in that class)
         return [f"k3_diag<{cg_dtype}, {G}>", f"k1_diag<double, {G}, 0|1>", f"k2_diag<double, {G}, 0>",

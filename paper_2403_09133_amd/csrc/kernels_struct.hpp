@@ -166,6 +166,13 @@ __global__ void __launch_bounds__(kBlock) k1_pair(
 // (columns 2l and 2l + 1, exactly the first level of the G-lane tree), then the
 // remaining levels run over GV lanes, and every term is evaluated by the same
 // expression.  Needs rows aligned to 16 bytes (ld even) and r <= 2 GV.
+// X3 = 1 (ranks 17 .. 24 with GV = 8): each lane also holds column 2 GV + lane,
+// so 8 lanes cover 24 columns instead of 16 lanes covering 32 (a third fewer
+// bytes gathered per partner row, twice the constraints per wave in flight);
+// a lane's sum is (pair sum) + third term, the same expression in every map
+// of this form, so the forward maps, the line search and the gradient form
+// agree bit for bit with each other (not with the one-column form).  Needs
+// ld >= 3 GV.
 // Chunks come from the XCD lists: workgroup b serves list b mod kXcds, whose
 // partners all lie in one block of rows, so the partner rows one XCD gathers
 // stay in its L2.
@@ -176,7 +183,7 @@ __device__ __forceinline__ int xchunk_of(const int* __restrict__ xoff, int GV) {
   return c < xoff[x + 1] ? c : -1;
 }
 
-template <int GV, int MODE>
+template <int GV, int MODE, int X3 = 0>
 __global__ void __launch_bounds__(kBlock) k1_pair_v2(
     const int* __restrict__ xoff, const int* __restrict__ chunk_row,
     const int* __restrict__ chunk_start, const int* __restrict__ chunk_end,
@@ -195,10 +202,11 @@ __global__ void __launch_bounds__(kBlock) k1_pair_v2(
   if (chunk < 0) return;
   const int row = chunk_row[chunk];
   const int i0 = chunk_start[chunk], i1 = chunk_end[chunk];
-  const int c0 = 2 * lane;
-  const bool on0 = c0 < r, on1 = c0 + 1 < r;
+  const int c0 = 2 * lane, c2 = 2 * GV + lane;
+  const bool on0 = c0 < r, on1 = c0 + 1 < r, on2 = X3 && c2 < r;
   const d2 uj = *reinterpret_cast<const d2*>(U + row * ld + c0);
   const d2 vj = *reinterpret_cast<const d2*>(V + row * ld + c0);
+  const double uj2 = X3 ? U[row * ld + c2] : 0.0, vj2 = X3 ? V[row * ld + c2] : 0.0;
   const double mult = MODE == 0 ? scale : 1.0;
   for (int i = i0; i < i1; i += kUnroll) {
     const int cnt = min(kUnroll, i1 - i);
@@ -206,10 +214,15 @@ __global__ void __launch_bounds__(kBlock) k1_pair_v2(
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) k[u] = u < cnt ? pk[i + u] : row;
     d2 vk[kUnroll], uk[kUnroll];
+    double vk2[kUnroll], uk2[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       vk[u] = *reinterpret_cast<const d2*>(V + k[u] * ld + c0);
       uk[u] = *reinterpret_cast<const d2*>(U + k[u] * ld + c0);
+      if (X3) {
+        vk2[u] = V[k[u] * ld + c2];
+        uk2[u] = U[k[u] * ld + c2];
+      }
     }
     double d[kUnroll], d2s[kUnroll];
 #pragma unroll
@@ -225,6 +238,15 @@ __global__ void __launch_bounds__(kBlock) k1_pair_v2(
       }
       d[u] = s0 + s1;
       d2s[u] = q0 + q1;
+      if (X3) {
+        double s2 = 0.0, q2 = 0.0;
+        if (on2) {
+          s2 += uj2 * vk2[u] + uk2[u] * vj2;
+          if (MODE == 3) q2 += vj2 * vk2[u];
+        }
+        d[u] = d[u] + s2;
+        d2s[u] = d2s[u] + q2;
+      }
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) d[u] = group_sum<GV>(d[u]);
@@ -278,8 +300,9 @@ __global__ void __launch_bounds__(kBlock) k1_pair_v2(
 // the seven sums of the quartic (the order of linesearch_partials):
 //   p2.p2, p1.p2, p1.p1, p0.p2, p0.p1, lam.p1, lam.p2,   p0 = z - b.
 // Nothing m-sized is written: each block leaves its seven partials at
-// part[t * gridDim.x + block].  Groups of at least 4 lanes (GV >= 4).
-template <int GV>
+// part[t * gridDim.x + block].  Groups of at least 4 lanes (GV >= 4); X3 as
+// in k1_pair_v2.
+template <int GV, int X3 = 0>
 __global__ void __launch_bounds__(kBlock) k1_pair_ls(
     const int* __restrict__ xoff, const int* __restrict__ chunk_row,
     const int* __restrict__ chunk_start, const int* __restrict__ chunk_end,
@@ -299,20 +322,26 @@ __global__ void __launch_bounds__(kBlock) k1_pair_ls(
   if (chunk >= 0) {
     const int row = chunk_row[chunk];
     const int i0 = chunk_start[chunk], i1 = chunk_end[chunk];
-    const int c0 = 2 * lane;
-    const bool on0 = c0 < r, on1 = c0 + 1 < r;
+    const int c0 = 2 * lane, c2 = 2 * GV + lane;
+    const bool on0 = c0 < r, on1 = c0 + 1 < r, on2 = X3 && c2 < r;
     const d2 uj = *reinterpret_cast<const d2*>(U + row * ld + c0);
     const d2 dj = *reinterpret_cast<const d2*>(D + row * ld + c0);
+    const double uj2 = X3 ? U[row * ld + c2] : 0.0, dj2 = X3 ? D[row * ld + c2] : 0.0;
     for (int i = i0; i < i1; i += kUnroll) {
       const int cnt = min(kUnroll, i1 - i);
       int k[kUnroll];
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) k[u] = u < cnt ? pk[i + u] : row;
       d2 dk[kUnroll], uk[kUnroll];
+      double dk2[kUnroll], uk2[kUnroll];
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
         dk[u] = *reinterpret_cast<const d2*>(D + k[u] * ld + c0);
         uk[u] = *reinterpret_cast<const d2*>(U + k[u] * ld + c0);
+        if (X3) {
+          dk2[u] = D[k[u] * ld + c2];
+          uk2[u] = U[k[u] * ld + c2];
+        }
       }
       double d[kUnroll], dd[kUnroll];
 #pragma unroll
@@ -328,6 +357,15 @@ __global__ void __launch_bounds__(kBlock) k1_pair_ls(
         }
         d[u] = sa + sb;
         dd[u] = qa + qb;
+        if (X3) {
+          double sc2 = 0.0, qc2 = 0.0;
+          if (on2) {
+            sc2 += uj2 * dk2[u] + uk2[u] * dj2;
+            qc2 += dj2 * dk2[u];
+          }
+          d[u] = d[u] + sc2;
+          dd[u] = dd[u] + qc2;
+        }
       }
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) d[u] = group_sum<GV>(d[u]);
@@ -642,7 +680,10 @@ __global__ void __launch_bounds__(kBlock) kpair_rows(
 // GV = G / 2 lanes, so a group takes the same entries in the same order as a
 // G-lane group of the one-column form, the within-entry sums follow the same
 // tree (a lane adds its two columns first) and the cross-group sums pair the
-// same groups.  The output equals MODE 2's bit for bit.
+// same groups.  The output equals MODE 2's bit for bit.  X3 = 1 (ranks
+// 17 .. 24, GV = 8) adds column 2 GV + lane per lane as in k1_pair_v2, with
+// the entry sums of that form (then 4 groups serve a row, and the output
+// equals the X3 forward map fed to the adjoint, not MODE 2).
 //
 // z (optional): the forward map A(V V^T) as a by-product.  Each entry's inner
 // product is the forward map's expression in the forward map's order, so the
@@ -652,7 +693,7 @@ __global__ void __launch_bounds__(kBlock) kpair_rows(
 // order.  The values are collected in the entries' LDS slots and written as
 // one contiguous run per staged pass.
 // ===========================================================================
-template <int GV>
+template <int GV, int X3 = 0>
 __global__ void __launch_bounds__(kBlock) kpair_grad_v2(
     int n, const int* __restrict__ cptr, const int* __restrict__ ccol,
     const double* __restrict__ cval, double c_scale, const int* __restrict__ inc_ptr,
@@ -674,21 +715,23 @@ __global__ void __launch_bounds__(kBlock) kpair_grad_v2(
   double* cfw = s_cf[hid];
   double* biw = s_bi[hid];
   if (row < n) {  // uniform over the half-wave
-    const int c0 = 2 * lane;
-    const bool on0 = c0 < r, on1 = c0 + 1 < r;
-    double vt0 = 0.0, vt1 = 0.0;
+    const int c0 = 2 * lane, c2 = 2 * GV + lane;
+    const bool on0 = c0 < r, on1 = c0 + 1 < r, on2 = X3 && c2 < r;
+    double vt0 = 0.0, vt1 = 0.0, vt2 = 0.0;
     {
       const d2 v = *reinterpret_cast<const d2*>(V + row * ld + c0);
       if (on0) vt0 = v[0];
       if (on1) vt1 = v[1];
+      if (on2) vt2 = V[row * ld + c2];
     }
-    double acc0 = 0.0, acc1 = 0.0;
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
     if (c_scale != 0.0) {
       for (int e = cptr[row] + grp; e < cptr[row + 1]; e += NG) {
         const int k = ccol[e];
         const double a = c_scale * cval[e];
         if (on0) acc0 += a * V[k * ld + c0];
         if (on1) acc1 += a * V[k * ld + c0 + 1];
+        if (on2) acc2 += a * V[k * ld + c2];
       }
     }
     const int e0 = inc_ptr[row], e1 = inc_ptr[row + 1];
@@ -720,12 +763,16 @@ __global__ void __launch_bounds__(kBlock) kpair_grad_v2(
           p[u] = (ok ? nbw[ju] : row) * ld;
           coef[u] = ok ? cfw[ju] : 0.0;
         }
-        double vp0[kGU], vp1[kGU], d[kGU];
+        double vp0[kGU], vp1[kGU], vp2[kGU], d[kGU];
 #pragma unroll
         for (int u = 0; u < kGU; ++u) {
           const d2 v = *reinterpret_cast<const d2*>(V + p[u] + c0);
           vp0[u] = on0 ? v[0] : 0.0;
           vp1[u] = on1 ? v[1] : 0.0;
+          if (X3) {
+            const double v2 = V[p[u] + c2];
+            vp2[u] = on2 ? v2 : 0.0;
+          }
         }
 #pragma unroll
         for (int u = 0; u < kGU; ++u) {
@@ -733,6 +780,11 @@ __global__ void __launch_bounds__(kBlock) kpair_grad_v2(
           s0 += vt0 * vp0[u] + vp0[u] * vt0;
           s1 += vt1 * vp1[u] + vp1[u] * vt1;
           d[u] = s0 + s1;
+          if (X3) {
+            double s2 = 0.0;
+            s2 += vt2 * vp2[u] + vp2[u] * vt2;
+            d[u] = d[u] + s2;
+          }
         }
 #pragma unroll
         for (int u = 0; u < kGU; ++u) d[u] = group_sum<GV>(d[u]);
@@ -750,6 +802,7 @@ __global__ void __launch_bounds__(kBlock) kpair_grad_v2(
         for (int u = 0; u < kGU; ++u) {
           if (on0) acc0 += coef[u] * vp0[u];
           if (on1) acc1 += coef[u] * vp1[u];
+          if (on2) acc2 += coef[u] * vp2[u];
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -768,10 +821,12 @@ __global__ void __launch_bounds__(kBlock) kpair_grad_v2(
     for (int o = GV; o < HW; o <<= 1) {
       acc0 += __shfl_xor(acc0, o, 64);
       acc1 += __shfl_xor(acc1, o, 64);
+      if (X3) acc2 += __shfl_xor(acc2, o, 64);
     }
     if (grp == 0) {
       if (on0) out[row * ldo + c0] = out_scale * acc0;
       if (on1) out[row * ldo + c0 + 1] = out_scale * acc1;
+      if (on2) out[row * ldo + c2] = out_scale * acc2;
     }
   }
 }

@@ -104,25 +104,33 @@ static bool pair_v2_ok(const Problem& P, const void* U, const void* V, int r, in
          (reinterpret_cast<uintptr_t>(V) % 16) == 0;
 }
 
-#define LORADS_DISPATCH_V2(G, CALL)                      \
-  do {                                                   \
-    switch (G) {                                         \
-      case 2: { constexpr int GV = 1; CALL; } break;     \
-      case 4: { constexpr int GV = 2; CALL; } break;     \
-      case 8: { constexpr int GV = 4; CALL; } break;     \
-      case 16: { constexpr int GV = 8; CALL; } break;    \
-      default: { constexpr int GV = 16; CALL; } break;   \
-    }                                                    \
+// GV lanes per constraint (pair_v2_lanes) and the third-column form X3 for
+// ranks 17 .. 24 (G = lane_group(r) = 32 there, so ld >= 32 >= 3 GV)
+#define LORADS_DISPATCH_V2(G, r, CALL)                                   \
+  do {                                                                   \
+    switch (G) {                                                         \
+      case 2: { constexpr int GV = 1, X3 = 0; CALL; } break;             \
+      case 4: { constexpr int GV = 2, X3 = 0; CALL; } break;             \
+      case 8: { constexpr int GV = 4, X3 = 0; CALL; } break;             \
+      case 16: { constexpr int GV = 8, X3 = 0; CALL; } break;            \
+      default:                                                           \
+        if ((r) <= 24) { constexpr int GV = 8, X3 = 1; CALL; }           \
+        else { constexpr int GV = 16, X3 = 0; CALL; }                    \
+        break;                                                           \
+    }                                                                    \
   } while (0)
 
-// groups of G / 2 >= 4 lanes (the fused line search stages per group)
-#define LORADS_DISPATCH_LS(G, CALL)                      \
-  do {                                                   \
-    switch (G) {                                         \
-      case 8: { constexpr int GV = 4; CALL; } break;     \
-      case 16: { constexpr int GV = 8; CALL; } break;    \
-      default: { constexpr int GV = 16; CALL; } break;   \
-    }                                                    \
+// groups of at least 4 lanes (the fused line search stages per group)
+#define LORADS_DISPATCH_LS(G, r, CALL)                                   \
+  do {                                                                   \
+    switch (G) {                                                         \
+      case 8: { constexpr int GV = 4, X3 = 0; CALL; } break;             \
+      case 16: { constexpr int GV = 8, X3 = 0; CALL; } break;            \
+      default:                                                           \
+        if ((r) <= 24) { constexpr int GV = 8, X3 = 1; CALL; }           \
+        else { constexpr int GV = 16, X3 = 0; CALL; }                    \
+        break;                                                           \
+    }                                                                    \
   } while (0)
 
 // ---------------------------------------------------------------------------
@@ -145,7 +153,7 @@ static void op_forward_impl(Problem& P, const T* U, const T* V, int r, int ld, T
   } else if (P.structure == LORADS_STRUCT_PAIR && std::is_same<T, double>::value &&
              pair_v2_ok(P, U, V, r, ld)) {
     check_pair_offsets(P, ld);
-    LORADS_DISPATCH_V2(G, (k1_pair_v2<GV, 0><<<xchunk_grid(P, GV), kBlock, 0, s>>>(
+    LORADS_DISPATCH_V2(G, r, (k1_pair_v2<GV, 0, X3><<<xchunk_grid(P, GV), kBlock, 0, s>>>(
                               P.xchunk_off.p, P.xchunk_row.p, P.xchunk_start.p, P.xchunk_end.p, P.pk.p,
                               P.pcoef.p, P.pair_coef, (const double*)U, (const double*)V, r, ld,
                               (double*)z, scale, nullptr, nullptr, 0.0, nullptr)));
@@ -197,7 +205,7 @@ static void op_forward_w_impl(Problem& P, const double* U, const double* V, int 
                              nullptr, 0)));
   } else if (pair_v2_ok(P, U, V, r, ld)) {
     check_pair_offsets(P, ld);
-    LORADS_DISPATCH_V2(G, (k1_pair_v2<GV, 1><<<xchunk_grid(P, GV), kBlock, 0, s>>>(
+    LORADS_DISPATCH_V2(G, r, (k1_pair_v2<GV, 1, X3><<<xchunk_grid(P, GV), kBlock, 0, s>>>(
                               P.xchunk_off.p, P.xchunk_row.p, P.xchunk_start.p, P.xchunk_end.p, P.pk.p,
                               P.pcoef.p, P.pair_coef, U, V, r, ld, z, 1.0, lam, P.b.p, rho, w)));
   } else if (P.structure == LORADS_STRUCT_PAIR) {
@@ -226,7 +234,7 @@ void op_forward_pair(Problem& P, const double* U, const double* D, int r, int ld
     check_pair_offsets(P, ld);
     const int G = lane_group(r);
     if (pair_v2_ok(P, U, D, r, ld)) {
-      LORADS_DISPATCH_V2(G, (k1_pair_v2<GV, 3><<<xchunk_grid(P, GV), kBlock, 0, s>>>(
+      LORADS_DISPATCH_V2(G, r, (k1_pair_v2<GV, 3, X3><<<xchunk_grid(P, GV), kBlock, 0, s>>>(
                                 P.xchunk_off.p, P.xchunk_row.p, P.xchunk_start.p, P.xchunk_end.p,
                                 P.pk.p, P.pcoef.p, P.pair_coef, U, D, r, ld, p1, 1.0, nullptr, nullptr,
                                 0.0, p2)));
@@ -248,10 +256,10 @@ bool op_linesearch_pair(Problem& P, const double* U, const double* D, int r, int
                         const double* z, const double* lam, double* part, hipStream_t s) {
   const int G = lane_group(r);
   if (!pair_v2_ok(P, U, D, r, ld) || G < 8) return false;
-  if (xchunk_grid(P, G / 2) != ls_blocks(P, r)) fail(LORADS_EINVAL, "line-search grid mismatch");
+  if (xchunk_grid(P, pair_v2_lanes(r)) != ls_blocks(P, r)) fail(LORADS_EINVAL, "line-search grid mismatch");
   check_pair_offsets(P, ld);
   P.prof.run(3, bytes_linesearch_pair(P, r), s, [&] {
-    LORADS_DISPATCH_LS(G, (k1_pair_ls<GV><<<ls_blocks(P, r), kBlock, 0, s>>>(
+    LORADS_DISPATCH_LS(G, r, (k1_pair_ls<GV, X3><<<ls_blocks(P, r), kBlock, 0, s>>>(
                               P.xchunk_off.p, P.xchunk_row.p, P.xchunk_start.p, P.xchunk_end.p,
                               P.pk.p, P.pcoef.p, P.pair_coef, U, D, r, ld, z, P.b.p, lam, part)));
     HIPCHK(hipGetLastError());
@@ -342,7 +350,7 @@ void op_grad_pair(Problem& P, const double* U, int r, int ld, double rho, double
     if (r > 4 * G) fail(LORADS_EINVAL, "rank above 256 is not supported");
     if (v2) {
       const int grid = std::max(1, (P.n + kBlock / 32 - 1) / (kBlock / 32));  // two rows per wave
-      LORADS_DISPATCH_V2(G, (kpair_grad_v2<GV><<<grid, kBlock, 0, s>>>(
+      LORADS_DISPATCH_V2(G, r, (kpair_grad_v2<GV, X3><<<grid, kBlock, 0, s>>>(
                                 P.n, P.cptr.p, P.ccol.p, P.cval.p, 1.0, P.inc_ptr.p, P.inc_nb.p,
                                 P.pair_coef, U, r, ld, out, ldo, out_scale, P.inc_lb.p, rho,
                                 P.rptr.p, z)));

@@ -299,11 +299,15 @@ struct CgXpartsScope {
 };
 // grid of the fused line-search pass at rank r (groups of G/2 lanes), i.e. its
 // count of block partials
-inline int ls_blocks(const Problem& P, int r) {
+// lanes per constraint of the FP64 two-column maps at rank r: half the
+// power-of-two group, except 8 lanes with a third column each for r = 17 .. 24
+inline int pair_v2_lanes(int r) {
+  if (r > 16 && r <= 24) return 8;
   int g = 1;
   while (g < r && g < 64) g <<= 1;
-  return xchunk_grid(P, std::max(1, g / 2));
+  return std::max(1, g / 2);
 }
+inline int ls_blocks(const Problem& P, int r) { return xchunk_grid(P, pair_v2_lanes(r)); }
 // gradient form for PAIR problems with a uniform coefficient:
 //   out = out_scale (C + A*(lam + rho (A(U U^T) - b))) U
 // with lam and b read per incident entry (refresh_inc_lam after lam changes);
