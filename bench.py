@@ -79,13 +79,15 @@ def class_kernels(structure: str, r: int, cg_dtype: str, n=None) -> list:
         esz = 4 if cg_dtype == "float" else 8
         vw = 16 // esz
         ld = (r + 64 // esz - 1) // (64 // esz) * (64 // esz)
-        gv = pow2_group((r + vw - 1) // vw)
-        if gv * vw <= ld and gv <= 16:
+        # FP64 at ranks 17..24: 8 lanes with an extra 8-byte vector each
+        x3 = 1 if esz == 8 and 16 < r <= 24 and ld >= 24 else 0
+        gv = 16 // vw if x3 else pow2_group((r + vw - 1) // vw)
+        if x3 or (gv * vw <= ld and gv <= 16):
             # rows of [W | P] above one XCD's 4 MiB L2: split by partner block
             if n is not None and n * 2 * ld * esz > (4 << 20):
-                cg = f"kpair_cg_xvec<{cg_dtype}, {gv}> + xcg_combine<{cg_dtype}>"
+                cg = f"kpair_cg_xvec<{cg_dtype}, {gv}, {x3}> + xcg_combine<{cg_dtype}>"
             else:
-                cg = f"kpair_cg_vec<{cg_dtype}, {gv}>"
+                cg = f"kpair_cg_vec<{cg_dtype}, {gv}, {x3}>"
         else:
             cg = f"kpair_rows<{cg_dtype}, {G}, 1>"
         # FP64 maps: G / 2 lanes of two columns; 8 lanes of three for r = 17..24

@@ -845,22 +845,30 @@ __global__ void __launch_bounds__(kBlock) kpair_grad_v2(
 // is padded to a whole number of steps with entries (own row, coefficient 0),
 // so the step loop runs without lane guards.  The FP32 form's launch bound
 // asks for 7 waves per SIMD (at most 72 VGPRs; the unbounded allocation gives
-// 6), which measured 3% faster on the completion solves; the FP64 form keeps
-// its natural allocation (7 waves would spill).
+// 6), which measured 3% faster on the completion solves; the FP64 form and
+// the X3 forms keep their natural allocation (7 waves would spill).
+// X3 = 1 (ranks 17 .. 24, G VW = 16): each lane also holds VW / 2 columns
+// from G VW + lane VW / 2 on, loaded as one 8-byte vector, so G lanes cover
+// 24 columns (a quarter fewer bytes gathered than 32-column groups, twice the
+// constraints per wave); the lane's chain runs on over those columns.  Needs
+// ld >= 24.  The solver uses it in FP64 (whose 64-byte rows hold 24 columns
+// at these ranks, too few for 16 lanes of two).
 // ===========================================================================
-template <typename T, int G>
-__global__ void __launch_bounds__(kBlock, (sizeof(T) == 4 ? 7 : 1)) kpair_cg_vec(
+template <typename T, int G, int X3 = 0>
+__global__ void __launch_bounds__(kBlock, (sizeof(T) == 4 && !X3 ? 7 : 1)) kpair_cg_vec(
     int n, const int* __restrict__ inc_ptr, const int* __restrict__ inc_nb,
     const int* __restrict__ inc_id, const T* __restrict__ pcoef, double pair_coef,
     const T* __restrict__ WP, int ld, int r, T* __restrict__ Q, double* __restrict__ sc,
     int parity, double* __restrict__ part) {
   using A = typename OpAcc<T>::type;
   constexpr int VW = 16 / (int)sizeof(T);
+  constexpr int VH = X3 ? VW / 2 : 1;  // columns of the lane's extra 8-byte vector
   constexpr int NG = 64 / G;
   constexpr int CH = kPairStage;
   constexpr int STEP = NG * kUnroll;  // entries per step of a wave (divides CH)
   static_assert(CH % STEP == 0, "staging chunk must hold whole steps");
   typedef T vec __attribute__((ext_vector_type(16 / sizeof(T))));
+  typedef T hvec __attribute__((ext_vector_type(8 / sizeof(T))));
   __shared__ double sh[kBlock / 64];
   __shared__ int s_nb[kBlock / 64][CH];
   __shared__ A s_cf[kBlock / 64][CH];
@@ -888,6 +896,15 @@ __global__ void __launch_bounds__(kBlock, (sizeof(T) == 4 ? 7 : 1)) kpair_cg_vec
         pt[v] = (A)p[v];
         acc[v] = 0;
       }
+    }
+    const int cx = G * VW + lane * VH;  // first extra column (X3)
+    const int xsh = (cx - c0) * (int)sizeof(T);
+    A accx[VH], ptx[VH], vtx[VH];
+#pragma unroll
+    for (int h = 0; h < VH; ++h) {
+      vtx[h] = X3 ? (A)WP[row * ldw + cx + h] : (A)0;
+      ptx[h] = X3 ? (A)WP[row * ldw + ld + cx + h] : (A)0;
+      accx[h] = 0;
     }
     const A a2u = (A)(pair_coef * pair_coef);
     const int own = row * rowb;
@@ -925,10 +942,15 @@ __global__ void __launch_bounds__(kBlock, (sizeof(T) == 4 ? 7 : 1)) kpair_cg_vec
           coef[u] = cfw[j + u * NG];
         }
         vec wv[kUnroll], pv[kUnroll];
+        hvec wx[kUnroll], px[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           wv[u] = __builtin_bit_cast(vec, __builtin_amdgcn_raw_buffer_load_b128(rs, off[u], 0, 0));
           pv[u] = __builtin_bit_cast(vec, __builtin_amdgcn_raw_buffer_load_b128(rs, off[u], pofs, 0));
+          if (X3) {
+            wx[u] = __builtin_bit_cast(hvec, __builtin_amdgcn_raw_buffer_load_b64(rs, off[u] + xsh, 0, 0));
+            px[u] = __builtin_bit_cast(hvec, __builtin_amdgcn_raw_buffer_load_b64(rs, off[u] + xsh, pofs, 0));
+          }
         }
         A d[kUnroll];
 #pragma unroll
@@ -941,14 +963,26 @@ __global__ void __launch_bounds__(kBlock, (sizeof(T) == 4 ? 7 : 1)) kpair_cg_vec
             s = fma(pt[v], (A)wv[u][v], s);
             s = fma((A)pv[u][v], vt[v], s);
           }
+          if (X3) {
+#pragma unroll
+            for (int h = 0; h < VH; ++h) {
+              s = fma(ptx[h], (A)wx[u][h], s);
+              s = fma((A)px[u][h], vtx[h], s);
+            }
+          }
           d[u] = s;
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) d[u] = group_sum<G>(d[u]) * coef[u];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u)
+        for (int u = 0; u < kUnroll; ++u) {
 #pragma unroll
           for (int v = 0; v < VW; ++v) acc[v] += d[u] * (A)wv[u][v];
+          if (X3) {
+#pragma unroll
+            for (int h = 0; h < VH; ++h) accx[h] += d[u] * (A)wx[u][h];
+          }
+        }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
@@ -957,6 +991,11 @@ __global__ void __launch_bounds__(kBlock, (sizeof(T) == 4 ? 7 : 1)) kpair_cg_vec
 #pragma unroll
     for (int v = 0; v < VW; ++v)
       for (int o = G; o < 64; o <<= 1) acc[v] += __shfl_xor(acc[v], o, 64);
+    if (X3) {
+#pragma unroll
+      for (int h = 0; h < VH; ++h)
+        for (int o = G; o < 64; o <<= 1) accx[h] += __shfl_xor(accx[h], o, 64);
+    }
     if (grp == 0) {
       const double gamma = sc[S_GAMMA], rho = sc[S_RHO];
 #pragma unroll
@@ -966,6 +1005,17 @@ __global__ void __launch_bounds__(kBlock, (sizeof(T) == 4 ? 7 : 1)) kpair_cg_vec
           const T qv = (T)(gamma * (double)pt[v] + rho * (double)acc[v]);
           Q[row * ld + c] = qv;
           pq += (double)pt[v] * (double)qv;
+        }
+      }
+      if (X3) {
+#pragma unroll
+        for (int h = 0; h < VH; ++h) {
+          const int c = cx + h;
+          if (c < r) {
+            const T qv = (T)(gamma * (double)ptx[h] + rho * (double)accx[h]);
+            Q[row * ld + c] = qv;
+            pq += (double)ptx[h] * (double)qv;
+          }
         }
       }
     }
@@ -982,22 +1032,24 @@ __global__ void __launch_bounds__(kBlock, (sizeof(T) == 4 ? 7 : 1)) kpair_cg_vec
 // rho^-1 (Q - gamma P) for the row, sum_e a^2 (<P_row, W_p> + <P_p, W_row>) W_p,
 // to xparts[(x n + row) ld + c]; an XCD thus gathers the [W | P] rows of one
 // block only.  Otherwise the computation of kpair_cg_vec (same staging,
-// buffer loads and per-group order within the run).  xcg_combine then forms
+// buffer loads, per-group order within the run and X3 form).  xcg_combine then forms
 // Q = gamma P + rho sum_x xparts[x] in block order and the partials of <P, Q>.
 // ===========================================================================
-template <typename T, int G>
-__global__ void __launch_bounds__(kBlock, (sizeof(T) == 4 ? 7 : 1)) kpair_cg_xvec(
+template <typename T, int G, int X3 = 0>
+__global__ void __launch_bounds__(kBlock, (sizeof(T) == 4 && !X3 ? 7 : 1)) kpair_cg_xvec(
     int n, const int* __restrict__ inc_xptr, const int* __restrict__ inc_nb,
     const int* __restrict__ inc_id, const T* __restrict__ pcoef, double pair_coef,
     const T* __restrict__ WP, int ld, int r, typename OpAcc<T>::type* __restrict__ xparts,
     const double* __restrict__ sc, int parity) {
   using A = typename OpAcc<T>::type;
   constexpr int VW = 16 / (int)sizeof(T);
+  constexpr int VH = X3 ? VW / 2 : 1;  // columns of the lane's extra 8-byte vector
   constexpr int NG = 64 / G;
   constexpr int CH = kPairStage;
   constexpr int STEP = NG * kUnroll;
   static_assert(CH % STEP == 0, "staging chunk must hold whole steps");
   typedef T vec __attribute__((ext_vector_type(16 / sizeof(T))));
+  typedef T hvec __attribute__((ext_vector_type(8 / sizeof(T))));
   __shared__ int s_nb[kBlock / 64][CH];
   __shared__ A s_cf[kBlock / 64][CH];
   if (sc[S_DONE + parity] != 0.0) return;
@@ -1024,6 +1076,15 @@ __global__ void __launch_bounds__(kBlock, (sizeof(T) == 4 ? 7 : 1)) kpair_cg_xve
       pt[v] = (A)p[v];
       acc[v] = 0;
     }
+  }
+  const int cx = G * VW + lane * VH;  // first extra column (X3)
+  const int xsh = (cx - c0) * (int)sizeof(T);
+  A accx[VH], ptx[VH], vtx[VH];
+#pragma unroll
+  for (int h = 0; h < VH; ++h) {
+    vtx[h] = X3 ? (A)WP[row * ldw + cx + h] : (A)0;
+    ptx[h] = X3 ? (A)WP[row * ldw + ld + cx + h] : (A)0;
+    accx[h] = 0;
   }
   const A a2u = (A)(pair_coef * pair_coef);
   const int own = row * rowb;
@@ -1061,10 +1122,15 @@ __global__ void __launch_bounds__(kBlock, (sizeof(T) == 4 ? 7 : 1)) kpair_cg_xve
         coef[u] = cfw[j + u * NG];
       }
       vec wv[kUnroll], pv[kUnroll];
+      hvec wx[kUnroll], px[kUnroll];
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
         wv[u] = __builtin_bit_cast(vec, __builtin_amdgcn_raw_buffer_load_b128(rs, off[u], 0, 0));
         pv[u] = __builtin_bit_cast(vec, __builtin_amdgcn_raw_buffer_load_b128(rs, off[u], pofs, 0));
+        if (X3) {
+          wx[u] = __builtin_bit_cast(hvec, __builtin_amdgcn_raw_buffer_load_b64(rs, off[u] + xsh, 0, 0));
+          px[u] = __builtin_bit_cast(hvec, __builtin_amdgcn_raw_buffer_load_b64(rs, off[u] + xsh, pofs, 0));
+        }
       }
       A d[kUnroll];
 #pragma unroll
@@ -1076,14 +1142,26 @@ __global__ void __launch_bounds__(kBlock, (sizeof(T) == 4 ? 7 : 1)) kpair_cg_xve
           sm = fma(pt[v], (A)wv[u][v], sm);
           sm = fma((A)pv[u][v], vt[v], sm);
         }
+        if (X3) {
+#pragma unroll
+          for (int h = 0; h < VH; ++h) {
+            sm = fma(ptx[h], (A)wx[u][h], sm);
+            sm = fma((A)px[u][h], vtx[h], sm);
+          }
+        }
         d[u] = sm;
       }
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) d[u] = group_sum<G>(d[u]) * coef[u];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u)
+      for (int u = 0; u < kUnroll; ++u) {
 #pragma unroll
         for (int v = 0; v < VW; ++v) acc[v] += d[u] * (A)wv[u][v];
+        if (X3) {
+#pragma unroll
+          for (int h = 0; h < VH; ++h) accx[h] += d[u] * (A)wx[u][h];
+        }
+      }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -1092,12 +1170,24 @@ __global__ void __launch_bounds__(kBlock, (sizeof(T) == 4 ? 7 : 1)) kpair_cg_xve
 #pragma unroll
   for (int v = 0; v < VW; ++v)
     for (int o = G; o < 64; o <<= 1) acc[v] += __shfl_xor(acc[v], o, 64);
+  if (X3) {
+#pragma unroll
+    for (int h = 0; h < VH; ++h)
+      for (int o = G; o < 64; o <<= 1) accx[h] += __shfl_xor(accx[h], o, 64);
+  }
   if (grp == 0) {
     A* dst = xparts + ((size_t)x * n + row) * ld;
 #pragma unroll
     for (int v = 0; v < VW; ++v) {
       const int c = c0 + v;
       if (c < r) dst[c] = acc[v];
+    }
+    if (X3) {
+#pragma unroll
+      for (int h = 0; h < VH; ++h) {
+        const int c = cx + h;
+        if (c < r) dst[c] = accx[h];
+      }
     }
   }
 }

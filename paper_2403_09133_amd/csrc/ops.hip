@@ -380,10 +380,14 @@ int op_cg(Problem& P, const T* W, int ldw, int r, int ld, const T* Pd, const T* 
   if (P.structure != LORADS_STRUCT_PAIR && (ld != r || ldw != r || P2))
     fail(LORADS_EINVAL, "CG buffers must be compact");
   // PAIR on the CG layout: one kernel with 16-byte column vectors per lane
+  // (FP64 at ranks 17 .. 24: 8 lanes with an extra 8-byte vector each, 24
+  // columns; in FP32 the 8-lane 32-column form measured faster than 4 lanes
+  // with the extra vector, 327 against 483 us at m = 15.7M)
   constexpr int VW = 16 / (int)sizeof(T);
-  const int gv = pow2_group((r + VW - 1) / VW);
+  const bool x3 = sizeof(T) == 8 && r > 16 && r <= 24 && ld >= 24;
+  const int gv = x3 ? 16 / VW : pow2_group((r + VW - 1) / VW);
   const bool vec = P.structure == LORADS_STRUCT_PAIR && P2 && P2 == W + ld && ldw == 2 * ld &&
-                   ld % VW == 0 && gv * VW <= ld && gv <= 16 &&
+                   ld % VW == 0 && (x3 || (gv * VW <= ld && gv <= 16)) &&
                    (size_t)P.n * ldw * sizeof(T) < ((size_t)1 << 31);
   // factor arrays larger than one XCD's L2 (with the caller's partials): the
   // operator split by partner block, then the combining pass
@@ -427,38 +431,42 @@ int op_cg(Problem& P, const T* W, int ldw, int r, int ld, const T* Pd, const T* 
     if (xcd) {
       Acc* xp = static_cast<Acc*>(P.cg_xparts);
       const int xgrid = kXcds * ((P.n + kBlock / 64 - 1) / (kBlock / 64));
-#define LORADS_CG_XVEC(GG)                                                                         \
-  kpair_cg_xvec<T, GG><<<xgrid, kBlock, 0, s>>>(P.n, P.inc_xptr.p, P.inc_nb.p, P.inc_id.p,         \
-                                                pc<T>(P), P.pair_coef, W, ld, r, xp, sc, parity)
-      switch (gv) {
-        case 1: LORADS_CG_XVEC(1); break;
-        case 2: LORADS_CG_XVEC(2); break;
-        case 4: LORADS_CG_XVEC(4); break;
-        case 8: LORADS_CG_XVEC(8); break;
-        default: LORADS_CG_XVEC(16); break;
+#define LORADS_CG_XVEC(GG, X)                                                                      \
+  kpair_cg_xvec<T, GG, X><<<xgrid, kBlock, 0, s>>>(P.n, P.inc_xptr.p, P.inc_nb.p, P.inc_id.p,      \
+                                                   pc<T>(P), P.pair_coef, W, ld, r, xp, sc, parity)
+      if (x3) {
+        if constexpr (sizeof(T) == 8) LORADS_CG_XVEC(8, 1);
+      } else switch (gv) {
+        case 1: LORADS_CG_XVEC(1, 0); break;
+        case 2: LORADS_CG_XVEC(2, 0); break;
+        case 4: LORADS_CG_XVEC(4, 0); break;
+        case 8: LORADS_CG_XVEC(8, 0); break;
+        default: LORADS_CG_XVEC(16, 0); break;
       }
 #undef LORADS_CG_XVEC
       const int cgrid = grid_for((size_t)P.n * r, 1024);
       P.ensure_part(cgrid);
       xcg_combine<T><<<cgrid, kBlock, 0, s>>>(P.n, r, ld, xp, W, Q, sc, parity, P.part.p);
     } else if (vec) {
-#define LORADS_CG_VEC(GG)                                                                          \
+#define LORADS_CG_VEC(GG, X)                                                                       \
   do {                                                                                             \
     if (ext)                                                                                       \
-      hipExtLaunchKernelGGL(kpair_cg_vec<T, GG>, dim3(grid), dim3(kBlock), 0, s, ev0, ev1, 0u,      \
+      hipExtLaunchKernelGGL(kpair_cg_vec<T, GG, X>, dim3(grid), dim3(kBlock), 0, s, ev0, ev1, 0u,   \
                             P.n, P.inc_ptr.p, P.inc_nb.p, P.inc_id.p, pc<T>(P), P.pair_coef, W, ld, \
                             r, Q, sc, parity, P.part.p);                                           \
     else                                                                                           \
-      kpair_cg_vec<T, GG><<<grid, kBlock, 0, s>>>(P.n, P.inc_ptr.p, P.inc_nb.p, P.inc_id.p,        \
-                                                  pc<T>(P), P.pair_coef, W, ld, r, Q, sc, parity,   \
-                                                  P.part.p);                                       \
+      kpair_cg_vec<T, GG, X><<<grid, kBlock, 0, s>>>(P.n, P.inc_ptr.p, P.inc_nb.p, P.inc_id.p,     \
+                                                     pc<T>(P), P.pair_coef, W, ld, r, Q, sc,        \
+                                                     parity, P.part.p);                             \
   } while (0)
-      switch (gv) {
-        case 1: LORADS_CG_VEC(1); break;
-        case 2: LORADS_CG_VEC(2); break;
-        case 4: LORADS_CG_VEC(4); break;
-        case 8: LORADS_CG_VEC(8); break;
-        default: LORADS_CG_VEC(16); break;
+      if (x3) {
+        if constexpr (sizeof(T) == 8) LORADS_CG_VEC(8, 1);
+      } else switch (gv) {
+        case 1: LORADS_CG_VEC(1, 0); break;
+        case 2: LORADS_CG_VEC(2, 0); break;
+        case 4: LORADS_CG_VEC(4, 0); break;
+        case 8: LORADS_CG_VEC(8, 0); break;
+        default: LORADS_CG_VEC(16, 0); break;
       }
 #undef LORADS_CG_VEC
     } else {
