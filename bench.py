@@ -5,10 +5,14 @@ Headline workload: the planted rank-5 matrix-completion SDP with M of order
 20000 x 20000 (X of order 40000), 15,683,710 observed entries drawn as the
 paper's completion generator draws them (800 d uniform cells, duplicates
 merged), C = I/2, solved by the two-phase method (Burer-Monteiro warm start,
-then ADMM with CG subproblem solves) to KKT residual eq. (stop) <= 1e-6, CG in
-FP32 with FP64 right-hand sides, dual updates and residuals; the initial rank
-round(ln m) = 17.  A second entry repeats it on the completion instance of
-order 10000 (4,605,170 entries, rank 15).
+then ADMM with CG subproblem solves) to KKT residual eq. (stop) <= 1e-6; the
+initial rank round(ln m) = 17.  The timed form is the mixed one: CG iterations
+and the two maps of Phase I's exact line search in FP32, the gradient, the
+quartic's sums, right-hand sides, dual updates and residuals in FP64
+(--precision selects another).  The FP32-CG form (line search in FP64) and the
+plain FP64 form are solved from the same starts beside it.  A second entry
+repeats the timed form on the completion instance of order 10000 (4,605,170
+entries, rank 15).
 
 One step = one full two-phase solve, the instance already resident in HBM
 (setup is outside the timed region); timed step i starts from its own random
@@ -25,7 +29,7 @@ roofline: the dominant kernel class of the timed steps (all classes carry HIP
          HBM peak; `traffic` is the measured HBM bytes per launch of that class
          on this workload (FETCH_SIZE + WRITE_SIZE, profiles/hbm_traffic.json)
          while the kernel sources are unchanged, else null.
-roofline_fp64: the same for the plain FP64 solve.
+roofline_fp64, roofline_fp32_cg: the same for the comparison solves.
 ops_cold_warm: forward map and adjoint product alone at the solve's rank, FP32
          and FP64, warm (back to back) and cold (a 1 GiB buffer written before
          each call, flushing the 256 MB Infinity Cache and the L2s).
@@ -57,6 +61,8 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_2403_09133_amd/csrc/kernels_struct.hpp", "paper_2403_09133_amd/csrc/kernels.hpp",
                   "paper_2403_09133_amd/csrc/ops.hip", "paper_2403_09133_amd/csrc/common.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+# solver forms (lorads_options.precision)
+PREC_NAMES = {0: "fp64", 1: "fp32_cg", 2: "mixed"}
 
 # kernel classes timed by the library (lorads_result.prof_*)
 CLASSES = ["fused CG operator", "forward map A(UV^T)", "adjoint (C + A*(w))V", "line search A(UD^T+DU^T), A(DD^T)"]
@@ -69,9 +75,10 @@ def pow2_group(k: int) -> int:
     return g
 
 
-def class_kernels(structure: str, r: int, cg_dtype: str, n=None) -> list:
+def class_kernels(structure: str, r: int, cg_dtype: str, n=None, mixed=False) -> list:
     """The kernel each class runs for a structure and rank (the names rocprofv3
-    reports), so that a line names what was timed."""
+    reports), so that a line names what was timed; mixed: the line search's
+    maps on FP32 copies."""
     G = pow2_group(r)
     if structure == "pair":
         # the CG layout pads rows to 64 bytes; the vector form needs its lane
@@ -93,7 +100,10 @@ def class_kernels(structure: str, r: int, cg_dtype: str, n=None) -> list:
         # FP64 maps: G / 2 lanes of two columns; 8 lanes of three for r = 17..24
         X3 = 1 if 16 < r <= 24 else 0
         GV = 8 if X3 else max(1, G // 2)
-        return [cg, f"k1_pair_v2<{GV}, 0, {X3}>", f"kpair_grad_v2<{GV}, {X3}>", f"k1_pair_ls<{GV}, {X3}>"]
+        ls = f"k1_pair_ls<{GV}, {X3}>"
+        if mixed and r >= 9:
+            ls = f"k1_pair_ls_f32<{max(4, pow2_group((r + 3) // 4))}>"
+        return [cg, f"k1_pair_v2<{GV}, 0, {X3}>", f"kpair_grad_v2<{GV}, {X3}>", ls]
     if structure == "diag":
         # the line search's two maps run as forward maps (counted in that class)
         return [f"k3_diag<{cg_dtype}, {G}>", f"k1_diag<double, {G}, 0|1>", f"k2_diag<double, {G}, 0>",
@@ -244,14 +254,14 @@ def roofline_of(results, workload, structure, prec, n):
     launches = [sum(r["prof_launches"][k] for r in results) for k in range(K)]
     kbytes = [sum(r["prof_bytes"][k] for r in results) for k in range(K)]
     rank = results[-1]["rank"]
-    names = class_kernels(structure, rank, "float" if prec == 1 else "double", n)
+    names = class_kernels(structure, rank, "float" if prec != 0 else "double", n, mixed=prec == 2)
     kernels = {CLASSES[k]: dict(kernel=names[k], launches=int(launches[k]), total_ms=round(ms[k], 3),
                                 mean_us=round(ms[k] * 1e3 / max(1, launches[k]), 2),
                                 gbs=round(kbytes[k] / (ms[k] * 1e-3) / 1e9, 1) if ms[k] > 0 else None)
                for k in range(K)}
     dom = int(np.argmax(ms))
     achieved = kbytes[dom] / (ms[dom] * 1e-3) / 1e9 if ms[dom] > 0 else 0.0
-    pname = "fp32_cg" if prec == 1 else "fp64"
+    pname = PREC_NAMES[prec]
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4),
                 traffic=recorded_traffic(workload, pname, CLASSES[dom]),
@@ -441,9 +451,10 @@ def calibration_copy():
     log(f"copy of {a.numel() * 4} bytes done")
 
 
-def workload_leg(key, steps, warmup, prec, with_fp64=True, with_ops=True):
-    """Timed solves of one workload: the FP32-CG (or given) form with its
-    roofline, the FP64 form with its roofline, and the operators alone."""
+def workload_leg(key, steps, warmup, prec, compare=(0,), with_ops=True):
+    """Timed solves of one workload: the given form with its roofline, each
+    form in `compare` from the same starts with its roofline, and the
+    operators alone."""
     import torch
     import sdpgen
     from paper_2403_09133_amd import Context
@@ -481,17 +492,21 @@ def workload_leg(key, steps, warmup, prec, with_fp64=True, with_ops=True):
         leg["mc_recovery_error"] = dict(
             sampled_1e6_cells=completion_recovery_error_sampled(0.5 * (U + V), p.meta["L"], p.meta["R"]),
             note="||U1 U2^T - M||_F / ||M||_F on 10^6 uniformly drawn cells")
-    if with_fp64:
-        # the plain FP64 solve from the same starts
-        r64s, wall64 = timed_solves(ctx, p, r0, 0, [], timed_starts)
-        r64 = r64s[-1]
-        roof64, kern64 = roofline_of(r64s, key, info["structure"], 0, p.n)
-        leg["fp64"] = dict(s=round(wall64 / len(r64s), 4), status=[r["status"] for r in r64s],
-                           kkt=max(r["kkt"] for r in r64s), obj=r64["obj"],
-                           admm_iters=[r["admm_iters"] for r in r64s], cg_iters=[r["cg_iters"] for r in r64s],
-                           roofline=roof64, kernels=kern64)
-        leg["obj_rel_diff_vs_fp64"] = max(abs(a["obj"] - b["obj"]) / max(1.0, abs(b["obj"]))
-                                          for a, b in zip(results, r64s))
+    for cp in compare:
+        if cp == prec:
+            continue
+        # the same solves in another form, from the same starts
+        rcs, wallc = timed_solves(ctx, p, r0, cp, [], timed_starts)
+        rc = rcs[-1]
+        roofc, kernc = roofline_of(rcs, key, info["structure"], cp, p.n)
+        leg.setdefault("compare", {})[PREC_NAMES[cp]] = dict(
+            s=round(wallc / len(rcs), 4), status=[r["status"] for r in rcs], kkt=max(r["kkt"] for r in rcs),
+            obj=rc["obj"], admm_iters=[r["admm_iters"] for r in rcs], cg_iters=[r["cg_iters"] for r in rcs],
+            alm_inner=[r["alm_inner"] for r in rcs], steps_s=[round(r["t_total"], 4) for r in rcs],
+            roofline=roofc, kernels=kernc)
+        if cp == 0:
+            leg["obj_rel_diff_vs_fp64"] = max(abs(a["obj"] - b["obj"]) / max(1.0, abs(b["obj"]))
+                                              for a, b in zip(results, rcs))
     if with_ops:
         leg["ops_cold_warm"] = ops_cold_warm(ctx, p, last["rank"])
     ctx.close()
@@ -513,6 +528,9 @@ def main():
                     help="skip the one-at-a-time solve of the 512 batched instances")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-warm-start leg")
     ap.add_argument("--fp64-only", action="store_true", help="time the plain FP64 form in the timed steps")
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp32_cg", "fp64"],
+                    help="form of the timed steps (mixed: FP32 CG and FP32 line-search maps)")
+    ap.add_argument("--no-fp32-cg", action="store_true", help="skip the FP32-CG comparison solve")
     ap.add_argument("--ops-profile", type=int, default=0, metavar="REPS",
                     help="only run REPS applications of each operator at the workload's size (FP32, "
                          "initial rank) and a 256 MiB device copy, for hardware-counter runs")
@@ -531,11 +549,13 @@ def main():
     if args.ops_profile:
         ops_profile(args.workload, args.ops_profile)
         return
-    prec = 0 if args.fp64_only else 1
-    leg = workload_leg(args.workload, args.steps, args.warmup, prec, with_fp64=not args.no_fp64,
+    prec = 0 if args.fp64_only else {"mixed": 2, "fp32_cg": 1, "fp64": 0}[args.precision]
+    compare = [c for c, off in ((0, args.no_fp64), (1, args.no_fp32_cg)) if not off and c != prec]
+    leg = workload_leg(args.workload, args.steps, args.warmup, prec, compare=compare,
                        with_ops=not args.no_ops)
     p = leg["p"]
-    tkey = "fp32_cg" if prec == 1 else "fp64"
+    tkey = PREC_NAMES[prec]
+    cmp_ = leg.get("compare", {})
     line = {
         "metric": "A(UV^T)+A^*(y)V as HBM GB/s; time-to-1e-6 KKT residual, FP32/batched vs FP64",
         "value": round(leg["value"], 2),
@@ -547,32 +567,33 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if prec == 1 else "f64",
+        "dtype": "f32+f64" if prec != 0 else "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload], "n_X": p.n, "m": p.m,
                    "r0": leg["r0"], "kkt_tol": 1e-6},
         "roofline": leg["roofline"],
     }
-    if "fp64" in leg:
-        line["roofline_fp64"] = leg["fp64"]["roofline"]
+    for name, c in cmp_.items():
+        line[f"roofline_{name}"] = c["roofline"]
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p, leg["r0"])
     line["time_to_kkt_s"] = {tkey: round(leg["wall"] / args.steps, 4)}
-    if "fp64" in leg:
-        line["time_to_kkt_s"]["fp64"] = leg["fp64"]["s"]
+    for name, c in cmp_.items():
+        line["time_to_kkt_s"][name] = c["s"]
+    if "obj_rel_diff_vs_fp64" in leg:
         line["obj_rel_diff_vs_fp64"] = leg["obj_rel_diff_vs_fp64"]
     line["steps_detail"] = leg["steps"]
     line["solve"] = leg["solve"]
     line["kernels"] = leg["kernels"]
-    if "fp64" in leg:
-        line["fp64_solve"] = {k: v for k, v in leg["fp64"].items() if k != "roofline"}
+    for name, c in cmp_.items():
+        line[f"{name}_solve"] = {k: v for k, v in c.items() if k != "roofline"}
     line["setup_s"] = leg["setup_s"]
     if "mc_recovery_error" in leg:
         line["mc_recovery_error"] = leg["mc_recovery_error"]
     if "ops_cold_warm" in leg:
         line["ops_cold_warm"] = {args.workload: leg["ops_cold_warm"]}
     if not args.no_secondary and args.workload != "mc_10000":
-        sec = workload_leg("mc_10000", 5, 1, prec, with_fp64=False, with_ops=not args.no_ops)
+        sec = workload_leg("mc_10000", 5, 1, prec, compare=(), with_ops=not args.no_ops)
         line["secondary"] = {"mc_10000": dict(ms_per_step=round(sec["wall"] / 5 * 1e3, 3), steps=sec["steps"],
                                               value=round(sec["value"], 2), roofline=sec["roofline"],
                                               solve=sec["solve"], kernels=sec["kernels"])}

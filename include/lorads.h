@@ -56,6 +56,8 @@ typedef enum {
 } lorads_status;
 
 typedef enum { LORADS_F64 = 0, LORADS_F32 = 1 } lorads_dtype;
+/* the third solver precision (lorads_options.precision) */
+#define LORADS_MIXED 2
 
 /* Constraint structure detected by lorads_setup. */
 typedef enum {
@@ -92,7 +94,15 @@ typedef struct {
   int32_t precision;       /* LORADS_F64: plain FP64 method.  LORADS_F32: CG
                               iterations in FP32 on FP32 copies of the fixed
                               factor; U, V, lambda, right-hand sides, dual
-                              updates, decisions and residuals stay FP64 */
+                              updates, decisions and residuals stay FP64.
+                              LORADS_MIXED (2): as LORADS_F32, and the two
+                              maps of Phase I's exact line search,
+                              A(U D^T + D U^T) and A(D D^T), read FP32 copies
+                              of U and the direction D (FP32 inner products;
+                              the quartic's sums, the gradient, z, lambda and
+                              every decision stay FP64).  Applies to
+                              symmetric-pair structures with one coefficient
+                              and r >= 9; elsewhere it runs as LORADS_F32 */
   double eps;              /* final tolerance on eq. (stop), default 1e-6 */
   double switch_tol;       /* phase-I exit on primal infeasibility, default 1e-3
                               (Section 5.1: 1e-3 for most instances; its 1e-2
@@ -204,6 +214,13 @@ lorads_status lorads_setup(const lorads_problem *probs, int32_t nprob, lorads_ct
 /* Structure class, n and m of problem `prob`. */
 lorads_status lorads_problem_info(const lorads_ctx *ctx, int32_t prob, int32_t *structure,
                                   int32_t *n, int32_t *m);
+
+/* Layout flags of problem `prob` (*flags, a bit set):
+ * LORADS_FLAG_DENSE_C: C has at least n^2 / 4 entries and n >= 256, so it is
+ * also kept dense (n x ldc, FP64 and FP32) and every product with C runs on
+ * the matrix cores (MFMA), for r <= 64; otherwise its sparse rows are used. */
+#define LORADS_FLAG_DENSE_C 1
+lorads_status lorads_problem_flags(const lorads_ctx *ctx, int32_t prob, int32_t *flags);
 
 /* z = A(U V^T), z_i = <A_i, U V^T> (definition of the linear map, Section 1).
  * U, V: device, n x r (ld); z: device, m.  Enqueued on stream. */

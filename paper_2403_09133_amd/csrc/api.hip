@@ -161,6 +161,14 @@ lorads_status lorads_problem_info(const lorads_ctx* ctx, int32_t prob, int32_t* 
   });
 }
 
+lorads_status lorads_problem_flags(const lorads_ctx* ctx, int32_t prob, int32_t* flags) {
+  return guarded(const_cast<lorads_ctx*>(ctx), [&] {
+    Problem& P = get(const_cast<lorads_ctx*>(ctx), prob);
+    if (!flags) fail(LORADS_EINVAL, "flags");
+    *flags = P.cdense.n ? LORADS_FLAG_DENSE_C : 0;
+  });
+}
+
 void lorads_destroy(lorads_ctx* ctx) {
   if (!ctx) return;
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
@@ -327,7 +335,8 @@ lorads_status lorads_admm_solve(lorads_ctx* ctx, const lorads_options* opt, lora
   lorads_status st = guarded(ctx, [&] {
     if (!ctx || !opt || !res) fail(LORADS_EINVAL, "null argument");
     const lorads_options& o = *opt;
-    if (o.precision != LORADS_F64 && o.precision != LORADS_F32) fail(LORADS_EINVAL, "precision");
+    if (o.precision != LORADS_F64 && o.precision != LORADS_F32 && o.precision != LORADS_MIXED)
+      fail(LORADS_EINVAL, "precision");
     if (!(o.eps > 0) || o.max_admm_iter < 0 || o.lbfgs_mem < 1 || o.lbfgs_mem > 16 ||
         o.rho_every < 1 || o.profile < 0 || o.profile > 2)
       fail(LORADS_EINVAL, "invalid options");

@@ -843,7 +843,7 @@ void batch_solve(std::vector<std::unique_ptr<Problem>>& probs, Batch& B, const l
   B.S.alloc(F * o.lbfgs_mem);
   B.Y.alloc(F * o.lbfgs_mem);
   a.S = B.S.p; a.Y = B.Y.p;
-  const bool f32 = o.precision == LORADS_F32;
+  const bool f32 = o.precision != LORADS_F64;
   const size_t esz = f32 ? sizeof(float) : sizeof(double);
   for (DevBuf<char>* buf : {&B.X, &B.R, &B.P, &B.Q, &B.W}) buf->alloc(F * esz);
   a.X = B.X.p; a.R = B.R.p; a.P = B.P.p; a.Q = B.Q.p; a.W = B.W.p;

@@ -102,7 +102,8 @@ constexpr int kPairChunk = 32;     // PAIR forward map: constraints per work ite
 // XCDs of the part: consecutive workgroups of a launch are dealt to them in
 // turn, so workgroup b runs on XCD b mod kXcds (each with its own L2)
 constexpr int kXcds = 8;
-constexpr int kR1Seg = 64;         // RANK1: entries of a_i per segment (one lane group)
+constexpr int kR1Seg = 64;
+constexpr int kDenseCMinN = 256;  // smallest order for which a dense C is stored dense         // RANK1: entries of a_i per segment (one lane group)
 
 inline int pow2_group(int r) {
   int g = 1;

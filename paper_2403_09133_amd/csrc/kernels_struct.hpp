@@ -832,6 +832,97 @@ __global__ void __launch_bounds__(kBlock) kpair_grad_v2(
 }
 
 // ===========================================================================
+// Line search of the mixed form on FP32 copies of U and D (PAIR, uniform
+// coefficient, XCD chunk lists as k1_pair_ls): four columns per lane loaded as
+// one 16-byte vector, G = pow2(ceil(r / 4)) >= 4 lanes per constraint.  The
+// inner products are formed in FP32; p1 = 2 a (<U_j, D_k> + <U_k, D_j>) and
+// p2 = 2 a <D_j, D_k> are rounded to FP64 in the group's LDS slots and the
+// seven sums of the quartic run in FP64 with z, b and lam (all FP64) read as
+// contiguous runs.  Rows need ld >= 4 G (zero padding).
+template <int G>
+__global__ void __launch_bounds__(kBlock) k1_pair_ls_f32(
+    const int* __restrict__ xoff, const int* __restrict__ chunk_row,
+    const int* __restrict__ chunk_start, const int* __restrict__ chunk_end,
+    const int* __restrict__ pk, double pair_coef, const float* __restrict__ U,
+    const float* __restrict__ D, int ld, const double* __restrict__ z,
+    const double* __restrict__ b, const double* __restrict__ lam, double* __restrict__ part) {
+  static_assert(G >= 4, "the chunk results are staged per group");
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  __shared__ double s1[(kBlock / G) * kPairChunk];
+  __shared__ double s2[(kBlock / G) * kPairChunk];
+  __shared__ double sh[kBlock / 64];
+  const int chunk = xchunk_of(xoff, G);
+  const int lane = threadIdx.x & (G - 1);
+  const int gslot = (threadIdx.x / G) * kPairChunk;
+  double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (chunk >= 0) {
+    const int row = chunk_row[chunk];
+    const int i0 = chunk_start[chunk], i1 = chunk_end[chunk];
+    const int c0 = 4 * lane;
+    const f4 uj = *reinterpret_cast<const f4*>(U + row * ld + c0);
+    const f4 dj = *reinterpret_cast<const f4*>(D + row * ld + c0);
+    for (int i = i0; i < i1; i += kUnroll) {
+      const int cnt = min(kUnroll, i1 - i);
+      int k[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) k[u] = u < cnt ? pk[i + u] : row;
+      f4 dk[kUnroll], uk[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        dk[u] = *reinterpret_cast<const f4*>(D + k[u] * ld + c0);
+        uk[u] = *reinterpret_cast<const f4*>(U + k[u] * ld + c0);
+      }
+      float d[kUnroll], dd[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        float sa = uj[0] * dk[u][0];
+        sa = fmaf(uk[u][0], dj[0], sa);
+        float qa = dj[0] * dk[u][0];
+#pragma unroll
+        for (int v = 1; v < 4; ++v) {
+          sa = fmaf(uj[v], dk[u][v], sa);
+          sa = fmaf(uk[u][v], dj[v], sa);
+          qa = fmaf(dj[v], dk[u][v], qa);
+        }
+        d[u] = sa;
+        dd[u] = qa;
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) d[u] = group_sum<G>(d[u]);
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) dd[u] = group_sum<G>(dd[u]);
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        if (lane == (u & (G - 1)) && u < cnt) {
+          const int id = i + u;
+          s1[gslot + (id - i0)] = 2.0 * ((double)d[u] * pair_coef);
+          s2[gslot + (id - i0)] = 2.0 * pair_coef * (double)dd[u];
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int q = lane; q < i1 - i0; q += G) {
+      const double p1 = s1[gslot + q], p2 = s2[gslot + q];
+      const double p0 = z[i0 + q] - b[i0 + q], l = lam[i0 + q];
+      acc[0] += p2 * p2;
+      acc[1] += p1 * p2;
+      acc[2] += p1 * p1;
+      acc[3] += p0 * p2;
+      acc[4] += p0 * p1;
+      acc[5] += l * p1;
+      acc[6] += l * p2;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 7; ++t) {
+    const double bs = block_sum(acc[t], sh);
+    if (threadIdx.x == 0) part[(size_t)t * gridDim.x + blockIdx.x] = bs;
+  }
+}
+
+// ===========================================================================
 // PAIR CG operator on the CG layout (rows padded to 64 bytes, W and the
 // direction interleaved: row p = [W_p | P_p], stride ldw = 2 ld, zero padding).
 // A lane holds VW = 16 / sizeof(T) contiguous columns loaded as one 16-byte

@@ -5,6 +5,7 @@
 #include <chrono>
 
 #include "kernels.hpp"
+#include "kernels_dense.hpp"
 #include "kernels_rank1.hpp"
 #include "kernels_struct.hpp"
 #include "problem.hpp"
@@ -289,6 +290,16 @@ static void op_adjoint_impl(Problem& P, const T* w, double c_scale, const T* V, 
                             T* out, int ldo, double out_scale, hipStream_t s) {
   const int G = lane_group(r);
   if (r > 4 * G) fail(LORADS_EINVAL, "rank above 256 is not supported");
+  if (P.cdense.n && c_scale != 0.0 && r <= 16 * kDenseNT) {
+    // dense C on the matrix cores: the A* part alone, then C V added to it
+    if (w == nullptr) {
+      cdense_apply<T>(P, V, r, ld, out, ldo, out_scale * c_scale, 0.0, s);
+      return;
+    }
+    op_adjoint_impl<T>(P, w, 0.0, V, r, ld, out, ldo, out_scale, s);
+    cdense_apply<T>(P, V, r, ld, out, ldo, out_scale * c_scale, 1.0, s);
+    return;
+  }
   if (P.structure == LORADS_STRUCT_RANK1) {
     // S_i = a_i^T V with weight c_i w_i, then the row pass (C alone without w)
     const R1Work<T> wk = r1_work<T>(P, r);
@@ -344,6 +355,9 @@ void op_grad_pair(Problem& P, const double* U, int r, int ld, double rho, double
     op_forward<double>(P, U, U, r, ld, z, 1.0, s);
     z = nullptr;
   }
+  // dense C: the kernels take the sparse part as empty and C U is added after
+  const bool dense = P.cdense.n && r <= 16 * kDenseNT;
+  const double cs = dense ? 0.0 : 1.0;
   P.prof.run(2, bytes_grad_pair(P, r), s, [&] {
     check_pair_offsets(P, std::max(ld, ldo));
     const int G = lane_group(r);
@@ -351,15 +365,75 @@ void op_grad_pair(Problem& P, const double* U, int r, int ld, double rho, double
     if (v2) {
       const int grid = std::max(1, (P.n + kBlock / 32 - 1) / (kBlock / 32));  // two rows per wave
       LORADS_DISPATCH_V2(G, r, (kpair_grad_v2<GV, X3><<<grid, kBlock, 0, s>>>(
-                                P.n, P.cptr.p, P.ccol.p, P.cval.p, 1.0, P.inc_ptr.p, P.inc_nb.p,
+                                P.n, P.cptr.p, P.ccol.p, P.cval.p, cs, P.inc_ptr.p, P.inc_nb.p,
                                 P.pair_coef, U, r, ld, out, ldo, out_scale, P.inc_lb.p, rho,
                                 P.rptr.p, z)));
     } else {
       LORADS_DISPATCH_GK(G, r, (kpair_rows<double, G, 2, KC><<<waves_grid(P.n), kBlock, 0, s>>>(
-                               P.n, P.cptr.p, P.ccol.p, P.cval.p, 1.0, P.inc_ptr.p, P.inc_nb.p,
+                               P.n, P.cptr.p, P.ccol.p, P.cval.p, cs, P.inc_ptr.p, P.inc_nb.p,
                                P.inc_id.p, nullptr, P.pair_coef, nullptr, U, nullptr, r, ld, out, ldo,
                                out_scale, nullptr, 0, nullptr, P.inc_lb.p, rho)));
     }
+    HIPCHK(hipGetLastError());
+    if (dense) cdense_apply<double>(P, U, r, ld, out, ldo, out_scale, 1.0, s);
+  });
+}
+
+template <typename T>
+void cdense_apply(Problem& P, const T* V, int r, int ld, T* out, int ldo, double alpha, double beta,
+                  hipStream_t s) {
+  if (P.cdense.n == 0 || r < 1 || r > 16 * kDenseNT || ld < r || ldo < r)
+    fail(LORADS_EINVAL, "dense C product: unsupported shape");
+  const T* C = sizeof(T) == 8 ? (const T*)(const void*)P.cdense.p : (const T*)(const void*)P.cdensef.p;
+  const int tiles = (P.n + 15) / 16;
+  const int kblocks = P.ldc / kDenseK;
+  // about 2048 waves: ranges of whole 64-column blocks
+  const int want = std::max(1, std::min(kblocks, (2048 + tiles - 1) / tiles));
+  const int kchunk = (kblocks + want - 1) / want * kDenseK;
+  const int splits = (P.ldc + kchunk - 1) / kchunk;
+  const size_t need = (size_t)splits * P.n * r * sizeof(T);
+  if (P.cdpart.n < need) P.cdpart.alloc(need);
+  T* part = reinterpret_cast<T*>(P.cdpart.p);
+  const int waves = tiles * splits;
+  cdense_partial<T><<<(waves + kBlock / 64 - 1) / (kBlock / 64), kBlock, 0, s>>>(
+      P.n, P.ldc, C, V, r, ld, tiles, splits, kchunk, part);
+  cdense_finish<T><<<grid_for((size_t)P.n * r), kBlock, 0, s>>>(P.n, r, splits, part, alpha, beta,
+                                                                out, ldo);
+  HIPCHK(hipGetLastError());
+}
+template void cdense_apply<double>(Problem&, const double*, int, int, double*, int, double, double,
+                                   hipStream_t);
+template void cdense_apply<float>(Problem&, const float*, int, int, float*, int, double, double,
+                                  hipStream_t);
+
+int pair_f32_lanes(const Problem& P, int r, int ld) {
+  if (P.structure != LORADS_STRUCT_PAIR || P.pcoef.n != 0 || P.nxchunks == 0 || r < 1 || r > 128)
+    return 0;
+  const int g = std::max(4, pow2_group((r + 3) / 4));
+  return (ld % 4 == 0 && ld >= 4 * g && g <= 32) ? g : 0;
+}
+
+#define LORADS_DISPATCH_F32(Gv, CALL)                  \
+  do {                                                 \
+    switch (Gv) {                                      \
+      case 4: { constexpr int GF = 4; CALL; } break;   \
+      case 8: { constexpr int GF = 8; CALL; } break;   \
+      case 16: { constexpr int GF = 16; CALL; } break; \
+      default: { constexpr int GF = 32; CALL; } break; \
+    }                                                  \
+  } while (0)
+
+void op_linesearch_pair_f32(Problem& P, const float* U32, const float* D32, int r, int ld,
+                            const double* z, const double* lam, double* part, hipStream_t s) {
+  const int g = pair_f32_lanes(P, r, ld);
+  if (g == 0 || (reinterpret_cast<uintptr_t>(U32) % 16) != 0 ||
+      (reinterpret_cast<uintptr_t>(D32) % 16) != 0)
+    fail(LORADS_EINVAL, "mixed line search: layout not supported");
+  check_pair_offsets(P, ld);
+  P.prof.run(3, bytes_linesearch_pair_f32(P, r), s, [&] {
+    LORADS_DISPATCH_F32(g, (k1_pair_ls_f32<GF><<<xchunk_grid(P, GF), kBlock, 0, s>>>(
+                               P.xchunk_off.p, P.xchunk_row.p, P.xchunk_start.p, P.xchunk_end.p,
+                               P.pk.p, P.pair_coef, U32, D32, ld, z, P.b.p, lam, part)));
     HIPCHK(hipGetLastError());
   });
 }
@@ -512,7 +586,9 @@ double bytes_linesearch_pair(const Problem& P, int r) {
 
 double bytes_adjoint(const Problem& P, int r, int s, bool with_c) {
   const double nr = (double)P.n * r * s;
-  const double cbytes = with_c ? (double)P.cval.n * (4 + s) + (double)(P.n + 1) * 4 : 0.0;
+  const double cbytes = !with_c ? 0.0
+                        : P.cdense.n ? (double)P.n * P.ldc * s
+                                     : (double)P.cval.n * (4 + s) + (double)(P.n + 1) * 4;
   if (P.structure == LORADS_STRUCT_DIAG) return (double)P.m * (4 + 2 * s) + 2.0 * nr + cbytes;
   if (P.structure == LORADS_STRUCT_RANK1)  // a by constraint and by row, w, c, V, out
     return 2.0 * (double)P.r1idx.n * (4 + s) + (double)(P.r1nseg + P.m + P.n + 2) * 4 +
@@ -523,12 +599,18 @@ double bytes_adjoint(const Problem& P, int r, int s, bool with_c) {
 }
 
 double bytes_cprod(const Problem& P, int r, int s) {
+  if (P.cdense.n) return (double)P.n * P.ldc * s + 2.0 * (double)P.n * r * s;
   return (double)P.cval.n * (4 + s) + (double)(P.n + 1) * 4 + 2.0 * (double)P.n * r * s;
 }
 
 double bytes_grad_pair(const Problem& P, int r) {
   // the gradient form applies both maps: A(U U^T) entry by entry and the adjoint
   return bytes_forward(P, r, 8) + bytes_adjoint(P, r, 8, true);
+}
+
+// mixed-form line search: the factor reads at 4 bytes
+double bytes_linesearch_pair_f32(const Problem& P, int r) {
+  return (double)P.m * 8 + 3.0 * P.m * 8 + 2.0 * P.n * r * 4;
 }
 
 double bytes_cg_op(const Problem& P, int r, int s) {

@@ -156,6 +156,14 @@ struct Problem {
   DevBuf<double> cval;
   DevBuf<double> cdiag;  // diagonal C only: C_jj by row (zero where absent), else empty
   DevBuf<float> cvalf;
+  // dense C (at least a quarter of the n^2 entries, n >= kDenseCMinN): also
+  // stored n x ldc row-major (ldc a multiple of 64, zero padding), FP64 and
+  // FP32; products with C then run on the matrix cores (cdense_apply), with
+  // their split partials in cdpart
+  DevBuf<double> cdense;
+  DevBuf<float> cdensef;
+  int ldc = 0;
+  DevBuf<char> cdpart;
 
   // RANK1 structure: A_i = r1c[i] a_i a_i^T.  a_i's entries (index, value) in
   // constraint CSR r1ptr / r1idx / r1val, cut into segments of at most
@@ -318,6 +326,23 @@ bool grad_pair_ready(const Problem& P);
 void refresh_inc_lam(Problem& P, hipStream_t s);
 void op_grad_pair(Problem& P, const double* U, int r, int ld, double rho, double* out, int ldo,
                   double out_scale, hipStream_t s, double* z = nullptr);
+// line search of the mixed form on FP32 copies U32, D32 of U and D (same row
+// stride ld, zero padding): lanes per constraint at rank r, 0 where the form
+// does not apply (needs PAIR with a uniform coefficient, ld >= 4 lanes and
+// groups of at least 4 lanes)
+int pair_f32_lanes(const Problem& P, int r, int ld);
+// the fused line search from U32, D32: 7 x ls_blocks_f32 block partials in part
+void op_linesearch_pair_f32(Problem& P, const float* U32, const float* D32, int r, int ld,
+                            const double* z, const double* lam, double* part, hipStream_t s);
+inline int ls_blocks_f32(const Problem& P, int r, int ld) {
+  const int g = pair_f32_lanes(P, r, ld);
+  return g ? xchunk_grid(P, g) : 0;
+}
+double bytes_linesearch_pair_f32(const Problem& P, int r);
+// out = alpha C V + beta out (first r columns) with the dense copy of C
+template <typename T>
+void cdense_apply(Problem& P, const T* V, int r, int ld, T* out, int ldo, double alpha, double beta,
+                  hipStream_t s);
 // leading dimension of the CG work buffers: PAIR problems pad rows to a
 // multiple of 64 bytes (zero padding), so every row the CG operator gathers
 // sits in whole, aligned 64-byte sectors; other structures use r

@@ -318,6 +318,18 @@ std::unique_ptr<Problem> ingest(const lorads_problem& p, hipStream_t s) {
         if (cptr[j + 1] > cptr[j]) cd[j] = cval[cptr[j]];
       P->cdiag.upload(cd, s);
     }
+    // a dense C (a quarter of the entries or more) is also kept dense, for
+    // the matrix-core products
+    if (n >= kDenseCMinN && n <= 32768 && (double)nc >= 0.25 * (double)n * n) {
+      const int ldc = (n + 63) / 64 * 64;
+      std::vector<double> cdn((size_t)n * ldc, 0.0);
+      for (int j = 0; j < n; ++j)
+        for (int e = cptr[j]; e < cptr[j + 1]; ++e) cdn[(size_t)j * ldc + ccol[e]] += cval[e];
+      std::vector<float> cdf(cdn.begin(), cdn.end());
+      P->cdense.upload(cdn, s);
+      P->cdensef.upload(cdf, s);
+      P->ldc = ldc;
+    }
   }
 
   // ---------------- DIAG layout ----------------

@@ -195,6 +195,24 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
   F.load(P, r, alm_ld(P, r), s);
   alm_alloc(A, n, m, r, F.ld, o.lbfgs_mem, s);
   double* U = F.U;
+  // mixed form: FP32 copies of U and of the direction for the line search's
+  // maps (same row stride, zero padding); gf = lanes per constraint
+  DevBuf<float> U32, D32;
+  int gf = 0;
+  auto cast_rows = [&](const double* X, float* Y) {
+    copy_rows<double, float><<<gridN((size_t)n * r), kBlock, 0, s>>>(n, r, X, F.ld, Y, F.ld);
+    HIPCHK(hipGetLastError());
+  };
+  auto setup_mixed = [&]() {
+    gf = o.precision == LORADS_MIXED ? pair_f32_lanes(P, r, F.ld) : 0;
+    if (!gf) return;
+    U32.alloc((size_t)n * F.ld);
+    U32.zero(s);
+    D32.alloc((size_t)n * F.ld);
+    D32.zero(s);
+    cast_rows(U, U32.p);
+  };
+  setup_mixed();
   // factor dots in the compact summation order whatever the row stride
   auto adot = [&](const double* X, const double* Y, double scale, int slot, hipStream_t st) {
     dot_rows_to_slot(P, n, r, F.ld, X, Y, scale, slot, st);
@@ -310,17 +328,26 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
         (P.structure == LORADS_STRUCT_PAIR && P.cdiag.n > 0) ? P.cdiag.p : nullptr;
     // PAIR: the two maps and their seven m-vector sums in one pass (nothing
     // m-sized written); otherwise the maps, then the sums
-    if (A.lsp.n < (size_t)7 * ls_blocks(P, r)) A.lsp.alloc((size_t)7 * ls_blocks(P, r));
+    const int nls = gf ? ls_blocks_f32(P, r, F.ld) : ls_blocks(P, r);
+    if (A.lsp.n < (size_t)7 * nls) A.lsp.alloc((size_t)7 * nls);
     auto line_search = [&](int nread) {
-      const bool fused = op_linesearch_pair(P, U, A.D.p, r, F.ld, P.zbuf.p, P.lam.p, A.lsp.p, s);
+      bool fused;
+      if (gf) {
+        // the direction's FP32 copy (D changes before every search)
+        cast_rows(A.D.p, D32.p);
+        op_linesearch_pair_f32(P, U32.p, D32.p, r, F.ld, P.zbuf.p, P.lam.p, A.lsp.p, s);
+        fused = true;
+      } else {
+        fused = op_linesearch_pair(P, U, A.D.p, r, F.ld, P.zbuf.p, P.lam.p, A.lsp.p, s);
+      }
       if (!fused) op_forward_pair(P, U, A.D.p, r, F.ld, A.p1.p, A.p2.p, s);
       if (!cdiag)
         op_adjoint<double>(P, (const double*)nullptr, 1.0, A.D.p, r, F.ld, A.CD.p, F.ld, 1.0, s);
       // the two maps, and C D (a product with C alone)
-      info.op_bytes += 2 * bytes_forward(P, r, 8) + bytes_cprod(P, r, 8);
+      info.op_bytes += 2 * bytes_forward(P, r, gf ? 4 : 8) + bytes_cprod(P, r, 8);
       linesearch_slots(P, n, r, F.ld, A.CD.p, U, A.D.p, P.zbuf.p, A.p1.p, A.p2.p, P.lam.p,
                        S_GEN + 1, s, part_gd, cdiag, h, nread, fused ? A.lsp.p : nullptr,
-                       fused ? ls_blocks(P, r) : 0);
+                       fused ? nls : 0);
     };
     // A step's curvature pair enters the memory at once, before its <S, Y>
     // is known on the host, so the next direction and line search are queued
@@ -402,6 +429,7 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
       // enters the memory now (the oldest pair is dropped when full) and
       // leaves it again at the next read if <S, Y> <= 0.
       lbfgs_step_kernel<<<gridN(N), kBlock, 0, s>>>(N, alpha, A.D.p, A.Sn.p, U);
+      if (gf) cast_rows(U, U32.p);
       alm_gradient(P, A, U, A.Gn.p, rho, s, info.op_bytes);
       lbfgs_pair_kernel<<<rg, kBlock, 0, s>>>(Nc, r, F.ld, A.Gn.p, A.G.p, A.Yn.p, A.Sn.p,
                                               part_pair);
@@ -429,6 +457,7 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
       warm_pending = false;
       if (!(v < v_start)) {
         HIPCHK(hipMemcpyAsync(U, U_start.p, (size_t)n * F.ld * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (gf) cast_rows(U, U32.p);
         P.lam.zero(s);
         refresh_inc_lam(P, s);
         rho = rho_start;
@@ -461,6 +490,7 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
       F.load(P, r, alm_ld(P, r), s);
       U = F.U;
       alm_alloc(A, n, m, r, F.ld, o.lbfgs_mem, s);
+      setup_mixed();
       ++growths;
       op_forward<double>(P, U, U, r, F.ld, P.zbuf.p, 1.0, s);
       info.op_bytes += bytes_forward(P, r, 8);
@@ -635,7 +665,7 @@ static void phase2_t(Problem& P, const lorads_options& o, double rho, SolveInfo&
 
 void phase2(Problem& P, const lorads_options& o, double rho, SolveInfo& info, hipStream_t s,
             std::chrono::steady_clock::time_point t_start) {
-  if (o.precision == LORADS_F32)
+  if (o.precision != LORADS_F64)
     phase2_t<float>(P, o, rho, info, s, t_start);
   else
     phase2_t<double>(P, o, rho, info, s, t_start);

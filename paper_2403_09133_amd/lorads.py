@@ -20,6 +20,8 @@ _lib = None
 LORADS_OK, LORADS_MAXITER, LORADS_TIMELIMIT = 0, 1, 2
 LORADS_EINVAL, LORADS_ENOMEM, LORADS_EDEVICE, LORADS_ENUMERIC, LORADS_ESTATE = -1, -2, -3, -4, -5
 F64, F32 = 0, 1
+MIXED = 2  # solver precision: FP32 CG and FP32 line-search maps
+LORADS_FLAG_DENSE_C = 1
 STRUCT_NAMES = {0: "generic", 1: "diag", 2: "pair", 3: "rank1"}
 
 
@@ -71,7 +73,8 @@ class Result_(C.Structure):
 
 
 EXPORTED = [
-    "lorads_default_options", "lorads_setup", "lorads_problem_info", "lorads_apply_A",
+    "lorads_default_options", "lorads_setup", "lorads_problem_info", "lorads_problem_flags",
+    "lorads_apply_A",
     "lorads_apply_AT_V", "lorads_cg_solve", "lorads_cg_solve_noalloc", "lorads_admm_solve",
     "lorads_get_solution",
     "lorads_gram", "lorads_dual_lambda_min", "lorads_destroy", "lorads_last_error",
@@ -245,9 +248,11 @@ class Context:
 
     # -- entry points ------------------------------------------------------
     def problem_info(self, prob: int = 0):
-        s, n, m = C.c_int32(), C.c_int32(), C.c_int32()
+        s, n, m, f = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
         self._check(load().lorads_problem_info(self.h, prob, C.byref(s), C.byref(n), C.byref(m)))
-        return dict(structure=STRUCT_NAMES[s.value], n=n.value, m=m.value)
+        self._check(load().lorads_problem_flags(self.h, prob, C.byref(f)))
+        return dict(structure=STRUCT_NAMES[s.value], n=n.value, m=m.value,
+                    c_dense=bool(f.value & LORADS_FLAG_DENSE_C))
 
     def apply_A(self, U, V, z, prob: int = 0, stream=None):
         """z = A(U V^T) on device tensors (n x r row-major, z of length m)."""

@@ -190,12 +190,12 @@ def _nuclear_norm_planted(L, R):
 
 
 @pytest.mark.parametrize("name", ["mc_10000", "mc_20000"])
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_fullsize_completion_solve(device, name, precision):
     """The completion solves of the benchmark (n_X = 20000, m = 4,605,170,
     r = 15, and the headline n_X = 40000, m = 15,683,710, r = 17; ranks
-    round(ln m)), with the benchmarked options and start, FP64 and
-    FP32-CG: it meets eq. (stop); the oracle recomputes the objective, the
+    round(ln m)), with the benchmarked options and start, FP64, FP32-CG and
+    mixed (FP32 Phase-I maps as well): it meets eq. (stop); the oracle recomputes the objective, the
     primal infeasibility and the gap (Appendix B) from the returned factors and
     multipliers at full size; the objective equals the nuclear norm of the
     planted matrix (the completion SDP's value at exact recovery) and the

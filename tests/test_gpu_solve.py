@@ -62,7 +62,7 @@ def _lib_opts(p, r0, **kw):
 
 
 @pytest.mark.parametrize("name", sorted(CASES))
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_solve_matches_oracle(device, name, precision):
     from paper_2403_09133_amd import Context
     p, _ = CASES[name]
@@ -130,7 +130,7 @@ def test_iteration_cap_status(device):
 
 
 @pytest.mark.parametrize("name", ["mc_60x50", "maxcut_er200"])
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_solve_bitwise_reproducible(device, name, precision):
     # every reduction has a fixed order and the launch schedule does not enter
     # the arithmetic, so a solve repeated in the same context or in a new one
