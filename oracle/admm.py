@@ -14,6 +14,11 @@ with W the fixed factor and x = W + D, the residual at x0 = W is
     R0 = -(C + A*(lam + rho (A(W W^T) - b))) W,
 the negative gradient of L_rho in the free factor at W, so CG solves M_W D = R0.
 
+With the quadratic objective f(X) = <C, X> + (mu/2) ||X||_F^2 (Section 1's
+convex f), grad f(U W^T) W = C W + mu U (W^T W) is still linear in the free
+factor, so both subproblems stay linear systems: the operator gains
+mu P (W^T W) and R0 the term -mu W (W^T W).
+
 Stop, eq. (stop): max{ ||A(U V^T) - b||_2 / (1 + ||b||_inf),
                        gamma ||V^{k+1} - V^k||_F / (1 + ||V^k||_F) } < eps.
 rho schedule (Section 5.1): every 5th iteration rho <- min(1.2 rho, rho_max),
@@ -34,13 +39,17 @@ def grad_factor(prob, W, lam, rho):
     factor evaluated at the fixed factor W (both factors equal W)."""
     z = operators.forward(prob, W, W)
     w = lam + rho * (z - prob.b)
-    return operators.adjoint(prob, w, 1.0, W)
+    g = operators.adjoint(prob, w, 1.0, W)
+    mu = operators.mu_of(prob)
+    if mu != 0.0:
+        g = g + mu * (W @ (W.T @ W))
+    return g
 
 
 def alf(prob, U, V, lam, rho, gamma):
-    """eq. (ALF) with f(X) = <C, X>."""
+    """eq. (ALF) with f(X) = <C, X> + (mu/2) ||X||_F^2."""
     z = operators.forward(prob, U, V) - prob.b
-    return (operators.cost_inner(prob, U, V) + 0.5 * gamma * float(np.sum((U - V) ** 2))
+    return (operators.objective(prob, U, V) + 0.5 * gamma * float(np.sum((U - V) ** 2))
             + float(lam @ z) + 0.5 * rho * float(z @ z))
 
 

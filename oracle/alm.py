@@ -18,6 +18,12 @@ U U^T + a (U D^T + D U^T) + a^2 D D^T; its coefficients need A(U D^T), A(D D^T),
 <C D, U> and <C D, D>, and the step is the minimiser among the positive real
 roots of the cubic derivative.
 
+With the quadratic objective f(X) = <C, X> + (mu/2) ||X||_F^2 (Section 1's
+convex f) the same holds with <C, U U^T> replaced by f(U U^T): the gradient
+gains 2 mu U (U^T U), and ||(U + a D)(U + a D)^T||_F^2 = ||A0 + a A1 + a^2 A2||_F^2
+with A0 = U^T U, A1 = U^T D + D^T U, A2 = D^T D adds to every coefficient of the
+quartic.
+
 The inner and outer rules, tolerances and rank-growth trigger are the readings
 documented in `oracle/options.py`.
 """
@@ -32,12 +38,16 @@ from . import operators, rng
 
 def objective_parts(prob, U, lam, rho):
     z = operators.forward(prob, U, U) - prob.b
-    return operators.cost_inner(prob, U, U) + float(lam @ z) + 0.5 * rho * float(z @ z)
+    return operators.objective(prob, U, U) + float(lam @ z) + 0.5 * rho * float(z @ z)
 
 
 def gradient(prob, U, z, lam, rho):
     w = lam + rho * (z - prob.b)
-    return 2.0 * operators.adjoint(prob, w, 1.0, U)
+    g = 2.0 * operators.adjoint(prob, w, 1.0, U)
+    mu = operators.mu_of(prob)
+    if mu != 0.0:
+        g = g + 2.0 * mu * (U @ (U.T @ U))
+    return g
 
 
 def quartic_coefficients(prob, U, D, z, lam, rho):
@@ -53,6 +63,15 @@ def quartic_coefficients(prob, U, D, z, lam, rho):
     q3 = rho * float(p1 @ p2)
     q2 = c2 + float(lam @ p2) + 0.5 * rho * (float(p1 @ p1) + 2.0 * float(p0 @ p2))
     q1 = c1 + float(lam @ p1) + rho * float(p0 @ p1)
+    mu = operators.mu_of(prob)
+    if mu != 0.0:
+        A0, A2 = U.T @ U, D.T @ D
+        A1 = U.T @ D + D.T @ U
+        ip = lambda X, Y: float(np.sum(X * Y))
+        q1 += mu * ip(A0, A1)
+        q2 += 0.5 * mu * (ip(A1, A1) + 2.0 * ip(A0, A2))
+        q3 += mu * ip(A1, A2)
+        q4 += 0.5 * mu * ip(A2, A2)
     return q1, q2, q3, q4
 
 

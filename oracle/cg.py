@@ -19,9 +19,17 @@ from . import operators
 
 
 def cg_operator(prob, W: np.ndarray, rho: float, gamma: float):
+    """M_W(P) = gamma P + rho A*(A(P W^T)) W, plus mu P (W^T W) for the
+    quadratic objective (mu/2) ||X||_F^2."""
+    mu = operators.mu_of(prob)
+    G = W.T @ W if mu != 0.0 else None
+
     def apply(P):
         t = operators.forward(prob, P, W)
-        return gamma * P + operators.adjoint(prob, rho * t, 0.0, W)
+        out = gamma * P + operators.adjoint(prob, rho * t, 0.0, W)
+        if G is not None:
+            out = out + mu * (P @ G)
+        return out
     return apply
 
 

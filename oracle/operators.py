@@ -44,6 +44,30 @@ def cost_inner(prob, U: np.ndarray, V: np.ndarray) -> float:
     return float(np.sum(c * np.where(j == k, d_jk, d_jk + d_kj)))
 
 
+def mu_of(prob) -> float:
+    return float(getattr(prob, "mu", 0.0))
+
+
+def objective(prob, U: np.ndarray, V: np.ndarray) -> float:
+    """f(U V^T) for f(X) = <C, X> + (mu / 2) ||X||_F^2 (Section 1 allows any
+    convex smooth f; this is the quadratic one), with
+    ||U V^T||_F^2 = <U^T U, V^T V>."""
+    mu = mu_of(prob)
+    val = cost_inner(prob, U, V)
+    if mu != 0.0:
+        val += 0.5 * mu * float(np.sum((U.T @ U) * (V.T @ V)))
+    return val
+
+
+def grad_apply(prob, U: np.ndarray, V: np.ndarray, W: np.ndarray) -> np.ndarray:
+    """grad f(U V^T) W = C W + mu U (V^T W)."""
+    out = cost_apply(prob, W)
+    mu = mu_of(prob)
+    if mu != 0.0:
+        out = out + mu * (U @ (V.T @ W))
+    return out
+
+
 def assemble(prob, w: np.ndarray, c_scale: float) -> sp.csr_matrix:
     """The symmetric sparse matrix c_scale * C + sum_i w_i A_i."""
     w = np.asarray(w, dtype=np.float64)

@@ -53,6 +53,8 @@ class Problem:
     b: np.ndarray      # float64, length m
     kind: str = "generic"           # "maxcut" | "mc" | "generic"
     meta: dict = dataclasses.field(default_factory=dict)
+    # objective f(X) = <C, X> + (mu / 2) ||X||_F^2 (mu = 0: the linear SDP)
+    mu: float = 0.0
 
     def __post_init__(self):
         self.c_row = np.ascontiguousarray(self.c_row, dtype=np.int32)
