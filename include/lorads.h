@@ -85,6 +85,10 @@ typedef struct {
   const int32_t *a_col;      /* [a_nnz] */
   const double *a_val;       /* [a_nnz], finite */
   const double *b;           /* [m], finite */
+  double mu;                 /* objective f(X) = <C, X> + (mu / 2) ||X||_F^2
+                                (Section 1's convex f; mu = 0: the linear SDP);
+                                finite and >= 0 (EINVAL otherwise); the
+                                batched solve takes mu = 0 only */
 } lorads_problem;
 
 /* Solver parameters.  lorads_default_options() fills the documented defaults;
@@ -176,11 +180,14 @@ typedef struct {
   int32_t alm_outer, alm_inner, rank_growths;
   int32_t admm_iters;
   int64_t cg_iters;        /* total CG iterations of phase II */
-  double obj;              /* <C, U_hat U_hat^T>, U_hat = (U + V)/2 */
+  double obj;              /* f(X) at X = U_hat U_hat^T, U_hat = (U + V)/2:
+                              <C, X> (+ (mu/2) ||X||_F^2) */
   double dual_obj;         /* b^T y with y = -lambda */
   double pinf;             /* ||A(X) - b||_2 / (1 + ||b||_1)      (App. B) */
-  double dinf;             /* |min(0, lambda_min(C - A*(y)))| / (1 + ||vec C||_1) */
-  double gap;              /* (<C,X> - b^T y) / (1 + |<C,X>| + |b^T y|) */
+  double dinf;             /* |min(0, lambda_min(C - A*(y)))| / (1 + ||vec C||_1);
+                              with mu != 0, C + mu X in place of C */
+  double gap;              /* (<C,X> - b^T y) / (1 + |<C,X>| + |b^T y|); with
+                              mu != 0, <C + mu X, X> in place of <C, X> */
   double lambda_min;       /* smallest eigenvalue of the dual slack */
   double kkt;              /* final value of eq. (stop) */
   double pinf_stop;        /* ||A(UV^T) - b||_2 / (1 + ||b||_inf) at exit */
@@ -241,7 +248,9 @@ lorads_status lorads_apply_AT_V(lorads_ctx *ctx, int32_t prob, const void *w, do
  * out: solution).  Stops when ||R - M X||_F <= tol ||R - M x0||_F or after
  * maxit iterations.  W, R, X: device n x r (ld).  Blocks the host until done;
  * *iters and *relres (host, may be NULL) receive the iteration count and the
- * final relative residual.  Returns MAXITER if the tolerance was not met. */
+ * final relative residual.  Returns MAXITER if the tolerance was not met.
+ * This is the linear objective's operator: a problem's mu is not applied
+ * here (solves add mu X (W^T W) themselves). */
 lorads_status lorads_cg_solve(lorads_ctx *ctx, int32_t prob, const void *W, double rho,
                               double gamma, const void *R, void *X, int32_t r, int32_t ld,
                               double tol, int32_t maxit, int32_t dtype, int32_t *iters,
@@ -298,7 +307,9 @@ lorads_status lorads_gram(const void *A, const void *B, int64_t n, int32_t ra, i
 
 /* Smallest eigenvalue of the dual slack C + A*(lambda) (= C - A*(y), y = -lambda)
  * by Lanczos with full reorthogonalisation (Appendix B's dual infeasibility).
- * lambda: device, m, FP64, caller order.  Blocks the host. */
+ * lambda: device, m, FP64, caller order.  Blocks the host.  With mu != 0 the
+ * solver's own measures use grad f(X) = C + mu X in place of C; this call
+ * takes C alone. */
 lorads_status lorads_dual_lambda_min(lorads_ctx *ctx, int32_t prob, const void *lambda,
                                      int32_t max_steps, double *out);
 

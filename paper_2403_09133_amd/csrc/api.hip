@@ -365,7 +365,8 @@ lorads_status lorads_admm_solve(lorads_ctx* ctx, const lorads_options* opt, lora
       }
       return;
     }
-    if (o.batch_mode == 1) fail(LORADS_EINVAL, "batched solve needs >= 2 problems, all with diagonal constraints");
+    if (o.batch_mode == 1)
+      fail(LORADS_EINVAL, "batched solve needs >= 2 problems, all with diagonal constraints and mu = 0");
     for (size_t pi = 0; pi < ctx->probs.size(); ++pi) {
       Problem& P = *ctx->probs[pi];
       if (!o.init_U[pi]) fail(LORADS_EINVAL, "init_U missing for problem " + std::to_string(pi));

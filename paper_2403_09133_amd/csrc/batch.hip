@@ -736,7 +736,7 @@ finish:
 bool batch_eligible(const std::vector<std::unique_ptr<Problem>>& probs) {
   if (probs.size() < 2) return false;
   for (auto& p : probs)
-    if (p->structure != LORADS_STRUCT_DIAG) return false;
+    if (p->structure != LORADS_STRUCT_DIAG || p->mu != 0.0) return false;
   return true;
 }
 

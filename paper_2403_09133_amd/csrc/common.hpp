@@ -86,6 +86,7 @@ enum Slot : int {
   S_PQ = 12,
   S_GEN = 16,  // 16..63 general-purpose reduction outputs
   S_PAIRS = 64,  // 64..80: <S, Y> of each L-BFGS pair buffer (memory <= 16, plus one)
+  S_QUAD = 84,   // 84..87: the quartic's Gram terms of the quadratic objective
   S_COUNT = 96
 };
 

@@ -4,6 +4,7 @@
 #include <algorithm>
 
 #include "kernels.hpp"
+#include "kernels_quad.hpp"
 #include "solver.hpp"
 
 namespace lorads {
@@ -161,10 +162,13 @@ static double ritz_residual(const std::vector<double>& a, const std::vector<doub
   return std::fabs(beta * x[k - 1]);
 }
 
-double dual_lambda_min(Problem& P, const double* lam, int max_steps, hipStream_t s) {
+double dual_lambda_min(Problem& P, const double* lam, int max_steps, hipStream_t s,
+                       const double* Uh, int r) {
   const int n = P.n;
   const int kmax = std::max(2, std::min(max_steps, n));
-  DevBuf<double> Qb, y, c;
+  const bool quad = Uh != nullptr && P.mu != 0.0 && r > 0;
+  DevBuf<double> Qb, y, c, tq;
+  if (quad) tq.alloc(r);
   Qb.alloc((size_t)kmax * n);
   y.alloc(n);
   c.alloc(kmax + 1);
@@ -181,6 +185,11 @@ double dual_lambda_min(Problem& P, const double* lam, int max_steps, hipStream_t
   for (; k < kmax; ++k) {
     double* qk = Qb.p + (size_t)k * n;
     op_adjoint<double>(P, lam, 1.0, qk, 1, 1, y.p, 1, 1.0, s);
+    if (quad) {
+      // + mu Uh (Uh^T q_k)
+      gram_small<double>(P, n, r, 1, Uh, r, qk, 1, tq.p, s);
+      add_xg<double, double><<<grid_for((size_t)n), kBlock, 0, s>>>(n, r, 1, Uh, r, tq.p, P.mu, y.p, 1);
+    }
     // full reorthogonalisation, twice (classical Gram-Schmidt); the first
     // pass's coefficient on q_k is alpha_k = <q_k, S q_k>
     double ak = 0.0;
@@ -232,12 +241,25 @@ void final_metrics(Problem& P, lorads_result& res, hipStream_t s, int lanczos_st
   double h[3];
   read_slots(P, S_GEN, h, 3, s);
   const double zb = std::sqrt(h[0]);
-  res.obj = h[1];
+  // quadratic objective: f(X) = <C, X> + (mu/2) ||X||^2 with ||X||^2 = ||Uh^T Uh||^2;
+  // the measures are taken at grad f(X) = C + mu X (<grad f(X), X> in the gap)
+  double xx = 0.0;
+  if (P.mu != 0.0) {
+    DevBuf<double> g;
+    g.alloc((size_t)r * r);
+    gram_small<double>(P, n, r, r, Uh.p, r, Uh.p, r, g.p, s);
+    std::vector<double> gh((size_t)r * r);
+    HIPCHK(hipMemcpyAsync(gh.data(), g.p, gh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (double v : gh) xx += v * v;
+  }
+  res.obj = h[1] + 0.5 * P.mu * xx;
+  const double gx = h[1] + P.mu * xx;
   res.dual_obj = h[2];
   res.pinf = zb / (1.0 + P.b_1);
-  res.lambda_min = lanczos_steps > 0 ? dual_lambda_min(P, P.lam.p, lanczos_steps, s) : NAN;
+  res.lambda_min = lanczos_steps > 0 ? dual_lambda_min(P, P.lam.p, lanczos_steps, s, Uh.p, r) : NAN;
   res.dinf = std::fabs(std::min(0.0, res.lambda_min)) / (1.0 + P.c_1);
-  res.gap = (res.obj - res.dual_obj) / (1.0 + std::fabs(res.obj) + std::fabs(res.dual_obj));
+  res.gap = (gx - res.dual_obj) / (1.0 + std::fabs(gx) + std::fabs(res.dual_obj));
 }
 
 }  // namespace lorads

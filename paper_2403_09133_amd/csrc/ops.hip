@@ -6,6 +6,7 @@
 
 #include "kernels.hpp"
 #include "kernels_dense.hpp"
+#include "kernels_quad.hpp"
 #include "kernels_rank1.hpp"
 #include "kernels_struct.hpp"
 #include "problem.hpp"
@@ -406,6 +407,24 @@ template void cdense_apply<double>(Problem&, const double*, int, int, double*, i
 template void cdense_apply<float>(Problem&, const float*, int, int, float*, int, double, double,
                                   hipStream_t);
 
+template <typename T>
+void gram_small(Problem& P, int n, int ra, int rb, const T* X, int ldx, const T* Y, int ldy, double* G,
+                hipStream_t s) {
+  if (ra < 1 || rb < 1 || ra > 256 || rb > 256) fail(LORADS_EINVAL, "small Gram: bad shape");
+  const int rr = ra * rb;
+  // at most 2^21 partial entries (16 MB)
+  const int nb = std::max(1, std::min(kGramBlocks, (1 << 21) / rr));
+  const size_t need = (size_t)nb * rr;
+  if (P.qpart.n < need) P.qpart.alloc(need);
+  gram_rr_partial<T><<<nb, kBlock, 0, s>>>(n, ra, rb, X, ldx, Y, ldy, P.qpart.p);
+  gram_rr_finish<<<std::max(1, (rr + kBlock - 1) / kBlock), kBlock, 0, s>>>(rr, nb, P.qpart.p, G);
+  HIPCHK(hipGetLastError());
+}
+template void gram_small<double>(Problem&, int, int, int, const double*, int, const double*, int, double*,
+                                 hipStream_t);
+template void gram_small<float>(Problem&, int, int, int, const float*, int, const float*, int, double*,
+                                hipStream_t);
+
 int pair_f32_lanes(const Problem& P, int r, int ld) {
   if (P.structure != LORADS_STRUCT_PAIR || P.pcoef.n != 0 || P.nxchunks == 0 || r < 1 || r > 128)
     return 0;
@@ -749,7 +768,7 @@ void linesearch_slots(Problem& P, int n, int r, int ld, const double* CD, const 
 template <typename T>
 int cg_run(Problem& P, const T* W, int ldw, int r, int ld, double rho, double gamma, T* R, T* X,
            T* Pd, T* P2, T* Q, T* t, double tol, int maxit, hipStream_t s, double* relres,
-           double* op_bytes) {
+           double* op_bytes, const double* quadG) {
   const size_t N = (size_t)P.n * ld;  // padding entries are zero and stay zero
   const double sv[2] = {gamma, rho};
   set_slots(P, S_GAMMA, sv, 2, s);
@@ -777,6 +796,13 @@ int cg_run(Problem& P, const T* W, int ldw, int r, int ld, double rho, double ga
       P.prof.run_ext(0, bytes_cg_op(P, r, sizeof(T)), [&](hipEvent_t e0, hipEvent_t e1) {
         np = op_cg<T>(P, W, ldw, r, ld, Pd, P2, Q, t, par, s, e0, e1);
       });
+      if (quadG) {
+        // the quadratic objective's term mu P (W^T W), its partials after the operator's
+        const int gq = grid_for((size_t)P.n * r, 512);
+        P.ensure_part((size_t)np + gq);
+        cg_quad<T><<<gq, kBlock, 0, s>>>(P.n, r, ld, Pd, quadG, P.mu, Q, P.sc.p, par, P.part.p + np);
+        np += gq;
+      }
       cg_alpha_finish<<<1, kBlock, 0, s>>>(np, P.part.p, P.sc.p, par);
       cg_update<T><<<gridv, kBlock, 0, s>>>(N, X, R, Pd, Q, P.sc.p, par, P.part.p);
       cg_direction<T><<<gridv, kBlock, 0, s>>>(N, R, Pd, P.sc.p, par, P2, ld, gridv, P.part.p);
@@ -818,7 +844,7 @@ template int op_cg<double>(Problem&, const double*, int, int, int, const double*
 template int op_cg<float>(Problem&, const float*, int, int, int, const float*, const float*, float*, float*, int, hipStream_t, hipEvent_t, hipEvent_t);
 template void dot_to_slot<double, double>(Problem&, size_t, const double*, const double*, double, int, hipStream_t);
 template void dot_to_slot<float, float>(Problem&, size_t, const float*, const float*, double, int, hipStream_t);
-template int cg_run<double>(Problem&, const double*, int, int, int, double, double, double*, double*, double*, double*, double*, double*, double, int, hipStream_t, double*, double*);
-template int cg_run<float>(Problem&, const float*, int, int, int, double, double, float*, float*, float*, float*, float*, float*, double, int, hipStream_t, double*, double*);
+template int cg_run<double>(Problem&, const double*, int, int, int, double, double, double*, double*, double*, double*, double*, double*, double, int, hipStream_t, double*, double*, const double*);
+template int cg_run<float>(Problem&, const float*, int, int, int, double, double, float*, float*, float*, float*, float*, float*, double, int, hipStream_t, double*, double*, const double*);
 
 }  // namespace lorads

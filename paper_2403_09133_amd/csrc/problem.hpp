@@ -138,6 +138,8 @@ struct Problem {
   int structure = LORADS_STRUCT_GENERIC;
   bool perm_identity = true;
   double b_inf = 0, b_1 = 0, b_2 = 0, c_fro = 0, c_1 = 0;
+  // objective f(X) = <C, X> + (mu / 2) ||X||_F^2 (mu = 0: the linear SDP)
+  double mu = 0;
   int64_t a_nnz = 0, c_nnz = 0;
 
   DevBuf<int> perm;  // internal -> caller id
@@ -156,6 +158,8 @@ struct Problem {
   DevBuf<double> cval;
   DevBuf<double> cdiag;  // diagonal C only: C_jj by row (zero where absent), else empty
   DevBuf<float> cvalf;
+  // partials of the small Gram products of the quadratic objective
+  DevBuf<double> qpart;
   // dense C (at least a quarter of the n^2 entries, n >= kDenseCMinN): also
   // stored n x ldc row-major (ldc a multiple of 64, zero padding), FP64 and
   // FP32; products with C then run on the matrix cores (cdense_apply), with
@@ -339,6 +343,11 @@ inline int ls_blocks_f32(const Problem& P, int r, int ld) {
   return g ? xchunk_grid(P, g) : 0;
 }
 double bytes_linesearch_pair_f32(const Problem& P, int r);
+// G = X^T Y (ra x rb, FP64, row-major) for n-row factors X (ra columns, row
+// stride ldx) and Y (rb, ldy), in a fixed order; partials in P.qpart
+template <typename T>
+void gram_small(Problem& P, int n, int ra, int rb, const T* X, int ldx, const T* Y, int ldy, double* G,
+                hipStream_t s);
 // out = alpha C V + beta out (first r columns) with the dense copy of C
 template <typename T>
 void cdense_apply(Problem& P, const T* V, int r, int ld, T* out, int ldo, double alpha, double beta,
@@ -394,9 +403,11 @@ inline int grid_for(size_t N, int cap = 2048) {
 
 // CG on M_W D = R from D = X (X holds x0 = 0 normally; R holds R0 - M x0).
 // Buffers dense n x r of type T.  Returns iterations; *relres = ||R||/||R0||.
+// quadG (r x r, FP64, optional): W^T W of the quadratic objective, whose term
+// P.mu P (W^T W) the operator then includes.
 template <typename T>
 int cg_run(Problem& P, const T* W, int ldw, int r, int ld, double rho, double gamma, T* R, T* X,
            T* Pd, T* P2, T* Q, T* t, double tol, int maxit, hipStream_t s, double* relres,
-           double* op_bytes);
+           double* op_bytes, const double* quadG = nullptr);
 
 }  // namespace lorads

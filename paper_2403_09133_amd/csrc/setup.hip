@@ -48,6 +48,7 @@ void validate(const lorads_problem& p) {
   }
   for (int i = 0; i < m; ++i) check(cnt[i] > 0, "constraint " + std::to_string(i) + " has no triplet");
   for (int i = 0; i < m; ++i) check(std::isfinite(p.b[i]), "non-finite b");
+  check(std::isfinite(p.mu) && p.mu >= 0.0, "mu must be finite and >= 0 (a convex objective)");
 }
 
 std::unique_ptr<Problem> ingest(const lorads_problem& p, hipStream_t s) {
@@ -58,6 +59,7 @@ std::unique_ptr<Problem> ingest(const lorads_problem& p, hipStream_t s) {
 
   auto P = std::make_unique<Problem>();
   P->n = n;
+  P->mu = p.mu;
   P->m = m;
   P->a_nnz = p.a_nnz;
   P->c_nnz = p.c_nnz;

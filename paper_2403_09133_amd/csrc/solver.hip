@@ -8,6 +8,7 @@
 #include <complex>
 
 #include "kernels.hpp"
+#include "kernels_quad.hpp"
 #include "solver.hpp"
 
 namespace lorads {
@@ -97,6 +98,8 @@ double gamma_of(const Problem& P, const lorads_options& o, double rho) {
 struct AlmState {
   int n, m, r, ld;
   DevBuf<double> G, Gn, D, Q, CD, p1, p2, Sn, Yn;
+  // quadratic objective: U^T U (at the last gradient), U^T D, D^T D
+  DevBuf<double> gUU, gUD, gDD;
   DevBuf<double> lsp;  // block partials of the fused line-search pass
   std::vector<DevBuf<double>> S, Y;
   // slot of sc holding <S, Y> of each pair buffer (it travels with the buffer)
@@ -125,6 +128,7 @@ static void alm_alloc(AlmState& A, int n, int m, int r, int ld, int mem, hipStre
     b->zero(s);
   }
   A.p1.alloc(m); A.p2.alloc(m);
+  A.gUU.alloc((size_t)r * r); A.gUD.alloc((size_t)r * r); A.gDD.alloc((size_t)r * r);
 
   A.S.resize(mem); A.Y.resize(mem);
   A.sy.resize(mem);
@@ -139,9 +143,12 @@ static void alm_alloc(AlmState& A, int n, int m, int r, int ld, int mem, hipStre
   A.head = A.count = 0;
 }
 
-// G = 2 (C + A*(lam + rho (z - b))) U with z = A(U U^T) recomputed
+// G = 2 (C + A*(lam + rho (z - b))) U with z = A(U U^T) recomputed, plus
+// 2 mu U (U^T U) for the quadratic objective (U^T U kept for the line search)
 static void alm_gradient(Problem& P, AlmState& A, const double* U, double* G, double rho,
-                         hipStream_t s, double& bytes) {
+                         hipStream_t s, double& bytes);
+static void alm_gradient_linear(Problem& P, AlmState& A, const double* U, double* G, double rho,
+                                hipStream_t s, double& bytes) {
   if (grad_pair_ready(P)) {
     // the gradient forms w per entry and returns z = A(U U^T) for the line
     // search and the infeasibility
@@ -151,6 +158,17 @@ static void alm_gradient(Problem& P, AlmState& A, const double* U, double* G, do
     op_forward_w(P, U, U, A.r, A.ld, P.zbuf.p, P.wbuf.p, P.lam.p, rho, s);
     op_adjoint<double>(P, P.wbuf.p, 1.0, U, A.r, A.ld, G, A.ld, 2.0, s);
     bytes += bytes_forward(P, A.r, 8) + bytes_adjoint(P, A.r, 8, true);
+  }
+}
+
+static void alm_gradient(Problem& P, AlmState& A, const double* U, double* G, double rho,
+                         hipStream_t s, double& bytes) {
+  alm_gradient_linear(P, A, U, G, rho, s, bytes);
+  if (P.mu != 0.0) {
+    gram_small<double>(P, A.n, A.r, A.r, U, A.ld, U, A.ld, A.gUU.p, s);
+    add_xg<double, double><<<grid_for((size_t)A.n * A.r), kBlock, 0, s>>>(A.n, A.r, A.r, U, A.ld, A.gUU.p,
+                                                                         2.0 * P.mu, G, A.ld);
+    HIPCHK(hipGetLastError());
   }
 }
 
@@ -328,6 +346,7 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
         (P.structure == LORADS_STRUCT_PAIR && P.cdiag.n > 0) ? P.cdiag.p : nullptr;
     // PAIR: the two maps and their seven m-vector sums in one pass (nothing
     // m-sized written); otherwise the maps, then the sums
+    double hq[4] = {0.0, 0.0, 0.0, 0.0};  // quadratic objective's quartic terms
     const int nls = gf ? ls_blocks_f32(P, r, F.ld) : ls_blocks(P, r);
     if (A.lsp.n < (size_t)7 * nls) A.lsp.alloc((size_t)7 * nls);
     auto line_search = [&](int nread) {
@@ -345,9 +364,17 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
         op_adjoint<double>(P, (const double*)nullptr, 1.0, A.D.p, r, F.ld, A.CD.p, F.ld, 1.0, s);
       // the two maps, and C D (a product with C alone)
       info.op_bytes += 2 * bytes_forward(P, r, gf ? 4 : 8) + bytes_cprod(P, r, 8);
+      if (P.mu != 0.0) {
+        // the quadratic objective's quartic terms (U^T U is the last gradient's)
+        gram_small<double>(P, n, r, r, U, F.ld, A.D.p, F.ld, A.gUD.p, s);
+        gram_small<double>(P, n, r, r, A.D.p, F.ld, A.D.p, F.ld, A.gDD.p, s);
+        quad_coefs<<<1, kBlock, 0, s>>>(r, A.gUU.p, A.gUD.p, A.gDD.p, P.sc.p, S_QUAD);
+        HIPCHK(hipGetLastError());
+      }
       linesearch_slots(P, n, r, F.ld, A.CD.p, U, A.D.p, P.zbuf.p, A.p1.p, A.p2.p, P.lam.p,
                        S_GEN + 1, s, part_gd, cdiag, h, nread, fused ? A.lsp.p : nullptr,
                        fused ? nls : 0);
+      if (P.mu != 0.0) read_slots(P, S_QUAD, hq, 4, s);
     };
     // A step's curvature pair enters the memory at once, before its <S, Y>
     // is known on the host, so the next direction and line search are queued
@@ -413,10 +440,11 @@ void phase1(Problem& P, const lorads_options& o, SolveInfo& info, hipStream_t s)
         const double c1 = h[0], c2 = h[1];
         const double p22 = h[2], p12 = h[3], p11 = h[4], p02 = h[5], p01 = h[6], l1 = h[7],
                      l2 = h[8];
-        const double q4 = 0.5 * rho * p22;
-        const double q3 = rho * p12;
-        const double q2 = c2 + l2 + 0.5 * rho * (p11 + 2.0 * p02);
-        const double q1 = c1 + l1 + rho * p01;
+        const double mu = P.mu;
+        const double q4 = 0.5 * rho * p22 + 0.5 * mu * hq[3];
+        const double q3 = rho * p12 + mu * hq[2];
+        const double q2 = c2 + l2 + 0.5 * rho * (p11 + 2.0 * p02) + 0.5 * mu * hq[1];
+        const double q1 = c1 + l1 + rho * p01 + mu * hq[0];
         alpha = quartic_step(q1, q2, q3, q4);
         if (alpha > 0.0 || A.count == 0) break;
         // retry along steepest descent with a cleared memory
@@ -545,7 +573,7 @@ template <typename T>
 static int half_step(Problem& P, const double* W, double* out, int r, double rho, double gamma,
                      double tol, int maxit, CgBufs<T>& B, DevBuf<double>& R64, hipStream_t s,
                      SolveInfo& info, const double* Wp = nullptr, double* outp = nullptr,
-                     int ldp = 0) {
+                     int ldp = 0, double* gW = nullptr) {
   const int ld = B.ld;
   const size_t N = (size_t)P.n * ld;  // CG layout
   double* R = std::is_same<T, double>::value ? reinterpret_cast<double*>(B.R.p) : R64.p;
@@ -560,6 +588,13 @@ static int half_step(Problem& P, const double* W, double* out, int r, double rho
     op_adjoint<double>(P, P.wbuf.p, 1.0, W, r, r, R, ld, -1.0, s);
     info.op_bytes += bytes_forward(P, r, 8) + bytes_adjoint(P, r, 8, true);
   }
+  if (P.mu != 0.0) {
+    // quadratic objective: grad f(W W^T) W gains mu W (W^T W); the operator
+    // gains mu P (W^T W)
+    gram_small<double>(P, P.n, r, r, W, r, W, r, gW, s);
+    add_xg<double, double><<<grid_for((size_t)P.n * r), kBlock, 0, s>>>(P.n, r, r, W, r, gW, -P.mu, R, ld);
+    HIPCHK(hipGetLastError());
+  }
   if constexpr (!std::is_same<T, double>::value)
     convert_kernel<double, float><<<gridN(N), kBlock, 0, s>>>(N, R64.p, B.R.p);
   copy_rows<double, T><<<gridN((size_t)P.n * r), kBlock, 0, s>>>(P.n, r, W, r, B.W.p, B.ldw);
@@ -569,7 +604,7 @@ static int half_step(Problem& P, const double* W, double* out, int r, double rho
   {
     CgXpartsScope xs(P, B.xparts.n ? B.xparts.p : nullptr);
     it = cg_run<T>(P, B.W.p, B.ldw, r, ld, rho, gamma, B.R.p, B.X.p, B.Pd.p, B.P2, B.Q.p, B.t.p,
-                   tol, maxit, s, &rel, &info.op_bytes);
+                   tol, maxit, s, &rel, &info.op_bytes, P.mu != 0.0 ? gW : nullptr);
   }
   add_rows<double, T><<<gridN((size_t)P.n * r), kBlock, 0, s>>>(P.n, r, W, r, B.X.p, ld, out);
   if (outp)
@@ -596,6 +631,8 @@ static void phase2_t(Problem& P, const lorads_options& o, double rho, SolveInfo&
   }
   CgBufs<T> B;
   B.alloc(P, n, m, ldc, P.structure == LORADS_STRUCT_PAIR, s);
+  DevBuf<double> gW;  // W^T W of the quadratic objective
+  if (P.mu != 0.0) gW.alloc((size_t)r * r);
   refresh_inc_lam(P, s);
   // PAIR: zero-padded FP64 copies of U and V (rows of whole 64-byte sectors),
   // kept equal to the masters, for the gradient form and the dual update's
@@ -625,9 +662,9 @@ static void phase2_t(Problem& P, const lorads_options& o, double rho, SolveInfo&
     HIPCHK(hipMemcpyAsync(Vold.p, P.V.p, N * sizeof(double), hipMemcpyDeviceToDevice, s));
     dot_to_slot<double, double>(P, N, Vold.p, Vold.p, 1.0, S_GEN + 2, s);
     const int iu = half_step<T>(P, P.V.p, P.U.p, r, rho, gamma, tol, maxit, B, R64, s, info,
-                                padded ? Vp.p : nullptr, padded ? Up.p : nullptr, ldp);
+                                padded ? Vp.p : nullptr, padded ? Up.p : nullptr, ldp, gW.p);
     const int iv = half_step<T>(P, P.U.p, P.V.p, r, rho, gamma, tol, maxit, B, R64, s, info,
-                                padded ? Up.p : nullptr, padded ? Vp.p : nullptr, ldp);
+                                padded ? Up.p : nullptr, padded ? Vp.p : nullptr, ldp, gW.p);
     cg_total += iu + iv;
     // z = A(U V^T); lam += rho (z - b); residual norms
     if (padded) op_forward<double>(P, Up.p, Vp.p, r, ldp, P.zbuf.p, 1.0, s);

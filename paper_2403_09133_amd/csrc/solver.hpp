@@ -32,7 +32,10 @@ void phase2(Problem& P, const lorads_options& o, double rho, SolveInfo& info, hi
 // Appendix-B measures of U_hat = (U + V)/2 and lam; fills the result fields.
 void final_metrics(Problem& P, lorads_result& res, hipStream_t s, int lanczos_steps);
 // lambda_min(C + A*(lam)) by Lanczos, lam in internal order
-double dual_lambda_min(Problem& P, const double* lam, int max_steps, hipStream_t s);
+// smallest eigenvalue of C + A*(lam), plus P.mu Uh Uh^T when Uh (n x r, the
+// solution factor of the quadratic objective) is given
+double dual_lambda_min(Problem& P, const double* lam, int max_steps, hipStream_t s,
+                       const double* Uh = nullptr, int r = 0);
 // G = A^T B (ra x rb, row-major), FP64 MFMA
 void gram(const double* A, const double* B, int64_t n, int ra, int rb, int lda, int ldb,
           double* G, hipStream_t s);

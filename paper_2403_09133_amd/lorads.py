@@ -36,7 +36,7 @@ class Problem_(C.Structure):
         ("n", C.c_int32), ("m", C.c_int32),
         ("c_nnz", C.c_int64), ("c_row", C.c_void_p), ("c_col", C.c_void_p), ("c_val", C.c_void_p),
         ("a_nnz", C.c_int64), ("a_con", C.c_void_p), ("a_row", C.c_void_p), ("a_col", C.c_void_p),
-        ("a_val", C.c_void_p), ("b", C.c_void_p),
+        ("a_val", C.c_void_p), ("b", C.c_void_p), ("mu", C.c_double),
     ]
 
 
@@ -213,7 +213,7 @@ class Context:
             arr[i] = Problem_(int(p.n), int(p.m), int(cols["c_row"].size), _ptr(cols["c_row"]),
                               _ptr(cols["c_col"]), _ptr(cols["c_val"]), int(cols["a_row"].size),
                               _ptr(cols["a_con"]), _ptr(cols["a_row"]), _ptr(cols["a_col"]),
-                              _ptr(cols["a_val"]), _ptr(cols["b"]))
+                              _ptr(cols["a_val"]), _ptr(cols["b"]), float(getattr(p, "mu", 0.0)))
         h = C.c_void_p()
         st = lib.lorads_setup(arr, len(problems), C.byref(h))
         self._keep = []

@@ -45,6 +45,8 @@ def test_default_options():
     (lambda p: setattr(p, "b", np.where(np.arange(p.m) == 2, np.inf, p.b)), "non-finite b"),
     (lambda p: setattr(p, "a_con", np.where(np.arange(p.a_nnz) == 0, p.m + 5, p.a_con)), "constraint id"),
     (lambda p: setattr(p, "c_col", np.where(np.arange(p.c_nnz) == 0, -1, p.c_col)), "out of range"),
+    (lambda p: setattr(p, "mu", -0.5), "mu must be finite and >= 0"),
+    (lambda p: setattr(p, "mu", float("nan")), "mu must be finite and >= 0"),
 ])
 def test_setup_rejects_malformed_input_on_host(mutation, msg):
     from paper_2403_09133_amd import Context, lorads

@@ -131,3 +131,24 @@ def test_cg_operator_is_the_subproblem_hessian(mu):
     assert np.linalg.norm(M(P) - diff) <= 1e-6 * np.linalg.norm(diff)
     # and R0 is the negative gradient at x0 = W
     assert np.linalg.norm(-admm.grad_factor(p, W, lam, rho) + grad_u(W)) <= 1e-6 * np.linalg.norm(grad_u(W))
+
+
+def _fully_observed(n1, n2, seed):
+    """Completion with every cell observed and mu scaled to the planted matrix:
+    X* = [U S U^T, M; M^T, V S V^T] (M = U S V^T) for every mu >= 0 (per
+    singular pair, min (a + b)/2 + (mu/2)(a^2 + b^2) s.t. a b >= s^2 is at
+    a = b = s), so f* = sum s + 2 mu sum s^2 (||X*||_F^2 = 4 sum s^2)."""
+    p = sdpgen.mc_planted(n1, n2, 2, seed, count=n1 * n2)
+    M = p.meta["L"] @ p.meta["R"].T
+    s = np.linalg.svd(M, compute_uv=False)
+    p.mu = 0.25 * s.sum() / (s ** 2).sum()
+    return p, s.sum() + 2.0 * p.mu * (s ** 2).sum()
+
+
+@pytest.mark.parametrize("n1,n2,seed", [(8, 6, 4), (30, 24, 7)])
+def test_fully_observed_completion_with_mu(n1, n2, seed):
+    p, want = _fully_observed(n1, n2, seed)
+    out = oracle.lorads.lorads(p, sdpgen.random_init_U(p.n, sdpgen.rank_rule_2lnm(p.m), 3),
+                               Options(**paper_defaults(p.kind, p.n)))
+    assert out["phase2"]["converged"]
+    assert abs(out["metrics"]["obj"] - want) <= 1e-6 * want
