@@ -82,6 +82,13 @@ def test_solve_matches_oracle(device, name, precision):
     assert abs(m["pinf"] - res["pinf"]) <= 1e-9
     assert abs(m["lambda_min"] - res["lambda_min"]) <= 1e-7 * max(1.0, abs(m["lambda_min"]))
     assert abs(m["gap"] - res["gap"]) <= 1e-9
+    # the stop test's first term, recomputed by the oracle from the returned
+    # factors: ||A(U V^T) - b||_2 / (1 + ||b||_inf) (eq. (stop)); the reported
+    # eq. (stop) value is at least this term
+    nrm = oracle.operators.norms(p)
+    pstop = float(np.linalg.norm(oracle.operators.forward(p, U, V) - p.b)) / (1.0 + nrm["b_inf"])
+    assert abs(pstop - res["pinf_stop"]) <= 1e-10 * max(1.0, pstop) + 1e-15, (pstop, res["pinf_stop"])
+    assert res["kkt"] >= res["pinf_stop"] and res["kkt"] >= res["dres_stop"]
     if precision == 0:
         # Same trajectory as the oracle up to rounding, where rounding cannot
         # steer it: perturbing U0 by 1e-15 (relative) moves the oracle's own
