@@ -172,10 +172,12 @@ def host_cpu() -> dict:
     return dict(model=model, nproc=os.cpu_count())
 
 
-def cpu_baseline(p, r: int, budget_s: float = 20.0):
+def cpu_baseline(p, r: int, budget_s: float = 20.0, e2e=("maxcut_er200",)):
     """The oracle's forward map and adjoint product (FP64, numpy) on the host,
     one thread, for a bounded number of applications; plus the oracle's
-    end-to-end solve of the MaxCut instance of order 200 to eq. (stop)."""
+    end-to-end solves to eq. (stop) of the named instances (by default the
+    MaxCut instance of order 200), one thread, from the library's initial
+    rank."""
     try:
         from threadpoolctl import threadpool_limits
     except Exception:  # pragma: no cover
@@ -198,11 +200,20 @@ def cpu_baseline(p, r: int, budget_s: float = 20.0):
             t = time.perf_counter() - t0
             if t > budget_s / 2 or reps >= 8:
                 break
-        q = sdpgen.config_instance("maxcut_er200")
-        U0 = sdpgen.random_init_U(q.n, 8, 3)
-        t1 = time.perf_counter()
-        out = oracle.lorads.lorads(q, U0, Options(**paper_defaults(q.kind, q.n)), with_metrics=False)
-        t_e2e = time.perf_counter() - t1
+        solves = []
+        for name in e2e:
+            q = sdpgen.config_instance(name)
+            r0 = initial_rank(q)
+            U0 = sdpgen.random_init_U(q.n, r0, 3)
+            log(f"oracle end-to-end solve of {name} (n = {q.n}, m = {q.m}, r0 = {r0})")
+            t1 = time.perf_counter()
+            out = oracle.lorads.lorads(q, U0, Options(**paper_defaults(q.kind, q.n)), with_metrics=False,
+                                       progress=lambda msg, nm=name: log(f"oracle {nm}: {msg}"))
+            t_e2e = time.perf_counter() - t1
+            log(f"oracle {name}: {t_e2e:.1f} s")
+            solves.append(dict(workload=f"{name} (n = {q.n}, m = {q.m}, r0 = {r0}), FP64 numpy, 1 thread",
+                               s=round(t_e2e, 3), admm_iters=int(out["phase2"]["iters"]),
+                               converged=bool(out["phase2"]["converged"])))
     finally:
         if ctx is not None and hasattr(ctx, "unregister"):
             ctx.unregister()
@@ -211,9 +222,7 @@ def cpu_baseline(p, r: int, budget_s: float = 20.0):
                 sample=f"{reps} x (A(UV^T) + (C + A*(y))V) at full size, r={r}, FP64 numpy, "
                        f"{t:.1f} s on the host",
                 host=host_cpu(),
-                oracle_time_to_kkt_s=dict(workload="maxcut_er200 (n = m = 200, r0 = 8), FP64 numpy, 1 thread",
-                                          s=round(t_e2e, 3), admm_iters=int(out["phase2"]["iters"]),
-                                          converged=bool(out["phase2"]["converged"])))
+                oracle_time_to_kkt_s=solves)
 
 
 def starts(p, r0, steps, warmup):
@@ -520,6 +529,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="mc_20000", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--oracle-e2e", default="maxcut_er200", metavar="NAMES",
+                    help="comma-separated instances the oracle solves end to end in the CPU baseline "
+                         "(maxcut_er200, maxcut_torus100, maxcut_gnm20000; the larger ones take minutes)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solve")
     ap.add_argument("--no-secondary", action="store_true", help="skip the second completion workload")
     ap.add_argument("--no-ops", action="store_true", help="skip the cold / warm operator timings")
@@ -576,7 +588,7 @@ def main():
     for name, c in cmp_.items():
         line[f"roofline_{name}"] = c["roofline"]
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(p, leg["r0"])
+        line["cpu_baseline"] = cpu_baseline(p, leg["r0"], e2e=[x for x in args.oracle_e2e.split(",") if x])
     line["time_to_kkt_s"] = {tkey: round(leg["wall"] / args.steps, 4)}
     for name, c in cmp_.items():
         line["time_to_kkt_s"][name] = c["s"]

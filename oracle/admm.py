@@ -65,7 +65,8 @@ def half_step(prob, W, lam, rho, gamma, tol, maxit):
     return W + D, it
 
 
-def admm(prob, U0, V0, lam0, rho0, opts, trace=None):
+def admm(prob, U0, V0, lam0, rho0, opts, trace=None, progress=None):
+    """progress (optional): called with a status line every 100 iterations."""
     U = np.array(U0, dtype=np.float64)
     V = np.array(V0, dtype=np.float64)
     lam = np.array(lam0, dtype=np.float64)
@@ -95,6 +96,8 @@ def admm(prob, U0, V0, lam0, rho0, opts, trace=None):
         lam = lam_new
         cg_total += it_u + it_v
         k += 1
+        if progress is not None and k % 100 == 0:
+            progress(f"ADMM {k}: eq. (stop) {kkt:.3e}")
         if kkt < opts.eps:
             break
         if k % opts.rho_every == 0 and rho < opts.rho_max:

@@ -158,7 +158,8 @@ def lbfgs_inner(prob, U, lam, rho, tol, cap, mem, c_fro):
         it += 1
 
 
-def alm(prob, U0, lam0, opts, rho0=None):
+def alm(prob, U0, lam0, opts, rho0=None, progress=None):
+    """progress (optional): called with a status line after every inner solve."""
     U = np.array(U0, dtype=np.float64)
     lam = np.array(lam0, dtype=np.float64)
     nrm = operators.norms(prob)
@@ -175,6 +176,8 @@ def alm(prob, U0, lam0, opts, rho0=None):
         U, z, it, conv = lbfgs_inner(prob, U, lam, rho, tol, cap, opts.lbfgs_mem, nrm["c_fro"])
         inner_total += it
         v = float(np.linalg.norm(z - prob.b)) / (1.0 + nrm["b_inf"])
+        if progress is not None:
+            progress(f"ALM outer {outer}: {it} inner iterations, rank {U.shape[1]}, infeasibility {v:.3e}")
         # a hard inner solve raises the rank only while Phase I goes on: once
         # the infeasibility meets the switching tolerance the phase ends
         if not conv and r < r_cap and it >= cap and v > opts.switch_tol:

@@ -14,17 +14,17 @@ from . import alm as alm_mod
 from . import metrics
 
 
-def lorads(prob, U0, opts, lam0=None, with_metrics=True):
+def lorads(prob, U0, opts, lam0=None, with_metrics=True, progress=None):
     lam0 = np.zeros(prob.m) if lam0 is None else np.asarray(lam0, dtype=np.float64)
     if opts.phase1:
-        p1 = alm_mod.alm(prob, U0, lam0, opts)
+        p1 = alm_mod.alm(prob, U0, lam0, opts, progress=progress)
         U, lam, rho = p1["U"], p1["lam"], p1["rho"]
     else:
         p1 = None
         U, lam = np.asarray(U0, dtype=np.float64), lam0
         rho = opts.rho0 if opts.rho0 > 0 else 1.0 / max(1.0, float(np.max(np.abs(prob.b))))
     rho_admm = opts.h * rho
-    p2 = admm_mod.admm(prob, U, U, lam, rho_admm, opts)
+    p2 = admm_mod.admm(prob, U, U, lam, rho_admm, opts, progress=progress)
     Uh = 0.5 * (p2["U"] + p2["V"])
     out = dict(phase1=p1, phase2=p2, U_hat=Uh, lam=p2["lam"], rank=Uh.shape[1])
     if with_metrics:
