@@ -399,15 +399,29 @@ def _rank_one_triplets(con: int, idx, val):
 
 def snl(n_sensors: int, n_anchors: int, radius: float, seed: int, d: int = 2) -> Problem:
     """SDP relaxation of sensor network localization (Section 3) with exact
-    distances: Z of order d + n_sensors, Z[:d, :d] = I written with rank-one
-    constraints (Z_kk = 1 and <(e_k + e_l)(e_k + e_l)^T, Z> = 2), one constraint
-    <(0; e_i - e_j)(0; e_i - e_j)^T, Z> = |x_i - x_j|^2 per sensor pair closer
-    than `radius` and <(a_k; -e_j)(a_k; -e_j)^T, Z> = |a_k - x_j|^2 per
-    anchor-sensor pair closer than `radius`; C = 0.  Sensors and anchors are
-    uniform in [-0.5, 0.5]^d; the true positions are kept in meta."""
+    distances, sensors and anchors uniform in [-0.5, 0.5]^d (see
+    snl_positions)."""
     rng = np.random.default_rng(seed)
     X = rng.uniform(-0.5, 0.5, (n_sensors, d))
     A = rng.uniform(-0.5, 0.5, (n_anchors, d))
+    p = snl_positions(X, A, radius)
+    p.meta.update(seed=seed, family=f"SNL({n_sensors}, {n_anchors}, r={radius})")
+    return p
+
+
+def snl_positions(X, A, radius: float = np.inf) -> Problem:
+    """SDP relaxation of sensor network localization (Section 3) for given
+    sensor positions X (n_s x d) and anchors A (n_a x d), exact distances:
+    Z of order d + n_s, Z[:d, :d] = I written with rank-one constraints
+    (Z_kk = 1 and <(e_k + e_l)(e_k + e_l)^T, Z> = 2), one constraint
+    <(0; e_i - e_j)(0; e_i - e_j)^T, Z> = |x_i - x_j|^2 per sensor pair closer
+    than `radius` and <(a_k; -e_j)(a_k; -e_j)^T, Z> = |a_k - x_j|^2 per
+    anchor-sensor pair closer than `radius`; C = 0.  The true positions are
+    kept in meta."""
+    X = np.atleast_2d(np.asarray(X, dtype=np.float64))
+    A = np.atleast_2d(np.asarray(A, dtype=np.float64))
+    n_sensors, d = X.shape
+    n_anchors = A.shape[0]
     parts, b = [], []
 
     def add(idx, val, rhs):
@@ -435,8 +449,8 @@ def snl(n_sensors: int, n_anchors: int, radius: float, seed: int, d: int = 2) ->
     n = d + n_sensors
     return Problem(n=n, m=len(b), c_row=np.zeros(0), c_col=np.zeros(0), c_val=np.zeros(0),
                    a_con=con, a_row=row, a_col=col, a_val=val, b=np.asarray(b), kind="snl",
-                   meta={"seed": seed, "d": d, "sensors": X, "anchors": A, "sensor_pairs": ss,
-                         "anchor_pairs": sa, "family": f"SNL({n_sensors}, {n_anchors}, r={radius})"})
+                   meta={"d": d, "sensors": X, "anchors": A, "sensor_pairs": ss,
+                         "anchor_pairs": sa, "family": f"SNL({n_sensors}, {n_anchors})"})
 
 
 def min_bisection(n: int, ei, ej, w, meta: Optional[dict] = None) -> Problem:

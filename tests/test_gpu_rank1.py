@@ -4,7 +4,8 @@ point against the oracle (FP64 to 1e-12 norm-wise, FP32 to its bounds), and
 solves against the closed forms and the oracle's solves: sensor network
 localization recovers the sensors (Section 3's relaxation with exact
 distances), cycle bisection reaches n (1 - cos(2 pi / n)) / 2, and a random
-graph's bisection matches the oracle's objective."""
+graph's bisection matches the oracle's objective; and Section 3's escape
+example: ADMM leaves the point where a rank-2 Burer-Monteiro run is trapped."""
 import math
 
 import numpy as np
@@ -164,3 +165,37 @@ def test_bisection_matches_oracle(device, precision):
     m = oracle.metrics.appendix_b(p, 0.5 * (U + V), lam)
     assert abs(m["obj"] - res["obj"]) <= 1e-10 * max(1.0, abs(m["obj"]))
     assert abs(m["lambda_min"] - res["lambda_min"]) <= 1e-7 * max(1.0, abs(m["lambda_min"]))
+
+
+@pytest.mark.parametrize("case", [0, 1, 2, 3, 4])
+def test_admm_escapes_where_burer_monteiro_is_trapped(device, case):
+    """Section 3's escape example on self-made anchors (one sensor, three
+    anchors, a spurious minimum of the rank-d problem; the cases and their
+    pins are in tests/test_oracle_rank_one.py): the library's Phase I at rank
+    2 from the spurious point stays trapped like the oracle's (the sensor more
+    than 0.5 from the truth, within 1e-2 of the oracle's, whose inner solves
+    stop at a gradient tolerance of a tenth of an infeasibility near 0.1), and
+    its ADMM from that factor (lambda = 0, its own rho rule) meets eq. (stop)
+    and places the sensor to 1e-4."""
+    from paper_2403_09133_amd import Context
+    from tests.test_oracle_rank_one import ESCAPE_CASES, ESCAPE_PHASE1_OUTER, escape_instance, sensor_of
+    A, xs, xsp = (np.asarray(v, dtype=np.float64) for v in ESCAPE_CASES[case])
+    p = escape_instance(ESCAPE_CASES[case])
+    U0 = np.array([[1.0, 0.0], [0.0, 1.0], list(xsp)])
+    ref = oracle.alm.alm(p, U0, np.zeros(p.m), Options(r_max=2, alm_outer_max=ESCAPE_PHASE1_OUTER))
+    print(f"[test] escape case {case}", flush=True)
+    with Context(p) as ctx:
+        assert ctx.problem_info()["structure"] == "rank1"
+        res1 = ctx.admm_solve([U0], _lib_opts(p, 2, r_max=2, alm_outer_max=ESCAPE_PHASE1_OUTER,
+                                              max_admm_iter=0))[0]
+        U1, _, _ = ctx.get_solution(0, res1["rank"])
+        assert res1["rank"] == 2 and res1["alm_outer"] == ref["outer"]
+        x1 = sensor_of(U1)
+        assert np.linalg.norm(x1 - xs) > 0.5 and res1["pinf"] > 1e-2
+        assert np.linalg.norm(x1 - sensor_of(ref["U"])) <= 1e-2
+        res2 = ctx.admm_solve([U1], _lib_opts(p, 2, r_max=2, phase1=0))[0]
+        U2, V2, _ = ctx.get_solution(0, res2["rank"])
+    print(f"[test] escape case {case}: trapped at {x1}, ADMM {res2['admm_iters']} iterations, "
+          f"kkt {res2['kkt']:.2e}", flush=True)
+    assert res2["status"] == 0 and res2["kkt"] < 1e-6, res2
+    assert np.linalg.norm(sensor_of(0.5 * (U2 + V2)) - xs) <= 1e-4
