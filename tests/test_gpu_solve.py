@@ -95,10 +95,14 @@ def test_solve_matches_oracle(device, name, precision):
         # eq.(stop) value after 60 ADMM iterations by 26% on torus12 and 5e-4 on
         # er200 (MaxCut factors are unique only up to rotation, and the tail
         # near 1e-6 is slow), but by 4e-11 on mc_60x50 and 1e-7 on generic_10x8.
-        # So the iteration count is held to 10% everywhere, and the state after
-        # a fixed number of iterations is compared on the stable cases.
+        # On er200 the same perturbation moves the oracle's own ADMM count from
+        # 1727 to anywhere in 1168 .. 1629 (ten perturbations; no spread on the
+        # other cases), so its count is held to 35% and every other case's to
+        # 10%, and the state after a fixed number of iterations is compared on
+        # the stable cases.
         assert res["rank"] == ref["rank"]
-        assert abs(res["admm_iters"] - ref["phase2"]["iters"]) <= max(2, 0.10 * ref["phase2"]["iters"])
+        band = 0.35 if name == "maxcut_er200" else 0.10
+        assert abs(res["admm_iters"] - ref["phase2"]["iters"]) <= max(2, band * ref["phase2"]["iters"])
         if name in ("mc_60x50", "generic_10x8"):
             K = max(1, ref["phase2"]["iters"] // 2)
             p, _ = CASES[name]
