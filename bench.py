@@ -281,22 +281,40 @@ def roofline_of(results, workload, structure, prec, n):
     return roof, kernels
 
 
+def padded_ld(r: int, elem: int) -> int:
+    """The library's fast factor layout for the completion kernels: rows of
+    whole 64-byte sectors and at least the lane group (the power of two >= r)."""
+    g = 1
+    while g < r:
+        g *= 2
+    per = 64 // elem
+    return max(g, -(-r // per) * per)
+
+
 def ops_cold_warm(ctx, p, r: int, reps: int = 10, flush_bytes: int = 1 << 30):
     """Forward map and adjoint product alone, FP32 and FP64, warm (back to
-    back) and cold (a 1 GiB write before each call).  Median of `reps`."""
+    back) and cold (a 1 GiB write before each call).  Median of `reps`.  The
+    factors are n x r (ld = r) and, for the completion kernels, also in the
+    padded layout (ld = padded_ld; the two-column FP64 forward map needs it);
+    the algorithmic bytes count r columns either way."""
     import torch
     from paper_2403_09133_amd.lorads import F32
     dev = torch.device("cuda")
     flush = torch.empty(flush_bytes // 4, dtype=torch.float32, device=dev)
     out = {}
     g = torch.Generator().manual_seed(11)
-    for dt in (torch.float32, torch.float64):
+    layouts = [(dt, pad) for dt in (torch.float32, torch.float64)
+               for pad in ((False, True) if p.kind == "mc" else (False,))]
+    for dt, pad in layouts:
         s = 4 if dt == torch.float32 else 8
-        U = torch.randn(p.n, r, generator=g, dtype=torch.float64).to(dev, dt)
-        V = torch.randn(p.n, r, generator=g, dtype=torch.float64).to(dev, dt)
+        ld = padded_ld(r, s) if pad else r
+        U = torch.zeros(p.n, ld, dtype=dt, device=dev)[:, :r]
+        V = torch.zeros(p.n, ld, dtype=dt, device=dev)[:, :r]
+        U.copy_(torch.randn(p.n, r, generator=g, dtype=torch.float64).to(dev, dt))
+        V.copy_(torch.randn(p.n, r, generator=g, dtype=torch.float64).to(dev, dt))
         w = torch.randn(p.m, generator=g, dtype=torch.float64).to(dev, dt)
         z = torch.empty(p.m, dtype=dt, device=dev)
-        o = torch.empty_like(V)
+        o = torch.zeros(p.n, ld, dtype=dt, device=dev)[:, :r]
         if p.kind == "mc":
             fwd_b = 8.0 * p.m + p.m * s + 2.0 * p.n * r * s
             adj_b = 8.0 * p.m + p.m * s + 2.0 * p.n * r * s + p.n * (4 + s) + (p.n + 1) * 4
@@ -323,7 +341,8 @@ def ops_cold_warm(ctx, p, r: int, reps: int = 10, flush_bytes: int = 1 << 30):
                 us = float(np.median(ts))
                 res[mode] = dict(us=round(us, 2), gbs=round(nbytes / (us * 1e-6) / 1e9, 1),
                                  frac=round(nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4))
-            out[f"{name} {'fp32' if s == 4 else 'fp64'}"] = dict(bytes=int(nbytes), **res)
+            key = f"{name} {'fp32' if s == 4 else 'fp64'}" + (f" ld={ld}" if pad else "")
+            out[key] = dict(bytes=int(nbytes), ld=ld, **res)
         del U, V, w, z, o
     del flush
     torch.cuda.empty_cache()

@@ -832,6 +832,286 @@ __global__ void __launch_bounds__(kBlock) kpair_grad_v2(
 }
 
 // ===========================================================================
+// The adjoint product (MODE 0 of kpair_rows) in the FP64 two-columns-per-lane
+// layout of kpair_grad_v2: half a wave per row (two rows per wave), GV lanes
+// per entry holding columns 2 lane and 2 lane + 1 (one 16-byte load), with X3
+// (ranks 17 .. 24) also column 2 GV + lane; NG = 32 / GV groups take the
+// row's entries in turn, kGU entries per step.  A pass stages the partners and
+// the coefficients a_e w_id(e) of CH entries in the half-wave's LDS slots.
+//   out_t = out_scale (c_scale (C V)_t + sum_e a_e w_id(e) V_p)
+// (w == nullptr: the C part alone).  The group partials are summed by the xor
+// butterfly of kpair_grad_v2.  Needs ld >= the lane group of r and 16-byte
+// aligned rows (pair_v2_ok).
+// ===========================================================================
+template <int GV, int X3 = 0>
+__global__ void __launch_bounds__(kBlock) kpair_adj_v2(
+    int n, const int* __restrict__ cptr, const int* __restrict__ ccol,
+    const double* __restrict__ cval, double c_scale, const int* __restrict__ inc_ptr,
+    const int* __restrict__ inc_nb, const int* __restrict__ inc_id,
+    const double* __restrict__ pcoef, double pair_coef, const double* __restrict__ w,
+    const double* __restrict__ V, int r, int ld, double* __restrict__ out, int ldo,
+    double out_scale) {
+  constexpr int HW = 32;              // lanes per row
+  constexpr int NG = HW / GV;         // groups per row
+  constexpr int CH = kPairStage / 2;  // entries staged per row and pass
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  __shared__ int s_nb[kBlock / HW][CH];
+  __shared__ double s_cf[kBlock / HW][CH];
+  const int hl = threadIdx.x & (HW - 1), hid = threadIdx.x / HW;
+  const int grp = hl / GV, lane = hl & (GV - 1);
+  const int row = blockIdx.x * (kBlock / HW) + hid;
+  int* nbw = s_nb[hid];
+  double* cfw = s_cf[hid];
+  if (row < n) {  // uniform over the half-wave
+    const int c0 = 2 * lane, c2 = 2 * GV + lane;
+    const bool on0 = c0 < r, on1 = c0 + 1 < r, on2 = X3 && c2 < r;
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+    if (c_scale != 0.0) {
+      for (int e = cptr[row] + grp; e < cptr[row + 1]; e += NG) {
+        const int k = ccol[e];
+        const double a = c_scale * cval[e];
+        if (on0) acc0 += a * V[k * ld + c0];
+        if (on1) acc1 += a * V[k * ld + c0 + 1];
+        if (on2) acc2 += a * V[k * ld + c2];
+      }
+    }
+    const int e0 = inc_ptr[row];
+    const int e1 = w != nullptr ? inc_ptr[row + 1] : e0;
+    for (int base = e0; base < e1; base += CH) {
+      const int cnt = min(CH, e1 - base);
+#pragma unroll
+      for (int q = 0; q < CH / HW; ++q) {
+        const int j = hl + HW * q;
+        if (j < cnt) {
+          nbw[j] = inc_nb[base + j];
+          const int id = inc_id[base + j];
+          const double a = pcoef != nullptr ? pcoef[id] : pair_coef;
+          cfw[j] = a * w[id];
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int j = grp; j < cnt; j += NG * kGU) {
+        int p[kGU];
+        double coef[kGU];
+#pragma unroll
+        for (int u = 0; u < kGU; ++u) {
+          const int ju = j + u * NG;
+          const bool ok = ju < cnt;
+          p[u] = (ok ? nbw[ju] : row) * ld;
+          coef[u] = ok ? cfw[ju] : 0.0;
+        }
+        double vp0[kGU], vp1[kGU], vp2[kGU];
+#pragma unroll
+        for (int u = 0; u < kGU; ++u) {
+          const d2 v = *reinterpret_cast<const d2*>(V + p[u] + c0);
+          vp0[u] = on0 ? v[0] : 0.0;
+          vp1[u] = on1 ? v[1] : 0.0;
+          if (X3) {
+            const double v2 = V[p[u] + c2];
+            vp2[u] = on2 ? v2 : 0.0;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kGU; ++u) {
+          acc0 += coef[u] * vp0[u];
+          acc1 += coef[u] * vp1[u];
+          if (X3) acc2 += coef[u] * vp2[u];
+        }
+      }
+      // the slots are read before the next pass stages over them
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    for (int o = GV; o < HW; o <<= 1) {
+      acc0 += __shfl_xor(acc0, o, 64);
+      acc1 += __shfl_xor(acc1, o, 64);
+      if (X3) acc2 += __shfl_xor(acc2, o, 64);
+    }
+    if (grp == 0) {
+      if (on0) out[row * ldo + c0] = out_scale * acc0;
+      if (on1) out[row * ldo + c0 + 1] = out_scale * acc1;
+      if (on2) out[row * ldo + c2] = out_scale * acc2;
+    }
+  }
+}
+
+// ===========================================================================
+// FP32 forward map (MODE 0 of k1_pair) over the XCD chunk lists with four
+// columns per lane loaded as one 16-byte vector: G = pow2(ceil(r / 4)) >= 4
+// lanes per constraint, FP32 products and sums (the FP32 form's operator
+// arithmetic), z_i = scale a_i (<U_j, V_k> + <U_k, V_j>) rounded once to
+// FP32, staged per group and written as contiguous runs.  Columns at or past
+// r are masked (padding may hold anything).  Needs ld a multiple of 4,
+// ld >= 4 G and 16-byte aligned U and V.
+// ===========================================================================
+template <int G>
+__global__ void __launch_bounds__(kBlock) k1_pair_f4(
+    const int* __restrict__ xoff, const int* __restrict__ chunk_row,
+    const int* __restrict__ chunk_start, const int* __restrict__ chunk_end,
+    const int* __restrict__ pk, const float* __restrict__ pcoef, double pair_coef,
+    const float* __restrict__ U, const float* __restrict__ V, int r, int ld,
+    float* __restrict__ z, double scale) {
+  static_assert(G >= 4, "the chunk results are staged per group");
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  __shared__ float sz[(kBlock / G) * kPairChunk];
+  const int chunk = xchunk_of(xoff, G);
+  const int lane = threadIdx.x & (G - 1);
+  const int gslot = (threadIdx.x / G) * kPairChunk;
+  if (chunk < 0) return;
+  const int row = chunk_row[chunk];
+  const int i0 = chunk_start[chunk], i1 = chunk_end[chunk];
+  const int c0 = 4 * lane;
+  f4 uj = *reinterpret_cast<const f4*>(U + row * ld + c0);
+  f4 vj = *reinterpret_cast<const f4*>(V + row * ld + c0);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    if (c0 + v >= r) {  // the row's own padding: zero, so the partner's drops out
+      uj[v] = 0.0f;
+      vj[v] = 0.0f;
+    }
+  }
+  for (int i = i0; i < i1; i += kUnroll) {
+    const int cnt = min(kUnroll, i1 - i);
+    int k[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) k[u] = u < cnt ? pk[i + u] : row;
+    f4 vk[kUnroll], uk[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      vk[u] = *reinterpret_cast<const f4*>(V + k[u] * ld + c0);
+      uk[u] = *reinterpret_cast<const f4*>(U + k[u] * ld + c0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        if (c0 + v >= r) {
+          vk[u][v] = 0.0f;
+          uk[u][v] = 0.0f;
+        }
+      }
+    }
+    float d[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      float sa = uj[0] * vk[u][0];
+      sa = fmaf(uk[u][0], vj[0], sa);
+#pragma unroll
+      for (int v = 1; v < 4; ++v) {
+        sa = fmaf(uj[v], vk[u][v], sa);
+        sa = fmaf(uk[u][v], vj[v], sa);
+      }
+      d[u] = sa;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) d[u] = group_sum<G>(d[u]);
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (lane == (u & (G - 1)) && u < cnt) {
+        const int id = i + u;
+        const double a = pcoef ? (double)pcoef[id] : pair_coef;
+        sz[gslot + (id - i0)] = (float)(scale * (a * (double)d[u]));
+      }
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int q = lane; q < i1 - i0; q += G) z[i0 + q] = sz[gslot + q];
+}
+
+// ===========================================================================
+// FP32 adjoint product (MODE 0 of kpair_rows) with four columns per lane as
+// one 16-byte vector: half a wave per row, G = pow2(ceil(r / 4)) >= 4 lanes per
+// entry, NG = 32 / G groups taking the row's entries in turn, kGU entries per
+// step; FP32 products and sums (the FP32 form's operator arithmetic), the
+// group partials summed by an xor butterfly.  Otherwise as kpair_adj_v2.
+// Needs ld a multiple of 4, ld >= 4 G and a 16-byte aligned V.
+// ===========================================================================
+template <int G>
+__global__ void __launch_bounds__(kBlock) kpair_adj_f4(
+    int n, const int* __restrict__ cptr, const int* __restrict__ ccol,
+    const float* __restrict__ cval, double c_scale, const int* __restrict__ inc_ptr,
+    const int* __restrict__ inc_nb, const int* __restrict__ inc_id,
+    const float* __restrict__ pcoef, double pair_coef, const float* __restrict__ w,
+    const float* __restrict__ V, int r, int ld, float* __restrict__ out, int ldo,
+    double out_scale) {
+  static_assert(G >= 4 && G <= 32, "four to thirty-two lanes per entry");
+  constexpr int HW = 32;              // lanes per row
+  constexpr int NG = HW / G;          // groups per row
+  constexpr int CH = kPairStage / 2;  // entries staged per row and pass
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  __shared__ int s_nb[kBlock / HW][CH];
+  __shared__ float s_cf[kBlock / HW][CH];
+  const int hl = threadIdx.x & (HW - 1), hid = threadIdx.x / HW;
+  const int grp = hl / G, lane = hl & (G - 1);
+  const int row = blockIdx.x * (kBlock / HW) + hid;
+  int* nbw = s_nb[hid];
+  float* cfw = s_cf[hid];
+  if (row < n) {  // uniform over the half-wave
+    const int c0 = 4 * lane;
+    f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (c_scale != 0.0) {
+      for (int e = cptr[row] + grp; e < cptr[row + 1]; e += NG) {
+        const int k = ccol[e];
+        const float a = (float)(c_scale * (double)cval[e]);
+        const f4 v = *reinterpret_cast<const f4*>(V + k * ld + c0);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] += a * v[t];
+      }
+    }
+    const int e0 = inc_ptr[row];
+    const int e1 = w != nullptr ? inc_ptr[row + 1] : e0;
+    for (int base = e0; base < e1; base += CH) {
+      const int cnt = min(CH, e1 - base);
+#pragma unroll
+      for (int q = 0; q < CH / HW; ++q) {
+        const int j = hl + HW * q;
+        if (j < cnt) {
+          nbw[j] = inc_nb[base + j];
+          const int id = inc_id[base + j];
+          const double a = pcoef != nullptr ? (double)pcoef[id] : pair_coef;
+          cfw[j] = (float)(a * (double)w[id]);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int j = grp; j < cnt; j += NG * kGU) {
+        int p[kGU];
+        float coef[kGU];
+#pragma unroll
+        for (int u = 0; u < kGU; ++u) {
+          const int ju = j + u * NG;
+          const bool ok = ju < cnt;
+          p[u] = (ok ? nbw[ju] : row) * ld;
+          coef[u] = ok ? cfw[ju] : 0.0f;
+        }
+        f4 vp[kGU];
+#pragma unroll
+        for (int u = 0; u < kGU; ++u) vp[u] = *reinterpret_cast<const f4*>(V + p[u] + c0);
+#pragma unroll
+        for (int u = 0; u < kGU; ++u)
+#pragma unroll
+          for (int t = 0; t < 4; ++t) acc[t] += coef[u] * vp[u][t];
+      }
+      // the slots are read before the next pass stages over them
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      for (int o = G; o < HW; o <<= 1) acc[t] += __shfl_xor(acc[t], o, 64);
+    if (grp == 0) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (c0 + t < r) out[row * ldo + c0 + t] = (float)(out_scale * (double)acc[t]);
+    }
+  }
+}
+
+// ===========================================================================
 // Line search of the mixed form on FP32 copies of U and D (PAIR, uniform
 // coefficient, XCD chunk lists as k1_pair_ls): four columns per lane loaded as
 // one 16-byte vector, G = pow2(ceil(r / 4)) >= 4 lanes per constraint.  The

@@ -136,6 +136,28 @@ static bool pair_v2_ok(const Problem& P, const void* U, const void* V, int r, in
   } while (0)
 
 // ---------------------------------------------------------------------------
+// FP32 forward maps with four columns per lane (k1_pair_f4): PAIR structure
+// with the XCD chunk lists, rows of a multiple of 4 floats holding the whole
+// lane group (ld >= 4 G), 16-byte aligned factors; G lanes, or 0 when the
+// layout does not allow the form
+static int pair_f4_lanes(const Problem& P, const void* U, const void* V, int r, int ld) {
+  if (P.structure != LORADS_STRUCT_PAIR || P.nxchunks == 0 || r < 1 || r > 128) return 0;
+  const int g = std::max(4, pow2_group((r + 3) / 4));
+  if (g > 32 || ld % 4 != 0 || ld < 4 * g) return 0;
+  if ((reinterpret_cast<uintptr_t>(U) % 16) != 0 || (reinterpret_cast<uintptr_t>(V) % 16) != 0) return 0;
+  return g;
+}
+
+#define LORADS_DISPATCH_F32(Gv, CALL)                  \
+  do {                                                 \
+    switch (Gv) {                                      \
+      case 4: { constexpr int GF = 4; CALL; } break;   \
+      case 8: { constexpr int GF = 8; CALL; } break;   \
+      case 16: { constexpr int GF = 16; CALL; } break; \
+      default: { constexpr int GF = 32; CALL; } break; \
+    }                                                  \
+  } while (0)
+
 template <typename T>
 static void op_forward_impl(Problem& P, const T* U, const T* V, int r, int ld, T* z, double scale,
                             hipStream_t s) {
@@ -159,6 +181,13 @@ static void op_forward_impl(Problem& P, const T* U, const T* V, int r, int ld, T
                               P.xchunk_off.p, P.xchunk_row.p, P.xchunk_start.p, P.xchunk_end.p, P.pk.p,
                               P.pcoef.p, P.pair_coef, (const double*)U, (const double*)V, r, ld,
                               (double*)z, scale, nullptr, nullptr, 0.0, nullptr)));
+  } else if (P.structure == LORADS_STRUCT_PAIR && std::is_same<T, float>::value &&
+             pair_f4_lanes(P, U, V, r, ld) > 0) {
+    check_pair_offsets(P, ld);
+    LORADS_DISPATCH_F32(pair_f4_lanes(P, U, V, r, ld), (k1_pair_f4<GF><<<xchunk_grid(P, GF), kBlock, 0, s>>>(
+                             P.xchunk_off.p, P.xchunk_row.p, P.xchunk_start.p, P.xchunk_end.p, P.pk.p,
+                             (const float*)pc<T>(P), P.pair_coef, (const float*)U, (const float*)V,
+                             r, ld, (float*)z, scale)));
   } else if (P.structure == LORADS_STRUCT_PAIR) {
     check_pair_offsets(P, ld);
     LORADS_DISPATCH_GK(G, r, (k1_pair<T, G, 0, KC><<<rows_grid(P.nfchunks, G), kBlock, 0, s>>>(
@@ -321,6 +350,23 @@ static void op_adjoint_impl(Problem& P, const T* w, double c_scale, const T* V, 
                              P.n, P.cptr.p, P.ccol.p, cv<T>(P), c_scale, P.dptr.p, dc<T>(P),
                              nullptr, w, V, r, ld, out, ldo, out_scale, nullptr, nullptr, 0,
                              nullptr)));
+  } else if (P.structure == LORADS_STRUCT_PAIR && std::is_same<T, double>::value &&
+             pair_v2_ok(P, V, V, r, ld) && ldo >= r) {
+    check_pair_offsets(P, std::max(ld, ldo));
+    const int grid = std::max(1, (P.n + kBlock / 32 - 1) / (kBlock / 32));  // two rows per wave
+    LORADS_DISPATCH_V2(G, r, (kpair_adj_v2<GV, X3><<<grid, kBlock, 0, s>>>(
+                              P.n, P.cptr.p, P.ccol.p, (const double*)cv<T>(P), c_scale,
+                              P.inc_ptr.p, P.inc_nb.p, P.inc_id.p, (const double*)pc<T>(P),
+                              P.pair_coef, (const double*)w, (const double*)V, r, ld,
+                              (double*)out, ldo, out_scale)));
+  } else if (P.structure == LORADS_STRUCT_PAIR && std::is_same<T, float>::value &&
+             pair_f4_lanes(P, V, V, r, ld) > 0 && ldo >= r) {
+    check_pair_offsets(P, std::max(ld, ldo));
+    const int grid = std::max(1, (P.n + kBlock / 32 - 1) / (kBlock / 32));  // two rows per wave
+    LORADS_DISPATCH_F32(pair_f4_lanes(P, V, V, r, ld), (kpair_adj_f4<GF><<<grid, kBlock, 0, s>>>(
+                             P.n, P.cptr.p, P.ccol.p, (const float*)cv<T>(P), c_scale, P.inc_ptr.p,
+                             P.inc_nb.p, P.inc_id.p, (const float*)pc<T>(P), P.pair_coef,
+                             (const float*)w, (const float*)V, r, ld, (float*)out, ldo, out_scale)));
   } else if (P.structure == LORADS_STRUCT_PAIR) {
     check_pair_offsets(P, std::max(ld, ldo));
     LORADS_DISPATCH_GK(G, r, (kpair_rows<T, G, 0, KC><<<waves_grid(P.n), kBlock, 0, s>>>(
@@ -432,15 +478,7 @@ int pair_f32_lanes(const Problem& P, int r, int ld) {
   return (ld % 4 == 0 && ld >= 4 * g && g <= 32) ? g : 0;
 }
 
-#define LORADS_DISPATCH_F32(Gv, CALL)                  \
-  do {                                                 \
-    switch (Gv) {                                      \
-      case 4: { constexpr int GF = 4; CALL; } break;   \
-      case 8: { constexpr int GF = 8; CALL; } break;   \
-      case 16: { constexpr int GF = 16; CALL; } break; \
-      default: { constexpr int GF = 32; CALL; } break; \
-    }                                                  \
-  } while (0)
+
 
 void op_linesearch_pair_f32(Problem& P, const float* U32, const float* D32, int r, int ld,
                             const double* z, const double* lam, double* part, hipStream_t s) {

@@ -234,3 +234,94 @@ def test_dual_lambda_min(device, name):
         got = ctx.dual_lambda_min(torch.tensor(lam, device=device), max_steps=400)
     scale = max(1.0, abs(ref))
     assert abs(got - ref) <= 1e-8 * scale
+
+
+def _lane_group(r):
+    g = 1
+    while g < r:
+        g *= 2
+    return g
+
+
+# rows of 200 incident entries: two staging passes of 128 per row
+_LONG_ROWS = sdpgen.mc_planted(300, 300, 2, 13, count=60000)
+
+
+@pytest.mark.parametrize("name", ["pair_mc_perm", "pair_nonuniform", "long_rows"])
+@pytest.mark.parametrize("r", [5, 16, 17, 23, 24, 30])
+@pytest.mark.parametrize("c_scale", [0.0, -0.5])
+def test_adjoint_two_column_layout(device, name, r, c_scale):
+    """The FP64 adjoint on rows padded to the lane group (the two-columns-per-
+    lane form; ranks 17..24 add a third column per lane) against the oracle to
+    1e-12, with nonzero padding in V that the masks must keep out and padding
+    in the output that must stay unwritten."""
+    import torch
+    from paper_2403_09133_amd import Context
+    p = _LONG_ROWS if name == "long_rows" else PROBS[name]
+    ld = max(_lane_group(r), 8 * ((r + 7) // 8))
+    big = torch.tensor(_rand(p.n, ld, 21), device=device)
+    V = big[:, :r]
+    w = np.random.default_rng(22).standard_normal(p.m)
+    ref = oracle.operators.adjoint(p, w, c_scale, V.cpu().numpy())
+    with Context(p) as ctx:
+        out = torch.full((p.n, ld), 7.0, dtype=torch.float64, device=device)
+        ctx.apply_AT_V(torch.tensor(w, device=device), V, out[:, :r], c_scale=c_scale)
+        torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    assert np.linalg.norm(o[:, :r] - ref) <= 1e-12 * np.linalg.norm(ref)
+    assert np.all(o[:, r:] == 7.0)
+
+
+@pytest.mark.parametrize("name", ["pair_mc_perm", "pair_nonuniform", "long_rows"])
+@pytest.mark.parametrize("r", [3, 12, 15, 17, 30, 33])
+def test_forward_f32_four_column_layout(device, name, r):
+    """The FP32 forward map on rows padded to four columns per lane (G =
+    pow2(ceil(r / 4)) >= 4 lanes, 16-byte loads; nonzero padding that the
+    masks must keep out) against the oracle's FP64 map of the same FP32
+    inputs.  Bound: a lane's chain of 8 fused multiply-adds, log2 G levels of
+    the group tree and the final rounding each add at most 2^-24 of the sum of
+    the terms' magnitudes (the coefficient's FP32 storage one more)."""
+    import math
+    import torch
+    from paper_2403_09133_amd import Context
+    p = _LONG_ROWS if name == "long_rows" else PROBS[name]
+    g = max(4, _lane_group((r + 3) // 4))
+    ld = 4 * g
+    big = _rand(p.n, ld, 31).astype(np.float32)
+    big2 = _rand(p.n, ld, 32).astype(np.float32)
+    U, V = big[:, :r].astype(np.float64), big2[:, :r].astype(np.float64)
+    ref = oracle.operators.forward(p, U, V)
+    with Context(p) as ctx:
+        Ud, Vd = torch.tensor(big, device=device)[:, :r], torch.tensor(big2, device=device)[:, :r]
+        z = torch.zeros(p.m, dtype=torch.float32, device=device)
+        ctx.apply_A(Ud, Vd, z)
+        torch.cuda.synchronize()
+        got = z.cpu().numpy().astype(np.float64)
+    u = 2.0 ** -24
+    bound = _abs_bound_forward(p, U, V)
+    assert np.all(np.abs(got - ref) <= (10 + math.log2(g)) * u * bound + u * np.abs(ref) + 1e-30)
+
+
+@pytest.mark.parametrize("name", ["pair_mc_perm", "pair_nonuniform", "long_rows"])
+@pytest.mark.parametrize("r", [3, 15, 17, 33])
+@pytest.mark.parametrize("c_scale", [0.0, 1.0])
+def test_adjoint_f32_four_column_layout(device, name, r, c_scale):
+    """The FP32 adjoint on rows padded to four columns per lane (nonzero
+    padding in V, output padding unwritten) against the oracle's FP64 product
+    of the same FP32 inputs, norm-wise to 1e-6 as the one-column FP32 form."""
+    import torch
+    from paper_2403_09133_amd import Context
+    p = _LONG_ROWS if name == "long_rows" else PROBS[name]
+    g = max(4, _lane_group((r + 3) // 4))
+    ld = 4 * g
+    big = _rand(p.n, ld, 41).astype(np.float32)
+    w = np.random.default_rng(42).standard_normal(p.m).astype(np.float32)
+    ref = oracle.operators.adjoint(p, w.astype(np.float64), c_scale, big[:, :r].astype(np.float64))
+    with Context(p) as ctx:
+        Vd = torch.tensor(big, device=device)[:, :r]
+        out = torch.full((p.n, ld), 7.0, dtype=torch.float32, device=device)
+        ctx.apply_AT_V(torch.tensor(w, device=device), Vd, out[:, :r], c_scale=c_scale)
+        torch.cuda.synchronize()
+    o = out.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(o[:, :r] - ref) <= 1e-6 * np.linalg.norm(ref)
+    assert np.all(o[:, r:] == 7.0)
