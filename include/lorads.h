@@ -119,7 +119,8 @@ typedef struct {
   int32_t max_admm_iter;   /* 5000 (paper) */
   double time_limit;       /* seconds; <= 0: none */
   double gamma_fixed;      /* > 0: fixed gamma; 0: the library's gamma rule */
-  double gamma_scale;      /* gamma rule: gamma = gamma_scale * (1 + ||C||_F / sqrt(n)) */
+  double gamma_scale;      /* gamma rule: gamma = gamma_scale * (1 + scale), scale
+                              as gamma_rule selects */
   double cg_tol_max;       /* CG relative tolerance tau = min(cg_tol_max, */
   double cg_tol_floor;     /*   max(cg_tol_floor, cg_tol_kkt * KKT_prev))  */
   double cg_tol_kkt;
@@ -172,6 +173,15 @@ typedef struct {
                               the first Phase-I outer iteration does not lower the
                               primal infeasibility; such problems are solved one
                               after the other (batch_mode 1: EINVAL).  Default 0 */
+  int32_t gamma_rule;      /* scale of the gamma rule (gamma_fixed = 0):
+                              0: gamma = gamma_scale (1 + ||C||_F / sqrt(n)), the
+                              cost's per-row scale (default);
+                              1: gamma = gamma_scale (1 + ||C||_2), the cost's
+                              operator norm, estimated once per problem by the
+                              power method on C (relative change < 1e-12, at most
+                              1000 products) -- for costs whose norm sits in few
+                              directions, such as -J of the Lovasz theta SDP.
+                              The batched launch takes rule 0 only */
 } lorads_options;
 
 typedef struct {

@@ -78,8 +78,9 @@ def admm(prob, U0, V0, lam0, rho0, opts, trace=None, progress=None):
     cg_total = 0
     k = 0
     pinf = dres = math.inf
+    c_norm2 = operators.cost_norm2(prob) if (opts.gamma_rule == 1 and opts.gamma_fixed <= 0) else None
     while k < opts.max_admm_iter:
-        gamma = opts.gamma(nrm["c_fro"], n)
+        gamma = opts.gamma(nrm["c_fro"], n, c_norm2)
         tol = cg_tolerance(opts, kkt)
         U, it_u = half_step(prob, V, lam, rho, gamma, tol, maxit)
         V_new, it_v = half_step(prob, U, lam, rho, gamma, tol, maxit)

@@ -96,6 +96,13 @@ def cost_apply(prob, V: np.ndarray) -> np.ndarray:
     return adjoint(prob, np.zeros(prob.m), 1.0, V)
 
 
+def cost_norm2(prob) -> float:
+    """||C||_2, the largest eigenvalue magnitude of the dense symmetric C."""
+    from .dense import dense_C
+    C = dense_C(prob)
+    return float(np.max(np.abs(np.linalg.eigvalsh(C)))) if prob.n else 0.0
+
+
 def norms(prob):
     """||b||_inf, ||b||_1 and the Frobenius and entrywise-1 norms of C (full
     symmetric matrix: off-diagonal triplets count twice)."""

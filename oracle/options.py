@@ -20,7 +20,12 @@ Readings where the paper is silent (the GPU library implements the same rules):
   * gamma is constant over the ADMM run, gamma = 1 + ||C||_F / sqrt(n): the
     penalty on U - V in units of the cost's per-row scale.  (Tying gamma to rho
     makes the proximal term dominate once rho reaches rho_max and the method
-    stalls; much smaller gamma lets U and V drift apart and diverge.)
+    stalls; much smaller gamma lets U and V drift apart and diverge.)  Where
+    the cost's norm sits in few directions (the Lovasz theta SDP's -J: per-row
+    scale sqrt(n), operator norm n) the per-row scale is too small and the
+    ADMM oscillates; that family takes gamma = 1 + ||C||_2 (gamma_rule 1),
+    which equals the per-row rule on completion (C = I/2) and measured slower
+    on MaxCut, where the per-row rule stays.
   * CG stops at ||R|| <= tau ||R0||, tau = min(0.1, max(floor, 0.01 * KKT_prev)),
     at most min(n r, 2000) iterations, warm start x0 = the other factor;
   * ALM: L-BFGS memory 4 with exact quartic line search; inner stop
@@ -48,7 +53,8 @@ class Options:
     rho_max: float = 5000.0
     max_admm_iter: int = 5000
     gamma_fixed: float = 0.0       # > 0: fixed gamma; 0: the scale rule below
-    gamma_scale: float = 1.0       # gamma = gamma_scale * (1 + ||C||_F / sqrt(n))
+    gamma_scale: float = 1.0       # gamma = gamma_scale * (1 + scale), scale by gamma_rule
+    gamma_rule: int = 0            # 0: ||C||_F / sqrt(n); 1: ||C||_2
     cg_tol_max: float = 0.1
     cg_tol_floor: float = 1e-12
     cg_tol_kkt: float = 1e-2
@@ -69,9 +75,11 @@ class Options:
     seed: int = 0                  # rank-growth column stream
     phase1: bool = True
 
-    def gamma(self, c_fro: float, n: int) -> float:
+    def gamma(self, c_fro: float, n: int, c_norm2: float = None) -> float:
         if self.gamma_fixed > 0:
             return self.gamma_fixed
+        if self.gamma_rule == 1:
+            return self.gamma_scale * (1.0 + c_norm2)
         return self.gamma_scale * (1.0 + c_fro / math.sqrt(n))
 
     def rank_cap(self, n: int, m: int) -> int:
@@ -92,4 +100,6 @@ def paper_defaults(kind: str, n: int) -> dict:
         return dict(switch_tol=1e-3, h=5.0 if n < 10000 else 2.5, lbfgs_mem=4)
     if kind == "partition":  # graph partition and bisection: h = 10 (Section 5.1)
         return dict(switch_tol=1e-3, h=10.0, lbfgs_mem=4)
+    if kind == "theta":  # Lovasz theta: gamma from the cost's operator norm (see above)
+        return dict(switch_tol=1e-3, h=1.0, lbfgs_mem=4, gamma_rule=1)
     return dict(switch_tol=1e-3, h=1.0, lbfgs_mem=4)

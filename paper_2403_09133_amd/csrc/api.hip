@@ -108,6 +108,7 @@ void lorads_default_options(lorads_options* o) {
   o->init_lambda = nullptr;
   o->init_rank = nullptr;
   o->warm_check = 0;
+  o->gamma_rule = 0;
 }
 
 lorads_status lorads_setup(const lorads_problem* probs, int32_t nprob, lorads_ctx** out) {
@@ -338,7 +339,7 @@ lorads_status lorads_admm_solve(lorads_ctx* ctx, const lorads_options* opt, lora
     if (o.precision != LORADS_F64 && o.precision != LORADS_F32 && o.precision != LORADS_MIXED)
       fail(LORADS_EINVAL, "precision");
     if (!(o.eps > 0) || o.max_admm_iter < 0 || o.lbfgs_mem < 1 || o.lbfgs_mem > 16 ||
-        o.rho_every < 1 || o.profile < 0 || o.profile > 2)
+        o.rho_every < 1 || o.profile < 0 || o.profile > 2 || o.gamma_rule < 0 || o.gamma_rule > 1)
       fail(LORADS_EINVAL, "invalid options");
     if (!o.init_U) fail(LORADS_EINVAL, "init_U is required (the random start is an input)");
     for (size_t pi = 0; pi < ctx->probs.size(); ++pi) {
@@ -352,7 +353,8 @@ lorads_status lorads_admm_solve(lorads_ctx* ctx, const lorads_options* opt, lora
       for (size_t pi = 0; pi < ctx->probs.size(); ++pi) warm_checked |= o.init_lambda[pi] != nullptr;
     if (o.batch_mode == 1 && warm_checked)
       fail(LORADS_EINVAL, "warm_check with a given init_lambda needs the sequential path");
-    if (o.batch_mode != 2 && !warm_checked && batch_eligible(ctx->probs)) {
+    const bool batch_ok = batch_eligible(ctx->probs) && (o.gamma_rule == 0 || o.gamma_fixed > 0);
+    if (o.batch_mode != 2 && !warm_checked && batch_ok) {
       // all problems in one persistent launch
       const auto t0 = std::chrono::steady_clock::now();
       batch_solve(ctx->probs, ctx->batch, o, res, s,
@@ -366,7 +368,8 @@ lorads_status lorads_admm_solve(lorads_ctx* ctx, const lorads_options* opt, lora
       return;
     }
     if (o.batch_mode == 1)
-      fail(LORADS_EINVAL, "batched solve needs >= 2 problems, all with diagonal constraints and mu = 0");
+      fail(LORADS_EINVAL, "batched solve needs >= 2 problems, all with diagonal constraints and mu = 0, "
+                          "and gamma rule 0");
     for (size_t pi = 0; pi < ctx->probs.size(); ++pi) {
       Problem& P = *ctx->probs[pi];
       if (!o.init_U[pi]) fail(LORADS_EINVAL, "init_U missing for problem " + std::to_string(pi));

@@ -162,6 +162,43 @@ static double ritz_residual(const std::vector<double>& a, const std::vector<doub
   return std::fabs(beta * x[k - 1]);
 }
 
+// ||C||_2 by the power method: v <- C v / ||C v|| from a fixed start (entries
+// 1 + ((i 2654435761) mod 1024) / 1024, normalised), the estimate ||C v|| with
+// ||v|| = 1 rising to max |eig(C)|; stops when it changes by less than 1e-12
+// relative, at C v = 0, or after 1000 products.  The products are the adjoint
+// with no multiplier (c_scale C V at rank 1).
+double cost_norm2(Problem& P, hipStream_t s) {
+  if (P.c_norm2 >= 0.0) return P.c_norm2;
+  const int n = P.n;
+  std::vector<double> h0(n);
+  double nn = 0.0;
+  for (int i = 0; i < n; ++i) {
+    h0[i] = 1.0 + (double)(((uint64_t)i * 2654435761ull) % 1024ull) / 1024.0;
+    nn += h0[i] * h0[i];
+  }
+  nn = std::sqrt(nn);
+  for (int i = 0; i < n; ++i) h0[i] /= nn;
+  DevBuf<double> v, w;
+  v.upload(h0, s);
+  w.alloc(n);
+  double est = 0.0, h[1];
+  for (int it = 0; it < 1000; ++it) {
+    op_adjoint<double>(P, (const double*)nullptr, 1.0, v.p, 1, 1, w.p, 1, 1.0, s);
+    dot_to_slot<double, double>(P, (size_t)n, w.p, w.p, 1.0, S_GEN, s);
+    read_slots(P, S_GEN, h, 1, s);
+    const double nrm = std::sqrt(h[0]);
+    if (!std::isfinite(nrm)) fail(LORADS_ENUMERIC, "non-finite product in the estimate of ||C||_2");
+    if (nrm == 0.0) { est = 0.0; break; }
+    axpby<double, double><<<grid_for((size_t)n), kBlock, 0, s>>>((size_t)n, 1.0 / nrm, w.p, 0.0, v.p);
+    HIPCHK(hipGetLastError());
+    const bool done = it > 0 && std::fabs(nrm - est) <= 1e-12 * nrm;
+    est = nrm;
+    if (done) break;
+  }
+  P.c_norm2 = est;
+  return est;
+}
+
 double dual_lambda_min(Problem& P, const double* lam, int max_steps, hipStream_t s,
                        const double* Uh, int r) {
   const int n = P.n;

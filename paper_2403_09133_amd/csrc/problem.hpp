@@ -138,6 +138,7 @@ struct Problem {
   int structure = LORADS_STRUCT_GENERIC;
   bool perm_identity = true;
   double b_inf = 0, b_1 = 0, b_2 = 0, c_fro = 0, c_1 = 0;
+  double c_norm2 = -1.0;  // ||C||_2 once estimated (cost_norm2), else negative
   // objective f(X) = <C, X> + (mu / 2) ||X||_F^2 (mu = 0: the linear SDP)
   double mu = 0;
   int64_t a_nnz = 0, c_nnz = 0;
@@ -371,6 +372,8 @@ double bytes_linesearch_pair(const Problem& P, int r);
 // ---------------------------------------------------------------------------
 void set_slots(Problem& P, int slot, const double* vals, int count, hipStream_t s);
 void read_slots(Problem& P, int slot, double* vals, int count, hipStream_t s);  // synchronises
+// ||C||_2 by the power method on C (cached in P.c_norm2); synchronises
+double cost_norm2(Problem& P, hipStream_t s);
 // lam += rho (z - b) and sc[slot] = ||z - b||^2 (rho = 0: norm only)
 void dual_update_slot(Problem& P, const double* z, double rho, double* lam, int slot, hipStream_t s);
 // the sums of the quartic line search in one pass: sc[slot] = 2 <CD, U>,

@@ -79,9 +79,14 @@ double quartic_step(double q1, double q2, double q3, double q4) {
   return best;
 }
 
+// gamma_rule 1 reads ||C||_2, which phase2 estimates before its first use
 double gamma_of(const Problem& P, const lorads_options& o, double rho) {
   (void)rho;
   if (o.gamma_fixed > 0) return o.gamma_fixed;
+  if (o.gamma_rule == 1) {
+    if (P.c_norm2 < 0.0) fail(LORADS_EINVAL, "gamma rule 1 before the estimate of ||C||_2");
+    return o.gamma_scale * (1.0 + P.c_norm2);
+  }
   return o.gamma_scale * (1.0 + P.c_fro / std::sqrt((double)P.n));
 }
 
@@ -702,6 +707,7 @@ static void phase2_t(Problem& P, const lorads_options& o, double rho, SolveInfo&
 
 void phase2(Problem& P, const lorads_options& o, double rho, SolveInfo& info, hipStream_t s,
             std::chrono::steady_clock::time_point t_start) {
+  if (o.gamma_rule == 1 && !(o.gamma_fixed > 0)) cost_norm2(P, s);
   if (o.precision != LORADS_F64)
     phase2_t<float>(P, o, rho, info, s, t_start);
   else

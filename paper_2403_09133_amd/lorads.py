@@ -54,7 +54,7 @@ class Options_(C.Structure):
         ("phase1", C.c_int32), ("verbose", C.c_int32), ("profile", C.c_int32),
         ("batch_mode", C.c_int32), ("batch_block", C.c_int32),
         ("init_U", C.c_void_p), ("init_lambda", C.c_void_p), ("init_rank", C.c_void_p),
-        ("warm_check", C.c_int32),
+        ("warm_check", C.c_int32), ("gamma_rule", C.c_int32),
     ]
 
 

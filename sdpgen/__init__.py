@@ -362,7 +362,7 @@ def lovasz_theta(n: int, edges) -> Problem:
     b = np.zeros(m)
     b[0] = 1.0
     return Problem(n=n, m=m, c_row=c_row, c_col=c_col, c_val=c_val, a_con=con,
-                   a_row=row, a_col=col, a_val=val, b=b, kind="generic",
+                   a_row=row, a_col=col, a_val=val, b=b, kind="theta",
                    meta={"graph_edges": len(edges)})
 
 

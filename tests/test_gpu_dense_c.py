@@ -14,11 +14,10 @@ its columns (partials added in a fixed order).  Checks:
     is the smallest eigenvalue of C (numpy's eigvalsh, independent code), to
     1e-6 relative, at n = 400 and at n = 2048, where the dense C (4.2M
     entries, 32 MB) is the solve's whole operator work.
-The Lovasz theta SDP of larger graphs is not used for a solve test: beyond
-n of about 10 the method under this library's readings of rho and gamma
-(shared with the oracle) ends Phase I at rho of 1e4 to 1e5 and the ADMM
-then oscillates (the oracle reaches eq. (stop) 1.4e-5 on C_15 and 0.74 on
-G(60, 0.1) after 1500 iterations).
+Solves of the Lovasz theta SDP beyond the small closed forms (odd cycles up
+to C_21, random graphs of order 40 and 60 against an interior-point solve)
+are in tests/test_gpu_solve.py; they take the family's gamma rule
+(gamma = 1 + ||C||_2).
 """
 import math
 

@@ -5,6 +5,8 @@ below 1e-6, for the FP64 path.  The Appendix-B measures the library reports are
 re-computed by the oracle from the returned U, V, lambda.  The FP32-CG form is
 held to the same objective tolerance (its residuals and dual updates are FP64).
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -204,6 +206,45 @@ def test_solve_lovasz_theta(device, name, precision):
     assert res["status"] == 0, res
     assert res["kkt"] < 1e-6
     assert abs(-res["obj"] - theta) <= 5e-6 * theta, (res["obj"], theta)
+
+
+_THETA_REF = {}
+
+
+def _theta_larger(name):
+    """Odd cycles (closed form) and random graphs (a dense interior-point solve,
+    independent code) of the Lovasz theta SDP beyond the small closed forms."""
+    from oracle import dense
+    from tests.pins import ipm
+    from tests.test_oracle_theta import random_theta
+    if name not in _THETA_REF:
+        if name.startswith("C"):
+            n = int(name[1:])
+            p = sdpgen.lovasz_theta(n, sdpgen.cycle_edges(n))
+            want = -n * math.cos(math.pi / n) / (1 + math.cos(math.pi / n))
+        else:
+            p = random_theta(40, 0.15, 5) if name == "er40" else random_theta(60, 0.1, 8)
+            want = ipm.solve(dense.dense_C(p), dense.dense_A(p), p.b)["obj"]
+        _THETA_REF[name] = (p, want)
+    return _THETA_REF[name]
+
+
+@pytest.mark.parametrize("name", ["C15", "C21", "er40", "er60"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solve_lovasz_theta_larger(device, name, precision):
+    """The theta family with its gamma rule (gamma = 1 + ||C||_2, the library's
+    power-method estimate of ||-J||_2 = n): meets eq. (stop) and the closed
+    form or the interior-point objective to 1e-6 relative."""
+    from paper_2403_09133_amd import Context
+    p, want = _theta_larger(name)
+    r0 = max(2, sdpgen.rank_rule_2lnm(p.m))
+    U0 = sdpgen.random_init_U(p.n, r0, 3)
+    print(f"[test] theta {name} precision {precision}", flush=True)
+    with Context(p) as ctx:
+        res = ctx.admm_solve([U0], _lib_opts(p, r0, precision=precision))[0]
+    assert abs(res["gamma"] - (1.0 + p.n)) <= 1e-9 * p.n
+    assert res["status"] == 0 and res["kkt"] < 1e-6, res
+    assert abs(res["obj"] - want) <= 1e-6 * abs(want), (res["obj"], want)
 
 
 # Rank growth (Sections 4.3 and 5.1): an inner solve that reaches
