@@ -121,3 +121,30 @@ def test_dense_min_eigenvalue_solve(device, n, precision):
           f"admm {res['admm_iters']}, {res['t_phase1'] + res['t_phase2']:.2f} s", flush=True)
     assert res["status"] == 0 and res["kkt"] < 1e-6, res
     assert abs(res["obj"] - want) <= 1e-6 * abs(want), (res["obj"], want)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_dense_theta_solve_certified(device, precision):
+    """theta(G(260, 0.05)): C = -J kept dense (every product with it on the
+    matrix cores), the family's gamma = 1 + ||C||_2, and an initial rank of 30
+    (the rank rule's 15 grows to 23 in Phase I, below the optimum's rank, where
+    the run stops at a stationary point with a negative dual slack eigenvalue).
+    The oracle recomputes the Appendix-B measures from the returned factors
+    and multipliers: P-infeasibility, dual infeasibility and gap all below
+    1e-6 certify the objective."""
+    from paper_2403_09133_amd import Context, default_options
+    p = PROBS["theta_er260"]
+    r0 = 30
+    U0 = sdpgen.random_init_U(p.n, r0, 3)
+    print(f"[test] dense theta precision {precision}", flush=True)
+    with Context(p) as ctx:
+        assert ctx.problem_info()["c_dense"]
+        res = ctx.admm_solve([U0], default_options(r0=r0, precision=precision, time_limit=100.0,
+                                                   **paper_defaults(p.kind, p.n)))[0]
+        U, V, lam = ctx.get_solution(0, res["rank"])
+    print(f"[test] obj {res['obj']:.10f} admm {res['admm_iters']} gamma {res['gamma']:.3f}", flush=True)
+    assert res["status"] == 0 and res["kkt"] < 1e-6, res
+    assert abs(res["gamma"] - (1.0 + p.n)) <= 1e-9 * p.n
+    m = oracle.metrics.appendix_b(p, 0.5 * (U + V), lam)
+    assert m["pinf"] <= 1e-6 and m["dinf"] <= 1e-6 and abs(m["gap"]) <= 1e-6, m
+    assert abs(m["obj"] - res["obj"]) <= 1e-10 * abs(m["obj"])
