@@ -349,6 +349,29 @@ def ops_cold_warm(ctx, p, r: int, reps: int = 10, flush_bytes: int = 1 << 30):
     return dict(rank=r, reps=reps, flush="1 GiB fill before each cold call", **out)
 
 
+def theta_leg():
+    """The Lovasz theta SDP of G(260, 0.05) (seed 8): C = -J kept dense (the
+    matrix-core products), the family's gamma = 1 + ||C||_2, initial rank 30,
+    FP64 and FP32-CG; time to eq. (stop) <= 1e-6 and the Appendix-B measures."""
+    import sdpgen
+    from paper_2403_09133_amd import Context, default_options
+    from oracle.options import paper_defaults
+    ei, ej = sdpgen.er_gnp_edges(260, 0.05, np.random.default_rng(8))
+    p = sdpgen.lovasz_theta(260, list(zip(ei.tolist(), ej.tolist())))
+    r0 = 30
+    U0 = sdpgen.random_init_U(p.n, r0, 3)
+    out = dict(workload="Lovasz theta of G(260, 0.05), seed 8: n = 260, m = %d, dense C, r0 = 30" % p.m)
+    with Context(p) as ctx:
+        out["c_dense"] = bool(ctx.problem_info()["c_dense"])
+        for name, prec in (("fp64", 0), ("fp32_cg", 1)):
+            res = ctx.admm_solve([U0], default_options(r0=r0, precision=prec, **paper_defaults(p.kind, p.n)))[0]
+            out[name] = dict(s=round(res["t_total"], 3), status=res["status"], kkt=res["kkt"],
+                             admm_iters=res["admm_iters"], obj=res["obj"], pinf=res["pinf"],
+                             dinf=res["dinf"], gap=res["gap"], gamma=res["gamma"])
+            log(f"theta G(260, 0.05) {name}: {res['t_total']:.2f}s status {res['status']} obj {res['obj']:.9f}")
+    return out
+
+
 def batch_leg(count: int = 512, sequential: bool = True):
     """Batched form: `count` MaxCut SDPs, n ~ U{50..2000}, average degree ~ U[3, 20],
     +-1 weights, rank ceil(log2 n) each, in one persistent launch (workgroup size
@@ -552,7 +575,8 @@ def main():
                     help="comma-separated instances the oracle solves end to end in the CPU baseline "
                          "(maxcut_er200, maxcut_torus100, maxcut_gnm20000; the larger ones take minutes)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solve")
-    ap.add_argument("--no-secondary", action="store_true", help="skip the second completion workload")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the second completion workload and the theta leg")
     ap.add_argument("--no-ops", action="store_true", help="skip the cold / warm operator timings")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form leg")
     ap.add_argument("--no-sequential", action="store_true",
@@ -630,6 +654,9 @@ def main():
                                               solve=sec["solve"], kernels=sec["kernels"])}
         if "ops_cold_warm" in sec:
             line.setdefault("ops_cold_warm", {})["mc_10000"] = sec["ops_cold_warm"]
+    if not args.no_secondary:
+        line["theta_dense"] = theta_leg()
+        line["time_to_kkt_s"]["theta_g260_fp64"] = line["theta_dense"]["fp64"]["s"]
     if not args.no_learned:
         line["learned_warm_start"] = learned_leg()
         line["time_to_kkt_s"]["learned_fp64_median"] = line["learned_warm_start"]["learned_median_s"]
