@@ -200,6 +200,25 @@ def cpu_baseline(p, r: int, budget_s: float = 20.0, e2e=("maxcut_er200",)):
             t = time.perf_counter() - t0
             if t > budget_s / 2 or reps >= 8:
                 break
+        # per-operator medians at full size on the other configurations
+        per_op = {}
+        for name, reps_ in (("maxcut_torus100", 5), ("mc_10000", 5)):
+            q = sdpgen.config_instance(name)
+            rq = initial_rank(q)
+            Uq = rng.standard_normal((q.n, rq))
+            Vq = rng.standard_normal((q.n, rq))
+            wq = rng.standard_normal(q.m)
+            tf, ta = [], []
+            for _ in range(reps_):
+                t1 = time.perf_counter()
+                oracle.operators.forward(q, Uq, Vq)
+                t2 = time.perf_counter()
+                oracle.operators.adjoint(q, wq, 1.0, Vq)
+                t3 = time.perf_counter()
+                tf.append(t2 - t1)
+                ta.append(t3 - t2)
+            per_op[name] = dict(rank=rq, reps=reps_, forward_s=round(float(np.median(tf)), 5),
+                                adjoint_s=round(float(np.median(ta)), 5))
         solves = []
         for name in e2e:
             q = sdpgen.config_instance(name)
@@ -222,6 +241,7 @@ def cpu_baseline(p, r: int, budget_s: float = 20.0, e2e=("maxcut_er200",)):
                 sample=f"{reps} x (A(UV^T) + (C + A*(y))V) at full size, r={r}, FP64 numpy, "
                        f"{t:.1f} s on the host",
                 host=host_cpu(),
+                per_operator_median=per_op,
                 oracle_time_to_kkt_s=solves)
 
 
