@@ -374,8 +374,8 @@ def theta_leg():
     matrix-core products), the family's gamma = 1 + ||C||_2, initial rank 30,
     FP64 and FP32-CG; time to eq. (stop) <= 1e-6 and the Appendix-B measures."""
     import sdpgen
-    from paper_2403_09133_amd import Context, default_options
-    from oracle.options import paper_defaults
+    from paper_2403_09133_amd import Context
+    from paper_2403_09133_amd.params import solver_options
     ei, ej = sdpgen.er_gnp_edges(260, 0.05, np.random.default_rng(8))
     p = sdpgen.lovasz_theta(260, list(zip(ei.tolist(), ej.tolist())))
     r0 = 30
@@ -384,7 +384,7 @@ def theta_leg():
     with Context(p) as ctx:
         out["c_dense"] = bool(ctx.problem_info()["c_dense"])
         for name, prec in (("fp64", 0), ("fp32_cg", 1)):
-            res = ctx.admm_solve([U0], default_options(r0=r0, precision=prec, **paper_defaults(p.kind, p.n)))[0]
+            res = ctx.admm_solve([U0], solver_options(p.kind, p.n, r0, prec))[0]
             out[name] = dict(s=round(res["t_total"], 3), status=res["status"], kkt=res["kkt"],
                              admm_iters=res["admm_iters"], obj=res["obj"], pinf=res["pinf"],
                              dinf=res["dinf"], gap=res["gap"], gamma=res["gamma"])
