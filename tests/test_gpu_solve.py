@@ -208,6 +208,29 @@ def test_solve_lovasz_theta(device, name, precision):
     assert abs(-res["obj"] - theta) <= 5e-6 * theta, (res["obj"], theta)
 
 
+
+@pytest.mark.parametrize("name", ["one_by_one", "single_edge", "edgeless5", "single_vertex"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_degenerate_instances(device, name, precision):
+    """The degenerate cases (a 1 x 1 SDP, one edge, no edges, one vertex) solve
+    to their closed forms; the oracle recomputes the primal infeasibility and
+    the objective from the returned factors."""
+    from paper_2403_09133_amd import Context
+    from tests.test_oracle_lorads import degenerate_instances, degenerate_rank
+    p, want = degenerate_instances()[name]
+    r0 = degenerate_rank(p)
+    U0 = sdpgen.random_init_U(p.n, r0, 3)
+    print(f"[test] degenerate {name} n={p.n} r0={r0} precision {precision}", flush=True)
+    with Context(p) as ctx:
+        res = ctx.admm_solve([U0], _lib_opts(p, r0, precision=precision))[0]
+        U, V, lam = ctx.get_solution(0, res["rank"])
+    assert res["status"] == 0 and res["kkt"] < 1e-6, res
+    assert abs(res["obj"] - want) <= 1e-6 * max(1.0, abs(want)), (res["obj"], want)
+    m = oracle.metrics.appendix_b(p, 0.5 * (U + V), lam)
+    assert m["pinf"] <= 1e-6
+    assert abs(m["obj"] - res["obj"]) <= 1e-10 * max(1.0, abs(m["obj"]))
+
+
 _THETA_REF = {}
 
 

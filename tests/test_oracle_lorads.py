@@ -103,3 +103,33 @@ def test_certificates_er():
     m = out["metrics"]
     assert out["phase2"]["kkt"] < 1e-6
     assert m["pinf"] <= 1e-6 and m["dinf"] <= 1e-5 and abs(m["gap"]) <= 5e-5
+
+
+def degenerate_instances():
+    """Degenerate SDPs and their optimal values: a 1 x 1 SDP, whose feasible set
+    is the single point X = b / a (optimum 3 * 2); MaxCut of one edge, where
+    X = [[1, -1], [-1, 1]] cuts it (min form: -1); and MaxCut of graphs without
+    edges, where C = 0 and every feasible X is optimal (0), down to a single
+    vertex.  The 1 x 1 case starts Phase I next to the stationary point U = 0
+    of its first subproblems, so it also exercises the growth of rho."""
+    one = sdpgen.Problem(n=1, m=1, c_row=[0], c_col=[0], c_val=[3.0], a_con=[0], a_row=[0],
+                         a_col=[0], a_val=[1.0], b=[2.0], kind="generic")
+    return {
+        "one_by_one": (one, 6.0),
+        "single_edge": (sdpgen.maxcut_from_edges(2, [0], [1], [1.0]), -1.0),
+        "edgeless5": (sdpgen.maxcut_from_edges(5, [], [], []), 0.0),
+        "single_vertex": (sdpgen.maxcut_from_edges(1, [], [], []), 0.0),
+    }
+
+
+def degenerate_rank(p):
+    return max(1, min(int(math.floor(math.sqrt(2.0 * p.m))), p.n))
+
+
+@pytest.mark.parametrize("name", ["one_by_one", "single_edge", "edgeless5", "single_vertex"])
+def test_degenerate_instances(name):
+    p, want = degenerate_instances()[name]
+    out = solve(p, degenerate_rank(p))
+    assert out["phase2"]["converged"]
+    assert abs(out["metrics"]["obj"] - want) <= 1e-6 * max(1.0, abs(want))
+    assert out["metrics"]["pinf"] <= 1e-6
