@@ -34,9 +34,10 @@ ops_cold_warm: forward map and adjoint product alone at the solve's rank, FP32
          and FP64, warm (back to back) and cold (a 1 GiB buffer written before
          each call, flushing the 256 MB Infinity Cache and the L2s).
 cpu_baseline: the FP64 numpy oracle's forward map and adjoint product at the
-         same size on the host, one thread, in the same unit; beside it the
-         oracle's end-to-end time to eq. (stop) <= 1e-6 on the MaxCut instance
-         of order 200.
+         same size on the host, one thread, in the same unit; beside it
+         per-operator medians on other configurations, the same loops with
+         numpy's thread pools unrestricted, and the oracle's end-to-end time
+         to eq. (stop) <= 1e-6 on the MaxCut instance of order 200.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -172,12 +173,33 @@ def host_cpu() -> dict:
     return dict(model=model, nproc=os.cpu_count())
 
 
-def cpu_baseline(p, r: int, budget_s: float = 20.0, e2e=("maxcut_er200",)):
+def per_operator(q, rq: int, reps: int, rng):
+    """Median time of the oracle's forward map and adjoint product on one
+    instance at rank rq (random factors and multipliers)."""
+    import oracle
+    Uq = rng.standard_normal((q.n, rq))
+    Vq = rng.standard_normal((q.n, rq))
+    wq = rng.standard_normal(q.m)
+    tf, ta = [], []
+    for _ in range(reps):
+        t1 = time.perf_counter()
+        oracle.operators.forward(q, Uq, Vq)
+        t2 = time.perf_counter()
+        oracle.operators.adjoint(q, wq, 1.0, Vq)
+        t3 = time.perf_counter()
+        tf.append(t2 - t1)
+        ta.append(t3 - t2)
+    return dict(rank=rq, reps=reps, forward_s=round(float(np.median(tf)), 5),
+                adjoint_s=round(float(np.median(ta)), 5))
+
+
+def cpu_baseline(p, r: int, budget_s: float = 20.0, e2e=("maxcut_er200",), name: str = "mc_20000"):
     """The oracle's forward map and adjoint product (FP64, numpy) on the host,
-    one thread, for a bounded number of applications; plus the oracle's
-    end-to-end solves to eq. (stop) of the named instances (by default the
-    MaxCut instance of order 200), one thread, from the library's initial
-    rank."""
+    one thread, for a bounded number of applications; per-operator medians on
+    other configurations, one thread and with numpy's thread pools
+    unrestricted (name: the timed workload's); plus the oracle's end-to-end
+    solves to eq. (stop) of the named instances (by default the MaxCut
+    instance of order 200), one thread, from the library's initial rank."""
     try:
         from threadpoolctl import threadpool_limits
     except Exception:  # pragma: no cover
@@ -204,21 +226,7 @@ def cpu_baseline(p, r: int, budget_s: float = 20.0, e2e=("maxcut_er200",)):
         per_op = {}
         for name, reps_ in (("maxcut_torus100", 5), ("mc_10000", 5)):
             q = sdpgen.config_instance(name)
-            rq = initial_rank(q)
-            Uq = rng.standard_normal((q.n, rq))
-            Vq = rng.standard_normal((q.n, rq))
-            wq = rng.standard_normal(q.m)
-            tf, ta = [], []
-            for _ in range(reps_):
-                t1 = time.perf_counter()
-                oracle.operators.forward(q, Uq, Vq)
-                t2 = time.perf_counter()
-                oracle.operators.adjoint(q, wq, 1.0, Vq)
-                t3 = time.perf_counter()
-                tf.append(t2 - t1)
-                ta.append(t3 - t2)
-            per_op[name] = dict(rank=rq, reps=reps_, forward_s=round(float(np.median(tf)), 5),
-                                adjoint_s=round(float(np.median(ta)), 5))
+            per_op[name] = per_operator(q, initial_rank(q), reps_, rng)
         solves = []
         for name in e2e:
             q = sdpgen.config_instance(name)
@@ -236,12 +244,21 @@ def cpu_baseline(p, r: int, budget_s: float = 20.0, e2e=("maxcut_er200",)):
     finally:
         if ctx is not None and hasattr(ctx, "unregister"):
             ctx.unregister()
+    # the same per-operator loops with numpy's thread pools unrestricted
+    per_op_all = dict(threads=os.cpu_count())
+    if threadpool_limits is not None:
+        from threadpoolctl import threadpool_info
+        per_op_all["threads"] = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    per_op_all["mc_10000"] = per_operator(sdpgen.config_instance("mc_10000"), initial_rank(
+        sdpgen.config_instance("mc_10000")), 5, rng)
+    per_op_all[name] = per_operator(p, r, 3, rng)
     bytes_pair = 2 * (8.0 * p.m + 8.0 * p.m + 2.0 * p.n * r * 8)
     return dict(value=round(reps * bytes_pair / t / 1e9, 4), unit="GB/s", cores=1, kind="oracle",
                 sample=f"{reps} x (A(UV^T) + (C + A*(y))V) at full size, r={r}, FP64 numpy, "
                        f"{t:.1f} s on the host",
                 host=host_cpu(),
                 per_operator_median=per_op,
+                per_operator_median_all_threads=per_op_all,
                 oracle_time_to_kkt_s=solves)
 
 
@@ -651,7 +668,8 @@ def main():
     for name, c in cmp_.items():
         line[f"roofline_{name}"] = c["roofline"]
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(p, leg["r0"], e2e=[x for x in args.oracle_e2e.split(",") if x])
+        line["cpu_baseline"] = cpu_baseline(p, leg["r0"], e2e=[x for x in args.oracle_e2e.split(",") if x],
+                                             name=args.workload)
     line["time_to_kkt_s"] = {tkey: round(leg["wall"] / args.steps, 4)}
     for name, c in cmp_.items():
         line["time_to_kkt_s"][name] = c["s"]
