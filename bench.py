@@ -193,11 +193,11 @@ def per_operator(q, rq: int, reps: int, rng):
                 adjoint_s=round(float(np.median(ta)), 5))
 
 
-def cpu_baseline(p, r: int, budget_s: float = 20.0, e2e=("maxcut_er200",), name: str = "mc_20000"):
+def cpu_baseline(p, r: int, budget_s: float = 20.0, e2e=("maxcut_er200",), workload: str = "mc_20000"):
     """The oracle's forward map and adjoint product (FP64, numpy) on the host,
     one thread, for a bounded number of applications; per-operator medians on
     other configurations, one thread and with numpy's thread pools
-    unrestricted (name: the timed workload's); plus the oracle's end-to-end
+    unrestricted (workload: the timed workload's name); plus the oracle's end-to-end
     solves to eq. (stop) of the named instances (by default the MaxCut
     instance of order 200), one thread, from the library's initial rank."""
     try:
@@ -251,7 +251,7 @@ def cpu_baseline(p, r: int, budget_s: float = 20.0, e2e=("maxcut_er200",), name:
         per_op_all["threads"] = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     per_op_all["mc_10000"] = per_operator(sdpgen.config_instance("mc_10000"), initial_rank(
         sdpgen.config_instance("mc_10000")), 5, rng)
-    per_op_all[name] = per_operator(p, r, 3, rng)
+    per_op_all[workload] = per_operator(p, r, 3, rng)
     bytes_pair = 2 * (8.0 * p.m + 8.0 * p.m + 2.0 * p.n * r * 8)
     return dict(value=round(reps * bytes_pair / t / 1e9, 4), unit="GB/s", cores=1, kind="oracle",
                 sample=f"{reps} x (A(UV^T) + (C + A*(y))V) at full size, r={r}, FP64 numpy, "
@@ -669,7 +669,7 @@ def main():
         line[f"roofline_{name}"] = c["roofline"]
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p, leg["r0"], e2e=[x for x in args.oracle_e2e.split(",") if x],
-                                             name=args.workload)
+                                             workload=args.workload)
     line["time_to_kkt_s"] = {tkey: round(leg["wall"] / args.steps, 4)}
     for name, c in cmp_.items():
         line["time_to_kkt_s"][name] = c["s"]
