@@ -33,6 +33,9 @@ roofline_fp64, roofline_fp32_cg: the same for the comparison solves.
 ops_cold_warm: forward map and adjoint product alone at the solve's rank, FP32
          and FP64, warm (back to back) and cold (a 1 GiB buffer written before
          each call, flushing the 256 MB Infinity Cache and the L2s).
+dense_cost: C V alone for a random dense symmetric C of order 8192 kept dense
+         (the matrix-core product), FP64 and FP32, ranks 4, 16, 32, warm and
+         cold, against the HBM and MFMA peaks.
 cpu_baseline: the FP64 numpy oracle's forward map and adjoint product at the
          same size on the host, one thread, in the same unit; beside it
          per-operator medians on other configurations, the same loops with
@@ -409,6 +412,67 @@ def theta_leg():
     return out
 
 
+def dense_cost_leg(n: int = 8192, ranks=(4, 16, 32), reps: int = 10, flush_bytes: int = 1 << 30):
+    """C V alone (lorads_apply_AT_V with a zero multiplier) for a random dense
+    symmetric C of order n, kept dense by the library (the matrix-core
+    product), FP64 and FP32, warm and cold (a 1 GiB write before each call),
+    median of `reps`.  The constraint is tr X = 1.  Algorithmic bytes:
+    C once (n^2 s), V in and C V out (2 n r s); flops 2 n^2 r."""
+    import torch
+    import sdpgen
+    from paper_2403_09133_amd import Context
+    rng = np.random.default_rng(21)
+    G = rng.standard_normal((n, n)) / math.sqrt(n)
+    ir, ic = np.triu_indices(n)
+    cv = 0.5 * (G[ir, ic] + G[ic, ir])
+    del G
+    ar = np.arange(n)
+    p = sdpgen.Problem(n=n, m=1, c_row=ir, c_col=ic, c_val=cv, a_con=np.zeros(n), a_row=ar,
+                       a_col=ar, a_val=np.ones(n), b=np.ones(1), kind="generic")
+    del ir, ic, cv
+    dev = torch.device("cuda")
+    g = torch.Generator().manual_seed(12)
+    out = dict(workload=f"random dense symmetric C of order {n} (seed 21), tr X = 1", n=n, reps=reps,
+               flush="1 GiB fill before each cold call")
+    with Context(p) as ctx:
+        out["c_dense"] = bool(ctx.problem_info()["c_dense"])
+        flush = torch.empty(flush_bytes // 4, dtype=torch.float32, device=dev)
+        for dt, tag, peak_tf in ((torch.float64, "fp64", 78.6), (torch.float32, "fp32", 157.3)):
+            sz = 8 if dt == torch.float64 else 4
+            for r in ranks:
+                V = torch.randn(n, r, generator=g, dtype=torch.float64).to(dev, dt)
+                w = torch.zeros(1, dtype=dt, device=dev)
+                o = torch.zeros(n, r, dtype=dt, device=dev)
+                ctx.apply_AT_V(w, V, o)
+                torch.cuda.synchronize()
+                nbytes = float(n) * n * sz + 2.0 * n * r * sz
+                flops = 2.0 * n * n * r
+                res = {}
+                for mode in ("warm", "cold"):
+                    ts = []
+                    for _ in range(reps):
+                        if mode == "cold":
+                            flush.fill_(1.0)
+                        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                        e0.record()
+                        ctx.apply_AT_V(w, V, o)
+                        e1.record()
+                        e1.synchronize()
+                        ts.append(e0.elapsed_time(e1) * 1e3)
+                    us = float(np.median(ts))
+                    res[mode] = dict(us=round(us, 2), gbs=round(nbytes / (us * 1e-6) / 1e9, 1),
+                                     frac=round(nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                                     tflops=round(flops / (us * 1e-6) / 1e12, 2),
+                                     mfma_frac=round(flops / (us * 1e-6) / 1e12 / peak_tf, 4))
+                out[f"CV {tag} r={r}"] = dict(bytes=int(nbytes), flops=int(flops), **res)
+                log(f"dense C V n={n} {tag} r={r}: cold {res['cold']['us']:.1f} us "
+                    f"({res['cold']['gbs']:.0f} GB/s), warm {res['warm']['us']:.1f} us")
+                del V, w, o
+        del flush
+    torch.cuda.empty_cache()
+    return out
+
+
 def batch_leg(count: int = 512, sequential: bool = True):
     """Batched form: `count` MaxCut SDPs, n ~ U{50..2000}, average degree ~ U[3, 20],
     +-1 weights, rank ceil(log2 n) each, in one persistent launch (workgroup size
@@ -695,6 +759,7 @@ def main():
     if not args.no_secondary:
         line["theta_dense"] = theta_leg()
         line["time_to_kkt_s"]["theta_g260_fp64"] = line["theta_dense"]["fp64"]["s"]
+        line["dense_cost"] = dense_cost_leg()
     if not args.no_learned:
         line["learned_warm_start"] = learned_leg()
         line["time_to_kkt_s"]["learned_fp64_median"] = line["learned_warm_start"]["learned_median_s"]

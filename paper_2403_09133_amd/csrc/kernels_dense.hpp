@@ -3,10 +3,10 @@
 // the products on the matrix cores (v_mfma_f64_16x16x4f64 in FP64,
 // v_mfma_f32_16x16x4f32 in FP32).  With r small against n the product reads
 // C once and is bound by that stream (r / 4 flop per byte of C in FP64), so
-// the work is cut into many waves: wave (t, s) takes the 16-row tile t of C
-// and the s-th range of columns k, stages 16 x 64 blocks of C in its LDS with
-// 16-byte loads, and accumulates its 16 x r partial product; cdense_finish
-// adds the partials of the ranges in range order (a fixed order).
+// the work is cut into many blocks: block (g, s) takes four 16-row tiles of C
+// and the s-th range of columns k, and accumulates their 16 x r partial
+// products; cdense_finish adds the partials of the ranges in range order (a
+// fixed order).
 #pragma once
 
 #include "kernels.hpp"
@@ -36,8 +36,16 @@ struct DenseMfma<float> {
   static __device__ __forceinline__ int row(int l, int v) { return 4 * (l / 16) + v; }
 };
 
-// part[(s n + i) r + c] = sum over the k of range s of C[i][k] V[k][c]
-template <typename T>
+// part[(s n + i) r + c] = sum over the k of range s of C[i][k] V[k][c].
+// A block of four waves takes four consecutive 16-row tiles of C (wave w the
+// tile 4 g + w) and the s-th range of columns k, in 64-column steps.  Each step
+// stages the 64 x (16 NT) block of V once for the four waves and each wave's
+// 16 x 64 block of C in LDS (16-byte loads of whole rows), and the loads of the
+// next step are issued before this step's MFMAs, so the stream of C overlaps
+// the products.  NT = ceil(r / 16) column tiles of V; a lane's operands are
+// A[m][k] = C[i0 + (l & 15)][k] and B[k][j] = V[k][16 q + (l & 15)] with
+// k = kb + kk + (l >> 4), the k's of a step taken in order.
+template <typename T, int NT>
 __global__ void __launch_bounds__(kBlock) cdense_partial(int n, int ldc, const T* __restrict__ C,
                                                          const T* __restrict__ V, int r, int ld,
                                                          int tiles, int splits, int kchunk,
@@ -45,55 +53,73 @@ __global__ void __launch_bounds__(kBlock) cdense_partial(int n, int ldc, const T
   using M = DenseMfma<T>;
   typedef T vec __attribute__((ext_vector_type(16 / sizeof(T))));
   constexpr int VW = 16 / (int)sizeof(T);
-  constexpr int SK = kDenseK + 1;  // padded LDS row
+  constexpr int SK = kDenseK + 1;        // padded LDS row of the C block
+  constexpr int RC = 16 * NT;            // V columns staged
+  constexpr int SV = RC + 1;             // padded LDS row of the V block
+  constexpr int CQ = 16 * kDenseK / (64 * VW);   // 16-byte C loads per lane and step
+  constexpr int VQ = kDenseK * RC / kBlock;      // V elements per thread and step
   __shared__ T sa[kBlock / 64][16 * SK];
+  __shared__ T sv[kDenseK * SV];
   const int l = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int gw = blockIdx.x * (kBlock / 64) + wid;
-  if (gw >= tiles * splits) return;  // wave-uniform; no block-wide synchronisation follows
-  const int t = gw / splits, sp = gw % splits;
+  const int sp = blockIdx.x % splits, tg = blockIdx.x / splits;
+  const int t = 4 * tg + wid;
+  const bool live = t < tiles;           // wave-uniform; every wave still takes the barriers
   const int i0 = 16 * t;
   const int k0 = sp * kchunk, k1 = min(ldc, k0 + kchunk);
-  const int nt = min(kDenseNT, (r + 15) / 16);
   T* a_lds = sa[wid];
-  typename M::acc4 acc[kDenseNT];
+  typename M::acc4 acc[NT];
 #pragma unroll
-  for (int q = 0; q < kDenseNT; ++q) acc[q] = typename M::acc4{0, 0, 0, 0};
-  for (int kb = k0; kb < k1; kb += kDenseK) {
-    // stage C[i0 .. i0 + 15][kb .. kb + 63] (rows past n read as zero)
+  for (int q = 0; q < NT; ++q) acc[q] = typename M::acc4{0, 0, 0, 0};
+  vec cr[CQ];
+  T vr[VQ];
+  // loads of the step at column kb into registers (rows of C past n and
+  // V entries outside n x r read as zero)
+  auto load_step = [&](int kb) {
 #pragma unroll
-    for (int q = 0; q < 16 * kDenseK / (64 * VW); ++q) {
+    for (int q = 0; q < CQ; ++q) {
       const int e = (q * 64 + l) * VW;
       const int row = e / kDenseK, kofs = e % kDenseK;
-      vec v;
 #pragma unroll
-      for (int w = 0; w < VW; ++w) v[w] = (T)0;
-      if (i0 + row < n) v = *reinterpret_cast<const vec*>(C + (size_t)(i0 + row) * ldc + kb + kofs);
-#pragma unroll
-      for (int w = 0; w < VW; ++w) a_lds[row * SK + kofs + w] = v[w];
+      for (int w = 0; w < VW; ++w) cr[q][w] = (T)0;
+      if (live && i0 + row < n) cr[q] = *reinterpret_cast<const vec*>(C + (size_t)(i0 + row) * ldc + kb + kofs);
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll 4
-    for (int kk = 0; kk < kDenseK; kk += 4) {
-      const T a = a_lds[(l & 15) * SK + kk + (l >> 4)];
-      const int krow = kb + kk + (l >> 4);
 #pragma unroll
-      for (int q = 0; q < kDenseNT; ++q) {
-        if (q < nt) {
-          const int col = 16 * q + (l & 15);
-          const T b = (krow < n && col < r) ? V[(size_t)krow * ld + col] : (T)0;
-          acc[q] = M::op(a, b, acc[q]);
-        }
+    for (int q = 0; q < VQ; ++q) {
+      const int e = q * kBlock + (int)threadIdx.x;
+      const int row = e / RC, col = e % RC;
+      vr[q] = (kb + row < n && col < r) ? V[(size_t)(kb + row) * ld + col] : (T)0;
+    }
+  };
+  if (k0 < k1) load_step(k0);
+  for (int kb = k0; kb < k1; kb += kDenseK) {
+#pragma unroll
+    for (int q = 0; q < CQ; ++q) {
+      const int e = (q * 64 + l) * VW;
+      const int row = e / kDenseK, kofs = e % kDenseK;
+#pragma unroll
+      for (int w = 0; w < VW; ++w) a_lds[row * SK + kofs + w] = cr[q][w];
+    }
+#pragma unroll
+    for (int q = 0; q < VQ; ++q) {
+      const int e = q * kBlock + (int)threadIdx.x;
+      sv[(e / RC) * SV + e % RC] = vr[q];
+    }
+    __syncthreads();
+    if (kb + kDenseK < k1) load_step(kb + kDenseK);  // in flight during the products
+    if (live) {
+#pragma unroll
+      for (int kk = 0; kk < kDenseK; kk += 4) {
+        const T a = a_lds[(l & 15) * SK + kk + (l >> 4)];
+        const T* brow = sv + (kk + (l >> 4)) * SV + (l & 15);
+#pragma unroll
+        for (int q = 0; q < NT; ++q) acc[q] = M::op(a, brow[16 * q], acc[q]);
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    __syncthreads();  // the blocks are read before the next step stages over them
   }
+  if (!live) return;
 #pragma unroll
-  for (int q = 0; q < kDenseNT; ++q) {
-    if (q >= nt) break;
+  for (int q = 0; q < NT; ++q) {
     const int col = 16 * q + (l & 15);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {

@@ -426,6 +426,10 @@ void op_grad_pair(Problem& P, const double* U, int r, int ld, double rho, double
   });
 }
 
+#ifndef LORADS_DENSE_BLOCKS
+#define LORADS_DENSE_BLOCKS 1024
+#endif
+
 template <typename T>
 void cdense_apply(Problem& P, const T* V, int r, int ld, T* out, int ldo, double alpha, double beta,
                   hipStream_t s) {
@@ -433,17 +437,23 @@ void cdense_apply(Problem& P, const T* V, int r, int ld, T* out, int ldo, double
     fail(LORADS_EINVAL, "dense C product: unsupported shape");
   const T* C = sizeof(T) == 8 ? (const T*)(const void*)P.cdense.p : (const T*)(const void*)P.cdensef.p;
   const int tiles = (P.n + 15) / 16;
+  const int groups = (tiles + 3) / 4;  // four tiles per block
   const int kblocks = P.ldc / kDenseK;
-  // about 2048 waves: ranges of whole 64-column blocks
-  const int want = std::max(1, std::min(kblocks, (2048 + tiles - 1) / tiles));
+  // about LORADS_DENSE_BLOCKS blocks: ranges of whole 64-column blocks
+  const int want = std::max(1, std::min(kblocks, (LORADS_DENSE_BLOCKS + groups - 1) / groups));
   const int kchunk = (kblocks + want - 1) / want * kDenseK;
   const int splits = (P.ldc + kchunk - 1) / kchunk;
   const size_t need = (size_t)splits * P.n * r * sizeof(T);
   if (P.cdpart.n < need) P.cdpart.alloc(need);
   T* part = reinterpret_cast<T*>(P.cdpart.p);
-  const int waves = tiles * splits;
-  cdense_partial<T><<<(waves + kBlock / 64 - 1) / (kBlock / 64), kBlock, 0, s>>>(
-      P.n, P.ldc, C, V, r, ld, tiles, splits, kchunk, part);
+  const int nt = (r + 15) / 16;
+  const int blocks = groups * splits;
+  switch (nt) {
+    case 1: cdense_partial<T, 1><<<blocks, kBlock, 0, s>>>(P.n, P.ldc, C, V, r, ld, tiles, splits, kchunk, part); break;
+    case 2: cdense_partial<T, 2><<<blocks, kBlock, 0, s>>>(P.n, P.ldc, C, V, r, ld, tiles, splits, kchunk, part); break;
+    case 3: cdense_partial<T, 3><<<blocks, kBlock, 0, s>>>(P.n, P.ldc, C, V, r, ld, tiles, splits, kchunk, part); break;
+    default: cdense_partial<T, 4><<<blocks, kBlock, 0, s>>>(P.n, P.ldc, C, V, r, ld, tiles, splits, kchunk, part); break;
+  }
   cdense_finish<T><<<grid_for((size_t)P.n * r), kBlock, 0, s>>>(P.n, r, splits, part, alpha, beta,
                                                                 out, ldo);
   HIPCHK(hipGetLastError());
