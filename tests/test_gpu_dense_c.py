@@ -9,7 +9,7 @@ its columns (partials added in a fixed order).  Checks:
   * lorads_apply_AT_V against the oracle's (c_scale C + A*(w)) V, FP64 to
     1e-12 and FP32 to 2e-5 relative, for a random dense symmetric C with
     general constraints (any transposed or misplaced tile fails) and for the
-    theta cost -J, ranks 1 .. 40 (one to three column tiles, ragged ones);
+    theta cost -J, ranks 1 .. 64 (one to four column tiles, ragged ones);
   * min <C, X> s.t. tr X = 1 with a random dense symmetric C: the optimum
     is the smallest eigenvalue of C (numpy's eigvalsh, independent code), to
     1e-6 relative, at n = 400 and at n = 2048, where the dense C (4.2M
@@ -55,7 +55,7 @@ def test_dense_flag(device):
 
 
 @pytest.mark.parametrize("name", sorted(PROBS))
-@pytest.mark.parametrize("r", [1, 5, 16, 23, 40])
+@pytest.mark.parametrize("r", [1, 5, 16, 23, 40, 50, 64])
 @pytest.mark.parametrize("c_scale", [1.0, -0.5])
 def test_dense_adjoint_f64(device, name, r, c_scale):
     import torch
@@ -75,11 +75,11 @@ def test_dense_adjoint_f64(device, name, r, c_scale):
 
 
 @pytest.mark.parametrize("name", sorted(PROBS))
-def test_dense_adjoint_f32(device, name):
+@pytest.mark.parametrize("r", [19, 64])
+def test_dense_adjoint_f32(device, name, r):
     import torch
     from paper_2403_09133_amd import Context
     p = PROBS[name]
-    r = 19
     rng = np.random.default_rng(2)
     V = rng.standard_normal((p.n, r)).astype(np.float32)
     w = rng.standard_normal(p.m).astype(np.float32)
