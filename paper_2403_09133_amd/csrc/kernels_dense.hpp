@@ -1,9 +1,11 @@
 // Dense cost matrix: out = alpha C V + beta out over the first r columns, with
-// C stored dense (n x ldc, row-major, ldc a multiple of 64, zero padding) and
+// C stored dense in 16 x 64 tiles (each tile one contiguous run of 1024
+// entries, row-major inside; the tiles of a 16-row band in column order, ldc
+// a multiple of 64, zero padding) and
 // the products on the matrix cores (v_mfma_f64_16x16x4f64 in FP64,
 // v_mfma_f32_16x16x4f32 in FP32).  With r small against n the product reads
 // C once and is bound by that stream (r / 4 flop per byte of C in FP64), so
-// the work is cut into many blocks: block (g, s) takes four 16-row tiles of C
+// the work is cut into many blocks: block (g, s) takes four or eight 16-row tiles of C
 // and the s-th range of columns k, and accumulates their 16 x r partial
 // products; cdense_finish adds the partials of the ranges in range order (a
 // fixed order).
@@ -37,16 +39,16 @@ struct DenseMfma<float> {
 };
 
 // part[(s n + i) r + c] = sum over the k of range s of C[i][k] V[k][c].
-// A block of four waves takes four consecutive 16-row tiles of C (wave w the
-// tile 4 g + w) and the s-th range of columns k, in 64-column steps.  Each step
-// stages the 64 x (16 NT) block of V once for the four waves and each wave's
-// 16 x 64 block of C in LDS (16-byte loads of whole rows), and the loads of the
+// A block of WPB waves takes WPB consecutive 16-row tiles of C (wave w the
+// tile WPB g + w) and the s-th range of columns k, in 64-column steps.  Each
+// step stages the 64 x (16 NT) block of V once for the WPB waves and each wave's
+// 16 x 64 tile of C in LDS (one contiguous 8 KB or 4 KB run), and the loads of the
 // next step are issued before this step's MFMAs, so the stream of C overlaps
 // the products.  NT = ceil(r / 16) column tiles of V; a lane's operands are
 // A[m][k] = C[i0 + (l & 15)][k] and B[k][j] = V[k][16 q + (l & 15)] with
 // k = kb + kk + (l >> 4), the k's of a step taken in order.
-template <typename T, int NT>
-__global__ void __launch_bounds__(kBlock) cdense_partial(int n, int ldc, const T* __restrict__ C,
+template <typename T, int NT, int WPB>
+__global__ void __launch_bounds__(64 * WPB) cdense_partial(int n, int ldc, const T* __restrict__ C,
                                                          const T* __restrict__ V, int r, int ld,
                                                          int tiles, int splits, int kchunk,
                                                          T* __restrict__ part) {
@@ -57,15 +59,19 @@ __global__ void __launch_bounds__(kBlock) cdense_partial(int n, int ldc, const T
   constexpr int RC = 16 * NT;            // V columns staged
   constexpr int SV = RC + 1;             // padded LDS row of the V block
   constexpr int CQ = 16 * kDenseK / (64 * VW);   // 16-byte C loads per lane and step
-  constexpr int VQ = kDenseK * RC / kBlock;      // V elements per thread and step
-  __shared__ T sa[kBlock / 64][16 * SK];
+  constexpr int BT = 64 * WPB;           // threads per block
+  constexpr int VQ = kDenseK * RC / BT;          // V elements per thread and step
+  static_assert(kDenseK * RC % BT == 0, "whole V elements per thread");
+  __shared__ T sa[WPB][16 * SK];
   __shared__ T sv[kDenseK * SV];
   const int l = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int sp = blockIdx.x % splits, tg = blockIdx.x / splits;
-  const int t = 4 * tg + wid;
+  const int t = WPB * tg + wid;
   const bool live = t < tiles;           // wave-uniform; every wave still takes the barriers
   const int i0 = 16 * t;
   const int k0 = sp * kchunk, k1 = min(ldc, k0 + kchunk);
+  // this wave's row band of tiles: a step reads one contiguous 16 x 64 tile
+  const T* ctile = C + (size_t)t * 16 * ldc;
   T* a_lds = sa[wid];
   typename M::acc4 acc[NT];
 #pragma unroll
@@ -81,11 +87,11 @@ __global__ void __launch_bounds__(kBlock) cdense_partial(int n, int ldc, const T
       const int row = e / kDenseK, kofs = e % kDenseK;
 #pragma unroll
       for (int w = 0; w < VW; ++w) cr[q][w] = (T)0;
-      if (live && i0 + row < n) cr[q] = *reinterpret_cast<const vec*>(C + (size_t)(i0 + row) * ldc + kb + kofs);
+      if (live && i0 + row < n) cr[q] = *reinterpret_cast<const vec*>(ctile + (size_t)(kb / kDenseK) * (16 * kDenseK) + e);
     }
 #pragma unroll
     for (int q = 0; q < VQ; ++q) {
-      const int e = q * kBlock + (int)threadIdx.x;
+      const int e = q * BT + (int)threadIdx.x;
       const int row = e / RC, col = e % RC;
       vr[q] = (kb + row < n && col < r) ? V[(size_t)(kb + row) * ld + col] : (T)0;
     }
@@ -101,7 +107,7 @@ __global__ void __launch_bounds__(kBlock) cdense_partial(int n, int ldc, const T
     }
 #pragma unroll
     for (int q = 0; q < VQ; ++q) {
-      const int e = q * kBlock + (int)threadIdx.x;
+      const int e = q * BT + (int)threadIdx.x;
       sv[(e / RC) * SV + e % RC] = vr[q];
     }
     __syncthreads();

@@ -437,7 +437,11 @@ void cdense_apply(Problem& P, const T* V, int r, int ld, T* out, int ldo, double
     fail(LORADS_EINVAL, "dense C product: unsupported shape");
   const T* C = sizeof(T) == 8 ? (const T*)(const void*)P.cdense.p : (const T*)(const void*)P.cdensef.p;
   const int tiles = (P.n + 15) / 16;
-  const int groups = (tiles + 3) / 4;  // four tiles per block
+  const int nt = (r + 15) / 16;
+  // eight tiles per block at one column tile (the staged V block is small, so
+  // two blocks of eight waves fit a CU), else four
+  const int wpb = nt == 1 ? 8 : 4;
+  const int groups = (tiles + wpb - 1) / wpb;
   const int kblocks = P.ldc / kDenseK;
   // about LORADS_DENSE_BLOCKS blocks: ranges of whole 64-column blocks
   const int want = std::max(1, std::min(kblocks, (LORADS_DENSE_BLOCKS + groups - 1) / groups));
@@ -446,13 +450,12 @@ void cdense_apply(Problem& P, const T* V, int r, int ld, T* out, int ldo, double
   const size_t need = (size_t)splits * P.n * r * sizeof(T);
   if (P.cdpart.n < need) P.cdpart.alloc(need);
   T* part = reinterpret_cast<T*>(P.cdpart.p);
-  const int nt = (r + 15) / 16;
   const int blocks = groups * splits;
   switch (nt) {
-    case 1: cdense_partial<T, 1><<<blocks, kBlock, 0, s>>>(P.n, P.ldc, C, V, r, ld, tiles, splits, kchunk, part); break;
-    case 2: cdense_partial<T, 2><<<blocks, kBlock, 0, s>>>(P.n, P.ldc, C, V, r, ld, tiles, splits, kchunk, part); break;
-    case 3: cdense_partial<T, 3><<<blocks, kBlock, 0, s>>>(P.n, P.ldc, C, V, r, ld, tiles, splits, kchunk, part); break;
-    default: cdense_partial<T, 4><<<blocks, kBlock, 0, s>>>(P.n, P.ldc, C, V, r, ld, tiles, splits, kchunk, part); break;
+    case 1: cdense_partial<T, 1, 8><<<blocks, 512, 0, s>>>(P.n, P.ldc, C, V, r, ld, tiles, splits, kchunk, part); break;
+    case 2: cdense_partial<T, 2, 4><<<blocks, 256, 0, s>>>(P.n, P.ldc, C, V, r, ld, tiles, splits, kchunk, part); break;
+    case 3: cdense_partial<T, 3, 4><<<blocks, 256, 0, s>>>(P.n, P.ldc, C, V, r, ld, tiles, splits, kchunk, part); break;
+    default: cdense_partial<T, 4, 4><<<blocks, 256, 0, s>>>(P.n, P.ldc, C, V, r, ld, tiles, splits, kchunk, part); break;
   }
   cdense_finish<T><<<grid_for((size_t)P.n * r), kBlock, 0, s>>>(P.n, r, splits, part, alpha, beta,
                                                                 out, ldo);

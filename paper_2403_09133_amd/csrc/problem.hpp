@@ -162,8 +162,9 @@ struct Problem {
   // partials of the small Gram products of the quadratic objective
   DevBuf<double> qpart;
   // dense C (at least a quarter of the n^2 entries, n >= kDenseCMinN): also
-  // stored n x ldc row-major (ldc a multiple of 64, zero padding), FP64 and
-  // FP32; products with C then run on the matrix cores (cdense_apply), with
+  // stored in 16 x 64 tiles, each one contiguous run (row bands of 16 rows,
+  // ldc a multiple of 64 columns, zero padding), FP64 and FP32; products with
+  // C then run on the matrix cores (cdense_apply), with
   // their split partials in cdpart
   DevBuf<double> cdense;
   DevBuf<float> cdensef;

@@ -323,10 +323,17 @@ std::unique_ptr<Problem> ingest(const lorads_problem& p, hipStream_t s) {
     // a dense C (a quarter of the entries or more) is also kept dense, for
     // the matrix-core products
     if (n >= kDenseCMinN && n <= 32768 && (double)nc >= 0.25 * (double)n * n) {
+      // tile-major: the 16 x 64 tile of rows 16 t .. 16 t + 15 and columns
+      // 64 b .. 64 b + 63 is one contiguous run of 1024 entries (row-major
+      // inside), the tiles of a row band in column order; entries past n are zero
       const int ldc = (n + 63) / 64 * 64;
-      std::vector<double> cdn((size_t)n * ldc, 0.0);
+      const size_t bands = (size_t)(n + 15) / 16, kb = (size_t)ldc / 64;
+      std::vector<double> cdn(bands * 16 * ldc, 0.0);
       for (int j = 0; j < n; ++j)
-        for (int e = cptr[j]; e < cptr[j + 1]; ++e) cdn[(size_t)j * ldc + ccol[e]] += cval[e];
+        for (int e = cptr[j]; e < cptr[j + 1]; ++e) {
+          const size_t c = (size_t)ccol[e];
+          cdn[(((size_t)(j / 16) * kb + c / 64) * 16 + (size_t)(j % 16)) * 64 + c % 64] += cval[e];
+        }
       std::vector<float> cdf(cdn.begin(), cdn.end());
       P->cdense.upload(cdn, s);
       P->cdensef.upload(cdf, s);
