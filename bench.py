@@ -196,11 +196,13 @@ def per_operator(q, rq: int, reps: int, rng):
                 adjoint_s=round(float(np.median(ta)), 5))
 
 
-def cpu_baseline(p, r: int, budget_s: float = 20.0, e2e=("maxcut_er200",), workload: str = "mc_20000"):
+def cpu_baseline(p, r: int, budget_s: float = 20.0, e2e=("maxcut_er200",), workload: str = "mc_20000",
+                 per_op=(("maxcut_torus100", 5), ("mc_10000", 5)), per_op_all=(("mc_10000", 5),)):
     """The oracle's forward map and adjoint product (FP64, numpy) on the host,
     one thread, for a bounded number of applications; per-operator medians on
     other configurations, one thread and with numpy's thread pools
-    unrestricted (workload: the timed workload's name); plus the oracle's end-to-end
+    unrestricted (per_op, per_op_all: configuration names and repetitions;
+    workload: the timed workload's name); plus the oracle's end-to-end
     solves to eq. (stop) of the named instances (by default the MaxCut
     instance of order 200), one thread, from the library's initial rank."""
     try:
@@ -226,10 +228,10 @@ def cpu_baseline(p, r: int, budget_s: float = 20.0, e2e=("maxcut_er200",), workl
             if t > budget_s / 2 or reps >= 8:
                 break
         # per-operator medians at full size on the other configurations
-        per_op = {}
-        for name, reps_ in (("maxcut_torus100", 5), ("mc_10000", 5)):
+        per_op_1 = {}
+        for name, reps_ in per_op:
             q = sdpgen.config_instance(name)
-            per_op[name] = per_operator(q, initial_rank(q), reps_, rng)
+            per_op_1[name] = per_operator(q, initial_rank(q), reps_, rng)
         solves = []
         for name in e2e:
             q = sdpgen.config_instance(name)
@@ -248,20 +250,21 @@ def cpu_baseline(p, r: int, budget_s: float = 20.0, e2e=("maxcut_er200",), workl
         if ctx is not None and hasattr(ctx, "unregister"):
             ctx.unregister()
     # the same per-operator loops with numpy's thread pools unrestricted
-    per_op_all = dict(threads=os.cpu_count())
+    all_threads = dict(threads=os.cpu_count())
     if threadpool_limits is not None:
         from threadpoolctl import threadpool_info
-        per_op_all["threads"] = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    per_op_all["mc_10000"] = per_operator(sdpgen.config_instance("mc_10000"), initial_rank(
-        sdpgen.config_instance("mc_10000")), 5, rng)
-    per_op_all[workload] = per_operator(p, r, 3, rng)
+        all_threads["threads"] = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    for name, reps_ in per_op_all:
+        q = sdpgen.config_instance(name)
+        all_threads[name] = per_operator(q, initial_rank(q), reps_, rng)
+    all_threads[workload] = per_operator(p, r, 3, rng)
     bytes_pair = 2 * (8.0 * p.m + 8.0 * p.m + 2.0 * p.n * r * 8)
     return dict(value=round(reps * bytes_pair / t / 1e9, 4), unit="GB/s", cores=1, kind="oracle",
                 sample=f"{reps} x (A(UV^T) + (C + A*(y))V) at full size, r={r}, FP64 numpy, "
                        f"{t:.1f} s on the host",
                 host=host_cpu(),
-                per_operator_median=per_op,
-                per_operator_median_all_threads=per_op_all,
+                per_operator_median=per_op_1,
+                per_operator_median_all_threads=all_threads,
                 oracle_time_to_kkt_s=solves)
 
 
